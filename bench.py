@@ -1,0 +1,156 @@
+"""Benchmark of the voting transform on one MI355X.
+
+A step is one pass of the hot path over one chip's catalog, already resident
+in HBM: sas_vote (reference epoch, window index, dense LDS vote over the
+whole velocity grid) followed by sas_peaks (device -> host candidates in
+canonical order).  Default workload: the wide-field chip (2048x4096 px,
+100 epochs over 4 h, 3000 noise detections per epoch plus 200 movers, 4 px
+bins, sector grid of 84,351 velocities, N_min = 25).
+
+Prints one JSON line (rank 0).  --gpus above 1 is refused: this build
+measures one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published / derived peaks
+HBM_PEAK_GBS = 8000.0
+N_CU, CLOCK_GHZ = 256, 2.4
+LDS_BANKS, LDS_BANK_BYTES = 32, 4
+# one 4-byte LDS access per bank per clock on every CU
+LDS_PEAK_GBS = N_CU * LDS_BANKS * LDS_BANK_BYTES * CLOCK_GHZ
+
+
+def _workload(name):
+    from paper_2509_26279_amd import synth
+    if name == "wide":
+        return synth.make_wide()
+    if name == "fast":
+        return synth.make_fast()
+    if name == "tiny":
+        return synth.make_tiny()
+    raise SystemExit("unknown workload " + name)
+
+
+def cpu_baseline(wl, v, seconds):
+    """The oracle as it stands, on the host cores, over a seeded velocity sample."""
+    import numpy as np
+
+    import oracle
+    threads = len(os.sched_getaffinity(0))
+    if os.environ.get("OMP_NUM_THREADS"):
+        threads = min(threads, int(os.environ["OMP_NUM_THREADS"]))
+    rng = np.random.default_rng(0)
+    probe = np.sort(rng.choice(len(v), size=min(threads, len(v)), replace=False))
+    t0 = time.perf_counter()
+    oracle.vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v[probe], wl.binw_q8, wl.n_min,
+                "epochs", 255, threads=threads)
+    dt = time.perf_counter() - t0
+    k = int(max(threads, min(len(v), threads * round(seconds / max(dt, 1e-3)))))
+    sample = np.sort(rng.choice(len(v), size=k, replace=False))
+    t0 = time.perf_counter()
+    c = oracle.vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v[sample], wl.binw_q8, wl.n_min,
+                    "epochs", 255, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": wl.n * k / dt, "unit": "votes/s", "cores": threads, "kind": "oracle",
+            "sample": "%d of %d velocities (seeded), full catalog of %d detections, %.1f s"
+                      % (k, len(v), wl.n, dt),
+            "candidates": int(len(c))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="wide")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU; --gpus %d is not supported by this build" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2509_26279_amd import sas
+
+    wl = _workload(args.workload)
+    v = sas.grid_from_spec(wl.grid, wl.binw_q8, wl.span_q16)
+    count_sat = 255 if wl.count_dtype == "u8" else 65535
+    plan = sas.Plan(v, wl.t_q16, wl.binw_q8, wl.n_min, wl.extent_q8, count_sat=count_sat)
+    info = plan.info()
+    s = sas.Search(plan, wl.n, cand_cap=1 << 22)
+    x, y, e = s.upload(wl.x_q8, wl.y_q8, wl.epoch)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        s.vote(x, y, e)
+        out = s.peaks()
+    torch.cuda.synchronize()
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        evs[k][0].record(stream)
+        s.vote(x, y, e)
+        evs[k][1].record(stream)
+        out = s.peaks()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    vote_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    ms_step = wall * 1000.0 / args.steps
+    votes = float(wl.n) * len(v)
+    n_cand = len(out)
+
+    lds_bytes = 4.0 * votes  # one 4-byte LDS atomic per vote
+    achieved = lds_bytes / (vote_ms * 1e-3) / 1e9
+    rec = {
+        "metric": "detection-velocity votes/s per chip",
+        "value": votes / (ms_step * 1e-3),
+        "unit": "votes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "%s chip: %dx%d px, %d epochs over %.0f h, %d detections, "
+                               "%d velocities, %.0f px bins, N_min %d"
+                               % (wl.name, wl.width_px, wl.height_px, wl.n_epochs, wl.span_h,
+                                  wl.n, len(v), wl.bin_px, wl.n_min),
+                   "n_detections": wl.n, "n_velocities": int(len(v)),
+                   "n_epochs": wl.n_epochs, "parallelism": "single-gpu"},
+        "candidates_per_s": n_cand / (ms_step * 1e-3),
+        "n_candidates": n_cand,
+        "vote_ms": vote_ms,
+        "vote_votes_per_s": votes / (vote_ms * 1e-3),
+        "plan": info,
+        "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / LDS_PEAK_GBS, "traffic": None,
+                     "kernel": "sas_vote (preparation + dense LDS vote)"},
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(wl, v, args.cpu_seconds)
+    plan.close()
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,233 @@
+/*
+ * sas.h - C ABI of the catalog shift-and-stack voting transform on MI355X.
+ *
+ * The method (Stetzler et al., "An Efficient Shift-and-Stack Algorithm
+ * Applied to Detection Catalogs", Sec. 2.1) takes a detection catalog
+ * C = [x_i, y_i, t_i], a set of trial velocities V, a cluster size Delta x
+ * and a minimum count N_min, and:
+ *   Step 1 (Project) moves every detection back to the reference epoch t0,
+ *          the earliest observation time in the catalog, along each trial
+ *          velocity (linear motion, eqs. 1-2);
+ *   Step 2 (Cluster) histograms the projected positions of each velocity with
+ *          square bins of side Delta x;
+ *   Step 3 (Find clusters) stops at bins whose count is below N_min.
+ * This library computes Steps 1-2 exactly and reports every bin whose count
+ * reaches N_min (the Step-3 threshold, without the greedy removal loop).
+ *
+ * Number formats (integers only cross the ABI):
+ *   positions   Q8 pixels          int32   x_q8 = floor(256 * x_px)
+ *   velocities  Q8 pixels / hour   int32
+ *   times       Q16 hours          int64   any origin
+ *   bin width   Q8 pixels          int32   (a power of two on the GPU path)
+ * With d = t[e] - t0 (Q16 h), the projected position is the exact Q24 value
+ *   X = 65536 * x - vx * d,  and the bin is bx = floor(X / (65536 * binw)),
+ * the same for y.  Bins are anchored at 0 and half open: [k b, (k+1) b).
+ * Count of a bin: the number of distinct epochs among its detections
+ * (SAS_MODE_EPOCHS) or the number of its detections (SAS_MODE_DETECTIONS).
+ *
+ * Memory: "host" pointers are ordinary CPU memory, "device" pointers are
+ * HIP device memory (hipMalloc or a framework's allocator) of the GPU that
+ * is current when the call is made.  The caller owns every buffer passed
+ * in; the library never frees them.  Plans own the device memory they
+ * allocate until sas_plan_destroy.
+ *
+ * Streams: `stream` arguments are hipStream_t values passed as void*;
+ * NULL means the default stream.  Asynchronous calls only enqueue work.
+ *
+ * Errors: every call returns a sas_status.  Argument errors are detected on
+ * the host before anything is enqueued.  Data errors found on the device
+ * (an epoch index >= E, a detection outside the declared footprint) are
+ * recorded in the sas_vote_result and reported by sas_peaks.  A failing
+ * HIP call returns SAS_E_DEVICE.  sas_last_error() gives a thread-local
+ * message describing the last failure of the calling thread.
+ */
+#ifndef SAS_H
+#define SAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sas_status;
+#define SAS_OK 0
+#define SAS_E_INVALID (-1)     /* bad argument or bad catalog data */
+#define SAS_E_NOMEM (-2)       /* device or host allocation failed */
+#define SAS_E_OVERFLOW (-3)    /* an output buffer is too small; the needed size is reported */
+#define SAS_E_DEVICE (-4)      /* a HIP call failed, or no usable GPU */
+#define SAS_E_UNSUPPORTED (-5) /* valid request outside what the GPU path implements */
+#define SAS_E_WORKSPACE (-6)   /* workspace smaller than sas_vote_workspace_size() */
+
+/* Device-side data errors (bits of sas_vote_result.status). */
+#define SAS_DATA_BAD_EPOCH 1   /* an epoch index >= n_epochs */
+#define SAS_DATA_OUTSIDE 2     /* a detection outside the plan's footprint */
+
+const char *sas_status_string(sas_status s);
+/* Message of the calling thread's last failing call ("" if none). */
+const char *sas_last_error(void);
+/* Library version string. */
+const char *sas_version(void);
+
+/* ------------------------------------------------------------------------
+ * Velocity grid (Sec. 2: the residuals of an object stay inside one cluster
+ * of size Delta x when each velocity component is off by at most
+ * Delta x / Delta t; eq. v_size counts the resulting set).
+ * ---------------------------------------------------------------------- */
+#define SAS_GRID_BOX 0     /* vx in [vmin, vmax], vy in [vy_min, vy_max]       */
+#define SAS_GRID_DISK 1    /* |v| <= vmax                                       */
+#define SAS_GRID_ANNULUS 2 /* vmin <= |v| <= vmax                               */
+#define SAS_GRID_SECTOR 3  /* annulus and direction within angle +- half_width   */
+
+typedef struct {
+    int32_t shape;          /* SAS_GRID_* */
+    double vmin, vmax;      /* px/h: box vx range, or speed range */
+    double vy_min, vy_max;  /* px/h: box only */
+    double angle_deg;       /* sector: centre direction (deg, from +x toward +y) */
+    double half_width_deg;  /* sector: half opening, in (0, 90) */
+    int32_t binw_q8;        /* Delta x, Q8 px (> 0) */
+    int64_t span_q16;       /* Delta t, Q16 h (> 0): last minus first epoch */
+    int32_t spacing_q8;     /* 0: floor(binw_q8 * 65536 / span_q16); else this value */
+} sas_grid_spec;
+
+/* Lattice spacing floor(binw_q8 * 65536 / span_q16) in Q8 px/h (>= 1). */
+sas_status sas_grid_spacing(int32_t binw_q8, int64_t span_q16, int32_t *spacing_out);
+
+/*
+ * sas_build_grid: lattice points (i s, j s) whose closed cell
+ * [p - s/2, p + s/2]^2 meets the region, written to v_out_host as
+ * (vx, vy) int32 pairs in row-major (vy, vx) order.  That order defines
+ * v_idx.  Two-call protocol: *n_out always receives the full count; if cap
+ * is smaller, only the first cap points are written and SAS_E_OVERFLOW is
+ * returned.  v_out_host == NULL with cap == 0 is a pure count query (SAS_OK).
+ * Host only; no device is touched.
+ */
+sas_status sas_build_grid(const sas_grid_spec *spec, int32_t *v_out_host, int64_t cap,
+                          int64_t *n_out);
+
+/* ------------------------------------------------------------------------
+ * Candidates and results
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    uint32_t v_idx;  /* index of the trial velocity in the plan's velocity set */
+    int32_t bx, by;  /* bin of the projected positions, anchored at 0 */
+    uint16_t count;  /* distinct epochs (or detections), capped at count_sat */
+    uint16_t flags;  /* bit 0: the true count exceeded count_sat */
+} sas_candidate;     /* 16 bytes */
+
+typedef struct {
+    int64_t n_cand;  /* total candidates found; may exceed the buffer capacity */
+    int32_t status;  /* SAS_DATA_* bits, 0 when the catalog was valid */
+    int32_t reserved;
+} sas_vote_result;   /* 16 bytes, device resident, written by sas_vote */
+
+#define SAS_MODE_EPOCHS 0
+#define SAS_MODE_DETECTIONS 1
+
+#define SAS_PATH_AUTO 0
+#define SAS_PATH_DENSE 1   /* LDS-resident count tiles (velocity block x spatial tile) */
+#define SAS_PATH_SORT 2    /* sort-by-bin-key in HBM */
+
+/* Launch shape of the dense path; zeros select the built-in defaults. */
+typedef struct {
+    int32_t tile_x, tile_y;     /* bins per LDS tile; tile_x * tile_y <= 16384 */
+    int32_t vblock_x, vblock_y; /* velocity-block extent in lattice steps */
+    int32_t cell_log2;          /* log2 of the window-index cell size in Q8 px */
+    int32_t sort_vblock;        /* velocities per sort-path block */
+    int32_t reserved[4];
+} sas_tuning;
+
+/* ------------------------------------------------------------------------
+ * Plans: host analysis of (velocity set, epochs, parameters, footprint).
+ * A plan fixes the work decomposition and holds its tables in device
+ * memory, so that sas_vote itself allocates nothing, never synchronises
+ * and can be captured into a HIP graph.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    const int32_t *v_host;  /* host [n_v][2] Q8 px/h; row j is velocity v_idx = j */
+    int64_t n_v;            /* >= 0 */
+    int32_t n_epochs;       /* E in [1, 256] */
+    const int64_t *t_q16;   /* host [E] epoch times, Q16 h; max - min < 2^31 */
+    int32_t binw_q8;        /* Delta x in Q8 px: a power of two in [1, 2^20] */
+    int32_t n_min;          /* >= 1 */
+    int32_t mode;           /* SAS_MODE_* */
+    int32_t count_sat;      /* 255 or 65535: largest reportable count */
+    int32_t path;           /* SAS_PATH_* */
+    int32_t extent_q8[4];   /* footprint x0, x1, y0, y1 (Q8): every detection must
+                               satisfy x0 <= x < x1 and y0 <= y < y1; |values| < 2^30 */
+    const sas_tuning *tuning; /* NULL: defaults */
+} sas_plan_desc;
+
+typedef struct sas_plan sas_plan;
+
+/*
+ * sas_plan_create: validate the description, decompose the work and upload
+ * the plan tables to the current device (allocates; synchronous).  The
+ * velocity array is copied; the caller may free it on return.
+ * Errors: SAS_E_INVALID (arguments; message in sas_last_error),
+ * SAS_E_UNSUPPORTED (bin width not a power of two, |v| * Delta t too large
+ * for 32-bit bins), SAS_E_NOMEM, SAS_E_DEVICE.
+ */
+sas_status sas_plan_create(const sas_plan_desc *desc, sas_plan **plan_out);
+sas_status sas_plan_destroy(sas_plan *plan);
+/* Work-decomposition facts: items, velocity blocks, path chosen. */
+typedef struct {
+    int64_t n_items;
+    int64_t n_blocks;
+    int32_t path;
+    int32_t tile_x, tile_y;
+    int32_t vblock_x, vblock_y;
+    int32_t cell_log2;
+    int64_t n_v;
+} sas_plan_info;
+sas_status sas_plan_get_info(const sas_plan *plan, sas_plan_info *info);
+
+/* Device workspace needed by sas_vote for a catalog of n detections. */
+sas_status sas_vote_workspace_size(const sas_plan *plan, int64_t n, size_t *bytes);
+
+/*
+ * sas_vote: enqueue the voting transform of one catalog on `stream`.
+ *   x_q8, y_q8, epoch: device [n]; epoch values in [0, n_epochs).
+ *   cand_dev:  device [cand_cap] candidate records (unordered).
+ *   res_dev:   device sas_vote_result; n_cand counts every candidate even
+ *              past cand_cap (later ones are not written).
+ *   workspace: device, >= sas_vote_workspace_size(plan, n) bytes,
+ *              256-byte aligned; its contents are scratch.
+ * Asynchronous: returns once the work is enqueued.  No allocation, no
+ * synchronisation, no memset nodes: safe to capture in a HIP graph.  Calls
+ * that share a workspace or a result must be ordered by the caller.
+ * Errors (host side, nothing enqueued): SAS_E_INVALID, SAS_E_WORKSPACE.
+ */
+sas_status sas_vote(const sas_plan *plan, const int32_t *x_q8, const int32_t *y_q8,
+                    const uint8_t *epoch, int64_t n, sas_candidate *cand_dev, int64_t cand_cap,
+                    sas_vote_result *res_dev, void *workspace, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Peaks: collect the candidates of a finished vote in a deterministic order.
+ * ---------------------------------------------------------------------- */
+#define SAS_ORDER_CANONICAL 0 /* (v_idx, by, bx) ascending */
+#define SAS_ORDER_BY_COUNT 1  /* count descending, then (v_idx, by, bx) */
+
+/*
+ * sas_peaks: synchronise `stream`, read the result and copy the candidates
+ * to out_host in the requested order; with top_k > 0 only the first top_k
+ * of that order (the "first clusters with the highest number of
+ * detections" of Sec. 3.3 when order is BY_COUNT).
+ *   *n_out receives the number of records written.
+ * Returns SAS_E_INVALID if the vote flagged bad catalog data (message
+ * names the flag), SAS_E_OVERFLOW if the vote found more candidates than
+ * cand_cap (then *n_out is the true total and the caller reruns with a
+ * larger buffer) or if out_cap is too small (then *n_out is the needed
+ * size).  The output is identical for every path, tuning and ordering of
+ * the input catalog.
+ */
+sas_status sas_peaks(const sas_candidate *cand_dev, const sas_vote_result *res_dev,
+                     int64_t cand_cap, int32_t order, int64_t top_k, sas_candidate *out_host,
+                     int64_t out_cap, int64_t *n_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SAS_H */

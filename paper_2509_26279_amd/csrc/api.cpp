@@ -1,0 +1,470 @@
+// Host side of libsas: argument validation, work decomposition (plans),
+// workspace layout, launches and candidate collection.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <memory>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace sas {
+
+thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+namespace {
+
+sas_status fail(sas_status s, const std::string &msg) {
+    set_error(msg);
+    return s;
+}
+
+sas_status hip_fail(hipError_t e, const char *what) {
+    return fail(SAS_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int64_t floor_div(__int128 a, __int128 b) {  // b > 0
+    __int128 q = a / b;
+    if ((a % b != 0) && (a < 0)) q -= 1;
+    return (int64_t)q;
+}
+
+int ilog2_exact(int64_t v) {  // -1 unless v is a power of two
+    if (v <= 0 || (v & (v - 1))) return -1;
+    int k = 0;
+    while ((int64_t(1) << k) < v) ++k;
+    return k;
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+}  // namespace
+}  // namespace sas
+
+using namespace sas;
+
+struct sas_plan {
+    int device = 0;
+    int32_t n_epochs = 0;
+    std::vector<int64_t> t;
+    int64_t span = 0;
+    int32_t binw = 0, log2b = 0, n_min = 1, mode = 0, count_sat = 65535, path = 0;
+    int32_t ext[4] = {0, 0, 0, 0};
+    int64_t n_v = 0;
+    int dense_mode = 0;
+    int32_t tile_x = 64, tile_y = 64, vbx = 8, vby = 8, cell_log2 = 15;
+    int32_t ncx = 1, ncy = 1;
+    int64_t n_cells = 0, n_items = 0, n_blocks = 0;
+    int32_t *d_vel = nullptr, *d_members = nullptr, *d_block_start = nullptr;
+    int32_t *d_block_vr = nullptr, *d_items = nullptr;
+    int64_t *d_t = nullptr;
+    std::vector<void *> allocs;
+};
+
+namespace {
+
+template <typename T>
+sas_status upload(sas_plan *p, T **dst, const std::vector<T> &src) {
+    const size_t bytes = std::max<size_t>(src.size(), 1) * sizeof(T);
+    void *d = nullptr;
+    hipError_t e = hipMalloc(&d, bytes);
+    if (e != hipSuccess) return fail(SAS_E_NOMEM, std::string("plan upload: ") + hipGetErrorString(e));
+    p->allocs.push_back(d);
+    if (!src.empty()) {
+        e = hipMemcpy(d, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "plan upload");
+    }
+    *dst = (T *)d;
+    return SAS_OK;
+}
+
+struct WsLayout {
+    size_t count, blocksum, cellid, rank, sx, sy, present, dt, total;
+};
+
+WsLayout ws_layout(const sas_plan *p, int64_t n) {
+    WsLayout L{};
+    size_t o = 0;
+    const int64_t n_count = p->n_cells + 1;
+    const int64_t nb = (n_count + kScanTile - 1) / kScanTile;
+    const size_t nn = (size_t)std::max<int64_t>(n, 1);
+    L.count = o; o = align_up(o + sizeof(int32_t) * n_count);
+    L.blocksum = o; o = align_up(o + sizeof(int32_t) * nb);
+    L.cellid = o; o = align_up(o + sizeof(int32_t) * nn);
+    L.rank = o; o = align_up(o + sizeof(int32_t) * nn);
+    L.sx = o; o = align_up(o + sizeof(int32_t) * nn);
+    L.sy = o; o = align_up(o + sizeof(int32_t) * nn);
+    L.present = o; o = align_up(o + sizeof(int32_t) * kMaxEpochs);
+    L.dt = o; o = align_up(o + sizeof(int32_t) * kMaxEpochs);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sas_status_string(sas_status s) {
+    switch (s) {
+    case SAS_OK: return "SAS_OK";
+    case SAS_E_INVALID: return "SAS_E_INVALID";
+    case SAS_E_NOMEM: return "SAS_E_NOMEM";
+    case SAS_E_OVERFLOW: return "SAS_E_OVERFLOW";
+    case SAS_E_DEVICE: return "SAS_E_DEVICE";
+    case SAS_E_UNSUPPORTED: return "SAS_E_UNSUPPORTED";
+    case SAS_E_WORKSPACE: return "SAS_E_WORKSPACE";
+    default: return "SAS_E_UNKNOWN";
+    }
+}
+
+const char *sas_last_error(void) { return g_last_error.c_str(); }
+
+const char *sas_version(void) { return "sas-mi355x 0.1 (gfx950)"; }
+
+sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
+    if (!d || !plan_out) return fail(SAS_E_INVALID, "sas_plan_create: null argument");
+    *plan_out = nullptr;
+    if (d->n_v < 0 || d->n_v >= ((int64_t)1 << 31))
+        return fail(SAS_E_INVALID, "sas_plan_create: n_v must be in [0, 2^31)");
+    if (d->n_v > 0 && !d->v_host) return fail(SAS_E_INVALID, "sas_plan_create: v_host is null");
+    if (d->n_epochs < 1 || d->n_epochs > kMaxEpochs)
+        return fail(SAS_E_INVALID, "sas_plan_create: n_epochs must be in [1, 256]");
+    if (!d->t_q16) return fail(SAS_E_INVALID, "sas_plan_create: t_q16 is null");
+    if (d->binw_q8 <= 0) return fail(SAS_E_INVALID, "sas_plan_create: binw_q8 must be > 0");
+    if (d->n_min < 1) return fail(SAS_E_INVALID, "sas_plan_create: n_min must be >= 1");
+    if (d->mode != SAS_MODE_EPOCHS && d->mode != SAS_MODE_DETECTIONS)
+        return fail(SAS_E_INVALID, "sas_plan_create: unknown mode");
+    if (d->count_sat != 255 && d->count_sat != 65535)
+        return fail(SAS_E_INVALID, "sas_plan_create: count_sat must be 255 or 65535");
+    if (d->path < SAS_PATH_AUTO || d->path > SAS_PATH_SORT)
+        return fail(SAS_E_INVALID, "sas_plan_create: unknown path");
+    const int32_t *ex = d->extent_q8;
+    for (int k = 0; k < 4; ++k)
+        if (ex[k] <= -(1 << 30) || ex[k] >= (1 << 30))
+            return fail(SAS_E_INVALID, "sas_plan_create: footprint values must satisfy |v| < 2^30");
+    if (!(ex[0] < ex[1] && ex[2] < ex[3]))
+        return fail(SAS_E_INVALID, "sas_plan_create: empty footprint");
+    const int log2b = ilog2_exact(d->binw_q8);
+    if (log2b < 0 || log2b > 20)
+        return fail(SAS_E_UNSUPPORTED,
+                    "sas_plan_create: the GPU path needs a power-of-two bin width <= 2^20 (Q8)");
+
+    int64_t tmin = d->t_q16[0], tmax = d->t_q16[0];
+    for (int e = 1; e < d->n_epochs; ++e) {
+        tmin = std::min(tmin, d->t_q16[e]);
+        tmax = std::max(tmax, d->t_q16[e]);
+    }
+    const __int128 span128 = (__int128)tmax - tmin;
+    if (span128 >= ((__int128)1 << 31))
+        return fail(SAS_E_INVALID, "sas_plan_create: epoch times must span less than 2^31 (Q16 h)");
+    const int64_t span = (int64_t)span128;
+
+    sas_tuning tu{};
+    if (d->tuning) tu = *d->tuning;
+    const int32_t TX = tu.tile_x ? tu.tile_x : 64, TY = tu.tile_y ? tu.tile_y : 64;
+    if (TX < 4 || TY < 1 || TX % 4 || TX > 1024 || TY > 1024 || (int64_t)TX * TY > 16384)
+        return fail(SAS_E_INVALID, "sas_plan_create: tile must satisfy 4 <= tile_x (multiple of 4), "
+                                   "tile_x * tile_y <= 16384");
+    const int32_t vbx = tu.vblock_x ? tu.vblock_x : 8, vby = tu.vblock_y ? tu.vblock_y : 8;
+    if (vbx < 1 || vby < 1 || vbx > 1024 || vby > 1024)
+        return fail(SAS_E_INVALID, "sas_plan_create: vblock sizes must be in [1, 1024]");
+    int tx_log = 0;
+    while ((1 << (tx_log + 1)) <= std::max(TX, TY)) ++tx_log;
+    int cl = tu.cell_log2 ? tu.cell_log2 : std::max(0, log2b + tx_log - 1);
+    if (cl < 0 || cl > 30) return fail(SAS_E_INVALID, "sas_plan_create: cell_log2 out of range");
+    auto ncells_of = [&](int c, int64_t lo, int64_t hi) { return ((hi - lo) + (1LL << c) - 1) >> c; };
+    while (ncells_of(cl, ex[0], ex[1]) > 32767 || ncells_of(cl, ex[2], ex[3]) > 32767) ++cl;
+    const int64_t ncx = ncells_of(cl, ex[0], ex[1]), ncy = ncells_of(cl, ex[2], ex[3]);
+    const int64_t n_cells = (int64_t)d->n_epochs * ncx * ncy;
+    if (n_cells >= ((int64_t)1 << 30))
+        return fail(SAS_E_INVALID, "sas_plan_create: window index too large; raise cell_log2");
+
+    // velocities: range checks
+    const int64_t n_v = d->n_v;
+    const __int128 B = (__int128)1 << (16 + log2b);
+    const __int128 lim_bins = (__int128)1 << 29;
+    for (int64_t j = 0; j < n_v; ++j) {
+        for (int a = 0; a < 2; ++a) {
+            const int64_t v = d->v_host[2 * j + a];
+            if ((__int128)(v < 0 ? -v : v) * span >= ((__int128)1 << 46))
+                return fail(SAS_E_UNSUPPORTED, "sas_plan_create: |v| * span too large (>= 2^46 Q24)");
+        }
+    }
+
+    {   // tile-relative Q8 coordinates are held in 32 bits by the kernels
+        int64_t vmax_abs = 0;
+        for (int64_t j = 0; j < 2 * n_v; ++j)
+            vmax_abs = std::max<int64_t>(vmax_abs, d->v_host[j] < 0 ? -(int64_t)d->v_host[j]
+                                                                    : d->v_host[j]);
+        const __int128 shift_q8 = ((__int128)vmax_abs * span >> 16) + 1;
+        const __int128 tile_q8 = (__int128)std::max(TX, TY) * d->binw_q8;
+        const __int128 reach = (__int128)std::max<int64_t>((int64_t)ex[1] - ex[0],
+                                                           (int64_t)ex[3] - ex[2]) +
+                               shift_q8 + tile_q8;
+        if (reach >= ((__int128)1 << 30))
+            return fail(SAS_E_UNSUPPORTED, "sas_plan_create: footprint + largest shift + tile "
+                                           "must stay below 2^30 Q8 px");
+    }
+
+    std::unique_ptr<sas_plan> p(new sas_plan());
+    hipError_t he = hipGetDevice(&p->device);
+    if (he != hipSuccess) return hip_fail(he, "sas_plan_create: no device");
+    p->n_epochs = d->n_epochs;
+    p->t.assign(d->t_q16, d->t_q16 + d->n_epochs);
+    p->span = span;
+    p->binw = d->binw_q8;
+    p->log2b = log2b;
+    p->n_min = d->n_min;
+    p->mode = d->mode;
+    p->count_sat = d->count_sat;
+    p->path = d->path == SAS_PATH_AUTO ? SAS_PATH_DENSE : d->path;
+    if (p->path == SAS_PATH_SORT)
+        return fail(SAS_E_UNSUPPORTED, "sas_plan_create: the sort path is not built in this library");
+    std::memcpy(p->ext, ex, sizeof(p->ext));
+    p->n_v = n_v;
+    p->dense_mode = d->mode == SAS_MODE_DETECTIONS ? kCountDet
+                    : (d->n_epochs <= 32 ? kMask32 : kCountEpo);
+    p->tile_x = TX;
+    p->tile_y = TY;
+    p->vbx = vbx;
+    p->vby = vby;
+    p->cell_log2 = cl;
+    p->ncx = (int32_t)ncx;
+    p->ncy = (int32_t)ncy;
+    p->n_cells = n_cells;
+
+    // velocity blocks: cells of vbx x vby natural lattice steps in velocity space
+    const int64_t s_ref = span > 0 ? std::max<int64_t>(1, ((int64_t)d->binw_q8 * 65536) / span)
+                                   : ((int64_t)1 << 30);
+    const int64_t BVX = (int64_t)vbx * s_ref, BVY = (int64_t)vby * s_ref;
+    std::vector<int32_t> order(n_v);
+    int64_t vxmin = 0, vymin = 0;
+    if (n_v > 0) {
+        vxmin = d->v_host[0];
+        vymin = d->v_host[1];
+        for (int64_t j = 1; j < n_v; ++j) {
+            vxmin = std::min<int64_t>(vxmin, d->v_host[2 * j]);
+            vymin = std::min<int64_t>(vymin, d->v_host[2 * j + 1]);
+        }
+    }
+    std::vector<int64_t> kx(n_v), ky(n_v);
+    for (int64_t j = 0; j < n_v; ++j) {
+        order[j] = (int32_t)j;
+        kx[j] = (d->v_host[2 * j] - vxmin) / BVX;
+        ky[j] = (d->v_host[2 * j + 1] - vymin) / BVY;
+    }
+    const int32_t *V = d->v_host;
+    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        if (ky[a] != ky[b]) return ky[a] < ky[b];
+        if (kx[a] != kx[b]) return kx[a] < kx[b];
+        if (V[2 * a + 1] != V[2 * b + 1]) return V[2 * a + 1] < V[2 * b + 1];
+        if (V[2 * a] != V[2 * b]) return V[2 * a] < V[2 * b];
+        return a < b;
+    });
+    const int64_t kMaxMembers = 256;
+    std::vector<int32_t> block_start, block_vr, items;
+    int64_t i = 0;
+    int64_t bx_min_all = 0, bx_max_all = 0;
+    bool first = true;
+    while (i < n_v) {
+        int64_t k = i;
+        while (k < n_v && k - i < kMaxMembers && ky[order[k]] == ky[order[i]] &&
+               kx[order[k]] == kx[order[i]])
+            ++k;
+        int32_t vx_lo = INT32_MAX, vx_hi = INT32_MIN, vy_lo = INT32_MAX, vy_hi = INT32_MIN;
+        for (int64_t m = i; m < k; ++m) {
+            const int32_t vx = V[2 * order[m]], vy = V[2 * order[m] + 1];
+            vx_lo = std::min(vx_lo, vx); vx_hi = std::max(vx_hi, vx);
+            vy_lo = std::min(vy_lo, vy); vy_hi = std::max(vy_hi, vy);
+        }
+        const int32_t blk = (int32_t)(block_start.size());
+        block_start.push_back((int32_t)i);
+        block_vr.insert(block_vr.end(), {vx_lo, vx_hi, vy_lo, vy_hi});
+        // projected footprint of the block over dt in [0, span]
+        const __int128 lox = (__int128)ex[0] * 65536 - (__int128)std::max<int64_t>(0, vx_hi) * span;
+        const __int128 hix = (__int128)ex[1] * 65536 - (__int128)std::min<int64_t>(0, vx_lo) * span;
+        const __int128 loy = (__int128)ex[2] * 65536 - (__int128)std::max<int64_t>(0, vy_hi) * span;
+        const __int128 hiy = (__int128)ex[3] * 65536 - (__int128)std::min<int64_t>(0, vy_lo) * span;
+        const int64_t bxl = floor_div(lox, B), bxh = floor_div(hix - 1, B);
+        const int64_t byl = floor_div(loy, B), byh = floor_div(hiy - 1, B);
+        for (int64_t v : {bxl, bxh, byl, byh})
+            if (v <= -lim_bins || v >= lim_bins)
+                return fail(SAS_E_UNSUPPORTED, "sas_plan_create: projected bins exceed +-2^29");
+        if (first) { bx_min_all = bxl; bx_max_all = bxh; first = false; }
+        const int64_t t0x = floor_div(bxl, TX), t1x = floor_div(bxh, TX);
+        const int64_t t0y = floor_div(byl, TY), t1y = floor_div(byh, TY);
+        for (int64_t ty = t0y; ty <= t1y; ++ty)
+            for (int64_t tx = t0x; tx <= t1x; ++tx)
+                items.insert(items.end(), {blk, (int32_t)(tx * TX), (int32_t)(ty * TY)});
+        i = k;
+    }
+    (void)bx_min_all; (void)bx_max_all;
+    block_start.push_back((int32_t)n_v);
+    p->n_blocks = (int64_t)block_start.size() - 1;
+    p->n_items = (int64_t)items.size() / 3;
+    if (p->n_items >= ((int64_t)1 << 31))
+        return fail(SAS_E_UNSUPPORTED, "sas_plan_create: too many work items");
+
+    std::vector<int32_t> vel(d->v_host, d->v_host + 2 * n_v);
+    sas_status st;
+    if ((st = upload(p.get(), &p->d_vel, vel)) != SAS_OK) goto fail_free;
+    if ((st = upload(p.get(), &p->d_members, order)) != SAS_OK) goto fail_free;
+    if ((st = upload(p.get(), &p->d_block_start, block_start)) != SAS_OK) goto fail_free;
+    if ((st = upload(p.get(), &p->d_block_vr, block_vr)) != SAS_OK) goto fail_free;
+    if ((st = upload(p.get(), &p->d_items, items)) != SAS_OK) goto fail_free;
+    if ((st = upload(p.get(), &p->d_t, p->t)) != SAS_OK) goto fail_free;
+    *plan_out = p.release();
+    return SAS_OK;
+fail_free:
+    for (void *a : p->allocs) hipFree(a);
+    p->allocs.clear();
+    return st;
+}
+
+sas_status sas_plan_destroy(sas_plan *p) {
+    if (!p) return SAS_OK;
+    for (void *a : p->allocs) hipFree(a);
+    delete p;
+    return SAS_OK;
+}
+
+sas_status sas_plan_get_info(const sas_plan *p, sas_plan_info *info) {
+    if (!p || !info) return fail(SAS_E_INVALID, "sas_plan_get_info: null argument");
+    info->n_items = p->n_items;
+    info->n_blocks = p->n_blocks;
+    info->path = p->path;
+    info->tile_x = p->tile_x;
+    info->tile_y = p->tile_y;
+    info->vblock_x = p->vbx;
+    info->vblock_y = p->vby;
+    info->cell_log2 = p->cell_log2;
+    info->n_v = p->n_v;
+    return SAS_OK;
+}
+
+sas_status sas_vote_workspace_size(const sas_plan *p, int64_t n, size_t *bytes) {
+    if (!p || !bytes || n < 0) return fail(SAS_E_INVALID, "sas_vote_workspace_size: bad argument");
+    *bytes = ws_layout(p, n).total;
+    return SAS_OK;
+}
+
+sas_status sas_vote(const sas_plan *p, const int32_t *x_q8, const int32_t *y_q8,
+                    const uint8_t *epoch, int64_t n, sas_candidate *cand_dev, int64_t cand_cap,
+                    sas_vote_result *res_dev, void *workspace, size_t ws_bytes, void *stream) {
+    if (!p) return fail(SAS_E_INVALID, "sas_vote: null plan");
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(SAS_E_INVALID, "sas_vote: n must be in [0, 2^31)");
+    if (n > 0 && (!x_q8 || !y_q8 || !epoch)) return fail(SAS_E_INVALID, "sas_vote: null catalog array");
+    if (!res_dev) return fail(SAS_E_INVALID, "sas_vote: null result pointer");
+    if (cand_cap < 0 || (cand_cap > 0 && !cand_dev))
+        return fail(SAS_E_INVALID, "sas_vote: bad candidate buffer");
+    const WsLayout L = ws_layout(p, n);
+    if (!workspace || ws_bytes < L.total)
+        return fail(SAS_E_WORKSPACE, "sas_vote: workspace smaller than sas_vote_workspace_size()");
+    if (((uintptr_t)workspace & 255) != 0)
+        return fail(SAS_E_INVALID, "sas_vote: workspace must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)workspace;
+    PrepBuffers pb;
+    pb.count = (int32_t *)(w + L.count);
+    pb.blocksum = (int32_t *)(w + L.blocksum);
+    pb.cellid = (int32_t *)(w + L.cellid);
+    pb.rank = (int32_t *)(w + L.rank);
+    pb.sx = (int32_t *)(w + L.sx);
+    pb.sy = (int32_t *)(w + L.sy);
+    pb.present = (int32_t *)(w + L.present);
+    pb.dt = (int32_t *)(w + L.dt);
+    hipError_t e = launch_prep(x_q8, y_q8, epoch, n, p->d_t, p->n_epochs, p->ncx, p->ncy,
+                               p->cell_log2, p->ext, p->n_cells, pb, res_dev, s);
+    if (e != hipSuccess) return hip_fail(e, "sas_vote: preparation launch");
+    if (n == 0 || p->n_v == 0) return SAS_OK;
+
+    DenseArgs a{};
+    a.cat.sx = pb.sx;
+    a.cat.sy = pb.sy;
+    a.cat.off = pb.count;
+    a.cat.dt = pb.dt;
+    a.cat.n_epochs = p->n_epochs;
+    a.cat.ncx = p->ncx;
+    a.cat.ncy = p->ncy;
+    a.cat.cell_log2 = p->cell_log2;
+    a.cat.x0 = p->ext[0];
+    a.cat.x1 = p->ext[1];
+    a.cat.y0 = p->ext[2];
+    a.cat.y1 = p->ext[3];
+    a.shift = 16 + p->log2b;
+    a.tile_x = p->tile_x;
+    a.tile_y = p->tile_y;
+    a.n_min = p->n_min;
+    a.count_sat = p->count_sat;
+    a.vel = p->d_vel;
+    a.members = p->d_members;
+    a.block_start = p->d_block_start;
+    a.block_vr = p->d_block_vr;
+    a.items = p->d_items;
+    a.n_items = p->n_items;
+    a.cand = cand_dev;
+    a.cand_cap = cand_cap;
+    a.res = res_dev;
+    e = launch_vote_dense(p->dense_mode, a, s);
+    if (e != hipSuccess) return hip_fail(e, "sas_vote: vote launch");
+    return SAS_OK;
+}
+
+sas_status sas_peaks(const sas_candidate *cand_dev, const sas_vote_result *res_dev,
+                     int64_t cand_cap, int32_t order, int64_t top_k, sas_candidate *out_host,
+                     int64_t out_cap, int64_t *n_out, void *stream) {
+    if (!res_dev || !n_out || cand_cap < 0 || out_cap < 0 || top_k < 0)
+        return fail(SAS_E_INVALID, "sas_peaks: bad argument");
+    if (order != SAS_ORDER_CANONICAL && order != SAS_ORDER_BY_COUNT)
+        return fail(SAS_E_INVALID, "sas_peaks: unknown order");
+    hipStream_t s = (hipStream_t)stream;
+    sas_vote_result r{};
+    hipError_t e = hipMemcpyAsync(&r, res_dev, sizeof(r), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "sas_peaks: reading the vote result");
+    *n_out = 0;
+    if (r.status & SAS_DATA_BAD_EPOCH)
+        return fail(SAS_E_INVALID, "sas_peaks: the catalog holds an epoch index >= n_epochs");
+    if (r.status & SAS_DATA_OUTSIDE)
+        return fail(SAS_E_INVALID, "sas_peaks: a detection lies outside the plan's footprint");
+    if (r.n_cand > cand_cap) {
+        *n_out = r.n_cand;
+        return fail(SAS_E_OVERFLOW, "sas_peaks: more candidates than the vote buffer held");
+    }
+    std::vector<sas_candidate> c((size_t)r.n_cand);
+    if (r.n_cand > 0) {
+        if (!cand_dev) return fail(SAS_E_INVALID, "sas_peaks: null candidate buffer");
+        e = hipMemcpyAsync(c.data(), cand_dev, sizeof(sas_candidate) * c.size(),
+                           hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "sas_peaks: copying candidates");
+    }
+    auto canon = [](const sas_candidate &a, const sas_candidate &b) {
+        if (a.v_idx != b.v_idx) return a.v_idx < b.v_idx;
+        if (a.by != b.by) return a.by < b.by;
+        return a.bx < b.bx;
+    };
+    if (order == SAS_ORDER_CANONICAL) {
+        std::sort(c.begin(), c.end(), canon);
+    } else {
+        std::sort(c.begin(), c.end(), [&](const sas_candidate &a, const sas_candidate &b) {
+            if (a.count != b.count) return a.count > b.count;
+            return canon(a, b);
+        });
+    }
+    const int64_t k = top_k > 0 ? std::min<int64_t>(top_k, (int64_t)c.size()) : (int64_t)c.size();
+    if (k > out_cap || (k > 0 && !out_host)) {
+        *n_out = k;
+        return fail(SAS_E_OVERFLOW, "sas_peaks: output capacity too small; *n_out holds the size");
+    }
+    if (k > 0) std::memcpy(out_host, c.data(), sizeof(sas_candidate) * (size_t)k);
+    *n_out = k;
+    return SAS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,262 @@
+"""Python binding of libsas (the C ABI in include/sas.h).
+
+Argument marshalling only: every step of the voting transform runs in the
+library's HIP kernels.  PyTorch supplies device memory and streams.  If the
+library is missing this module raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsas.so")
+
+SAS_OK = 0
+SAS_E_INVALID = -1
+SAS_E_NOMEM = -2
+SAS_E_OVERFLOW = -3
+SAS_E_DEVICE = -4
+SAS_E_UNSUPPORTED = -5
+SAS_E_WORKSPACE = -6
+
+GRID_SHAPES = {"box": 0, "disk": 1, "annulus": 2, "sector": 3}
+MODES = {"epochs": 0, "detections": 1}
+PATHS = {"auto": 0, "dense": 1, "sort": 2}
+ORDERS = {"canonical": 0, "by_count": 1}
+
+CAND_DTYPE = np.dtype([("v_idx", "<u4"), ("bx", "<i4"), ("by", "<i4"),
+                       ("count", "<u2"), ("flags", "<u2")])
+
+
+class SasError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_status_name(status), msg))
+        self.status = status
+
+
+class GridSpec(ctypes.Structure):
+    _fields_ = [("shape", ctypes.c_int32), ("vmin", ctypes.c_double), ("vmax", ctypes.c_double),
+                ("vy_min", ctypes.c_double), ("vy_max", ctypes.c_double),
+                ("angle_deg", ctypes.c_double), ("half_width_deg", ctypes.c_double),
+                ("binw_q8", ctypes.c_int32), ("span_q16", ctypes.c_int64),
+                ("spacing_q8", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
+                ("vblock_x", ctypes.c_int32), ("vblock_y", ctypes.c_int32),
+                ("cell_log2", ctypes.c_int32), ("sort_vblock", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("v_host", ctypes.c_void_p), ("n_v", ctypes.c_int64),
+                ("n_epochs", ctypes.c_int32), ("t_q16", ctypes.c_void_p),
+                ("binw_q8", ctypes.c_int32), ("n_min", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("count_sat", ctypes.c_int32),
+                ("path", ctypes.c_int32), ("extent_q8", ctypes.c_int32 * 4),
+                ("tuning", ctypes.c_void_p)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n_items", ctypes.c_int64), ("n_blocks", ctypes.c_int64),
+                ("path", ctypes.c_int32), ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
+                ("vblock_x", ctypes.c_int32), ("vblock_y", ctypes.c_int32),
+                ("cell_log2", ctypes.c_int32), ("n_v", ctypes.c_int64)]
+
+
+_lib = None
+
+EXPORTS = ["sas_status_string", "sas_last_error", "sas_version", "sas_grid_spacing",
+           "sas_build_grid", "sas_plan_create", "sas_plan_destroy", "sas_plan_get_info",
+           "sas_vote_workspace_size", "sas_vote", "sas_peaks"]
+
+
+def load():
+    """Load libsas.so (built by ``python -m paper_2509_26279_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libsas.so is not built (%s); run python -m paper_2509_26279_amd.build"
+                           % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    sig = {
+        "sas_status_string": (ctypes.c_char_p, [I32]),
+        "sas_last_error": (ctypes.c_char_p, []),
+        "sas_version": (ctypes.c_char_p, []),
+        "sas_grid_spacing": (I32, [I32, I64, P]),
+        "sas_build_grid": (I32, [P, P, I64, P]),
+        "sas_plan_create": (I32, [P, P]),
+        "sas_plan_destroy": (I32, [P]),
+        "sas_plan_get_info": (I32, [P, P]),
+        "sas_vote_workspace_size": (I32, [P, I64, P]),
+        "sas_vote": (I32, [P, P, P, P, I64, P, I64, P, P, SZ, P]),
+        "sas_peaks": (I32, [P, P, I64, I32, I64, P, I64, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _status_name(s):
+    try:
+        return load().sas_status_string(s).decode()
+    except Exception:  # library not loadable while formatting an error
+        return str(s)
+
+
+def _check(status):
+    if status != SAS_OK:
+        raise SasError(status, load().sas_last_error().decode())
+
+
+def version() -> str:
+    return load().sas_version().decode()
+
+
+# --------------------------------------------------------------------------- grid
+
+def grid_spacing(binw_q8: int, span_q16: int) -> int:
+    out = ctypes.c_int32()
+    _check(load().sas_grid_spacing(int(binw_q8), int(span_q16), ctypes.byref(out)))
+    return out.value
+
+
+def build_grid(shape, vmin=0.0, vmax=0.0, vy_min=0.0, vy_max=0.0, angle_deg=0.0,
+               half_width_deg=0.0, binw_q8=1024, span_q16=65536, spacing_q8=0) -> np.ndarray:
+    """Velocity lattice as int32 [n, 2] (Q8 px/h) in v_idx order."""
+    spec = GridSpec(GRID_SHAPES[shape] if isinstance(shape, str) else int(shape), vmin, vmax,
+                    vy_min, vy_max, angle_deg, half_width_deg, int(binw_q8), int(span_q16),
+                    int(spacing_q8))
+    n = ctypes.c_int64()
+    lib = load()
+    _check(lib.sas_build_grid(ctypes.byref(spec), None, 0, ctypes.byref(n)))
+    out = np.zeros((max(n.value, 1), 2), dtype=np.int32)
+    _check(lib.sas_build_grid(ctypes.byref(spec), out.ctypes.data, n.value, ctypes.byref(n)))
+    return out[:n.value]
+
+
+def grid_from_spec(spec, binw_q8: int, span_q16: int) -> np.ndarray:
+    """Grid of a ``synth.GridSpec``-like object (shape, vmin, vmax, ...)."""
+    return build_grid(spec.shape, spec.vmin, spec.vmax, spec.vy_min, spec.vy_max,
+                      spec.angle_deg, spec.half_width_deg, binw_q8, span_q16)
+
+
+# --------------------------------------------------------------------------- plans
+
+class Plan:
+    """A work decomposition for one (velocity set, epochs, parameters, footprint)."""
+
+    def __init__(self, velocities, t_q16, binw_q8, n_min, extent_q8, mode="epochs",
+                 count_sat=65535, path="auto", tuning=None):
+        lib = load()
+        self._v = np.ascontiguousarray(velocities, dtype=np.int32).reshape(-1, 2)
+        self._t = np.ascontiguousarray(t_q16, dtype=np.int64)
+        self._tuning = None
+        if tuning is not None:
+            self._tuning = Tuning(*[int(tuning.get(k, 0)) for k in
+                                    ("tile_x", "tile_y", "vblock_x", "vblock_y", "cell_log2",
+                                     "sort_vblock")])
+        desc = PlanDesc(self._v.ctypes.data, self._v.shape[0], self._t.shape[0],
+                        self._t.ctypes.data, int(binw_q8), int(n_min), MODES[mode],
+                        int(count_sat), PATHS[path], (ctypes.c_int32 * 4)(*map(int, extent_q8)),
+                        ctypes.addressof(self._tuning) if self._tuning is not None else None)
+        self._p = ctypes.c_void_p()
+        _check(lib.sas_plan_create(ctypes.byref(desc), ctypes.byref(self._p)))
+        self.n_v = self._v.shape[0]
+        self.n_epochs = self._t.shape[0]
+
+    @property
+    def handle(self):
+        return self._p
+
+    def info(self) -> dict:
+        inf = PlanInfo()
+        _check(load().sas_plan_get_info(self._p, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in PlanInfo._fields_}
+
+    def workspace_size(self, n: int) -> int:
+        out = ctypes.c_size_t()
+        _check(load().sas_vote_workspace_size(self._p, int(n), ctypes.byref(out)))
+        return out.value
+
+    def close(self):
+        if self._p:
+            load().sas_plan_destroy(self._p)
+            self._p = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def vote(plan: Plan, x, y, epoch, cand, res, workspace, stream=None):
+    """Enqueue sas_vote.  x, y: int32, epoch: uint8 device tensors;
+    cand: device tensor of >= 16*cap bytes; res: 16-byte device tensor;
+    workspace: device uint8 tensor."""
+    n = int(x.numel())
+    cap = cand.numel() * cand.element_size() // 16
+    _check(load().sas_vote(plan.handle, x.data_ptr(), y.data_ptr(), epoch.data_ptr(), n,
+                           cand.data_ptr(), cap, res.data_ptr(), workspace.data_ptr(),
+                           workspace.numel() * workspace.element_size(), _stream_handle(stream)))
+
+
+def peaks(cand, res, order="canonical", top_k=0, stream=None):
+    """Synchronise and return the candidates as a CAND_DTYPE array."""
+    lib = load()
+    cap = cand.numel() * cand.element_size() // 16
+    n = ctypes.c_int64()
+    out = np.zeros(max(cap, 1), dtype=CAND_DTYPE)
+    _check(lib.sas_peaks(cand.data_ptr(), res.data_ptr(), cap, ORDERS[order], int(top_k),
+                         out.ctypes.data, out.shape[0], ctypes.byref(n), _stream_handle(stream)))
+    return out[:n.value].copy()
+
+
+class Search:
+    """Device buffers for repeated searches of catalogs with one plan."""
+
+    def __init__(self, plan: Plan, n_max: int, cand_cap: int = 1 << 20, device="cuda"):
+        import torch
+        self.plan = plan
+        self.device = device
+        self.n_max = int(n_max)
+        self.ws = torch.empty(max(plan.workspace_size(self.n_max), 256), dtype=torch.uint8,
+                              device=device)
+        self.cand = torch.empty((max(int(cand_cap), 1), 4), dtype=torch.int32, device=device)
+        self.res = torch.zeros(4, dtype=torch.int32, device=device)
+
+    def upload(self, x_q8, y_q8, epoch):
+        import torch
+        x = torch.as_tensor(np.ascontiguousarray(x_q8, dtype=np.int32)).to(self.device)
+        y = torch.as_tensor(np.ascontiguousarray(y_q8, dtype=np.int32)).to(self.device)
+        e = torch.as_tensor(np.ascontiguousarray(epoch, dtype=np.uint8)).to(self.device)
+        return x, y, e
+
+    def vote(self, x, y, e, stream=None):
+        if x.numel() > self.n_max:
+            raise ValueError("catalog larger than this Search was sized for")
+        vote(self.plan, x, y, e, self.cand, self.res, self.ws, stream)
+
+    def peaks(self, order="canonical", top_k=0, stream=None):
+        return peaks(self.cand, self.res, order, top_k, stream)
+
+    def run(self, x_q8, y_q8, epoch, order="canonical", top_k=0):
+        x, y, e = self.upload(x_q8, y_q8, epoch)
+        self.vote(x, y, e)
+        return self.peaks(order, top_k)
