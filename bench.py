@@ -89,7 +89,8 @@ def main():
     wl = _workload(args.workload)
     v = sas.grid_from_spec(wl.grid, wl.binw_q8, wl.span_q16)
     count_sat = 255 if wl.count_dtype == "u8" else 65535
-    plan = sas.Plan(v, wl.t_q16, wl.binw_q8, wl.n_min, wl.extent_q8, count_sat=count_sat)
+    plan = sas.Plan(v, wl.t_q16, wl.binw_q8, wl.n_min, wl.extent_q8, count_sat=count_sat,
+                    tuning={"n_det_hint": wl.n})
     info = plan.info()
     s = sas.Search(plan, wl.n, cand_cap=1 << 22)
     x, y, e = s.upload(wl.x_q8, wl.y_q8, wl.epoch)

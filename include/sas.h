@@ -63,6 +63,7 @@ typedef int32_t sas_status;
 /* Device-side data errors (bits of sas_vote_result.status). */
 #define SAS_DATA_BAD_EPOCH 1   /* an epoch index >= n_epochs */
 #define SAS_DATA_OUTSIDE 2     /* a detection outside the plan's footprint */
+#define SAS_DATA_REFINE_FULL 4 /* more flagged cells than the plan's refinement list holds */
 
 const char *sas_status_string(sas_status s);
 /* Message of the calling thread's last failing call ("" if none). */
@@ -119,7 +120,8 @@ typedef struct {
 typedef struct {
     int64_t n_cand;  /* total candidates found; may exceed the buffer capacity */
     int32_t status;  /* SAS_DATA_* bits, 0 when the catalog was valid */
-    int32_t reserved;
+    int32_t n_spilled; /* diagnostic: tiles whose detection window exceeded the LDS
+                          staging capacity and were processed in chunks (same result) */
 } sas_vote_result;   /* 16 bytes, device resident, written by sas_vote */
 
 #define SAS_MODE_EPOCHS 0
@@ -131,11 +133,16 @@ typedef struct {
 
 /* Launch shape of the dense path; zeros select the built-in defaults. */
 typedef struct {
-    int32_t tile_x, tile_y;     /* bins per LDS tile; tile_x * tile_y <= 16384 */
-    int32_t vblock_x, vblock_y; /* velocity-block extent in lattice steps */
+    int32_t tile_x, tile_y;     /* histogram cells per tile: tile_x a power of two,
+                                   tile_x * tile_y <= 512 and a multiple of 4 */
+    int32_t vblock_x, vblock_y; /* velocity segment in lattice steps; vblock_x * vblock_y <= 32 */
     int32_t cell_log2;          /* log2 of the window-index cell size in Q8 px */
     int32_t sort_vblock;        /* velocities per sort-path block */
-    int32_t reserved[4];
+    int32_t n_det_hint;         /* expected detections per catalog: chooses the cell size */
+    int32_t coarse_log2;        /* histogram cells of 2^m x 2^m bins, m in [0, 3]; -1: single
+                                   bins; 0: chosen from n_det_hint */
+    int32_t refine_cap;         /* capacity of the list of flagged cells (0: chosen by the plan) */
+    int32_t reserved;
 } sas_tuning;
 
 /* ------------------------------------------------------------------------
@@ -173,12 +180,15 @@ sas_status sas_plan_create(const sas_plan_desc *desc, sas_plan **plan_out);
 sas_status sas_plan_destroy(sas_plan *plan);
 /* Work-decomposition facts: items, velocity blocks, path chosen. */
 typedef struct {
-    int64_t n_items;
+    int64_t n_items;   /* (velocity block, tile row) work items */
+    int64_t n_tiles;   /* (velocity block, tile) pairs */
     int64_t n_blocks;
     int32_t path;
     int32_t tile_x, tile_y;
     int32_t vblock_x, vblock_y;
     int32_t cell_log2;
+    int32_t coarse_log2;   /* histogram cells of 2^m x 2^m bins */
+    int32_t mode_variant;  /* 0 epoch masks, 1 detection counts, 2 counts + refinement */
     int64_t n_v;
 } sas_plan_info;
 sas_status sas_plan_get_info(const sas_plan *plan, sas_plan_info *info);

@@ -35,9 +35,7 @@ def sources():
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, src + ".o")
-    cmd = ["hipcc", *COMMON, *PER_FILE.get(src, [])]
-    if src.endswith(".hip"):
-        cmd += ["-x", "hip", *DEVICE]
+    cmd = ["hipcc", *COMMON, *PER_FILE.get(src, []), "-x", "hip", *DEVICE]
     cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

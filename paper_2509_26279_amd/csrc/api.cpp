@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <memory>
 #include <cstdio>
 #include <cstring>
@@ -43,6 +44,57 @@ int ilog2_exact(int64_t v) {  // -1 unless v is a power of two
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
+using Pt = std::pair<__int128, __int128>;
+
+__int128 cross(const Pt &o, const Pt &a, const Pt &b) {
+    return (a.first - o.first) * (b.second - o.second) - (a.second - o.second) * (b.first - o.first);
+}
+
+// Convex hull (monotone chain), counter-clockwise, exact integer predicates.
+std::vector<Pt> convex_hull(std::vector<Pt> p) {
+    std::sort(p.begin(), p.end());
+    p.erase(std::unique(p.begin(), p.end()), p.end());
+    if (p.size() < 3) return p;
+    std::vector<Pt> h(2 * p.size());
+    size_t k = 0;
+    for (size_t i = 0; i < p.size(); ++i) {
+        while (k >= 2 && cross(h[k - 2], h[k - 1], p[i]) <= 0) --k;
+        h[k++] = p[i];
+    }
+    for (size_t i = p.size() - 1, t = k + 1; i > 0; --i) {
+        while (k >= t && cross(h[k - 2], h[k - 1], p[i - 1]) <= 0) --k;
+        h[k++] = p[i - 1];
+    }
+    h.resize(k - 1);
+    return h;
+}
+
+// x range of the hull within the band ylo <= y <= yhi (false when empty).
+// Approximate in the last bits; callers widen the result.
+bool hull_x_range(const std::vector<Pt> &h, long double ylo, long double yhi, long double *xlo,
+                  long double *xhi) {
+    bool any = false;
+    long double lo = 0, hi = 0;
+    auto take = [&](long double x) {
+        if (!any) { lo = hi = x; any = true; }
+        lo = std::min(lo, x);
+        hi = std::max(hi, x);
+    };
+    const size_t n = h.size();
+    for (size_t i = 0; i < n; ++i) {
+        const long double px = (long double)h[i].first, py = (long double)h[i].second;
+        if (py >= ylo && py <= yhi) take(px);
+        const Pt &q = h[(i + 1) % n];
+        const long double qx = (long double)q.first, qy = (long double)q.second;
+        for (long double yl : {ylo, yhi}) {
+            if ((py - yl) * (qy - yl) <= 0 && py != qy) take(px + (yl - py) * (qx - px) / (qy - py));
+        }
+    }
+    *xlo = lo;
+    *xhi = hi;
+    return any;
+}
+
 }  // namespace
 }  // namespace sas
 
@@ -57,11 +109,11 @@ struct sas_plan {
     int32_t ext[4] = {0, 0, 0, 0};
     int64_t n_v = 0;
     int dense_mode = 0;
-    int32_t tile_x = 64, tile_y = 64, vbx = 8, vby = 8, cell_log2 = 15;
+    int32_t tile_x = 32, tile_y = 12, vbx = 8, vby = 4, cell_log2 = 11, coarse_log2 = 0;
     int32_t ncx = 1, ncy = 1;
-    int64_t n_cells = 0, n_items = 0, n_blocks = 0;
-    int32_t *d_vel = nullptr, *d_members = nullptr, *d_block_start = nullptr;
-    int32_t *d_block_vr = nullptr, *d_items = nullptr;
+    int64_t n_cells = 0, n_items = 0, n_segments = 0, n_tiles = 0, refine_cap = 0;
+    int32_t *d_vel = nullptr, *d_seg = nullptr, *d_seg_v = nullptr, *d_seg_vel = nullptr;
+    int32_t *d_items = nullptr;
     int64_t *d_t = nullptr;
     std::vector<void *> allocs;
 };
@@ -84,7 +136,7 @@ sas_status upload(sas_plan *p, T **dst, const std::vector<T> &src) {
 }
 
 struct WsLayout {
-    size_t count, blocksum, cellid, rank, sx, sy, present, dt, total;
+    size_t count, blocksum, cellid, rank, sxy, present, dt, refine_count, refine, total;
 };
 
 WsLayout ws_layout(const sas_plan *p, int64_t n) {
@@ -97,10 +149,11 @@ WsLayout ws_layout(const sas_plan *p, int64_t n) {
     L.blocksum = o; o = align_up(o + sizeof(int32_t) * nb);
     L.cellid = o; o = align_up(o + sizeof(int32_t) * nn);
     L.rank = o; o = align_up(o + sizeof(int32_t) * nn);
-    L.sx = o; o = align_up(o + sizeof(int32_t) * nn);
-    L.sy = o; o = align_up(o + sizeof(int32_t) * nn);
+    L.sxy = o; o = align_up(o + 2 * sizeof(int32_t) * nn);
     L.present = o; o = align_up(o + sizeof(int32_t) * kMaxEpochs);
     L.dt = o; o = align_up(o + sizeof(int32_t) * kMaxEpochs);
+    L.refine_count = o; o = align_up(o + sizeof(unsigned long long));
+    L.refine = o; o = align_up(o + sizeof(int4) * (p->dense_mode == kCountRef ? p->refine_cap : 1));
     L.total = o;
     return L;
 }
@@ -166,16 +219,56 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
 
     sas_tuning tu{};
     if (d->tuning) tu = *d->tuning;
-    const int32_t TX = tu.tile_x ? tu.tile_x : 64, TY = tu.tile_y ? tu.tile_y : 64;
-    if (TX < 4 || TY < 1 || TX % 4 || TX > 1024 || TY > 1024 || (int64_t)TX * TY > 16384)
-        return fail(SAS_E_INVALID, "sas_plan_create: tile must satisfy 4 <= tile_x (multiple of 4), "
-                                   "tile_x * tile_y <= 16384");
-    const int32_t vbx = tu.vblock_x ? tu.vblock_x : 8, vby = tu.vblock_y ? tu.vblock_y : 8;
-    if (vbx < 1 || vby < 1 || vbx > 1024 || vby > 1024)
-        return fail(SAS_E_INVALID, "sas_plan_create: vblock sizes must be in [1, 1024]");
-    int tx_log = 0;
-    while ((1 << (tx_log + 1)) <= std::max(TX, TY)) ++tx_log;
-    int cl = tu.cell_log2 ? tu.cell_log2 : std::max(0, log2b + tx_log - 1);
+    const int64_t n_v = d->n_v;
+    // natural lattice step Delta x / Delta t (Q8 px/h)
+    const int64_t s_ref = span > 0 ? std::max<int64_t>(1, ((int64_t)d->binw_q8 * 65536) / span)
+                                   : ((int64_t)1 << 30);
+    // Velocity segments: blocks of vbx x vby natural lattice steps, <= 32 velocities.
+    const int32_t vbx = tu.vblock_x ? tu.vblock_x : 8, vby = tu.vblock_y ? tu.vblock_y : 4;
+    if (vbx < 1 || vby < 1 || vbx * vby > kLanes)
+        return fail(SAS_E_INVALID, "sas_plan_create: vblock_x * vblock_y must be in [1, 32]");
+    int32_t TX = tu.tile_x ? tu.tile_x : 32, TY = tu.tile_y ? tu.tile_y : 12;
+    if (TX < 1 || TY < 1 || ilog2_exact(TX) < 0 || (int64_t)TX * TY * kLanes > kMaxCells ||
+        ((int64_t)TX * TY) % 4)
+        return fail(SAS_E_INVALID, "sas_plan_create: tile_x must be a power of two and "
+                                   "tile_x * tile_y a multiple of 4, at most 512");
+    if (tu.coarse_log2 < -1 || tu.coarse_log2 > 3)
+        return fail(SAS_E_INVALID, "sas_plan_create: coarse_log2 must be in [-1, 3]");
+    if (tu.refine_cap < 0) return fail(SAS_E_INVALID, "sas_plan_create: refine_cap must be >= 0");
+
+    // Cell size of the histogram.  A cell of 2^m x 2^m bins counts the
+    // detections of all its bins; only cells reaching N_min are refined into
+    // exact bins.  Choose the largest m whose expected number of pure-noise
+    // cells reaching N_min (Poisson counts at the catalog's mean density)
+    // stays small, so that sparse catalogs use far fewer cells per vote.
+    const double area = (double)((int64_t)ex[1] - ex[0]) * (double)((int64_t)ex[3] - ex[2]);
+    double expected_flags = 0.0;
+    int m = 0;
+    if (tu.coarse_log2 > 0) {
+        m = tu.coarse_log2;
+    } else if (tu.coarse_log2 == 0 && tu.n_det_hint > 0 && n_v > 0) {
+        const double lam1 = (double)tu.n_det_hint * (double)d->binw_q8 * d->binw_q8 / area;
+        for (int mm = 3; mm >= 1; --mm) {
+            const double lam = lam1 * (double)(1 << (2 * mm));
+            // P(Poisson(lam) >= n_min)
+            double term = std::exp(-lam), cdf = 0.0;
+            for (int k = 0; k < d->n_min; ++k) {
+                cdf += term;
+                term *= lam / (k + 1);
+            }
+            const double tail = std::max(0.0, 1.0 - cdf);
+            const double cells_per_v = area / ((double)d->binw_q8 * d->binw_q8 * (1 << (2 * mm)));
+            const double flags = tail * cells_per_v * (double)n_v;
+            if (lam < 0.5 * d->n_min && flags < 2.0e5) {
+                m = mm;
+                expected_flags = flags;
+                break;
+            }
+        }
+    }
+    const int kc = log2b + m;  // log2 of the cell width in Q8
+    int cl = tu.cell_log2;
+    if (!cl) cl = kc + 1;  // window-index cells of 2 x 2 histogram cells
     if (cl < 0 || cl > 30) return fail(SAS_E_INVALID, "sas_plan_create: cell_log2 out of range");
     auto ncells_of = [&](int c, int64_t lo, int64_t hi) { return ((hi - lo) + (1LL << c) - 1) >> c; };
     while (ncells_of(cl, ex[0], ex[1]) > 32767 || ncells_of(cl, ex[2], ex[3]) > 32767) ++cl;
@@ -185,8 +278,7 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
         return fail(SAS_E_INVALID, "sas_plan_create: window index too large; raise cell_log2");
 
     // velocities: range checks
-    const int64_t n_v = d->n_v;
-    const __int128 B = (__int128)1 << (16 + log2b);
+    const __int128 B = (__int128)1 << (16 + kc);  // one histogram cell in Q24
     const __int128 lim_bins = (__int128)1 << 29;
     for (int64_t j = 0; j < n_v; ++j) {
         for (int a = 0; a < 2; ++a) {
@@ -195,14 +287,13 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
                 return fail(SAS_E_UNSUPPORTED, "sas_plan_create: |v| * span too large (>= 2^46 Q24)");
         }
     }
-
     {   // tile-relative Q8 coordinates are held in 32 bits by the kernels
         int64_t vmax_abs = 0;
         for (int64_t j = 0; j < 2 * n_v; ++j)
             vmax_abs = std::max<int64_t>(vmax_abs, d->v_host[j] < 0 ? -(int64_t)d->v_host[j]
                                                                     : d->v_host[j]);
         const __int128 shift_q8 = ((__int128)vmax_abs * span >> 16) + 1;
-        const __int128 tile_q8 = (__int128)std::max(TX, TY) * d->binw_q8;
+        const __int128 tile_q8 = (__int128)std::max(TX, TY) << kc;
         const __int128 reach = (__int128)std::max<int64_t>((int64_t)ex[1] - ex[0],
                                                            (int64_t)ex[3] - ex[2]) +
                                shift_q8 + tile_q8;
@@ -227,8 +318,15 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
         return fail(SAS_E_UNSUPPORTED, "sas_plan_create: the sort path is not built in this library");
     std::memcpy(p->ext, ex, sizeof(p->ext));
     p->n_v = n_v;
-    p->dense_mode = d->mode == SAS_MODE_DETECTIONS ? kCountDet
-                    : (d->n_epochs <= 32 ? kMask32 : kCountEpo);
+    p->coarse_log2 = m;
+    if (m > 0 || (d->mode == SAS_MODE_EPOCHS && d->n_epochs > 32))
+        p->dense_mode = kCountRef;
+    else
+        p->dense_mode = d->mode == SAS_MODE_DETECTIONS ? kCountDet : kMask32;
+    p->refine_cap = tu.refine_cap ? tu.refine_cap
+                                  : std::min<int64_t>((int64_t)1 << 26,
+                                                      std::max<int64_t>((int64_t)1 << 22,
+                                                                        (int64_t)(16 * expected_flags)));
     p->tile_x = TX;
     p->tile_y = TY;
     p->vbx = vbx;
@@ -238,27 +336,25 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     p->ncy = (int32_t)ncy;
     p->n_cells = n_cells;
 
-    // velocity blocks: cells of vbx x vby natural lattice steps in velocity space
-    const int64_t s_ref = span > 0 ? std::max<int64_t>(1, ((int64_t)d->binw_q8 * 65536) / span)
-                                   : ((int64_t)1 << 30);
-    const int64_t BVX = (int64_t)vbx * s_ref, BVY = (int64_t)vby * s_ref;
-    std::vector<int32_t> order(n_v);
+    // Segments: velocities bucketed by blocks of vbx x vby natural lattice
+    // steps (row-major over blocks), at most kLanes per segment.
+    const int32_t *V = d->v_host;
     int64_t vxmin = 0, vymin = 0;
     if (n_v > 0) {
-        vxmin = d->v_host[0];
-        vymin = d->v_host[1];
+        vxmin = V[0];
+        vymin = V[1];
         for (int64_t j = 1; j < n_v; ++j) {
-            vxmin = std::min<int64_t>(vxmin, d->v_host[2 * j]);
-            vymin = std::min<int64_t>(vymin, d->v_host[2 * j + 1]);
+            vxmin = std::min<int64_t>(vxmin, V[2 * j]);
+            vymin = std::min<int64_t>(vymin, V[2 * j + 1]);
         }
     }
     std::vector<int64_t> kx(n_v), ky(n_v);
+    std::vector<int32_t> order(n_v);
     for (int64_t j = 0; j < n_v; ++j) {
         order[j] = (int32_t)j;
-        kx[j] = (d->v_host[2 * j] - vxmin) / BVX;
-        ky[j] = (d->v_host[2 * j + 1] - vymin) / BVY;
+        kx[j] = ((int64_t)V[2 * j] - vxmin) / ((int64_t)vbx * s_ref);
+        ky[j] = ((int64_t)V[2 * j + 1] - vymin) / ((int64_t)vby * s_ref);
     }
-    const int32_t *V = d->v_host;
     std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
         if (ky[a] != ky[b]) return ky[a] < ky[b];
         if (kx[a] != kx[b]) return kx[a] < kx[b];
@@ -266,56 +362,75 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
         if (V[2 * a] != V[2 * b]) return V[2 * a] < V[2 * b];
         return a < b;
     });
-    const int64_t kMaxMembers = 256;
-    std::vector<int32_t> block_start, block_vr, items;
-    int64_t i = 0;
-    int64_t bx_min_all = 0, bx_max_all = 0;
-    bool first = true;
+    std::vector<int32_t> seg, seg_v, seg_vel, items;
+    int64_t i = 0, n_tiles = 0;
     while (i < n_v) {
         int64_t k = i;
-        while (k < n_v && k - i < kMaxMembers && ky[order[k]] == ky[order[i]] &&
+        while (k < n_v && k - i < kLanes && ky[order[k]] == ky[order[i]] &&
                kx[order[k]] == kx[order[i]])
             ++k;
         int32_t vx_lo = INT32_MAX, vx_hi = INT32_MIN, vy_lo = INT32_MAX, vy_hi = INT32_MIN;
-        for (int64_t m = i; m < k; ++m) {
-            const int32_t vx = V[2 * order[m]], vy = V[2 * order[m] + 1];
-            vx_lo = std::min(vx_lo, vx); vx_hi = std::max(vx_hi, vx);
-            vy_lo = std::min(vy_lo, vy); vy_hi = std::max(vy_hi, vy);
+        for (int64_t q = i; q < k; ++q) {
+            vx_lo = std::min(vx_lo, V[2 * order[q]]);
+            vx_hi = std::max(vx_hi, V[2 * order[q]]);
+            vy_lo = std::min(vy_lo, V[2 * order[q] + 1]);
+            vy_hi = std::max(vy_hi, V[2 * order[q] + 1]);
         }
-        const int32_t blk = (int32_t)(block_start.size());
-        block_start.push_back((int32_t)i);
-        block_vr.insert(block_vr.end(), {vx_lo, vx_hi, vy_lo, vy_hi});
-        // projected footprint of the block over dt in [0, span]
-        const __int128 lox = (__int128)ex[0] * 65536 - (__int128)std::max<int64_t>(0, vx_hi) * span;
-        const __int128 hix = (__int128)ex[1] * 65536 - (__int128)std::min<int64_t>(0, vx_lo) * span;
-        const __int128 loy = (__int128)ex[2] * 65536 - (__int128)std::max<int64_t>(0, vy_hi) * span;
-        const __int128 hiy = (__int128)ex[3] * 65536 - (__int128)std::min<int64_t>(0, vy_lo) * span;
-        const int64_t bxl = floor_div(lox, B), bxh = floor_div(hix - 1, B);
-        const int64_t byl = floor_div(loy, B), byh = floor_div(hiy - 1, B);
-        for (int64_t v : {bxl, bxh, byl, byh})
-            if (v <= -lim_bins || v >= lim_bins)
-                return fail(SAS_E_UNSUPPORTED, "sas_plan_create: projected bins exceed +-2^29");
-        if (first) { bx_min_all = bxl; bx_max_all = bxh; first = false; }
-        const int64_t t0x = floor_div(bxl, TX), t1x = floor_div(bxh, TX);
-        const int64_t t0y = floor_div(byl, TY), t1y = floor_div(byh, TY);
-        for (int64_t ty = t0y; ty <= t1y; ++ty)
-            for (int64_t tx = t0x; tx <= t1x; ++tx)
-                items.insert(items.end(), {blk, (int32_t)(tx * TX), (int32_t)(ty * TY)});
+        const int32_t sg = (int32_t)(seg.size() / 4);
+        seg.insert(seg.end(), {vx_lo, vx_hi, vy_lo, vy_hi});
+        for (int l = 0; l < kLanes; ++l) {
+            const bool used = i + l < k;
+            seg_v.push_back(used ? order[i + l] : -1);
+            seg_vel.push_back(used ? V[2 * order[i + l]] : vx_lo);
+            seg_vel.push_back(used ? V[2 * order[i + l] + 1] : vy_lo);
+        }
+        // Tiles of this segment: the projections x - v dt of the footprint for
+        // v in the segment's box and dt in [0, span] lie inside the convex hull
+        // of the footprint's corners and their shifts by the box corners times
+        // span.  Every tile row gets the x range of that hull.
+        std::vector<std::pair<__int128, __int128>> pts;
+        for (int cx = 0; cx < 2; ++cx)
+            for (int cy = 0; cy < 2; ++cy) {
+                const __int128 X = (__int128)ex[cx] * 65536, Y = (__int128)ex[2 + cy] * 65536;
+                pts.push_back({X, Y});
+                for (int32_t ux : {vx_lo, vx_hi})
+                    for (int32_t uy : {vy_lo, vy_hi})
+                        pts.push_back({X - (__int128)ux * span, Y - (__int128)uy * span});
+            }
+        const std::vector<std::pair<__int128, __int128>> hull = convex_hull(pts);
+        __int128 ymin = hull[0].second, ymax = hull[0].second;
+        for (const auto &q : hull) { ymin = std::min(ymin, q.second); ymax = std::max(ymax, q.second); }
+        const __int128 RB = (__int128)TY * B;  // one tile row in Q24
+        const int64_t r0 = floor_div(ymin, RB), r1 = floor_div(ymax, RB);
+        for (int64_t r = r0; r <= r1; ++r) {
+            long double xlo, xhi;
+            if (!hull_x_range(hull, (long double)(r * RB), (long double)((r + 1) * RB), &xlo, &xhi))
+                continue;
+            const int64_t bxl = (int64_t)std::floor(xlo / (long double)B) - 1;
+            const int64_t bxh = (int64_t)std::floor(xhi / (long double)B) + 1;
+            const int64_t byl = r * TY, byh = r * TY + TY - 1;
+            for (int64_t v : {bxl, bxh, byl, byh})
+                if (v <= -lim_bins || v >= lim_bins)
+                    return fail(SAS_E_UNSUPPORTED, "sas_plan_create: projected bins exceed +-2^29");
+            const int64_t t0x = floor_div(bxl, TX), t1x = floor_div(bxh, TX);
+            items.insert(items.end(), {sg, (int32_t)(r * TY), (int32_t)(t0x * TX),
+                                       (int32_t)(t1x - t0x + 1)});
+            n_tiles += t1x - t0x + 1;
+        }
         i = k;
     }
-    (void)bx_min_all; (void)bx_max_all;
-    block_start.push_back((int32_t)n_v);
-    p->n_blocks = (int64_t)block_start.size() - 1;
-    p->n_items = (int64_t)items.size() / 3;
+    p->n_segments = (int64_t)seg.size() / 4;
+    p->n_items = (int64_t)items.size() / 4;
+    p->n_tiles = n_tiles;
     if (p->n_items >= ((int64_t)1 << 31))
         return fail(SAS_E_UNSUPPORTED, "sas_plan_create: too many work items");
 
-    std::vector<int32_t> vel(d->v_host, d->v_host + 2 * n_v);
+    std::vector<int32_t> vel(V, V + 2 * n_v);
     sas_status st;
     if ((st = upload(p.get(), &p->d_vel, vel)) != SAS_OK) goto fail_free;
-    if ((st = upload(p.get(), &p->d_members, order)) != SAS_OK) goto fail_free;
-    if ((st = upload(p.get(), &p->d_block_start, block_start)) != SAS_OK) goto fail_free;
-    if ((st = upload(p.get(), &p->d_block_vr, block_vr)) != SAS_OK) goto fail_free;
+    if ((st = upload(p.get(), &p->d_seg, seg)) != SAS_OK) goto fail_free;
+    if ((st = upload(p.get(), &p->d_seg_v, seg_v)) != SAS_OK) goto fail_free;
+    if ((st = upload(p.get(), &p->d_seg_vel, seg_vel)) != SAS_OK) goto fail_free;
     if ((st = upload(p.get(), &p->d_items, items)) != SAS_OK) goto fail_free;
     if ((st = upload(p.get(), &p->d_t, p->t)) != SAS_OK) goto fail_free;
     *plan_out = p.release();
@@ -336,12 +451,15 @@ sas_status sas_plan_destroy(sas_plan *p) {
 sas_status sas_plan_get_info(const sas_plan *p, sas_plan_info *info) {
     if (!p || !info) return fail(SAS_E_INVALID, "sas_plan_get_info: null argument");
     info->n_items = p->n_items;
-    info->n_blocks = p->n_blocks;
+    info->n_tiles = p->n_tiles;
+    info->n_blocks = p->n_segments;
     info->path = p->path;
     info->tile_x = p->tile_x;
     info->tile_y = p->tile_y;
     info->vblock_x = p->vbx;
     info->vblock_y = p->vby;
+    info->coarse_log2 = p->coarse_log2;
+    info->mode_variant = p->dense_mode;
     info->cell_log2 = p->cell_log2;
     info->n_v = p->n_v;
     return SAS_OK;
@@ -374,18 +492,17 @@ sas_status sas_vote(const sas_plan *p, const int32_t *x_q8, const int32_t *y_q8,
     pb.blocksum = (int32_t *)(w + L.blocksum);
     pb.cellid = (int32_t *)(w + L.cellid);
     pb.rank = (int32_t *)(w + L.rank);
-    pb.sx = (int32_t *)(w + L.sx);
-    pb.sy = (int32_t *)(w + L.sy);
+    pb.sxy = (int2 *)(w + L.sxy);
     pb.present = (int32_t *)(w + L.present);
     pb.dt = (int32_t *)(w + L.dt);
+    pb.refine_count = (unsigned long long *)(w + L.refine_count);
     hipError_t e = launch_prep(x_q8, y_q8, epoch, n, p->d_t, p->n_epochs, p->ncx, p->ncy,
                                p->cell_log2, p->ext, p->n_cells, pb, res_dev, s);
     if (e != hipSuccess) return hip_fail(e, "sas_vote: preparation launch");
     if (n == 0 || p->n_v == 0) return SAS_OK;
 
     DenseArgs a{};
-    a.cat.sx = pb.sx;
-    a.cat.sy = pb.sy;
+    a.cat.sxy = pb.sxy;
     a.cat.off = pb.count;
     a.cat.dt = pb.dt;
     a.cat.n_epochs = p->n_epochs;
@@ -396,17 +513,23 @@ sas_status sas_vote(const sas_plan *p, const int32_t *x_q8, const int32_t *y_q8,
     a.cat.x1 = p->ext[1];
     a.cat.y0 = p->ext[2];
     a.cat.y1 = p->ext[3];
-    a.shift = 16 + p->log2b;
+    a.log2b = p->log2b;
+    a.coarse_log2 = p->coarse_log2;
     a.tile_x = p->tile_x;
     a.tile_y = p->tile_y;
+    a.log2_tile_x = ilog2_exact(p->tile_x);
     a.n_min = p->n_min;
     a.count_sat = p->count_sat;
+    a.mode_epochs = p->mode == SAS_MODE_EPOCHS ? 1 : 0;
     a.vel = p->d_vel;
-    a.members = p->d_members;
-    a.block_start = p->d_block_start;
-    a.block_vr = p->d_block_vr;
+    a.seg = p->d_seg;
+    a.seg_v = p->d_seg_v;
+    a.seg_vel = p->d_seg_vel;
     a.items = p->d_items;
     a.n_items = p->n_items;
+    a.refine = (int4 *)(w + L.refine);
+    a.refine_count = pb.refine_count;
+    a.refine_cap = p->dense_mode == kCountRef ? p->refine_cap : 0;
     a.cand = cand_dev;
     a.cand_cap = cand_cap;
     a.res = res_dev;
@@ -432,6 +555,10 @@ sas_status sas_peaks(const sas_candidate *cand_dev, const sas_vote_result *res_d
         return fail(SAS_E_INVALID, "sas_peaks: the catalog holds an epoch index >= n_epochs");
     if (r.status & SAS_DATA_OUTSIDE)
         return fail(SAS_E_INVALID, "sas_peaks: a detection lies outside the plan's footprint");
+    if (r.status & SAS_DATA_REFINE_FULL)
+        return fail(SAS_E_OVERFLOW, "sas_peaks: more flagged histogram cells than the plan's "
+                                    "refinement list holds; raise tuning.refine_cap or use "
+                                    "tuning.coarse_log2 = -1");
     if (r.n_cand > cand_cap) {
         *n_out = r.n_cand;
         return fail(SAS_E_OVERFLOW, "sas_peaks: more candidates than the vote buffer held");

@@ -9,25 +9,31 @@
 namespace sas {
 
 constexpr int kMaxEpochs = 256;
-constexpr int kVoteThreads = 256;   // threads per dense-vote workgroup
-constexpr int kVoteKmax = 16;       // detections held in registers per thread
-constexpr int kVoteCap = kVoteThreads * kVoteKmax;
-constexpr int kSlots = 256;         // exact-epoch slots per tag round (EPOCHS with E > 32)
-constexpr uint32_t kTag = 0x80000000u;
+constexpr int kVoteThreads = 512;     // threads per vote workgroup (8 waves)
+constexpr int kLanes = 32;            // velocities of one segment: lanes 0-31 and 32-63
+                                      // of a wave vote two detections at once
+constexpr int kStageCap = 2048;       // window detections staged in LDS at a time
+constexpr int kBatch = 8;             // vote iterations per batch (16 staged detections)
+constexpr int kStagePad = 2 * kBatch; // readable slots past the stage
+constexpr int kFlagCap = 1024;        // lifted (velocity, bin) cells remembered per tile
+constexpr int kSlotWords = kMaxEpochs / 32;
+constexpr int kMaxCells = 16384;      // (bin, lane) cells of the LDS histogram (64 KiB)
+constexpr int64_t kMaxVoteGrid = 1 << 16;  // workgroups of one vote launch (grid-stride)
 
-// Dense-path kernel variants.
+constexpr int kRefineGrid = 2048;          // workgroups of the refinement launch
+
+// Histogram variants of the dense path.
 enum DenseMode : int {
-    kMask32 = 0,    // EPOCHS, E <= 32: one epoch bitmask word per bin
-    kCountDet = 1,  // DETECTIONS: one counter per bin
-    kCountEpo = 2,  // EPOCHS, E > 32: counter per bin filters, tags give exact epochs
+    kMask32 = 0,    // EPOCHS, E <= 32, single bins: epoch bitmask per cell, emitted directly
+    kCountDet = 1,  // DETECTIONS, single bins: counter per cell, emitted directly
+    kCountRef = 2,  // counter of detections as a filter; lifted cells are refined
 };
 
 // Catalog after preparation: detections grouped by (epoch, cell row, cell column).
 struct PreparedCatalog {
-    const int32_t *sx;    // [n_valid] x, Q8
-    const int32_t *sy;    // [n_valid] y, Q8
+    const int2 *sxy;      // [n_valid] (x, y), Q8
     const int32_t *off;   // [n_cells + 1] CSR offsets; cell = (e * ncy + cy) * ncx + cx
-    const int32_t *dt;    // [E] t[e] - t0, Q16 h (0 for epochs without detections)
+    const int32_t *dt;    // [E] t[e] - t0, Q16 h; -1 for epochs without detections
     int32_t n_epochs;
     int32_t ncx, ncy, cell_log2;
     int32_t x0, x1, y0, y1;
@@ -35,15 +41,21 @@ struct PreparedCatalog {
 
 struct DenseArgs {
     PreparedCatalog cat;
-    int32_t shift;        // 16 + log2(binw_q8): Q24 -> bin index
-    int32_t tile_x, tile_y;
+    int32_t log2b;            // bin width = 2^log2b Q8 px
+    int32_t coarse_log2;      // histogram cells of 2^m x 2^m bins (kCountRef only)
+    int32_t tile_x, tile_y;   // cells per tile; tile_x * tile_y * kLanes <= kMaxCells
+    int32_t log2_tile_x;      // tile_x is a power of two
     int32_t n_min, count_sat;
-    const int32_t *vel;         // [n_v][2]
-    const int32_t *members;     // v_idx, grouped by block
-    const int32_t *block_start; // [n_blocks + 1]
-    const int32_t *block_vr;    // [n_blocks][4] vx_lo, vx_hi, vy_lo, vy_hi
-    const int32_t *items;       // [n_items][3] block, tx0, ty0
+    int32_t mode_epochs;      // 1: count distinct epochs, 0: count detections
+    const int32_t *vel;       // [n_v][2] velocities, Q8 px/h
+    const int32_t *seg;       // [n_seg][4] vx_lo, vx_hi, vy_lo, vy_hi (Q8 px/h)
+    const int32_t *seg_v;     // [n_seg][kLanes] v_idx of each lane (-1: unused)
+    const int32_t *seg_vel;   // [n_seg][kLanes][2] velocity of each lane
+    const int32_t *items;     // [n_items][4] segment, ty0, first tx0, number of tiles (cells)
     int64_t n_items;
+    int4 *refine;             // [refine_cap] queued (v_idx, cell x, cell y, 0)
+    unsigned long long *refine_count;
+    int64_t refine_cap;
     sas_candidate *cand;
     int64_t cand_cap;
     sas_vote_result *res;
@@ -55,9 +67,10 @@ struct PrepBuffers {
     int32_t *blocksum;  // [scan blocks]
     int32_t *cellid;    // [n]
     int32_t *rank;      // [n]
-    int32_t *sx, *sy;   // [n]
+    int2 *sxy;          // [n]
     int32_t *present;   // [E]
     int32_t *dt;        // [E]
+    unsigned long long *refine_count;
 };
 
 constexpr int kScanThreads = 1024;

@@ -1,7 +1,8 @@
 // Catalog preparation for the voting transform.
 //
 //   * the reference epoch of Step 1 (Sec. 2.1): t0 is the earliest time at
-//     which the catalog holds a detection, and every epoch gets d_e = t_e - t0;
+//     which the catalog holds a detection, and every epoch that holds one gets
+//     d_e = t_e - t0 (the others get -1);
 //   * a window index: detections are grouped by (epoch, cell row, cell
 //     column) with a counting sort, so that a workgroup can fetch the
 //     detections that can land in its tile with one contiguous range per
@@ -51,7 +52,7 @@ __device__ int32_t block_exclusive_scan(int32_t v, int32_t *total) {
 }
 
 __global__ void k_prep_zero(int32_t *count, int64_t n_count, int32_t *present, int32_t n_epochs,
-                            sas_vote_result *res) {
+                            sas_vote_result *res, unsigned long long *refine_count) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_count; i += stride)
         count[i] = 0;
@@ -60,7 +61,8 @@ __global__ void k_prep_zero(int32_t *count, int64_t n_count, int32_t *present, i
         if (threadIdx.x == 0) {
             res->n_cand = 0;
             res->status = 0;
-            res->reserved = 0;
+            res->n_spilled = 0;
+            *refine_count = 0;
         }
     }
 }
@@ -144,20 +146,20 @@ __global__ void k_prep_reftime(const int64_t *t, const int32_t *present, int32_t
         __syncthreads();
     }
     const long long t0 = red[0];
-    if (e < n_epochs) dt[e] = (present[e] && t0 != LLONG_MAX) ? (int32_t)(t[e] - t0) : 0;
+    // epochs without detections get -1: nothing of theirs is ever projected
+    if (e < n_epochs) dt[e] = (present[e] && t0 != LLONG_MAX) ? (int32_t)(t[e] - t0) : -1;
 }
 
 __global__ void k_prep_scatter(const int32_t *__restrict__ x, const int32_t *__restrict__ y,
                                int64_t n, const int32_t *__restrict__ cellid,
                                const int32_t *__restrict__ rank, const int32_t *__restrict__ off,
-                               int32_t *__restrict__ sx, int32_t *__restrict__ sy) {
+                               int2 *__restrict__ sxy) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t c = cellid[i];
     if (c < 0) return;
     const int32_t pos = off[c] + rank[i];
-    sx[pos] = x[i];
-    sy[pos] = y[i];
+    sxy[pos] = make_int2(x[i], y[i]);
 }
 
 inline unsigned blocks_for(int64_t n, int threads) {
@@ -174,7 +176,7 @@ hipError_t launch_prep(const int32_t *x, const int32_t *y, const uint8_t *epoch,
     unsigned zb = blocks_for(n_count, 256);
     if (zb > 4096) zb = 4096;
     hipLaunchKernelGGL(k_prep_zero, dim3(zb), dim3(256), 0, stream, pb.count, n_count,
-                       pb.present, n_epochs, res);
+                       pb.present, n_epochs, res, pb.refine_count);
     if (n > 0) {
         hipLaunchKernelGGL(k_prep_count, dim3(blocks_for(n, 256)), dim3(256), 0, stream, x, y,
                            epoch, n, n_epochs, ncx, ncy, cell_log2, ext[0], ext[1], ext[2],
@@ -190,7 +192,7 @@ hipError_t launch_prep(const int32_t *x, const int32_t *y, const uint8_t *epoch,
                        n_epochs, pb.dt);
     if (n > 0) {
         hipLaunchKernelGGL(k_prep_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, stream, x, y,
-                           n, pb.cellid, pb.rank, pb.count, pb.sx, pb.sy);
+                           n, pb.cellid, pb.rank, pb.count, pb.sxy);
     }
     return hipGetLastError();
 }

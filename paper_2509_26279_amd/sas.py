@@ -49,7 +49,8 @@ class Tuning(ctypes.Structure):
     _fields_ = [("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
                 ("vblock_x", ctypes.c_int32), ("vblock_y", ctypes.c_int32),
                 ("cell_log2", ctypes.c_int32), ("sort_vblock", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("n_det_hint", ctypes.c_int32), ("coarse_log2", ctypes.c_int32),
+                ("refine_cap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class PlanDesc(ctypes.Structure):
@@ -62,10 +63,12 @@ class PlanDesc(ctypes.Structure):
 
 
 class PlanInfo(ctypes.Structure):
-    _fields_ = [("n_items", ctypes.c_int64), ("n_blocks", ctypes.c_int64),
+    _fields_ = [("n_items", ctypes.c_int64), ("n_tiles", ctypes.c_int64),
+                ("n_blocks", ctypes.c_int64),
                 ("path", ctypes.c_int32), ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
                 ("vblock_x", ctypes.c_int32), ("vblock_y", ctypes.c_int32),
-                ("cell_log2", ctypes.c_int32), ("n_v", ctypes.c_int64)]
+                ("cell_log2", ctypes.c_int32), ("coarse_log2", ctypes.c_int32),
+                ("mode_variant", ctypes.c_int32), ("n_v", ctypes.c_int64)]
 
 
 _lib = None
@@ -164,7 +167,8 @@ class Plan:
         if tuning is not None:
             self._tuning = Tuning(*[int(tuning.get(k, 0)) for k in
                                     ("tile_x", "tile_y", "vblock_x", "vblock_y", "cell_log2",
-                                     "sort_vblock")])
+                                     "sort_vblock", "n_det_hint", "coarse_log2",
+                                     "refine_cap")])
         desc = PlanDesc(self._v.ctypes.data, self._v.shape[0], self._t.shape[0],
                         self._t.ctypes.data, int(binw_q8), int(n_min), MODES[mode],
                         int(count_sat), PATHS[path], (ctypes.c_int32 * 4)(*map(int, extent_q8)),
@@ -255,6 +259,12 @@ class Search:
 
     def peaks(self, order="canonical", top_k=0, stream=None):
         return peaks(self.cand, self.res, order, top_k, stream)
+
+    def result(self) -> dict:
+        """The device-side vote result (synchronises): n_cand, status, n_spilled."""
+        r = self.res.cpu().numpy().view(np.int32)
+        n_cand = int(r[0].astype(np.int64) | (r[1].astype(np.int64) << 32))
+        return {"n_cand": n_cand, "status": int(r[2]), "n_spilled": int(r[3])}
 
     def run(self, x_q8, y_q8, epoch, order="canonical", top_k=0):
         x, y, e = self.upload(x_q8, y_q8, epoch)

@@ -82,7 +82,10 @@ def test_random_adversarial(gpu, seed, mode):
         o = oracle.vote(d["x_q8"], d["y_q8"], d["epoch"], d["t_q16"], d["v_q8"], d["binw_q8"],
                         n_min, mode)
         for tun in (None, dict(tile_x=4, tile_y=4, vblock_x=1, vblock_y=1),
-                    dict(tile_x=8, tile_y=16, vblock_x=3, vblock_y=2, cell_log2=9)):
+                    dict(tile_x=8, tile_y=16, vblock_x=3, vblock_y=2, cell_log2=9),
+                    dict(tile_x=2, tile_y=2, vblock_x=32, vblock_y=1, cell_log2=8),
+                    dict(coarse_log2=2), dict(coarse_log2=3, tile_x=4, tile_y=4),
+                    dict(coarse_log2=1, vblock_x=2, vblock_y=16)):
             g = gpu_vote(d["x_q8"], d["y_q8"], d["epoch"], d["t_q16"], d["v_q8"], d["binw_q8"],
                          n_min, mode, tuning=tun)
             assert_same(g, o)
@@ -102,7 +105,11 @@ def test_overfull_window_is_chunked(gpu, n_epochs, mode):
     for n_min in (1, 15, 60):
         _say(f"chunked E={n_epochs} mode={mode} n_min={n_min}")
         o = oracle.vote(x, y, e, t, v, 1024, n_min, mode)
-        g = gpu_vote(x, y, e, t, v, 1024, n_min, mode, extent=ext, cap=1 << 18)
+        plan = sas.Plan(v, t, 1024, n_min, ext, mode=mode)
+        srch = sas.Search(plan, len(x), cand_cap=1 << 18)
+        g = srch.run(x, y, e)
+        assert srch.result()["n_spilled"] > 0  # the chunked path did run
+        plan.close()
         assert_same(g, o)
 
 
@@ -137,7 +144,7 @@ def test_wide_full_grid_sampled_outputs(gpu):
     v = _grid(wl)
     _say(f"wide full grid n={wl.n} |V|={len(v)}")
     g = gpu_vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v, wl.binw_q8, wl.n_min, "epochs", 255,
-                 wl.extent_q8, cap=1 << 22)
+                 wl.extent_q8, cap=1 << 22, tuning=dict(n_det_hint=wl.n))
     assert len(g) > 0
     assert np.all(g["count"] >= wl.n_min) and np.all(g["count"] <= wl.n_epochs)
     key = g["v_idx"].astype(np.int64) << 40 | (g["by"].astype(np.int64) + (1 << 19)) << 20 | \
@@ -150,6 +157,30 @@ def test_wide_full_grid_sampled_outputs(gpu):
     o["v_idx"] = idx[o["v_idx"]]
     sub = g[np.isin(g["v_idx"], idx)]
     assert_same(sub, o)
+
+
+def test_fast_full_grid_every_tuning(gpu):
+    """The fast workload's whole 1.23e6-velocity grid under several launch
+    shapes: identical candidate lists, each checked against the oracle on the
+    velocities that produced candidates plus a seeded sample."""
+    wl = synth.make_fast()
+    v = _grid(wl)
+    lists = []
+    for tun in (dict(), dict(tile_x=16, tile_y=16), dict(tile_x=64, tile_y=8, vblock_x=16, vblock_y=2),
+                dict(tile_x=32, tile_y=4, vblock_x=7, vblock_y=3, cell_log2=14),
+                dict(coarse_log2=-1)):
+        tun["n_det_hint"] = wl.n
+        _say(f"fast full grid {tun}")
+        g = gpu_vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v, wl.binw_q8, wl.n_min, "epochs",
+                     65535, wl.extent_q8, tuning=tun, cap=1 << 20)
+        lists.append(g)
+    for g in lists[1:]:
+        assert_same(g, lists[0])
+    idx = np.union1d(np.unique(lists[0]["v_idx"]), _sampled_velocities(v, 24, 5))
+    o = oracle.vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v[idx], wl.binw_q8, wl.n_min)
+    o["v_idx"] = idx[o["v_idx"]]
+    assert_same(lists[0][np.isin(lists[0]["v_idx"], idx)], o)
+    assert len(o) > 0
 
 
 # ---------------------------------------------------------------- ABI behaviour
@@ -176,6 +207,15 @@ def test_overflow_two_call(gpu):
     g = gpu_vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v, wl.binw_q8, 3, extent=wl.extent_q8,
                  cap=len(o))
     assert_same(g, o)
+
+
+def test_refine_list_overflow_reported(gpu):
+    wl = synth.make_tiny()
+    v = _grid(wl)
+    with pytest.raises(sas.SasError) as ei:
+        gpu_vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v, wl.binw_q8, 3, extent=wl.extent_q8,
+                 tuning=dict(coarse_log2=2, refine_cap=1))
+    assert ei.value.status == sas.SAS_E_OVERFLOW and "refine" in str(ei.value)
 
 
 def test_bad_catalog_data_reported(gpu):
