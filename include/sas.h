@@ -64,6 +64,8 @@ typedef int32_t sas_status;
 #define SAS_DATA_BAD_EPOCH 1   /* an epoch index >= n_epochs */
 #define SAS_DATA_OUTSIDE 2     /* a detection outside the plan's footprint */
 #define SAS_DATA_REFINE_FULL 4 /* more flagged cells than the plan's refinement list holds */
+#define SAS_DATA_INTERNAL 8    /* a tile window exceeded the plan's run table or guard cells
+                                  (a library bug; the votes concerned were skipped) */
 
 const char *sas_status_string(sas_status s);
 /* Message of the calling thread's last failing call ("" if none). */
@@ -133,9 +135,14 @@ typedef struct {
 
 /* Launch shape of the dense path; zeros select the built-in defaults. */
 typedef struct {
-    int32_t tile_x, tile_y;     /* histogram cells per tile: tile_x a power of two,
-                                   tile_x * tile_y <= 512 and a multiple of 4 */
-    int32_t vblock_x, vblock_y; /* velocity segment in lattice steps; vblock_x * vblock_y <= 32 */
+    int32_t tile_x, tile_y;     /* interior histogram cells per tile (>= 1; the histogram with
+                                   its guard cells and the stage must fit in LDS) */
+    int32_t vblock_x, vblock_y; /* velocity segment in lattice steps; the product is at most
+                                   64 / groups */
+    int32_t groups;             /* lane groups G in {1, 2, 4}: a wave votes G detections per
+                                   instruction for 64 / G velocities */
+    int32_t stage_cap;          /* detections staged in LDS at a time (larger windows are
+                                   processed in chunks) */
     int32_t cell_log2;          /* log2 of the window-index cell size in Q8 px */
     int32_t sort_vblock;        /* velocities per sort-path block */
     int32_t n_det_hint;         /* expected detections per catalog: chooses the cell size */
@@ -190,8 +197,22 @@ typedef struct {
     int32_t coarse_log2;   /* histogram cells of 2^m x 2^m bins */
     int32_t mode_variant;  /* 0 epoch masks, 1 detection counts, 2 counts + refinement */
     int64_t n_v;
+    int32_t groups;        /* lane groups G */
+    int32_t hist_x, hist_y; /* histogram cells per tile, guard cells included */
+    int32_t stage_cap;
+    int32_t lds_bytes;     /* LDS per vote workgroup */
+    int32_t reserved;
 } sas_plan_info;
 sas_status sas_plan_get_info(const sas_plan *plan, sas_plan_info *info);
+
+/*
+ * sas_plan_set_probe: measurement hook.  Later sas_vote calls with this plan
+ * record the two hipEvent_t handles on their stream immediately before and
+ * after the vote kernel (preparation and refinement excluded), so that the
+ * caller can time that kernel alone.  NULL handles switch the hook off.  The
+ * events stay owned by the caller.
+ */
+sas_status sas_plan_set_probe(sas_plan *plan, void *ev_before, void *ev_after);
 
 /* Device workspace needed by sas_vote for a catalog of n detections. */
 sas_status sas_vote_workspace_size(const sas_plan *plan, int64_t n, size_t *bytes);

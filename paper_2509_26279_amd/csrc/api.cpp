@@ -109,11 +109,14 @@ struct sas_plan {
     int32_t ext[4] = {0, 0, 0, 0};
     int64_t n_v = 0;
     int dense_mode = 0;
-    int32_t tile_x = 32, tile_y = 12, vbx = 8, vby = 4, cell_log2 = 11, coarse_log2 = 0;
+    int32_t tile_x = 16, tile_y = 16, vbx = 8, vby = 8, groups = 1, cell_log2 = 11;
+    int32_t coarse_log2 = 0, hx = 0, hy = 0, stage_cap = 0, rows = 0, max_pairs = 0;
     int32_t ncx = 1, ncy = 1;
     int64_t n_cells = 0, n_items = 0, n_segments = 0, n_tiles = 0, refine_cap = 0;
+    size_t lds_bytes = 0;
     int32_t *d_vel = nullptr, *d_seg = nullptr, *d_seg_v = nullptr, *d_seg_vel = nullptr;
-    int32_t *d_items = nullptr;
+    int32_t *d_seg_guard = nullptr, *d_items = nullptr;
+    hipEvent_t probe[2] = {nullptr, nullptr};
     int64_t *d_t = nullptr;
     std::vector<void *> allocs;
 };
@@ -220,21 +223,15 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     sas_tuning tu{};
     if (d->tuning) tu = *d->tuning;
     const int64_t n_v = d->n_v;
+    const int64_t D = span;  // bound on every t_e - t0
     // natural lattice step Delta x / Delta t (Q8 px/h)
     const int64_t s_ref = span > 0 ? std::max<int64_t>(1, ((int64_t)d->binw_q8 * 65536) / span)
                                    : ((int64_t)1 << 30);
-    // Velocity segments: blocks of vbx x vby natural lattice steps, <= 32 velocities.
-    const int32_t vbx = tu.vblock_x ? tu.vblock_x : 8, vby = tu.vblock_y ? tu.vblock_y : 4;
-    if (vbx < 1 || vby < 1 || vbx * vby > kLanes)
-        return fail(SAS_E_INVALID, "sas_plan_create: vblock_x * vblock_y must be in [1, 32]");
-    int32_t TX = tu.tile_x ? tu.tile_x : 32, TY = tu.tile_y ? tu.tile_y : 12;
-    if (TX < 1 || TY < 1 || ilog2_exact(TX) < 0 || (int64_t)TX * TY * kLanes > kMaxCells ||
-        ((int64_t)TX * TY) % 4)
-        return fail(SAS_E_INVALID, "sas_plan_create: tile_x must be a power of two and "
-                                   "tile_x * tile_y a multiple of 4, at most 512");
     if (tu.coarse_log2 < -1 || tu.coarse_log2 > 3)
         return fail(SAS_E_INVALID, "sas_plan_create: coarse_log2 must be in [-1, 3]");
     if (tu.refine_cap < 0) return fail(SAS_E_INVALID, "sas_plan_create: refine_cap must be >= 0");
+    if (tu.tile_x < 0 || tu.tile_y < 0 || tu.stage_cap < 0 || tu.vblock_x < 0 || tu.vblock_y < 0)
+        return fail(SAS_E_INVALID, "sas_plan_create: negative tuning value");
 
     // Cell size of the histogram.  A cell of 2^m x 2^m bins counts the
     // detections of all its bins; only cells reaching N_min are refined into
@@ -267,19 +264,26 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
         }
     }
     const int kc = log2b + m;  // log2 of the cell width in Q8
-    int cl = tu.cell_log2;
-    if (!cl) cl = kc + 1;  // window-index cells of 2 x 2 histogram cells
-    if (cl < 0 || cl > 30) return fail(SAS_E_INVALID, "sas_plan_create: cell_log2 out of range");
-    auto ncells_of = [&](int c, int64_t lo, int64_t hi) { return ((hi - lo) + (1LL << c) - 1) >> c; };
-    while (ncells_of(cl, ex[0], ex[1]) > 32767 || ncells_of(cl, ex[2], ex[3]) > 32767) ++cl;
-    const int64_t ncx = ncells_of(cl, ex[0], ex[1]), ncy = ncells_of(cl, ex[2], ex[3]);
-    const int64_t n_cells = (int64_t)d->n_epochs * ncx * ncy;
-    if (n_cells >= ((int64_t)1 << 30))
-        return fail(SAS_E_INVALID, "sas_plan_create: window index too large; raise cell_log2");
+    const int64_t cellw = (int64_t)1 << kc;
+
+    // Lane groups and velocity blocks.  A block of k lattice steps spreads
+    // the projections of one detection over about k bins at the last epoch;
+    // the guard cells of a tile grow with that spread, so blocks are kept
+    // near one cell of spread where possible.
+    int G = tu.groups;
+    if (G == 0) {
+        const double spread8 = 7.0 * (double)d->binw_q8 / (double)cellw;  // 8 steps, in cells
+        G = spread8 <= 2.0 ? 1 : spread8 <= 4.0 ? 2 : 4;
+    }
+    if (G != 1 && G != 2 && G != 4)
+        return fail(SAS_E_INVALID, "sas_plan_create: groups must be 1, 2 or 4");
+    const int NV = 64 / G;
+    const int32_t vbx = tu.vblock_x ? tu.vblock_x : (G == 4 ? 4 : 8);
+    const int32_t vby = tu.vblock_y ? tu.vblock_y : (G == 1 ? 8 : 4);
+    if (vbx < 1 || vby < 1 || vbx * vby > NV)
+        return fail(SAS_E_INVALID, "sas_plan_create: vblock_x * vblock_y must be in [1, 64 / groups]");
 
     // velocities: range checks
-    const __int128 B = (__int128)1 << (16 + kc);  // one histogram cell in Q24
-    const __int128 lim_bins = (__int128)1 << 29;
     for (int64_t j = 0; j < n_v; ++j) {
         for (int a = 0; a < 2; ++a) {
             const int64_t v = d->v_host[2 * j + a];
@@ -287,16 +291,168 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
                 return fail(SAS_E_UNSUPPORTED, "sas_plan_create: |v| * span too large (>= 2^46 Q24)");
         }
     }
-    {   // tile-relative Q8 coordinates are held in 32 bits by the kernels
+
+    // Segments: velocities bucketed by blocks of vbx x vby natural lattice
+    // steps (row-major over blocks), at most NV per segment.
+    const int32_t *V = d->v_host;
+    int64_t vxmin = 0, vymin = 0;
+    if (n_v > 0) {
+        vxmin = V[0];
+        vymin = V[1];
+        for (int64_t j = 1; j < n_v; ++j) {
+            vxmin = std::min<int64_t>(vxmin, V[2 * j]);
+            vymin = std::min<int64_t>(vymin, V[2 * j + 1]);
+        }
+    }
+    std::vector<int64_t> kx(n_v), ky(n_v);
+    std::vector<int32_t> order(n_v);
+    for (int64_t j = 0; j < n_v; ++j) {
+        order[j] = (int32_t)j;
+        kx[j] = ((int64_t)V[2 * j] - vxmin) / ((int64_t)vbx * s_ref);
+        ky[j] = ((int64_t)V[2 * j + 1] - vymin) / ((int64_t)vby * s_ref);
+    }
+    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        if (ky[a] != ky[b]) return ky[a] < ky[b];
+        if (kx[a] != kx[b]) return kx[a] < kx[b];
+        if (V[2 * a + 1] != V[2 * b + 1]) return V[2 * a + 1] < V[2 * b + 1];
+        if (V[2 * a] != V[2 * b]) return V[2 * a] < V[2 * b];
+        return a < b;
+    });
+    // ceil((dv * D) / 65536) for dv >= 0: a bound on S(v + dv) - S(v) over
+    // every epoch, with S(v) = ceil(v d / 65536) and 0 <= d <= D.
+    auto spread_q8 = [&](int64_t dv) -> int64_t {
+        return (int64_t)(((__int128)dv * D + 65535) >> 16);
+    };
+    auto ceil_cells = [&](int64_t q8) -> int64_t { return (q8 + cellw - 1) >> kc; };
+    std::vector<int32_t> seg, seg_v, seg_vel, seg_guard;
+    int64_t guard_x = 0, guard_y = 0, spread_y_max = 0;
+    double spread_x_sum = 0, spread_y_sum = 0;
+    {
+        int64_t i = 0;
+        while (i < n_v) {
+            int64_t k = i;
+            while (k < n_v && k - i < NV && ky[order[k]] == ky[order[i]] &&
+                   kx[order[k]] == kx[order[i]])
+                ++k;
+            int32_t vx_lo = INT32_MAX, vx_hi = INT32_MIN, vy_lo = INT32_MAX, vy_hi = INT32_MIN;
+            for (int64_t q = i; q < k; ++q) {
+                vx_lo = std::min(vx_lo, V[2 * order[q]]);
+                vx_hi = std::max(vx_hi, V[2 * order[q]]);
+                vy_lo = std::min(vy_lo, V[2 * order[q] + 1]);
+                vy_hi = std::max(vy_hi, V[2 * order[q] + 1]);
+            }
+            seg.insert(seg.end(), {vx_lo, vx_hi, vy_lo, vy_hi});
+            spread_x_sum += (double)spread_q8((int64_t)vx_hi - vx_lo);
+            spread_y_sum += (double)spread_q8((int64_t)vy_hi - vy_lo);
+            spread_y_max = std::max(spread_y_max, spread_q8((int64_t)vy_hi - vy_lo));
+            for (int l = 0; l < NV; ++l) {
+                const bool used = i + l < k;
+                const int32_t u = used ? V[2 * order[i + l]] : vx_lo;
+                const int32_t w = used ? V[2 * order[i + l] + 1] : vy_lo;
+                seg_v.push_back(used ? order[i + l] : -1);
+                seg_vel.push_back(u);
+                seg_vel.push_back(w);
+                // left guard: room for S(u) - S(u_lo) plus one Q8 step (the
+                // padding detection); right guard: S(u_hi) - S(u)
+                const int64_t gx = ceil_cells(spread_q8((int64_t)u - vx_lo) + 1);
+                const int64_t gy = ceil_cells(spread_q8((int64_t)w - vy_lo) + 1);
+                const int64_t rx = ceil_cells(spread_q8((int64_t)vx_hi - u));
+                const int64_t ry = ceil_cells(spread_q8((int64_t)vy_hi - w));
+                if (gx >= 32768 || gy >= 32768 || gx + rx >= 32768 || gy + ry >= 32768)
+                    return fail(SAS_E_UNSUPPORTED, "sas_plan_create: velocity block spreads over "
+                                                   "too many cells; use a smaller vblock");
+                seg_guard.push_back((int32_t)(gx | (gy << 16)));
+                guard_x = std::max(guard_x, gx + rx);
+                guard_y = std::max(guard_y, gy + ry);
+            }
+            i = k;
+        }
+    }
+    const int64_t n_seg = (int64_t)seg.size() / 4;
+    const double spread_x_avg = n_seg ? spread_x_sum / n_seg : 0.0;  // Q8, at the last epoch
+    const double spread_y_avg = n_seg ? spread_y_sum / n_seg : 0.0;
+
+    // LDS budget of one workgroup: two workgroups per CU unless the tuning
+    // asks for more.
+    const size_t lds_static = dense_static_lds_bytes();
+    const size_t lds_cap = (size_t)kLdsPerCU - lds_static;
+    const size_t lds_target = (size_t)kLdsPerCU / 2 - 2048 - lds_static;  // 2 per CU, with slack
+    int cl = tu.cell_log2;
+    if (cl < 0 || cl > 30) return fail(SAS_E_INVALID, "sas_plan_create: cell_log2 out of range");
+    auto ncells_of = [&](int c, int64_t lo, int64_t hi) { return ((hi - lo) + (1LL << c) - 1) >> c; };
+    auto rows_bound = [&](int c, int64_t ty) {  // index rows one tile's window can touch
+        return (int64_t)((ty * cellw + spread_y_max - 1) >> c) + 2;
+    };
+    // tile shape: the largest interior under the histogram budget with the
+    // best ratio of interior to window area (exact windows: the window adds
+    // the average spread of a block to each side length)
+    int32_t TX = tu.tile_x, TY = tu.tile_y;
+    if (!TX || !TY) {
+        const size_t hist_budget = lds_target * 2 / 3;
+        double best = -1.0;
+        for (int ty = 1; ty <= 128; ++ty)
+            for (int tx = 1; tx <= 128; ++tx) {
+                if (tu.tile_x && tx != tu.tile_x) continue;
+                if (tu.tile_y && ty != tu.tile_y) continue;
+                const size_t hb = (size_t)(tx + guard_x) * (ty + guard_y) * NV * 4;
+                if (hb > hist_budget) continue;
+                const double wx = tx + 0.5 * spread_x_avg / cellw + 0.5;
+                const double wy = ty + 0.5 * spread_y_avg / cellw + 0.5;
+                const double score = (double)tx * ty / (wx * wy);
+                if (score > best + 1e-9) {
+                    best = score;
+                    TX = tx;
+                    TY = ty;
+                }
+            }
+        if (best < 0) {
+            TX = tu.tile_x ? tu.tile_x : 1;
+            TY = tu.tile_y ? tu.tile_y : 1;
+        }
+    }
+    if (TX < 1 || TY < 1 || TX > 4096 || TY > 4096)
+        return fail(SAS_E_INVALID, "sas_plan_create: tile_x and tile_y must be in [1, 4096]");
+    const int64_t HX = TX + guard_x, HY = TY + guard_y;
+    if (!cl) cl = kc + 1;  // window-index cells of 2 x 2 histogram cells
+    while (ncells_of(cl, ex[0], ex[1]) > 32767 || ncells_of(cl, ex[2], ex[3]) > 32767 ||
+           (int64_t)d->n_epochs * rows_bound(cl, TY) > 2048)
+        ++cl;
+    if (cl > 30) return fail(SAS_E_UNSUPPORTED, "sas_plan_create: footprint too large");
+    const int64_t ncx = ncells_of(cl, ex[0], ex[1]), ncy = ncells_of(cl, ex[2], ex[3]);
+    const int64_t n_cells = (int64_t)d->n_epochs * ncx * ncy;
+    if (n_cells >= ((int64_t)1 << 30))
+        return fail(SAS_E_INVALID, "sas_plan_create: window index too large; raise cell_log2");
+    const int64_t max_pairs = (int64_t)d->n_epochs * rows_bound(cl, TY);
+    const size_t hist_bytes = (size_t)HX * HY * NV * 4;
+    int64_t stage_cap = tu.stage_cap;
+    if (!stage_cap) {
+        const size_t fixed = dense_lds_bytes(G, (int)HX, (int)HY, 0, (int)max_pairs);
+        const size_t room = lds_target > fixed ? (lds_target - fixed) / sizeof(int2) : 0;
+        int64_t want = (int64_t)room;
+        if (tu.n_det_hint > 0) {
+            const double win = ((double)TX * cellw + 0.5 * spread_x_avg) *
+                               ((double)TY * cellw + 0.5 * spread_y_avg);
+            want = std::min<int64_t>(want, (int64_t)(1.5 * tu.n_det_hint * win / area) + 256);
+        }
+        stage_cap = std::max<int64_t>(want, 256);
+    }
+    stage_cap = (stage_cap + 1) & ~(int64_t)1;
+    const size_t lds = dense_lds_bytes(G, (int)HX, (int)HY, (int)stage_cap, (int)max_pairs);
+    if (HX > 65535 || HY > 65535 || hist_bytes > lds_cap || lds > lds_cap)
+        return fail(SAS_E_INVALID, "sas_plan_create: tile + guard cells + stage exceed the LDS of "
+                                   "a workgroup; lower tile_x, tile_y, stage_cap or vblock");
+    {   // window and projected positions are held in 32 bits by the kernels
         int64_t vmax_abs = 0;
         for (int64_t j = 0; j < 2 * n_v; ++j)
             vmax_abs = std::max<int64_t>(vmax_abs, d->v_host[j] < 0 ? -(int64_t)d->v_host[j]
                                                                     : d->v_host[j]);
         const __int128 shift_q8 = ((__int128)vmax_abs * span >> 16) + 1;
-        const __int128 tile_q8 = (__int128)std::max(TX, TY) << kc;
-        const __int128 reach = (__int128)std::max<int64_t>((int64_t)ex[1] - ex[0],
-                                                           (int64_t)ex[3] - ex[2]) +
-                               shift_q8 + tile_q8;
+        const __int128 tile_q8 = (__int128)(std::max(HX, HY) + 1) << kc;
+        const __int128 reach = (__int128)std::max<int64_t>(std::max<int64_t>(
+                                   std::abs((int64_t)ex[0]), std::abs((int64_t)ex[1])),
+                                   std::max<int64_t>(std::abs((int64_t)ex[2]),
+                                                     std::abs((int64_t)ex[3]))) +
+                               2 * shift_q8 + 2 * tile_q8;
         if (reach >= ((__int128)1 << 30))
             return fail(SAS_E_UNSUPPORTED, "sas_plan_create: footprint + largest shift + tile "
                                            "must stay below 2^30 Q8 px");
@@ -331,63 +487,29 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     p->tile_y = TY;
     p->vbx = vbx;
     p->vby = vby;
+    p->groups = G;
+    p->hx = (int32_t)HX;
+    p->hy = (int32_t)HY;
+    p->stage_cap = (int32_t)stage_cap;
+    p->max_pairs = (int32_t)max_pairs;
+    p->rows = (int32_t)rows_bound(cl, TY);
+    p->lds_bytes = lds + lds_static;
     p->cell_log2 = cl;
     p->ncx = (int32_t)ncx;
     p->ncy = (int32_t)ncy;
     p->n_cells = n_cells;
 
-    // Segments: velocities bucketed by blocks of vbx x vby natural lattice
-    // steps (row-major over blocks), at most kLanes per segment.
-    const int32_t *V = d->v_host;
-    int64_t vxmin = 0, vymin = 0;
-    if (n_v > 0) {
-        vxmin = V[0];
-        vymin = V[1];
-        for (int64_t j = 1; j < n_v; ++j) {
-            vxmin = std::min<int64_t>(vxmin, V[2 * j]);
-            vymin = std::min<int64_t>(vymin, V[2 * j + 1]);
-        }
-    }
-    std::vector<int64_t> kx(n_v), ky(n_v);
-    std::vector<int32_t> order(n_v);
-    for (int64_t j = 0; j < n_v; ++j) {
-        order[j] = (int32_t)j;
-        kx[j] = ((int64_t)V[2 * j] - vxmin) / ((int64_t)vbx * s_ref);
-        ky[j] = ((int64_t)V[2 * j + 1] - vymin) / ((int64_t)vby * s_ref);
-    }
-    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-        if (ky[a] != ky[b]) return ky[a] < ky[b];
-        if (kx[a] != kx[b]) return kx[a] < kx[b];
-        if (V[2 * a + 1] != V[2 * b + 1]) return V[2 * a + 1] < V[2 * b + 1];
-        if (V[2 * a] != V[2 * b]) return V[2 * a] < V[2 * b];
-        return a < b;
-    });
-    std::vector<int32_t> seg, seg_v, seg_vel, items;
-    int64_t i = 0, n_tiles = 0;
-    while (i < n_v) {
-        int64_t k = i;
-        while (k < n_v && k - i < kLanes && ky[order[k]] == ky[order[i]] &&
-               kx[order[k]] == kx[order[i]])
-            ++k;
-        int32_t vx_lo = INT32_MAX, vx_hi = INT32_MIN, vy_lo = INT32_MAX, vy_hi = INT32_MIN;
-        for (int64_t q = i; q < k; ++q) {
-            vx_lo = std::min(vx_lo, V[2 * order[q]]);
-            vx_hi = std::max(vx_hi, V[2 * order[q]]);
-            vy_lo = std::min(vy_lo, V[2 * order[q] + 1]);
-            vy_hi = std::max(vy_hi, V[2 * order[q] + 1]);
-        }
-        const int32_t sg = (int32_t)(seg.size() / 4);
-        seg.insert(seg.end(), {vx_lo, vx_hi, vy_lo, vy_hi});
-        for (int l = 0; l < kLanes; ++l) {
-            const bool used = i + l < k;
-            seg_v.push_back(used ? order[i + l] : -1);
-            seg_vel.push_back(used ? V[2 * order[i + l]] : vx_lo);
-            seg_vel.push_back(used ? V[2 * order[i + l] + 1] : vy_lo);
-        }
-        // Tiles of this segment: the projections x - v dt of the footprint for
-        // v in the segment's box and dt in [0, span] lie inside the convex hull
-        // of the footprint's corners and their shifts by the box corners times
-        // span.  Every tile row gets the x range of that hull.
+    // Tiles of each segment: the projections x - v dt of the footprint for v
+    // in the segment's box and dt in [0, span] lie inside the convex hull of
+    // the footprint's corners and their shifts by the box corners times span.
+    // Every tile row gets the x range of that hull.
+    const __int128 B = (__int128)1 << (16 + kc);  // one histogram cell in Q24
+    const __int128 lim_bins = (__int128)1 << 29;
+    std::vector<int32_t> items;
+    int64_t n_tiles = 0;
+    for (int64_t sg = 0; sg < n_seg; ++sg) {
+        const int32_t vx_lo = seg[4 * sg], vx_hi = seg[4 * sg + 1];
+        const int32_t vy_lo = seg[4 * sg + 2], vy_hi = seg[4 * sg + 3];
         std::vector<std::pair<__int128, __int128>> pts;
         for (int cx = 0; cx < 2; ++cx)
             for (int cy = 0; cy < 2; ++cy) {
@@ -413,13 +535,12 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
                 if (v <= -lim_bins || v >= lim_bins)
                     return fail(SAS_E_UNSUPPORTED, "sas_plan_create: projected bins exceed +-2^29");
             const int64_t t0x = floor_div(bxl, TX), t1x = floor_div(bxh, TX);
-            items.insert(items.end(), {sg, (int32_t)(r * TY), (int32_t)(t0x * TX),
+            items.insert(items.end(), {(int32_t)sg, (int32_t)(r * TY), (int32_t)(t0x * TX),
                                        (int32_t)(t1x - t0x + 1)});
             n_tiles += t1x - t0x + 1;
         }
-        i = k;
     }
-    p->n_segments = (int64_t)seg.size() / 4;
+    p->n_segments = n_seg;
     p->n_items = (int64_t)items.size() / 4;
     p->n_tiles = n_tiles;
     if (p->n_items >= ((int64_t)1 << 31))
@@ -431,6 +552,7 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     if ((st = upload(p.get(), &p->d_seg, seg)) != SAS_OK) goto fail_free;
     if ((st = upload(p.get(), &p->d_seg_v, seg_v)) != SAS_OK) goto fail_free;
     if ((st = upload(p.get(), &p->d_seg_vel, seg_vel)) != SAS_OK) goto fail_free;
+    if ((st = upload(p.get(), &p->d_seg_guard, seg_guard)) != SAS_OK) goto fail_free;
     if ((st = upload(p.get(), &p->d_items, items)) != SAS_OK) goto fail_free;
     if ((st = upload(p.get(), &p->d_t, p->t)) != SAS_OK) goto fail_free;
     *plan_out = p.release();
@@ -462,6 +584,21 @@ sas_status sas_plan_get_info(const sas_plan *p, sas_plan_info *info) {
     info->mode_variant = p->dense_mode;
     info->cell_log2 = p->cell_log2;
     info->n_v = p->n_v;
+    info->groups = p->groups;
+    info->hist_x = p->hx;
+    info->hist_y = p->hy;
+    info->stage_cap = p->stage_cap;
+    info->lds_bytes = (int32_t)p->lds_bytes;
+    info->reserved = 0;
+    return SAS_OK;
+}
+
+sas_status sas_plan_set_probe(sas_plan *p, void *ev_before, void *ev_after) {
+    if (!p) return fail(SAS_E_INVALID, "sas_plan_set_probe: null plan");
+    if ((ev_before == nullptr) != (ev_after == nullptr))
+        return fail(SAS_E_INVALID, "sas_plan_set_probe: give both events or neither");
+    p->probe[0] = (hipEvent_t)ev_before;
+    p->probe[1] = (hipEvent_t)ev_after;
     return SAS_OK;
 }
 
@@ -517,7 +654,11 @@ sas_status sas_vote(const sas_plan *p, const int32_t *x_q8, const int32_t *y_q8,
     a.coarse_log2 = p->coarse_log2;
     a.tile_x = p->tile_x;
     a.tile_y = p->tile_y;
-    a.log2_tile_x = ilog2_exact(p->tile_x);
+    a.hx = p->hx;
+    a.hy = p->hy;
+    a.stage_cap = p->stage_cap;
+    a.rows = p->rows;
+    a.max_pairs = p->max_pairs;
     a.n_min = p->n_min;
     a.count_sat = p->count_sat;
     a.mode_epochs = p->mode == SAS_MODE_EPOCHS ? 1 : 0;
@@ -525,6 +666,7 @@ sas_status sas_vote(const sas_plan *p, const int32_t *x_q8, const int32_t *y_q8,
     a.seg = p->d_seg;
     a.seg_v = p->d_seg_v;
     a.seg_vel = p->d_seg_vel;
+    a.seg_guard = p->d_seg_guard;
     a.items = p->d_items;
     a.n_items = p->n_items;
     a.refine = (int4 *)(w + L.refine);
@@ -533,7 +675,7 @@ sas_status sas_vote(const sas_plan *p, const int32_t *x_q8, const int32_t *y_q8,
     a.cand = cand_dev;
     a.cand_cap = cand_cap;
     a.res = res_dev;
-    e = launch_vote_dense(p->dense_mode, a, s);
+    e = launch_vote_dense(p->dense_mode, p->groups, a, s, p->probe[0], p->probe[1]);
     if (e != hipSuccess) return hip_fail(e, "sas_vote: vote launch");
     return SAS_OK;
 }
@@ -555,6 +697,9 @@ sas_status sas_peaks(const sas_candidate *cand_dev, const sas_vote_result *res_d
         return fail(SAS_E_INVALID, "sas_peaks: the catalog holds an epoch index >= n_epochs");
     if (r.status & SAS_DATA_OUTSIDE)
         return fail(SAS_E_INVALID, "sas_peaks: a detection lies outside the plan's footprint");
+    if (r.status & SAS_DATA_INTERNAL)
+        return fail(SAS_E_DEVICE, "sas_peaks: internal error: a tile window exceeded the plan's "
+                                  "run table or guard cells");
     if (r.status & SAS_DATA_REFINE_FULL)
         return fail(SAS_E_OVERFLOW, "sas_peaks: more flagged histogram cells than the plan's "
                                     "refinement list holds; raise tuning.refine_cap or use "

@@ -9,16 +9,10 @@
 namespace sas {
 
 constexpr int kMaxEpochs = 256;
-constexpr int kVoteThreads = 512;     // threads per vote workgroup (8 waves)
-constexpr int kLanes = 32;            // velocities of one segment: lanes 0-31 and 32-63
-                                      // of a wave vote two detections at once
-constexpr int kStageCap = 2048;       // window detections staged in LDS at a time
-constexpr int kBatch = 8;             // vote iterations per batch (16 staged detections)
-constexpr int kStagePad = 2 * kBatch; // readable slots past the stage
-constexpr int kFlagCap = 1024;        // lifted (velocity, bin) cells remembered per tile
+constexpr int kVoteThreads = 512;          // threads per vote workgroup (8 waves)
 constexpr int kSlotWords = kMaxEpochs / 32;
-constexpr int kMaxCells = 16384;      // (bin, lane) cells of the LDS histogram (64 KiB)
 constexpr int64_t kMaxVoteGrid = 1 << 16;  // workgroups of one vote launch (grid-stride)
+constexpr int kLdsPerCU = 160 * 1024;      // gfx950
 
 constexpr int kRefineGrid = 2048;          // workgroups of the refinement launch
 
@@ -43,15 +37,19 @@ struct DenseArgs {
     PreparedCatalog cat;
     int32_t log2b;            // bin width = 2^log2b Q8 px
     int32_t coarse_log2;      // histogram cells of 2^m x 2^m bins (kCountRef only)
-    int32_t tile_x, tile_y;   // cells per tile; tile_x * tile_y * kLanes <= kMaxCells
-    int32_t log2_tile_x;      // tile_x is a power of two
+    int32_t tile_x, tile_y;   // interior cells per tile
+    int32_t hx, hy;           // histogram cells per tile, guards included
+    int32_t stage_cap;        // detections staged in LDS at a time
+    int32_t rows;             // index rows a tile window can touch (planner bound)
+    int32_t max_pairs;        // capacity of the run table: E x rows
     int32_t n_min, count_sat;
     int32_t mode_epochs;      // 1: count distinct epochs, 0: count detections
     const int32_t *vel;       // [n_v][2] velocities, Q8 px/h
     const int32_t *seg;       // [n_seg][4] vx_lo, vx_hi, vy_lo, vy_hi (Q8 px/h)
-    const int32_t *seg_v;     // [n_seg][kLanes] v_idx of each lane (-1: unused)
-    const int32_t *seg_vel;   // [n_seg][kLanes][2] velocity of each lane
-    const int32_t *items;     // [n_items][4] segment, ty0, first tx0, number of tiles (cells)
+    const int32_t *seg_v;     // [n_seg][NV] v_idx of each lane (-1: unused)
+    const int32_t *seg_vel;   // [n_seg][NV][2] velocity of each lane
+    const int32_t *seg_guard; // [n_seg][NV] left guard cells gx | gy << 16
+    const int32_t *items;     // [n_items][4] segment, ty0, first tx0, number of tiles
     int64_t n_items;
     int4 *refine;             // [refine_cap] queued (v_idx, cell x, cell y, 0)
     unsigned long long *refine_count;
@@ -82,7 +80,11 @@ hipError_t launch_prep(const int32_t *x, const int32_t *y, const uint8_t *epoch,
                        int32_t cell_log2, const int32_t ext[4], int64_t n_cells,
                        const PrepBuffers &pb, sas_vote_result *res, hipStream_t stream);
 
-hipError_t launch_vote_dense(int mode, const DenseArgs &a, hipStream_t stream);
-size_t dense_lds_bytes(int mode, int tile_x, int tile_y);
+// groups: lane groups G (1, 2 or 4); segments hold 64 / G velocities.
+// ev0 / ev1 (optional) are recorded on the stream around the vote kernel.
+hipError_t launch_vote_dense(int mode, int groups, const DenseArgs &a, hipStream_t stream,
+                             hipEvent_t ev0, hipEvent_t ev1);
+size_t dense_lds_bytes(int groups, int hx, int hy, int stage_cap, int max_pairs);
+size_t dense_static_lds_bytes();
 
 }  // namespace sas

@@ -1,50 +1,58 @@
 // Dense LDS voting path for gfx950.
 //
 // Steps 1-2 of Sec. 2.1 (Project, Cluster) with the Step-3 threshold.  The
-// velocity grid is cut into segments of up to 32 velocities (8 x 4 lattice
-// blocks).  A workgroup takes a (segment, tile of TX x TY bins) and keeps
-// an LDS histogram of every (bin, velocity) cell, laid out [bin][32]:
-//   1. per epoch, the window of the original frame whose detections can land
-//      in the tile for some velocity of the segment is looked up in the window
-//      index and staged in LDS (tile-relative Q8 coordinates, epoch order);
-//   2. each wave takes epochs; lanes 0-31 and 32-63 carry the segment's 32
-//      velocities and vote two staged detections per instruction.  With
-//      d = t_e - t0 and S(v) = ceil(v d / 65536), the exact bin of Step 2
-//      floor((65536 x - v d) / (65536 b)) equals (x - S(v)) >> log2(b): one
-//      32-bit subtract and shift per axis; S is computed once per (lane,
-//      epoch).  A bin's 32 velocities are 32 consecutive words, so an atomic
-//      of a wave touches every LDS bank exactly twice;
-//   3. the atomic's return value identifies the unique vote that lifts a cell
-//      to N_min; lifted cells are emitted with a wavefront ballot and one
-//      global atomic per wave, or queued for refinement (below).
+// velocity grid is cut into segments of up to NV = 64 / G velocities (a block
+// of the velocity lattice).  A workgroup takes a (segment, row of tiles); a
+// tile is TX x TY histogram cells (a cell is one bin, or 2^m x 2^m bins for
+// the coarse filter below).  For each tile:
+//   1. per epoch, the exact window of the original frame whose detections can
+//      land in the tile for some velocity of the segment is computed; the
+//      window index (detections grouped by epoch, cell row, cell column) is
+//      read one thread per (epoch, cell row), and a block scan lays the runs
+//      out for a flat copy into a stage in LDS.  The copy keeps only the
+//      detections inside the exact window, grouped by epoch (large windows
+//      are staged in chunks);
+//   2. waves take epochs; lane = (group g < G, velocity j < NV), and the G
+//      groups vote G staged detections per instruction.  With d = t_e - t0
+//      and S(v) = ceil(v d / 65536), the bin of Step 2,
+//      floor((65536 x - v d) / (65536 b)), equals (x - S(v)) >> log2(b).  The
+//      histogram of every lane has guard cells on each side, sized from a
+//      bound on S(v) - S(v_lo) over the segment, so that a staged detection
+//      always lands inside it: a vote is two subtracts, two shifts, a
+//      multiply-add and an or for the address, and one LDS atomic with no
+//      return value and no bounds check.  The NV words of a bin are
+//      consecutive, so a group's lanes touch NV consecutive banks;
+//   3. one pass over the histogram reads and clears it; interior cells at or
+//      above N_min are emitted (wavefront ballot + one global atomic per
+//      wave) or queued for refinement.
 // Cell variants:
-//   kMask32  - EPOCHS with E <= 32: epoch bitmask per cell, emitted directly;
-//   kCountDet - DETECTIONS: counter per cell, emitted directly;
+//   kMask32  - EPOCHS with E <= 32: epoch bitmask per cell;
+//   kCountDet - DETECTIONS: counter per cell;
 //   kCountRef - counter of detections per cell as a filter: a bin can hold
 //               N_min distinct epochs (or detections) only if its cell holds
 //               N_min detections.  Used for EPOCHS with E > 32 and for coarse
-//               cells of 2^m x 2^m bins (sparse catalogs: far fewer cells per
-//               vote); lifted cells go to a list that k_refine resolves into
-//               exact bins.
+//               cells; k_refine resolves queued cells into exact bins.
 #include "internal.h"
 
 namespace sas {
 namespace {
 
 constexpr int T = kVoteThreads;
+constexpr int NW = T / 64;
 
 struct Shared {
     int32_t dt[kMaxEpochs];
-    int32_t sp[kMaxEpochs + 1];  // first window index of each epoch
-    int32_t rows[kMaxEpochs];    // cy0 | cy1 << 16   (cy0 > cy1: empty)
-    int32_t cols[kMaxEpochs];    // cx0 | cx1 << 16
-    int32_t wsum[T / 64];
-    int32_t sv[kLanes];          // segment: v_idx of each lane (-1: unused)
-    int32_t svx[kLanes];         // segment: velocity of each lane
-    int32_t svy[kLanes];
-    int32_t nflag;
-    int32_t max_rows;
+    int32_t es[4][kMaxEpochs];  // per epoch: S(vx_lo), S(vx_hi), S(vy_lo), S(vy_hi) of the segment
+    int32_t ecnt[kMaxEpochs];   // staged detections of the epoch in the current chunk
+    int32_t wsum[2][NW];        // block scan partials (alternating per tile)
+    int32_t sv[64];             // segment: v_idx of each velocity lane (-1: unused)
+    int32_t svx[64], svy[64];   // segment: velocity of each lane
+    int32_t sg[64];             // segment: left guard cells of each lane, gx | gy << 16
+    int32_t bad;
 };
+
+// Epochs per wave whose lane shifts stay in registers over a work item.
+constexpr int kEpochRegs = 16;
 
 // ceil(v * d / 65536) for d >= 0: the shift v (t_e - t0) in Q8 pixels,
 // rounded so that the floor of the shifted position is exact.
@@ -64,9 +72,8 @@ __device__ inline void write_cand(sas_candidate *cand, int64_t idx, uint32_t v_i
 
 // Wave-aggregated append: one global atomic per wave; returns the slot of
 // this lane (valid when ok).  All lanes of the wave must call.
-__device__ inline int64_t wave_append(bool ok, unsigned long long *counter, bool *any) {
+__device__ inline int64_t wave_append(bool ok, unsigned long long *counter) {
     const uint64_t mask = __ballot(ok);
-    *any = mask != 0;
     if (mask == 0) return 0;
     unsigned long long base = 0;
     if (__lane_id() == 0) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
@@ -76,15 +83,10 @@ __device__ inline int64_t wave_append(bool ok, unsigned long long *counter, bool
     return (int64_t)base + pre;
 }
 
-__device__ inline void emit(bool ok, uint32_t v_idx, int32_t bx, int32_t by, uint32_t cnt,
-                            sas_candidate *cand, int64_t cap, sas_vote_result *res, int count_sat) {
-    bool any;
-    const int64_t idx = wave_append(ok, (unsigned long long *)&res->n_cand, &any);
-    if (ok && idx < cap) write_cand(cand, idx, v_idx, bx, by, cnt, (uint32_t)count_sat);
-}
-
 // Exclusive scan over the T threads of the block; *total gets the sum.
-__device__ inline int32_t scan_block(int32_t v, int32_t *total, Shared &sh) {
+// wsum[NW] must not be read by an earlier call that some thread may still
+// be in (alternate two arrays).
+__device__ inline int32_t scan_block(int32_t v, int32_t *total, int32_t *wsum) {
     const int lane = __lane_id();
     const int wave = threadIdx.x >> 6;
     int32_t incl = v;
@@ -93,24 +95,18 @@ __device__ inline int32_t scan_block(int32_t v, int32_t *total, Shared &sh) {
         const int32_t o = __shfl_up(incl, d, 64);
         if (lane >= d) incl += o;
     }
-    if (lane == 63) sh.wsum[wave] = incl;
+    if (lane == 63) wsum[wave] = incl;
     __syncthreads();
     int32_t off = 0, tot = 0;
 #pragma unroll
-    for (int w = 0; w < T / 64; ++w) {
-        const int32_t s = sh.wsum[w];
+    for (int w = 0; w < NW; ++w) {
+        const int32_t s = wsum[w];
         off += (w < wave) ? s : 0;
         tot += s;
     }
     *total = tot;
     return off + incl - v;
 }
-
-struct Tile {
-    int32_t tx0, ty0;  // first cell-bin
-    int64_t ox, oy;    // origin, Q8
-    int32_t vx_lo, vx_hi, vy_lo, vy_hi;
-};
 
 // Cell rows/columns of the window index that an axis interval [lo, hi) of
 // Q8 positions touches, clamped to the footprint; false when none.
@@ -122,159 +118,12 @@ __device__ inline bool cell_span(int64_t lo, int64_t hi, int32_t f0, int32_t f1,
     return true;
 }
 
-// Per-epoch windows of the tile in the original frame: cell rows and
-// columns, window prefix sh.sp, and the total M (returned, block uniform).
-// Ends with a barrier.
-__device__ int32_t tile_windows(const DenseArgs &a, const Tile &t, Shared &sh) {
-    const PreparedCatalog &c = a.cat;
-    const int tid = threadIdx.x;
-    const int E = c.n_epochs;
-    int32_t cnt_e = 0;
-    if (tid == 0) sh.max_rows = 0;
-    if (tid < E) {
-        const int32_t d = c.dt[tid];
-        sh.dt[tid] = d;
-        int32_t rows = 1, cols = 0;  // empty
-        if (d >= 0) {
-            const int kc = a.log2b + a.coarse_log2;
-            const int64_t wx = (int64_t)a.tile_x << kc, wy = (int64_t)a.tile_y << kc;
-            const int64_t xlo = t.ox + shift_q8(t.vx_lo, d);
-            const int64_t xhi = t.ox + shift_q8(t.vx_hi, d) + wx;  // exclusive
-            const int64_t ylo = t.oy + shift_q8(t.vy_lo, d);
-            const int64_t yhi = t.oy + shift_q8(t.vy_hi, d) + wy;
-            int cx0, cx1, cy0, cy1;
-            if (cell_span(xlo, xhi, c.x0, c.x1, c.cell_log2, &cx0, &cx1) &&
-                cell_span(ylo, yhi, c.y0, c.y1, c.cell_log2, &cy0, &cy1)) {
-                for (int cy = cy0; cy <= cy1; ++cy) {
-                    const int64_t base = ((int64_t)tid * c.ncy + cy) * c.ncx;
-                    cnt_e += c.off[base + cx1 + 1] - c.off[base + cx0];
-                }
-                rows = cy0 | (cy1 << 16);
-                cols = cx0 | (cx1 << 16);
-            }
-        }
-        sh.rows[tid] = rows;
-        sh.cols[tid] = cols;
-    }
-    __syncthreads();
-    if (tid < E) {
-        const int nr = (sh.rows[tid] >> 16) - (sh.rows[tid] & 0xffff) + 1;
-        if (nr > 0) atomicMax(&sh.max_rows, nr);
-    }
-    int32_t M;
-    const int32_t ex = scan_block(cnt_e, &M, sh);
-    if (tid < E) sh.sp[tid] = ex;
-    if (tid == 0) sh.sp[E] = M;
-    __syncthreads();
-    return M;
-}
-
-// Copy window elements [c0, c1) (epoch order) into the stage as
-// tile-relative coordinates.  One thread per (epoch, cell row).
-__device__ void stage_chunk(const DenseArgs &a, const Shared &sh, const Tile &t, int2 *stage,
-                            int32_t c0, int32_t c1) {
-    const PreparedCatalog &c = a.cat;
-    const int E = c.n_epochs;
-    const int R = sh.max_rows;
-    for (int pr = threadIdx.x; pr < E * R; pr += T) {
-        const int e = pr / R, r = pr - (pr / R) * R;
-        const int cy0 = sh.rows[e] & 0xffff, cy1 = sh.rows[e] >> 16;
-        if (cy0 + r > cy1 || sh.sp[e + 1] <= c0 || sh.sp[e] >= c1) continue;
-        const int cx0 = sh.cols[e] & 0xffff, cx1 = sh.cols[e] >> 16;
-        int32_t dst = sh.sp[e];
-        for (int rr = 0; rr < r; ++rr) {
-            const int64_t b2 = ((int64_t)e * c.ncy + cy0 + rr) * c.ncx;
-            dst += c.off[b2 + cx1 + 1] - c.off[b2 + cx0];
-        }
-        const int64_t base = ((int64_t)e * c.ncy + cy0 + r) * c.ncx;
-        const int32_t src = c.off[base + cx0];
-        const int32_t len = c.off[base + cx1 + 1] - src;
-        const int32_t j0 = max(0, c0 - dst), j1 = min(len, c1 - dst);
-#pragma unroll 4
-        for (int32_t j = j0; j < j1; ++j) {
-            const int2 p = c.sxy[src + j];
-            stage[dst + j - c0] = make_int2((int32_t)(p.x - t.ox), (int32_t)(p.y - t.oy));
-        }
-    }
-}
-
-// Value of a lane's trash word: out-of-tile votes go there instead of being
-// masked off, and the value makes sure no such vote ever looks lifted.
-template <int MODE>
-__device__ inline uint32_t trash_value() {
-    return MODE == kMask32 ? 0xffffffffu : 0x7fffffffu;
-}
-
-// Vote every staged detection of the window with every lane velocity.  For
-// each epoch a wave takes, lanes compute the shifts of their velocity once;
-// then batches of kBatch iterations load 2 * kBatch staged detections, bin
-// them, issue all atomics, and only then look at the returned values.
-template <int MODE>
-__device__ void vote_window(const DenseArgs &a, Shared &sh, const Tile &t, int2 *stage,
-                            uint32_t *cells, int32_t *flags, int32_t M, int32_t my_vx,
-                            int32_t my_vy, bool lane_ok) {
-    const int E = a.cat.n_epochs;
-    const int wave = threadIdx.x >> 6, lane = __lane_id();
-    const int half = lane >> 5, l32 = lane & (kLanes - 1);
-    const uint32_t TX = (uint32_t)a.tile_x, TY = (uint32_t)a.tile_y;
-    const int lTX = a.log2_tile_x, kc = a.log2b + a.coarse_log2;
-    const uint32_t trash = (uint32_t)(a.tile_x * a.tile_y * kLanes + lane);
-    const uint32_t nmin = (uint32_t)a.n_min;
-    const int nch = (M + kStageCap - 1) / kStageCap;
-    for (int ch = 0; ch < nch; ++ch) {
-        const int32_t c0 = ch * kStageCap, c1 = min(M, c0 + kStageCap);
-        __syncthreads();  // the previous chunk (or tile) is no longer read
-        stage_chunk(a, sh, t, stage, c0, c1);
-        __syncthreads();
-        for (int e = wave; e < E; e += T / 64) {
-            const int32_t p0 = max(sh.sp[e], c0) - c0, p1 = min(sh.sp[e + 1], c1) - c0;
-            if (p0 >= p1) continue;
-            const int32_t d = sh.dt[e];
-            // an unused lane's shift puts every detection far outside the tile
-            const int32_t sx = lane_ok ? shift_q8(my_vx, d) : 0x40000000;
-            const int32_t sy = shift_q8(my_vy, d);
-            const uint32_t val = MODE == kMask32 ? (1u << e) : 1u;
-            for (int32_t i0 = p0 + half; i0 < p1; i0 += 2 * kBatch) {
-                int2 q[kBatch];
-#pragma unroll
-                for (int b = 0; b < kBatch; ++b) q[b] = stage[i0 + 2 * b];  // padded stage
-                uint32_t cell[kBatch];
-#pragma unroll
-                for (int b = 0; b < kBatch; ++b) {
-                    const int32_t bx = (q[b].x - sx) >> kc, by = (q[b].y - sy) >> kc;
-                    const bool ok = (i0 + 2 * b < p1) & ((uint32_t)bx < TX) & ((uint32_t)by < TY);
-                    const uint32_t c = ((((uint32_t)by << lTX) | (uint32_t)bx) << 5) | (uint32_t)l32;
-                    cell[b] = ok ? c : trash;
-                }
-                uint32_t old[kBatch];
-#pragma unroll
-                for (int b = 0; b < kBatch; ++b)
-                    old[b] = MODE == kMask32 ? atomicOr(&cells[cell[b]], val)
-                                             : atomicAdd(&cells[cell[b]], val);
-                bool any = false;
-#pragma unroll
-                for (int b = 0; b < kBatch; ++b) {
-                    const bool lifted = MODE == kMask32
-                                            ? (!(old[b] & val) && (uint32_t)__popc(old[b] | val) == nmin)
-                                            : old[b] == nmin - 1;
-                    any |= lifted;
-                }
-                if (any) {  // rare: record the lifted cells
-#pragma unroll
-                    for (int b = 0; b < kBatch; ++b) {
-                        const bool lifted =
-                            MODE == kMask32
-                                ? (!(old[b] & val) && (uint32_t)__popc(old[b] | val) == nmin)
-                                : old[b] == nmin - 1;
-                        if (lifted) {
-                            const int f = atomicAdd(&sh.nflag, 1);
-                            if (f < kFlagCap) flags[f] = (int32_t)cell[b];
-                        }
-                    }
-                }
-            }
-        }
-    }
+__device__ inline bool cell_span(int32_t lo, int32_t hi, int32_t f0, int32_t f1, int cl, int *c0,
+                                 int *c1) {
+    if (hi <= f0 || lo >= f1) return false;
+    *c0 = (max(lo, f0) - f0) >> cl;
+    *c1 = (min(hi, f1) - 1 - f0) >> cl;
+    return true;
 }
 
 template <int MODE>
@@ -282,91 +131,331 @@ __device__ inline uint32_t cell_count(uint32_t w) {
     return MODE == kMask32 ? (uint32_t)__popc(w) : w;
 }
 
-template <int MODE>
-__global__ void __launch_bounds__(T) k_vote_dense(DenseArgs a) {
-    extern __shared__ uint32_t smem[];
-    __shared__ Shared sh;
-    const int TX = a.tile_x, TY = a.tile_y;
-    const int ncell = TX * TY * kLanes;
-    uint32_t *cells = smem;
-    int32_t *flags = (int32_t *)(smem + ncell + 64);  // after the 64 trash words
-    int2 *stage = (int2 *)(smem + ncell + 64 + kFlagCap);
-    const int tid = threadIdx.x;
-    const int l32 = __lane_id() & (kLanes - 1);
-    const uint32_t nmin = (uint32_t)a.n_min;
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
-    for (int i = tid; i < ncell / 4; i += T) ((uint4 *)cells)[i] = make_uint4(0, 0, 0, 0);
-    if (tid < 64) cells[ncell + tid] = trash_value<MODE>();
-    for (int i = tid; i < kStagePad; i += T)  // padding past the stage: far outside any tile
-        stage[kStageCap + i] = make_int2(0x40000000, 0x40000000);
+// LDS address of histogram word (iy, ix, lane): iy * row_bytes + (ix << lb) +
+// lane_addr (the lane's word in bin 0), as one shift-add and one 24-bit
+// multiply-add.
+__device__ inline uint32_t hist_addr(uint32_t ix, uint32_t iy, uint32_t row_bytes, uint32_t lb,
+                                     uint32_t lane_addr) {
+    uint32_t t;
+    asm("v_lshl_add_u32 %0, %1, %2, %3" : "=v"(t) : "v"(ix), "s"(lb), "v"(lane_addr));
+    return __umul24(iy, row_bytes) + t;
+}
+
+template <int MODE>
+__device__ inline void lds_vote(uint32_t addr, uint32_t val) {
+    lds_u32 *p = (lds_u32 *)(uintptr_t)addr;
+    if (MODE == kMask32)
+        __hip_atomic_fetch_or(p, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    else
+        __hip_atomic_fetch_add(p, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Votes of n staged detections st[0, n) of one epoch: lane (g, j) takes
+// detections g, g + G, ...; (sx, sy) is the lane's shift plus its histogram
+// origin.  A group past the end votes (nx, ny), which lands in a guard cell
+// of every lane.
+template <int MODE, int G>
+__device__ inline void vote_run(const int2 *st, int32_t n, uint32_t sx, uint32_t sy, int kc,
+                                uint32_t row_bytes, uint32_t lane_addr, uint32_t val, int g,
+                                int32_t nx, int32_t ny) {
+    constexpr int LNV = G == 1 ? 6 : G == 2 ? 5 : 4;
+    constexpr int U = G == 1 ? 4 : 2;
+    int32_t i = 0;
+    for (; i + G * U <= n; i += G * U) {
+        int2 q[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) q[u] = st[i + u * G + g];
+        uint32_t addr[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t ix = ((uint32_t)q[u].x - sx) >> kc;
+            const uint32_t iy = ((uint32_t)q[u].y - sy) >> kc;
+            addr[u] = hist_addr(ix, iy, row_bytes, LNV + 2, lane_addr);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) lds_vote<MODE>(addr[u], val);
+    }
+    for (; i < n; i += G) {
+        int2 q = st[min(i + g, n - 1)];
+        if (G > 1 && i + g >= n) {
+            q.x = nx;
+            q.y = ny;
+        }
+        const uint32_t ix = ((uint32_t)q.x - sx) >> kc;
+        const uint32_t iy = ((uint32_t)q.y - sy) >> kc;
+        lds_vote<MODE>(hist_addr(ix, iy, row_bytes, LNV + 2, lane_addr), val);
+    }
+}
+
+// Dynamic LDS: histogram [HY][HX][NV] words, then the stage (int2), then the
+// run table of the window index (source offset and exclusive prefix of every
+// (epoch, row) pair).
+template <int MODE, int G>
+__global__ void __launch_bounds__(T) k_vote_dense(DenseArgs a) {
+    constexpr int NV = 64 / G;
+    constexpr int LNV = G == 1 ? 6 : G == 2 ? 5 : 4;
+    extern __shared__ uint4 smem4[];
+    __shared__ Shared sh;
+    uint32_t *hist = (uint32_t *)smem4;
+    const int hist_words = a.hx * a.hy * NV;
+    int2 *stage = (int2 *)(hist + hist_words);
+    int32_t *psrc = (int32_t *)(stage + a.stage_cap);
+    int32_t *pdst = psrc + a.max_pairs;
+
+    const PreparedCatalog &c = a.cat;
+    const int E = c.n_epochs;
+    const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
+    const int g = lane >> LNV, j = lane & (NV - 1);
+    const int kc = a.log2b + a.coarse_log2;
+    const int32_t cellw = (int32_t)1 << kc;
+    const int32_t W = a.tile_x << kc, H = a.tile_y << kc;  // tile size, Q8
+    const uint32_t nmin = (uint32_t)a.n_min;
+    const uint32_t row_bytes = (uint32_t)(a.hx * NV * 4);
+    // run table: pairs (epoch, index row r < R), epoch-major; thread tid owns
+    // pairs [p0, p0 + per)
+    const int R = a.rows;
+    const int np = E * R;  // <= max_pairs
+    const int per = (np + T - 1) / T;
+    const int p0 = tid * per;
+
+    for (int i = tid; i < hist_words / 4; i += T) smem4[i] = make_uint4(0, 0, 0, 0);
+    if (tid < E) sh.dt[tid] = c.dt[tid];
+    int parity = 0;
+
     for (int64_t item = blockIdx.x; item < a.n_items; item += gridDim.x) {
         const int32_t sg = a.items[4 * item], ty0 = a.items[4 * item + 1];
         const int32_t txf = a.items[4 * item + 2], ntiles = a.items[4 * item + 3];
-        __syncthreads();  // the previous item no longer reads the segment
-        if (tid < kLanes) {
-            const int64_t o = (int64_t)sg * kLanes + tid;
+        const int32_t vx_lo = a.seg[4 * sg], vx_hi = a.seg[4 * sg + 1];
+        const int32_t vy_lo = a.seg[4 * sg + 2], vy_hi = a.seg[4 * sg + 3];
+        __syncthreads();  // the previous item no longer reads the segment tables
+        if (tid < NV) {
+            const int64_t o = (int64_t)sg * NV + tid;
             sh.sv[tid] = a.seg_v[o];
             sh.svx[tid] = a.seg_vel[2 * o];
             sh.svy[tid] = a.seg_vel[2 * o + 1];
+            sh.sg[tid] = a.seg_guard[o];
         }
-        Tile t;
-        t.ty0 = ty0;
-        t.vx_lo = a.seg[4 * sg];
-        t.vx_hi = a.seg[4 * sg + 1];
-        t.vy_lo = a.seg[4 * sg + 2];
-        t.vy_hi = a.seg[4 * sg + 3];
-        const int kc = a.log2b + a.coarse_log2;
-        t.oy = (int64_t)ty0 * ((int64_t)1 << kc);
+        if (tid < E) {  // shifts of the segment's box edges
+            const int32_t d = sh.dt[tid];
+            sh.es[0][tid] = d >= 0 ? shift_q8(vx_lo, d) : 0;
+            sh.es[1][tid] = d >= 0 ? shift_q8(vx_hi, d) : 0;
+            sh.es[2][tid] = d >= 0 ? shift_q8(vy_lo, d) : 0;
+            sh.es[3][tid] = d >= 0 ? shift_q8(vy_hi, d) : 0;
+        }
+        if (tid == 0) sh.bad = 0;
         __syncthreads();
-        const int32_t my_v = sh.sv[l32];
-        const bool lane_ok = my_v >= 0;
-        const int32_t my_vx = sh.svx[l32], my_vy = sh.svy[l32];
+        const int32_t my_vx = sh.svx[j], my_vy = sh.svy[j];
+        const int32_t my_gx = sh.sg[j] & 0xffff, my_gy = sh.sg[j] >> 16;
+        const int32_t oy = ty0 * cellw;
+        // Q8 origin of this lane's histogram row 0: (ty0 - gy) cells
+        const uint32_t oy_lane = (uint32_t)(ty0 - my_gy) * (uint32_t)cellw;
+        const uint32_t lane_addr = (uint32_t)(uintptr_t)(lds_u32 *)hist + (uint32_t)(j * 4);
+
+        // Lane shifts of this wave's epochs e = wave + k NW (k < kEpochRegs),
+        // kept in registers for the whole item.  The window of any tile then
+        // lands inside every lane's histogram (tile independent; checked here).
+        int32_t Sx[kEpochRegs], Sy[kEpochRegs];
+        bool bad = false;
+#pragma unroll
+        for (int k = 0; k < kEpochRegs; ++k) {
+            const int e = wave + k * NW;
+            Sx[k] = 0;
+            Sy[k] = 0;
+            if (e < E) {
+                const int32_t d = sh.dt[e];
+                if (d >= 0) {
+                    Sx[k] = shift_q8(my_vx, d);
+                    Sy[k] = shift_q8(my_vy, d);
+                    const int64_t gxq = (int64_t)my_gx << kc, gyq = (int64_t)my_gy << kc;
+                    const int64_t lx = (int64_t)sh.es[0][e] - Sx[k] - 1 + gxq;
+                    const int64_t hx = (int64_t)sh.es[1][e] - Sx[k] + W - 1 + gxq;
+                    const int64_t ly = (int64_t)sh.es[2][e] - Sy[k] - 1 + gyq;
+                    const int64_t hy = (int64_t)sh.es[3][e] - Sy[k] + H - 1 + gyq;
+                    bad |= lx < 0 || ly < 0 || hx >= ((int64_t)a.hx << kc) ||
+                           hy >= ((int64_t)a.hy << kc);
+                }
+            }
+        }
+        for (int e = wave + kEpochRegs * NW; e < E; e += NW) {  // epochs past the registers
+            const int32_t d = sh.dt[e];
+            if (d < 0) continue;
+            const int64_t sxe = shift_q8(my_vx, d), sye = shift_q8(my_vy, d);
+            const int64_t gxq = (int64_t)my_gx << kc, gyq = (int64_t)my_gy << kc;
+            bad |= (int64_t)sh.es[0][e] - sxe - 1 + gxq < 0 ||
+                   (int64_t)sh.es[2][e] - sye - 1 + gyq < 0 ||
+                   (int64_t)sh.es[1][e] - sxe + W - 1 + gxq >= ((int64_t)a.hx << kc) ||
+                   (int64_t)sh.es[3][e] - sye + H - 1 + gyq >= ((int64_t)a.hy << kc);
+        }
+        if (bad) sh.bad = 1;
+        __syncthreads();
+        if (sh.bad) {  // excluded by the planner's guard cells; block uniform
+            if (tid == 0) atomicOr(&a.res->status, SAS_DATA_INTERNAL);
+            continue;
+        }
 
         for (int32_t ti = 0; ti < ntiles; ++ti) {
-            t.tx0 = txf + ti * TX;
-            t.ox = (int64_t)t.tx0 * ((int64_t)1 << kc);
-            if (tid == 0) sh.nflag = 0;
-            const int32_t M = tile_windows(a, t, sh);  // ends with a barrier
-            if (M == 0) continue;
-            if (M > kStageCap && tid == 0) atomicAdd(&a.res->n_spilled, 1);
+            const int32_t tx0 = txf + ti * a.tile_x;
+            const int32_t ox = tx0 * cellw;
+            const uint32_t ox_lane = (uint32_t)(tx0 - my_gx) * (uint32_t)cellw;
+            parity ^= 1;
 
-            vote_window<MODE>(a, sh, t, stage, cells, flags, M, my_vx, my_vy, lane_ok);
+            // 1. exact windows and run lengths, one thread per (epoch, index row);
+            //    then a block scan lays the runs out (epoch-major)
+            int32_t lsum = 0;
+            for (int k = 0; k < per; ++k) {
+                const int p = p0 + k;
+                if (p >= np) break;
+                const int e = p / R, r = p - e * R;
+                int32_t src = 0, len = 0;
+                if (sh.dt[e] >= 0) {
+                    const int32_t xlo = ox + sh.es[0][e], xhi = ox + sh.es[1][e] + W;
+                    const int32_t ylo = oy + sh.es[2][e], yhi = oy + sh.es[3][e] + H;
+                    int cx0, cx1, cy0, cy1;
+                    if (cell_span(xlo, xhi, c.x0, c.x1, c.cell_log2, &cx0, &cx1) &&
+                        cell_span(ylo, yhi, c.y0, c.y1, c.cell_log2, &cy0, &cy1)) {
+                        if (r == 0 && cy1 - cy0 + 1 > R)  // excluded by the planner
+                            atomicOr(&a.res->status, SAS_DATA_INTERNAL);
+                        if (cy0 + r <= cy1) {
+                            const int64_t base = ((int64_t)e * c.ncy + cy0 + r) * c.ncx;
+                            src = c.off[base + cx0];
+                            len = c.off[base + cx1 + 1] - src;
+                        }
+                    }
+                }
+                psrc[p] = src;
+                pdst[p] = len;
+                lsum += len;
+            }
+            if (tid < E) sh.ecnt[tid] = 0;
+            int32_t M;
+            int32_t run = scan_block(lsum, &M, sh.wsum[parity]);
+            for (int k = 0; k < per; ++k) {
+                const int p = p0 + k;
+                if (p >= np) break;
+                const int32_t len = pdst[p];
+                pdst[p] = run;
+                run += len;
+            }
+            if (tid == 0) pdst[np] = M;
+            if (M == 0) continue;  // block uniform; nothing to vote, the histogram is clear
+            if (M > a.stage_cap && tid == 0) atomicAdd(&a.res->n_spilled, 1);
+
+            // 2. stage and vote, chunk by chunk
+            for (int32_t c0 = 0; c0 < M; c0 += a.stage_cap) {
+                const int32_t c1 = min(M, c0 + a.stage_cap);
+                if (c0 > 0) {  // the previous chunk is voted: reset its counters
+                    __syncthreads();
+                    if (tid < E) sh.ecnt[tid] = 0;
+                }
+                __syncthreads();  // run table and counters ready
+                // each thread copies the part of its own runs inside [c0, c1),
+                // keeping the detections inside the exact window
+                for (int k = 0; k < per; ++k) {
+                    const int p = p0 + k;
+                    if (p >= np) break;
+                    const int32_t dst = pdst[p], len = pdst[p + 1] - dst;
+                    const int32_t j0 = max(0, c0 - dst), j1 = min(len, c1 - dst);
+                    if (j0 >= j1) continue;
+                    const int e = p / R;
+                    const int32_t src = psrc[p];
+                    const int32_t x0 = ox + sh.es[0][e], x1 = ox + sh.es[1][e] + W;
+                    const int32_t y0 = oy + sh.es[2][e], y1 = oy + sh.es[3][e] + H;
+                    const int32_t b = max(pdst[e * R], c0) - c0;
+                    for (int32_t jj = j0; jj < j1; jj += 8) {
+                        int2 q[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u)
+                            if (jj + u < j1) q[u] = c.sxy[src + jj + u];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            if (jj + u < j1 && q[u].x >= x0 && q[u].x < x1 && q[u].y >= y0 &&
+                                q[u].y < y1) {
+                                const int32_t slot = atomicAdd(&sh.ecnt[e], 1);
+                                stage[b + slot] = q[u];
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+
+                // vote: wave w takes epochs w, w + NW, ...; their counts and
+                // stage offsets are read once, one per lane
+                int32_t my_n = 0, my_b = 0;
+                {
+                    const int e = wave + lane * NW;
+                    if (e < E) {
+                        my_n = sh.ecnt[e];
+                        my_b = max(pdst[e * R], c0) - c0;
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < kEpochRegs; ++k) {
+                    const int e = wave + k * NW;
+                    if (e >= E) break;
+                    const int32_t n = __builtin_amdgcn_readlane(my_n, k);
+                    if (n == 0) continue;
+                    const int32_t b = __builtin_amdgcn_readlane(my_b, k);
+                    vote_run<MODE, G>(stage + b, n, (uint32_t)Sx[k] + ox_lane,
+                                      (uint32_t)Sy[k] + oy_lane, kc, row_bytes, lane_addr,
+                                      MODE == kMask32 ? (1u << e) : 1u, g,
+                                      ox + sh.es[0][e] - 1, oy + sh.es[2][e] - 1);
+                }
+                for (int k = kEpochRegs; wave + k * NW < E; ++k) {
+                    const int e = wave + k * NW;
+                    const int32_t n = __builtin_amdgcn_readlane(my_n, k);
+                    if (n == 0) continue;
+                    const int32_t b = __builtin_amdgcn_readlane(my_b, k);
+                    const int32_t d = sh.dt[e];
+                    vote_run<MODE, G>(stage + b, n, (uint32_t)shift_q8(my_vx, d) + ox_lane,
+                                      (uint32_t)shift_q8(my_vy, d) + oy_lane, kc, row_bytes,
+                                      lane_addr, MODE == kMask32 ? (1u << e) : 1u, g,
+                                      ox + sh.es[0][e] - 1, oy + sh.es[2][e] - 1);
+                }
+            }
             __syncthreads();
 
-            // emit (or queue) the lifted cells; with an overflowed list, scan
-            const int nflag = sh.nflag;
-            if (nflag > 0) {
-                const bool scan = nflag > kFlagCap;
-                const int n = scan ? ncell : nflag;
-                for (int f0 = 0; f0 < n; f0 += T) {
-                    const int f = f0 + tid;
-                    int cell = 0;
+            // 3. read and clear the histogram; emit or queue interior cells
+            for (int w0 = 0; w0 < hist_words / 4; w0 += T) {
+                const int w4 = w0 + tid;
+                uint4 h = make_uint4(0, 0, 0, 0);
+                if (w4 < hist_words / 4) {
+                    h = smem4[w4];
+                    smem4[w4] = make_uint4(0, 0, 0, 0);
+                }
+                const uint32_t m = max(max(cell_count<MODE>(h.x), cell_count<MODE>(h.y)),
+                                       max(cell_count<MODE>(h.z), cell_count<MODE>(h.w)));
+                if (!__any(m >= nmin)) continue;  // wave uniform
+                const uint32_t hw[4] = {h.x, h.y, h.z, h.w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int wi = 4 * w4 + k;
+                    const uint32_t cnt = cell_count<MODE>(hw[k]);
                     bool ok = false;
-                    uint32_t cnt = 0;
-                    if (f < n) {
-                        cell = scan ? f : flags[f];
-                        cnt = cell_count<MODE>(cells[cell]);
-                        ok = cnt >= nmin;
+                    uint32_t v = 0;
+                    int32_t bx = 0, by = 0;
+                    if (cnt >= nmin) {
+                        const int jj = wi & (NV - 1), bin = wi >> LNV;
+                        const int iy = bin / a.hx, ix = bin - iy * a.hx;
+                        const int cx = ix - (sh.sg[jj] & 0xffff), cy = iy - (sh.sg[jj] >> 16);
+                        ok = sh.sv[jj] >= 0 && cx >= 0 && cx < a.tile_x && cy >= 0 &&
+                             cy < a.tile_y;
+                        v = (uint32_t)sh.sv[jj];
+                        bx = tx0 + cx;
+                        by = ty0 + cy;
                     }
-                    const int bin = cell >> 5;
-                    const uint32_t v = (uint32_t)sh.sv[cell & (kLanes - 1)];
-                    const int32_t bx = t.tx0 + bin % TX, by = t.ty0 + bin / TX;
                     if (MODE == kCountRef) {
-                        bool any;
-                        const int64_t idx = wave_append(ok, (unsigned long long *)a.refine_count,
-                                                        &any);
-                        if (ok && idx < a.refine_cap)
-                            a.refine[idx] = make_int4((int32_t)v, bx, by, 0);
+                        const int64_t idx = wave_append(ok, a.refine_count);
+                        if (ok && idx < a.refine_cap) a.refine[idx] = make_int4((int32_t)v, bx, by, 0);
                     } else {
-                        emit(ok, v, bx, by, cnt, a.cand, a.cand_cap, a.res, a.count_sat);
+                        const int64_t idx = wave_append(ok, (unsigned long long *)&a.res->n_cand);
+                        if (ok && idx < a.cand_cap)
+                            write_cand(a.cand, idx, v, bx, by, cnt, (uint32_t)a.count_sat);
                     }
                 }
             }
-
-            // clear the histogram (and reset the trash words) for the next tile
-            __syncthreads();
-            for (int i = tid; i < ncell / 4; i += T) ((uint4 *)cells)[i] = make_uint4(0, 0, 0, 0);
-            if (tid < 64) cells[ncell + tid] = trash_value<MODE>();
+            // the next write to the histogram comes after several barriers
         }
     }
 }
@@ -378,7 +467,7 @@ __global__ void __launch_bounds__(T) k_vote_dense(DenseArgs a) {
 constexpr int kRefineBins = 64;  // up to 8 x 8 bins per cell
 
 __global__ void __launch_bounds__(T) k_refine(DenseArgs a) {
-    __shared__ uint32_t masks[T / 64][kRefineBins * kSlotWords];
+    __shared__ uint32_t masks[NW][kRefineBins * kSlotWords];
     const int wave = threadIdx.x >> 6, lane = __lane_id();
     uint32_t *mk = masks[wave];
     const PreparedCatalog &c = a.cat;
@@ -389,8 +478,7 @@ __global__ void __launch_bounds__(T) k_refine(DenseArgs a) {
     if (blockIdx.x == 0 && threadIdx.x == 0 && n_all > a.refine_cap)
         atomicOr(&a.res->status, SAS_DATA_REFINE_FULL);
     const int64_t n_q = min(n_all, a.refine_cap);
-    for (int64_t qi = (int64_t)blockIdx.x * (T / 64) + wave; qi < n_q;
-         qi += (int64_t)gridDim.x * (T / 64)) {
+    for (int64_t qi = (int64_t)blockIdx.x * NW + wave; qi < n_q; qi += (int64_t)gridDim.x * NW) {
         const int4 q = a.refine[qi];
         const int32_t v = q.x;
         const int32_t vx = a.vel[2 * (int64_t)v], vy = a.vel[2 * (int64_t)v + 1];
@@ -410,8 +498,8 @@ __global__ void __launch_bounds__(T) k_refine(DenseArgs a) {
             for (int cy = cy0; cy <= cy1; ++cy) {
                 const int64_t base = ((int64_t)e * c.ncy + cy) * c.ncx;
                 const int32_t j1 = c.off[base + cx1 + 1];
-                for (int32_t j = c.off[base + cx0]; j < j1; ++j) {
-                    const int2 p = c.sxy[j];
+                for (int32_t jj = c.off[base + cx0]; jj < j1; ++jj) {
+                    const int2 p = c.sxy[jj];
                     const int32_t bx = ((p.x - sx) >> k) - fbx0, by = ((p.y - sy) >> k) - fby0;
                     if ((uint32_t)bx < (uint32_t)cw && (uint32_t)by < (uint32_t)cw) {
                         const int bin = by * cw + bx;
@@ -433,49 +521,69 @@ __global__ void __launch_bounds__(T) k_refine(DenseArgs a) {
                 cnt = mk[lane * kSlotWords];
             }
         }
-        emit(lane < nb && cnt >= (uint32_t)a.n_min, (uint32_t)v, fbx0 + (lane % cw),
-             fby0 + (lane / cw), cnt, a.cand, a.cand_cap, a.res, a.count_sat);
+        const bool ok = lane < nb && cnt >= (uint32_t)a.n_min;
+        const int64_t idx = wave_append(ok, (unsigned long long *)&a.res->n_cand);
+        if (ok && idx < a.cand_cap)
+            write_cand(a.cand, idx, (uint32_t)v, fbx0 + (lane % cw), fby0 + (lane / cw), cnt,
+                       (uint32_t)a.count_sat);
         __builtin_amdgcn_wave_barrier();
     }
 }
 
-template <int MODE>
-hipError_t launch_mode(const DenseArgs &a, size_t lds, hipStream_t stream) {
+template <int MODE, int G>
+hipError_t launch_mg(const DenseArgs &a, size_t lds, hipStream_t stream, hipEvent_t ev0,
+                     hipEvent_t ev1) {
+    static size_t lds_set = 0;  // dynamic LDS limit raised so far for this kernel
+    if (lds > 65536 && lds > lds_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_vote_dense<MODE, G>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        lds_set = lds;
+    }
     const dim3 grid((unsigned)(a.n_items < kMaxVoteGrid ? a.n_items : kMaxVoteGrid)), block(T);
-    hipLaunchKernelGGL(k_vote_dense<MODE>, grid, block, lds, stream, a);
+    if (ev0) {
+        hipError_t e = hipEventRecord(ev0, stream);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_vote_dense<MODE, G>), grid, block, lds, stream, a);
+    if (ev1) {
+        hipError_t e = hipEventRecord(ev1, stream);
+        if (e != hipSuccess) return e;
+    }
     if (MODE == kCountRef)
         hipLaunchKernelGGL(k_refine, dim3(kRefineGrid), block, 0, stream, a);
     return hipGetLastError();
 }
 
-}  // namespace
-
-size_t dense_lds_bytes(int mode, int tile_x, int tile_y) {
-    (void)mode;
-    size_t b = (size_t)tile_x * tile_y * kLanes * sizeof(uint32_t);  // histogram
-    b += 64 * sizeof(uint32_t);                                      // trash words
-    b += (size_t)kFlagCap * sizeof(int32_t);                         // lifted cells
-    b += (size_t)(kStageCap + kStagePad) * sizeof(int2);             // staged window
-    return b;
+template <int MODE>
+hipError_t launch_m(int groups, const DenseArgs &a, size_t lds, hipStream_t s, hipEvent_t e0,
+                    hipEvent_t e1) {
+    switch (groups) {
+    case 1: return launch_mg<MODE, 1>(a, lds, s, e0, e1);
+    case 2: return launch_mg<MODE, 2>(a, lds, s, e0, e1);
+    default: return launch_mg<MODE, 4>(a, lds, s, e0, e1);
+    }
 }
 
-hipError_t launch_vote_dense(int mode, const DenseArgs &a, hipStream_t stream) {
+}  // namespace
+
+size_t dense_lds_bytes(int groups, int hx, int hy, int stage_cap, int max_pairs) {
+    size_t b = (size_t)hx * hy * (64 / groups) * sizeof(uint32_t);  // histogram
+    b += (size_t)stage_cap * sizeof(int2);                            // stage
+    b += (size_t)(2 * max_pairs + 1) * sizeof(int32_t);               // run table
+    return (b + 15) & ~(size_t)15;
+}
+
+size_t dense_static_lds_bytes() { return sizeof(Shared); }
+
+hipError_t launch_vote_dense(int mode, int groups, const DenseArgs &a, hipStream_t stream,
+                             hipEvent_t ev0, hipEvent_t ev1) {
     if (a.n_items <= 0) return hipSuccess;
-    const size_t lds = dense_lds_bytes(mode, a.tile_x, a.tile_y);
-    static bool attr_set[3] = {false, false, false};
-    if (lds > 65536 && !attr_set[mode]) {
-        const void *fn = mode == kMask32 ? (const void *)k_vote_dense<kMask32>
-                         : mode == kCountDet ? (const void *)k_vote_dense<kCountDet>
-                                             : (const void *)k_vote_dense<kCountRef>;
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds);
-        if (e != hipSuccess) return e;
-        attr_set[mode] = true;
-    }
+    const size_t lds = dense_lds_bytes(groups, a.hx, a.hy, a.stage_cap, a.max_pairs);
     switch (mode) {
-    case kMask32: return launch_mode<kMask32>(a, lds, stream);
-    case kCountDet: return launch_mode<kCountDet>(a, lds, stream);
-    default: return launch_mode<kCountRef>(a, lds, stream);
+    case kMask32: return launch_m<kMask32>(groups, a, lds, stream, ev0, ev1);
+    case kCountDet: return launch_m<kCountDet>(groups, a, lds, stream, ev0, ev1);
+    default: return launch_m<kCountRef>(groups, a, lds, stream, ev0, ev1);
     }
 }
 

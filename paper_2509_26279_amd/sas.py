@@ -48,6 +48,7 @@ class GridSpec(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
                 ("vblock_x", ctypes.c_int32), ("vblock_y", ctypes.c_int32),
+                ("groups", ctypes.c_int32), ("stage_cap", ctypes.c_int32),
                 ("cell_log2", ctypes.c_int32), ("sort_vblock", ctypes.c_int32),
                 ("n_det_hint", ctypes.c_int32), ("coarse_log2", ctypes.c_int32),
                 ("refine_cap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
@@ -68,14 +69,17 @@ class PlanInfo(ctypes.Structure):
                 ("path", ctypes.c_int32), ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
                 ("vblock_x", ctypes.c_int32), ("vblock_y", ctypes.c_int32),
                 ("cell_log2", ctypes.c_int32), ("coarse_log2", ctypes.c_int32),
-                ("mode_variant", ctypes.c_int32), ("n_v", ctypes.c_int64)]
+                ("mode_variant", ctypes.c_int32), ("n_v", ctypes.c_int64),
+                ("groups", ctypes.c_int32), ("hist_x", ctypes.c_int32),
+                ("hist_y", ctypes.c_int32), ("stage_cap", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
 
 EXPORTS = ["sas_status_string", "sas_last_error", "sas_version", "sas_grid_spacing",
            "sas_build_grid", "sas_plan_create", "sas_plan_destroy", "sas_plan_get_info",
-           "sas_vote_workspace_size", "sas_vote", "sas_peaks"]
+           "sas_plan_set_probe", "sas_vote_workspace_size", "sas_vote", "sas_peaks"]
 
 
 def load():
@@ -97,6 +101,7 @@ def load():
         "sas_plan_create": (I32, [P, P]),
         "sas_plan_destroy": (I32, [P]),
         "sas_plan_get_info": (I32, [P, P]),
+        "sas_plan_set_probe": (I32, [P, P, P]),
         "sas_vote_workspace_size": (I32, [P, I64, P]),
         "sas_vote": (I32, [P, P, P, P, I64, P, I64, P, P, SZ, P]),
         "sas_peaks": (I32, [P, P, I64, I32, I64, P, I64, P, P]),
@@ -166,9 +171,9 @@ class Plan:
         self._tuning = None
         if tuning is not None:
             self._tuning = Tuning(*[int(tuning.get(k, 0)) for k in
-                                    ("tile_x", "tile_y", "vblock_x", "vblock_y", "cell_log2",
-                                     "sort_vblock", "n_det_hint", "coarse_log2",
-                                     "refine_cap")])
+                                    ("tile_x", "tile_y", "vblock_x", "vblock_y", "groups",
+                                     "stage_cap", "cell_log2", "sort_vblock", "n_det_hint",
+                                     "coarse_log2", "refine_cap")])
         desc = PlanDesc(self._v.ctypes.data, self._v.shape[0], self._t.shape[0],
                         self._t.ctypes.data, int(binw_q8), int(n_min), MODES[mode],
                         int(count_sat), PATHS[path], (ctypes.c_int32 * 4)(*map(int, extent_q8)),
@@ -186,6 +191,13 @@ class Plan:
         inf = PlanInfo()
         _check(load().sas_plan_get_info(self._p, ctypes.byref(inf)))
         return {k: getattr(inf, k) for k, _ in PlanInfo._fields_}
+
+    def set_probe(self, ev_before=None, ev_after=None):
+        """Record two torch.cuda.Event objects around the vote kernel of later
+        votes with this plan (None, None: off)."""
+        h0 = ctypes.c_void_p(ev_before.cuda_event) if ev_before is not None else None
+        h1 = ctypes.c_void_p(ev_after.cuda_event) if ev_after is not None else None
+        _check(load().sas_plan_set_probe(self._p, h0, h1))
 
     def workspace_size(self, n: int) -> int:
         out = ctypes.c_size_t()

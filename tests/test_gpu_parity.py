@@ -81,11 +81,13 @@ def test_random_adversarial(gpu, seed, mode):
         _say(f"adversarial seed={seed} mode={mode} n_min={n_min}")
         o = oracle.vote(d["x_q8"], d["y_q8"], d["epoch"], d["t_q16"], d["v_q8"], d["binw_q8"],
                         n_min, mode)
-        for tun in (None, dict(tile_x=4, tile_y=4, vblock_x=1, vblock_y=1),
-                    dict(tile_x=8, tile_y=16, vblock_x=3, vblock_y=2, cell_log2=9),
-                    dict(tile_x=2, tile_y=2, vblock_x=32, vblock_y=1, cell_log2=8),
-                    dict(coarse_log2=2), dict(coarse_log2=3, tile_x=4, tile_y=4),
-                    dict(coarse_log2=1, vblock_x=2, vblock_y=16)):
+        for tun in (None, dict(tile_x=4, tile_y=4, vblock_x=1, vblock_y=1, groups=4),
+                    dict(tile_x=8, tile_y=16, vblock_x=3, vblock_y=2, cell_log2=9, groups=2),
+                    dict(tile_x=2, tile_y=2, vblock_x=32, vblock_y=2, cell_log2=8, groups=1),
+                    dict(coarse_log2=2, groups=1), dict(coarse_log2=3, tile_x=4, tile_y=4, groups=4),
+                    dict(coarse_log2=1, vblock_x=2, vblock_y=16, groups=2),
+                    dict(tile_x=5, tile_y=3, stage_cap=40, groups=4),
+                    dict(tile_x=7, tile_y=9, stage_cap=16, groups=1, vblock_x=5, vblock_y=7)):
             g = gpu_vote(d["x_q8"], d["y_q8"], d["epoch"], d["t_q16"], d["v_q8"], d["binw_q8"],
                          n_min, mode, tuning=tun)
             assert_same(g, o)
@@ -105,7 +107,7 @@ def test_overfull_window_is_chunked(gpu, n_epochs, mode):
     for n_min in (1, 15, 60):
         _say(f"chunked E={n_epochs} mode={mode} n_min={n_min}")
         o = oracle.vote(x, y, e, t, v, 1024, n_min, mode)
-        plan = sas.Plan(v, t, 1024, n_min, ext, mode=mode)
+        plan = sas.Plan(v, t, 1024, n_min, ext, mode=mode, tuning=dict(stage_cap=1024))
         srch = sas.Search(plan, len(x), cand_cap=1 << 18)
         g = srch.run(x, y, e)
         assert srch.result()["n_spilled"] > 0  # the chunked path did run
@@ -166,8 +168,10 @@ def test_fast_full_grid_every_tuning(gpu):
     wl = synth.make_fast()
     v = _grid(wl)
     lists = []
-    for tun in (dict(), dict(tile_x=16, tile_y=16), dict(tile_x=64, tile_y=8, vblock_x=16, vblock_y=2),
-                dict(tile_x=32, tile_y=4, vblock_x=7, vblock_y=3, cell_log2=14),
+    for tun in (dict(), dict(tile_x=16, tile_y=16, groups=4),
+                dict(tile_x=24, tile_y=8, vblock_x=8, vblock_y=2, groups=4),
+                dict(tile_x=12, tile_y=6, vblock_x=7, vblock_y=3, cell_log2=14, groups=2),
+                dict(tile_x=8, tile_y=8, groups=1, stage_cap=512),
                 dict(coarse_log2=-1)):
         tun["n_det_hint"] = wl.n
         _say(f"fast full grid {tun}")
