@@ -25,9 +25,20 @@ if ROOT not in sys.path:
 # MI355X published / derived peaks
 HBM_PEAK_GBS = 8000.0
 N_CU, CLOCK_GHZ = 256, 2.4
-LDS_BANKS, LDS_BANK_BYTES = 32, 4
-# one 4-byte LDS access per bank per clock on every CU
-LDS_PEAK_GBS = N_CU * LDS_BANKS * LDS_BANK_BYTES * CLOCK_GHZ
+SIMD_PER_CU, LANES_PER_SIMD = 4, 16
+# 32-bit integer vector ops: one per lane per clock on 4 x 16-lane SIMDs per
+# CU (the published 157.3 TFLOP/s fp32 vector peak counts an FMA as 2 and
+# packed fp32 as 2 more)
+INT_PEAK_TOPS = N_CU * SIMD_PER_CU * LANES_PER_SIMD * CLOCK_GHZ / 1000.0
+# LDS: one 4-byte access per bank per clock, 32 banks per CU
+LDS_BANKS = 32
+LDS_ATOMIC_PEAK = N_CU * LDS_BANKS * CLOCK_GHZ * 1e9  # lane atomics per second
+# Integer operations of one vote on the dense path: x - S_x, y - S_y, the two
+# floor divisions by the cell width (shifts), and the histogram word index
+# (bin row * row pitch + bin column * lanes + lane: one multiply-add and one
+# shift-add).  The count increment itself is the LDS atomic.
+OPS_PER_VOTE = 6
+VOTE_KERNEL = "k_vote_dense"
 
 
 def _workload(name):
@@ -39,6 +50,27 @@ def _workload(name):
     if name == "tiny":
         return synth.make_tiny()
     raise SystemExit("unknown workload " + name)
+
+
+def _kernel_source_hash():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2509_26279_amd", "csrc", "vote_dense.hip")
+    with open(src, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _traffic(workload):
+    """HBM bytes per vote-kernel launch from the committed PMC summary, or
+    None when there is none or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (VOTE_KERNEL, workload))
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != _kernel_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(wl, v, seconds):
@@ -101,24 +133,28 @@ def main():
         out = s.peaks()
     torch.cuda.synchronize()
 
+    # events around the whole step (vote + peaks) and, through the plan's
+    # probe, around the vote kernel alone on the stream it is launched on
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
+    for a, b in evs:  # create the underlying HIP events
+        a.record(stream)
+        b.record(stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        evs[k][0].record(stream)
+        plan.set_probe(evs[k][0], evs[k][1])
         s.vote(x, y, e)
-        evs[k][1].record(stream)
         out = s.peaks()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    vote_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    plan.set_probe(None, None)
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
     ms_step = wall * 1000.0 / args.steps
     votes = float(wl.n) * len(v)
     n_cand = len(out)
 
-    lds_bytes = 4.0 * votes  # one 4-byte LDS atomic per vote
-    achieved = lds_bytes / (vote_ms * 1e-3) / 1e9
+    achieved = OPS_PER_VOTE * votes / (kernel_ms * 1e-3) / 1e12
     rec = {
         "metric": "detection-velocity votes/s per chip",
         "value": votes / (ms_step * 1e-3),
@@ -140,12 +176,14 @@ def main():
                    "n_epochs": wl.n_epochs, "parallelism": "single-gpu"},
         "candidates_per_s": n_cand / (ms_step * 1e-3),
         "n_candidates": n_cand,
-        "vote_ms": vote_ms,
-        "vote_votes_per_s": votes / (vote_ms * 1e-3),
+        "vote_kernel_ms": kernel_ms,
+        "vote_kernel_votes_per_s": votes / (kernel_ms * 1e-3),
         "plan": info,
-        "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / LDS_PEAK_GBS, "traffic": None,
-                     "kernel": "sas_vote (preparation + dense LDS vote)"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": INT_PEAK_TOPS,
+                     "unit": "Tops/s", "frac": achieved / INT_PEAK_TOPS,
+                     "traffic": _traffic(wl.name), "kernel": VOTE_KERNEL,
+                     "ops_per_vote": OPS_PER_VOTE,
+                     "lds_atomic_frac": votes / (kernel_ms * 1e-3) / LDS_ATOMIC_PEAK},
     }
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(wl, v, args.cpu_seconds)

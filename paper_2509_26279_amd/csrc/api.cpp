@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "internal.h"
@@ -325,6 +326,7 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     };
     auto ceil_cells = [&](int64_t q8) -> int64_t { return (q8 + cellw - 1) >> kc; };
     std::vector<int32_t> seg, seg_v, seg_vel, seg_guard;
+    std::vector<int64_t> seg_ky;  // velocity-block row of each segment
     int64_t guard_x = 0, guard_y = 0, spread_y_max = 0;
     double spread_x_sum = 0, spread_y_sum = 0;
     {
@@ -342,6 +344,7 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
                 vy_hi = std::max(vy_hi, V[2 * order[q] + 1]);
             }
             seg.insert(seg.end(), {vx_lo, vx_hi, vy_lo, vy_hi});
+            seg_ky.push_back(ky[order[i]]);
             spread_x_sum += (double)spread_q8((int64_t)vx_hi - vx_lo);
             spread_y_sum += (double)spread_q8((int64_t)vy_hi - vy_lo);
             spread_y_max = std::max(spread_y_max, spread_q8((int64_t)vy_hi - vy_lo));
@@ -539,6 +542,25 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
                                        (int32_t)(t1x - t0x + 1)});
             n_tiles += t1x - t0x + 1;
         }
+    }
+    {   // Work order: segments of one velocity-block row share their y shifts,
+        // so (block row, band of tile rows, segment, tile row) keeps the
+        // windows of neighbouring items in one band of the catalog; the
+        // kernel gives each XCD a contiguous range of this order, so the
+        // workgroups resident on one XCD read from one L2-sized band.
+        const int64_t n_it = (int64_t)items.size() / 4;
+        const int64_t band = 4 * (int64_t)TY;
+        std::vector<int64_t> idx(n_it);
+        for (int64_t q = 0; q < n_it; ++q) idx[q] = q;
+        auto key = [&](int64_t q) {
+            const int64_t sgq = items[4 * q], tyq = items[4 * q + 1];
+            return std::make_tuple(seg_ky[sgq], floor_div(tyq, band), sgq, (int64_t)tyq);
+        };
+        std::stable_sort(idx.begin(), idx.end(), [&](int64_t u, int64_t w) { return key(u) < key(w); });
+        std::vector<int32_t> sorted(items.size());
+        for (int64_t q = 0; q < n_it; ++q)
+            for (int k = 0; k < 4; ++k) sorted[4 * q + k] = items[4 * idx[q] + k];
+        items.swap(sorted);
     }
     p->n_segments = n_seg;
     p->n_items = (int64_t)items.size() / 4;

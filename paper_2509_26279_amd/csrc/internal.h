@@ -13,6 +13,7 @@ constexpr int kVoteThreads = 512;          // threads per vote workgroup (8 wave
 constexpr int kSlotWords = kMaxEpochs / 32;
 constexpr int64_t kMaxVoteGrid = 1 << 16;  // workgroups of one vote launch (grid-stride)
 constexpr int kLdsPerCU = 160 * 1024;      // gfx950
+constexpr int kXcds = 8;                   // MI355X: accelerator dies, one L2 each
 
 constexpr int kRefineGrid = 2048;          // workgroups of the refinement launch
 

@@ -224,7 +224,12 @@ __global__ void __launch_bounds__(T) k_vote_dense(DenseArgs a) {
     if (tid < E) sh.dt[tid] = c.dt[tid];
     int parity = 0;
 
-    for (int64_t item = blockIdx.x; item < a.n_items; item += gridDim.x) {
+    // Workgroups are dispatched round-robin over the XCDs (each with its own
+    // L2); give XCD x the logical indices [x G / 8, (x + 1) G / 8) so that the
+    // workgroups resident on one XCD take neighbouring items.
+    const int64_t grid = gridDim.x;  // a multiple of kXcds
+    const int64_t logical = (int64_t)(blockIdx.x % kXcds) * (grid / kXcds) + blockIdx.x / kXcds;
+    for (int64_t item = logical; item < a.n_items; item += grid) {
         const int32_t sg = a.items[4 * item], ty0 = a.items[4 * item + 1];
         const int32_t txf = a.items[4 * item + 2], ntiles = a.items[4 * item + 3];
         const int32_t vx_lo = a.seg[4 * sg], vx_hi = a.seg[4 * sg + 1];
@@ -540,7 +545,8 @@ hipError_t launch_mg(const DenseArgs &a, size_t lds, hipStream_t stream, hipEven
         if (e != hipSuccess) return e;
         lds_set = lds;
     }
-    const dim3 grid((unsigned)(a.n_items < kMaxVoteGrid ? a.n_items : kMaxVoteGrid)), block(T);
+    const int64_t want = a.n_items < kMaxVoteGrid ? a.n_items : kMaxVoteGrid;
+    const dim3 grid((unsigned)((want + kXcds - 1) / kXcds * kXcds)), block(T);
     if (ev0) {
         hipError_t e = hipEventRecord(ev0, stream);
         if (e != hipSuccess) return e;
