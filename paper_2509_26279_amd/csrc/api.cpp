@@ -117,6 +117,11 @@ struct sas_plan {
     size_t lds_bytes = 0;
     int32_t *d_vel = nullptr, *d_seg = nullptr, *d_seg_v = nullptr, *d_seg_vel = nullptr;
     int32_t *d_seg_guard = nullptr, *d_items = nullptr;
+    // sort path
+    std::vector<SortBlock> sort_blocks;
+    int64_t sort_max_nv = 0;
+    int32_t sort_vblock = 0;
+    int32_t *d_sort_vel = nullptr, *d_sort_vidx = nullptr;
     hipEvent_t probe[2] = {nullptr, nullptr};
     int64_t *d_t = nullptr;
     std::vector<void *> allocs;
@@ -140,7 +145,9 @@ sas_status upload(sas_plan *p, T **dst, const std::vector<T> &src) {
 }
 
 struct WsLayout {
-    size_t count, blocksum, cellid, rank, sxy, present, dt, refine_count, refine, total;
+    size_t count, blocksum, cellid, rank, sxy, present, dt, refine_count, refine;
+    size_t keys, keys_alt, hist, hist_blocksum;  // sort path
+    size_t total;
 };
 
 WsLayout ws_layout(const sas_plan *p, int64_t n) {
@@ -157,7 +164,16 @@ WsLayout ws_layout(const sas_plan *p, int64_t n) {
     L.present = o; o = align_up(o + sizeof(int32_t) * kMaxEpochs);
     L.dt = o; o = align_up(o + sizeof(int32_t) * kMaxEpochs);
     L.refine_count = o; o = align_up(o + sizeof(unsigned long long));
-    L.refine = o; o = align_up(o + sizeof(int4) * (p->dense_mode == kCountRef ? p->refine_cap : 1));
+    L.refine = o;
+    o = align_up(o + sizeof(int4) * (p->path == SAS_PATH_DENSE && p->dense_mode == kCountRef
+                                         ? p->refine_cap : 1));
+    const int64_t keys = p->path == SAS_PATH_SORT ? p->sort_max_nv * std::max<int64_t>(n, 1) : 1;
+    const int64_t tiles = (keys + kSortKeysPerTile - 1) / kSortKeysPerTile;
+    const int64_t hist = 256 * tiles;
+    L.keys = o; o = align_up(o + sizeof(uint64_t) * keys);
+    L.keys_alt = o; o = align_up(o + sizeof(uint64_t) * keys);
+    L.hist = o; o = align_up(o + sizeof(int32_t) * hist);
+    L.hist_blocksum = o; o = align_up(o + sizeof(int32_t) * ((hist + kScanTile - 1) / kScanTile));
     L.total = o;
     return L;
 }
@@ -473,8 +489,6 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     p->mode = d->mode;
     p->count_sat = d->count_sat;
     p->path = d->path == SAS_PATH_AUTO ? SAS_PATH_DENSE : d->path;
-    if (p->path == SAS_PATH_SORT)
-        return fail(SAS_E_UNSUPPORTED, "sas_plan_create: the sort path is not built in this library");
     std::memcpy(p->ext, ex, sizeof(p->ext));
     p->n_v = n_v;
     p->coarse_log2 = m;
@@ -510,7 +524,7 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     const __int128 lim_bins = (__int128)1 << 29;
     std::vector<int32_t> items;
     int64_t n_tiles = 0;
-    for (int64_t sg = 0; sg < n_seg; ++sg) {
+    for (int64_t sg = 0; sg < n_seg && p->path == SAS_PATH_DENSE; ++sg) {
         const int32_t vx_lo = seg[4 * sg], vx_hi = seg[4 * sg + 1];
         const int32_t vy_lo = seg[4 * sg + 2], vy_hi = seg[4 * sg + 3];
         std::vector<std::pair<__int128, __int128>> pts;
@@ -568,6 +582,74 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     if (p->n_items >= ((int64_t)1 << 31))
         return fail(SAS_E_UNSUPPORTED, "sas_plan_create: too many work items");
 
+    // Sort path: blocks of consecutive segments, up to sort_vblock velocities,
+    // each with the bin extent every (velocity, detection) of it can reach.
+    std::vector<int32_t> sort_vel, sort_vidx;
+    if (p->path == SAS_PATH_SORT) {
+        int64_t vb = tu.sort_vblock;
+        if (vb <= 0)
+            vb = tu.n_det_hint > 0 ? std::max<int64_t>(1, std::min<int64_t>(1024,
+                                         ((int64_t)1 << 25) / tu.n_det_hint))
+                                   : 64;
+        const int lb = log2b;
+        auto bin_range = [&](int32_t v, int32_t lo, int32_t hi, int64_t *b0, int64_t *b1) {
+            // x - S(v, d) for x in [lo, hi), d in [0, D]: S is monotone in d
+            const int64_t sD = (int64_t)(((__int128)v * D + 65535) >> 16);
+            const int64_t smin = std::min<int64_t>(0, sD), smax = std::max<int64_t>(0, sD);
+            *b0 = floor_div((__int128)lo - smax, (__int128)1 << lb);
+            *b1 = floor_div((__int128)hi - 1 - smin, (__int128)1 << lb);
+        };
+        SortBlock cur{};
+        int64_t bx0 = 0, bx1 = 0, by0 = 0, by1 = 0;
+        auto flush = [&]() -> bool {
+            if (cur.nv == 0) return true;
+            const int64_t nbx = bx1 - bx0 + 1, nby = by1 - by0 + 1;
+            const __int128 span_keys = (__int128)cur.nv * nbx * nby;
+            int bits = 0;
+            while (((__int128)1 << bits) < span_keys) ++bits;
+            if (bits > 56 || nbx >= ((int64_t)1 << 31) || nby >= ((int64_t)1 << 31)) return false;
+            cur.bx0 = (int32_t)bx0;
+            cur.by0 = (int32_t)by0;
+            cur.nbx = (int32_t)nbx;
+            cur.nby = (int32_t)nby;
+            cur.key_bits = std::max(bits, 1);
+            p->sort_blocks.push_back(cur);
+            p->sort_max_nv = std::max<int64_t>(p->sort_max_nv, cur.nv);
+            cur = SortBlock{};
+            cur.v_off = (int32_t)(sort_vidx.size());
+            return true;
+        };
+        for (int64_t sg = 0; sg < n_seg; ++sg)
+            for (int l = 0; l < NV; ++l) {
+                const int32_t vi = seg_v[sg * NV + l];
+                if (vi < 0) continue;
+                const int32_t u = seg_vel[2 * (sg * NV + l)], w = seg_vel[2 * (sg * NV + l) + 1];
+                int64_t a0, a1, c0, c1;
+                bin_range(u, ex[0], ex[1], &a0, &a1);
+                bin_range(w, ex[2], ex[3], &c0, &c1);
+                if (cur.nv == 0) {
+                    bx0 = a0; bx1 = a1; by0 = c0; by1 = c1;
+                } else {
+                    bx0 = std::min(bx0, a0); bx1 = std::max(bx1, a1);
+                    by0 = std::min(by0, c0); by1 = std::max(by1, c1);
+                }
+                if (bx0 <= -((int64_t)1 << 31) || bx1 >= ((int64_t)1 << 31) ||
+                    by0 <= -((int64_t)1 << 31) || by1 >= ((int64_t)1 << 31))
+                    return fail(SAS_E_UNSUPPORTED, "sas_plan_create: sort-path bins exceed 32 bits");
+                sort_vel.push_back(u);
+                sort_vel.push_back(w);
+                sort_vidx.push_back(vi);
+                ++cur.nv;
+                if (cur.nv == vb && !flush())
+                    return fail(SAS_E_UNSUPPORTED, "sas_plan_create: sort keys exceed 64 bits; "
+                                                   "lower sort_vblock");
+            }
+        if (!flush())
+            return fail(SAS_E_UNSUPPORTED, "sas_plan_create: sort keys exceed 64 bits; lower "
+                                           "sort_vblock");
+        p->sort_vblock = (int32_t)vb;
+    }
+
     std::vector<int32_t> vel(V, V + 2 * n_v);
     sas_status st;
     if ((st = upload(p.get(), &p->d_vel, vel)) != SAS_OK) goto fail_free;
@@ -577,6 +659,8 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     if ((st = upload(p.get(), &p->d_seg_guard, seg_guard)) != SAS_OK) goto fail_free;
     if ((st = upload(p.get(), &p->d_items, items)) != SAS_OK) goto fail_free;
     if ((st = upload(p.get(), &p->d_t, p->t)) != SAS_OK) goto fail_free;
+    if ((st = upload(p.get(), &p->d_sort_vel, sort_vel)) != SAS_OK) goto fail_free;
+    if ((st = upload(p.get(), &p->d_sort_vidx, sort_vidx)) != SAS_OK) goto fail_free;
     *plan_out = p.release();
     return SAS_OK;
 fail_free:
@@ -596,7 +680,7 @@ sas_status sas_plan_get_info(const sas_plan *p, sas_plan_info *info) {
     if (!p || !info) return fail(SAS_E_INVALID, "sas_plan_get_info: null argument");
     info->n_items = p->n_items;
     info->n_tiles = p->n_tiles;
-    info->n_blocks = p->n_segments;
+    info->n_blocks = p->path == SAS_PATH_SORT ? (int64_t)p->sort_blocks.size() : p->n_segments;
     info->path = p->path;
     info->tile_x = p->tile_x;
     info->tile_y = p->tile_y;
@@ -659,6 +743,45 @@ sas_status sas_vote(const sas_plan *p, const int32_t *x_q8, const int32_t *y_q8,
                                p->cell_log2, p->ext, p->n_cells, pb, res_dev, s);
     if (e != hipSuccess) return hip_fail(e, "sas_vote: preparation launch");
     if (n == 0 || p->n_v == 0) return SAS_OK;
+
+    if (p->path == SAS_PATH_SORT) {
+        if (p->sort_max_nv * n >= ((int64_t)1 << 31))
+            return fail(SAS_E_INVALID, "sas_vote: sort block of n x sort_vblock keys exceeds 2^31; "
+                                       "lower tuning.sort_vblock");
+        SortArgs sa{};
+        sa.x = x_q8;
+        sa.y = y_q8;
+        sa.epoch = epoch;
+        sa.n = n;
+        sa.dt = pb.dt;
+        sa.n_epochs = p->n_epochs;
+        sa.log2b = p->log2b;
+        sa.n_min = p->n_min;
+        sa.count_sat = p->count_sat;
+        sa.mode_epochs = p->mode == SAS_MODE_EPOCHS ? 1 : 0;
+        sa.vel = p->d_sort_vel;
+        sa.v_idx = p->d_sort_vidx;
+        sa.keys = (uint64_t *)(w + L.keys);
+        sa.keys_alt = (uint64_t *)(w + L.keys_alt);
+        sa.hist = (int32_t *)(w + L.hist);
+        sa.hist_blocksum = (int32_t *)(w + L.hist_blocksum);
+        sa.cand = cand_dev;
+        sa.cand_cap = cand_cap;
+        sa.res = res_dev;
+        if (p->probe[0]) {
+            e = hipEventRecord(p->probe[0], s);
+            if (e != hipSuccess) return hip_fail(e, "sas_vote: probe");
+        }
+        for (const SortBlock &b : p->sort_blocks) {
+            e = launch_vote_sort_block(sa, b, s);
+            if (e != hipSuccess) return hip_fail(e, "sas_vote: sort-path launch");
+        }
+        if (p->probe[1]) {
+            e = hipEventRecord(p->probe[1], s);
+            if (e != hipSuccess) return hip_fail(e, "sas_vote: probe");
+        }
+        return SAS_OK;
+    }
 
     DenseArgs a{};
     a.cat.sxy = pb.sxy;

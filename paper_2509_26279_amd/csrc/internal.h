@@ -81,6 +81,41 @@ hipError_t launch_prep(const int32_t *x, const int32_t *y, const uint8_t *epoch,
                        int32_t cell_log2, const int32_t ext[4], int64_t n_cells,
                        const PrepBuffers &pb, sas_vote_result *res, hipStream_t stream);
 
+// Exclusive scan of n int32 in place (blocksum: (n + kScanTile - 1) / kScanTile).
+hipError_t launch_scan_exclusive(int32_t *data, int64_t n, int32_t *blocksum, hipStream_t stream);
+
+// Sort-by-bin-key path.  A sort block is a run of velocities whose keys are
+// generated, radix sorted and counted together.
+struct SortBlock {
+    int32_t v_off, nv;        // velocities [v_off, v_off + nv) of the block tables
+    int32_t bx0, by0;         // smallest bin any (velocity, detection) of the block reaches
+    int32_t nbx, nby;         // bin extent
+    int32_t key_bits;         // bits of (velocity, by, bx) in the key above the epoch byte
+    int32_t reserved;
+};
+
+struct SortArgs {
+    const int32_t *x, *y;
+    const uint8_t *epoch;
+    int64_t n;
+    const int32_t *dt;        // [E] d_e, -1 for epochs without detections
+    int32_t n_epochs;
+    int32_t log2b;
+    int32_t n_min, count_sat, mode_epochs;
+    const int32_t *vel;       // [n_v][2] velocities in block order
+    const int32_t *v_idx;     // [n_v] v_idx in block order
+    uint64_t *keys, *keys_alt;
+    int32_t *hist, *hist_blocksum;
+    sas_candidate *cand;
+    int64_t cand_cap;
+    sas_vote_result *res;
+};
+
+constexpr int kSortKeysPerTile = 4096;  // radix tile: 256 threads x 16 keys
+
+// Keys, radix sort and count of one sort block (blk: host copy of its table row).
+hipError_t launch_vote_sort_block(const SortArgs &a, const SortBlock &blk, hipStream_t stream);
+
 // groups: lane groups G (1, 2 or 4); segments hold 64 / G velocities.
 // ev0 / ev1 (optional) are recorded on the stream around the vote kernel.
 hipError_t launch_vote_dense(int mode, int groups, const DenseArgs &a, hipStream_t stream,

@@ -168,6 +168,17 @@ inline unsigned blocks_for(int64_t n, int threads) {
 
 }  // namespace
 
+hipError_t launch_scan_exclusive(int32_t *data, int64_t n, int32_t *blocksum, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nb), dim3(kScanThreads), 0, stream, data, n,
+                       blocksum);
+    hipLaunchKernelGGL(k_scan_blocksums, dim3(1), dim3(kScanThreads), 0, stream, blocksum, nb);
+    hipLaunchKernelGGL(k_scan_add, dim3(blocks_for(n, 256)), dim3(256), 0, stream, data, n,
+                       blocksum);
+    return hipGetLastError();
+}
+
 hipError_t launch_prep(const int32_t *x, const int32_t *y, const uint8_t *epoch, int64_t n,
                        const int64_t *t_dev, int32_t n_epochs, int32_t ncx, int32_t ncy,
                        int32_t cell_log2, const int32_t ext[4], int64_t n_cells,

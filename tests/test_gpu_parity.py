@@ -32,9 +32,10 @@ def _extent(x, y):
 
 
 def gpu_vote(x, y, e, t, v, binw, n_min, mode="epochs", count_sat=65535, extent=None,
-             tuning=None, cap=1 << 16, order="canonical", top_k=0):
+             tuning=None, cap=1 << 16, order="canonical", top_k=0, path="auto"):
     extent = extent if extent is not None else _extent(np.asarray(x), np.asarray(y))
-    plan = sas.Plan(v, t, binw, n_min, extent, mode=mode, count_sat=count_sat, tuning=tuning)
+    plan = sas.Plan(v, t, binw, n_min, extent, mode=mode, count_sat=count_sat, tuning=tuning,
+                    path=path)
     s = sas.Search(plan, max(len(x), 1), cand_cap=cap)
     try:
         return s.run(x, y, e, order=order, top_k=top_k)
@@ -260,3 +261,60 @@ def test_by_count_top_k(gpu):
     g = gpu_vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v, wl.binw_q8, 5, extent=wl.extent_q8,
                  order="by_count", top_k=25)
     assert_same(g, o[order][:25])
+
+
+# ---------------------------------------------------------------- sort-by-bin-key path
+
+def test_sort_path_tiny(gpu):
+    wl = synth.make_tiny()
+    v = _grid(wl)
+    for mode, n_min in (("epochs", 12), ("detections", 5)):
+        _say(f"sort tiny mode={mode}")
+        o = oracle.vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v, wl.binw_q8, n_min, mode, 255)
+        g = gpu_vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v, wl.binw_q8, n_min, mode, 255,
+                     wl.extent_q8, path="sort")
+        assert_same(g, o)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_sort_path_adversarial(gpu, seed):
+    d = synth.make_random_small(seed, n=400, n_epochs=[5, 20, 33, 40, 64, 100, 200, 256][seed],
+                                n_v=40, binw_q8=[256, 512, 1024, 2048][seed % 4],
+                                extent_q8=60 * 256, dup_frac=0.3)
+    for mode in ("epochs", "detections"):
+        for n_min in (1, 2, 3):
+            _say(f"sort adversarial seed={seed} mode={mode} n_min={n_min}")
+            o = oracle.vote(d["x_q8"], d["y_q8"], d["epoch"], d["t_q16"], d["v_q8"],
+                            d["binw_q8"], n_min, mode)
+            for vb in (1, 7, 64):
+                g = gpu_vote(d["x_q8"], d["y_q8"], d["epoch"], d["t_q16"], d["v_q8"],
+                             d["binw_q8"], n_min, mode, path="sort", tuning=dict(sort_vblock=vb))
+                assert_same(g, o)
+
+
+@pytest.mark.parametrize("maker,k", [(synth.make_wide, 96), (synth.make_fast, 64)])
+def test_sort_path_full_size_subset(gpu, maker, k):
+    wl = maker()
+    v = _grid(wl)
+    idx = _sampled_velocities(v, k, 29)
+    _say(f"sort {wl.name} subset={len(idx)}")
+    o = oracle.vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v[idx], wl.binw_q8, wl.n_min,
+                    "epochs", 65535)
+    g = gpu_vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v[idx], wl.binw_q8, wl.n_min, "epochs",
+                 65535, wl.extent_q8, cap=1 << 20, path="sort")
+    assert_same(g, o)
+
+
+def test_sort_and_dense_agree_on_fast_sample(gpu):
+    """Both paths over a seeded 2 % sample of the fast grid."""
+    wl = synth.make_fast()
+    v = _grid(wl)
+    idx = _sampled_velocities(v, len(v) // 50, 31)
+    _say(f"sort vs dense fast sample={len(idx)}")
+    out = {}
+    for path in ("dense", "sort"):
+        out[path] = gpu_vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v[idx], wl.binw_q8,
+                             wl.n_min - 8, "epochs", 65535, wl.extent_q8, cap=1 << 22,
+                             path=path, tuning=dict(n_det_hint=wl.n))
+    assert len(out["dense"]) > 0
+    assert_same(out["sort"], out["dense"])
