@@ -109,6 +109,20 @@ sas_status sas_grid_spacing(int32_t binw_q8, int64_t span_q16, int32_t *spacing_
 sas_status sas_build_grid(const sas_grid_spec *spec, int32_t *v_out_host, int64_t cap,
                           int64_t *n_out);
 
+/*
+ * sas_threshold_n_min: the threshold rule of Sec. 2.2.  With mu noise
+ * detections per bin per epoch (Poisson), a pure-noise bin holds a noise
+ * detection in an epoch with probability 1 - exp(-mu); its distinct epochs
+ * are Binomial(E, 1 - exp(-mu)) (SAS_MODE_EPOCHS) and its detections
+ * Poisson(E mu) (SAS_MODE_DETECTIONS).  *n_min_out receives the smallest
+ * N_min with n_stacks * P(count >= N_min) <= n_false, n_stacks being the
+ * number of independent stacks of eq. (N_stacks), |V| Omega / Delta x^2.
+ * Host only.  Errors: SAS_E_INVALID (arguments, or no N_min <= E reaches
+ * n_false in EPOCHS mode).
+ */
+sas_status sas_threshold_n_min(int32_t n_epochs, double mu, double n_stacks, double n_false,
+                               int32_t mode, int32_t *n_min_out);
+
 /* ------------------------------------------------------------------------
  * Candidates and results
  * ---------------------------------------------------------------------- */
@@ -233,6 +247,53 @@ sas_status sas_vote_workspace_size(const sas_plan *plan, int64_t n, size_t *byte
 sas_status sas_vote(const sas_plan *plan, const int32_t *x_q8, const int32_t *y_q8,
                     const uint8_t *epoch, int64_t n, sas_candidate *cand_dev, int64_t cand_cap,
                     sas_vote_result *res_dev, void *workspace, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batches: many catalogs (e.g. the chips of one night, each with its own
+ * plan: grid, epochs, threshold, footprint) voted by one persistent launch
+ * per kernel class.  The chips' work items are merged into one list (largest
+ * chips first) that the resident workgroups walk together, so chips of very
+ * different sizes keep every CU busy.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    const sas_plan *plan;           /* dense-path plan of this chip (kept alive by the caller) */
+    const int32_t *x_q8, *y_q8;     /* device [n] */
+    const uint8_t *epoch;           /* device [n] */
+    int64_t n;
+    sas_candidate *cand_dev;        /* device [cand_cap] */
+    int64_t cand_cap;
+    sas_vote_result *res_dev;       /* device */
+} sas_batch_chip;
+
+typedef struct sas_batch sas_batch;
+
+/* Device workspace of a batch (all chips' workspaces plus the queues). */
+sas_status sas_batch_workspace_size(const sas_batch_chip *chips, int32_t n_chips, size_t *bytes);
+
+/*
+ * sas_batch_create: bind n_chips catalogs, outputs and one workspace
+ * (>= sas_batch_workspace_size, 256-byte aligned), merge the chips' work
+ * items into one list per kernel class and upload the
+ * tables (allocates; synchronous).  The bound buffers must stay valid while
+ * the batch is used; their contents may change between votes.
+ * Errors: SAS_E_INVALID (arguments, a plan that is not on the dense path),
+ * SAS_E_WORKSPACE, SAS_E_NOMEM, SAS_E_DEVICE.
+ */
+sas_status sas_batch_create(const sas_batch_chip *chips, int32_t n_chips, void *workspace,
+                            size_t ws_bytes, sas_batch **batch_out);
+sas_status sas_batch_destroy(sas_batch *batch);
+
+/*
+ * sas_vote_batch: enqueue the voting transform of every bound chip on
+ * `stream`; each chip's candidates and result go to its own buffers
+ * (collect them with sas_peaks).  No allocation, no synchronisation, no
+ * memset nodes: safe to capture in a HIP graph and replay.
+ */
+sas_status sas_vote_batch(const sas_batch *batch, void *stream);
+
+/* Measurement hook: record ev_before / ev_after around the batch's vote
+ * kernels (first class launch to last) on the call's stream; NULL, NULL off. */
+sas_status sas_batch_set_probe(sas_batch *batch, void *ev_before, void *ev_after);
 
 /* ------------------------------------------------------------------------
  * Peaks: collect the candidates of a finished vote in a deterministic order.

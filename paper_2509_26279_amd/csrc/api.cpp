@@ -117,6 +117,8 @@ struct sas_plan {
     size_t lds_bytes = 0;
     int32_t *d_vel = nullptr, *d_seg = nullptr, *d_seg_v = nullptr, *d_seg_vel = nullptr;
     int32_t *d_seg_guard = nullptr, *d_items = nullptr;
+    std::vector<int32_t> h_items;  // host copy of the work items
+    double footprint_cells = 1.0;  // cells of the footprint (batch cost estimates)
     // sort path
     std::vector<SortBlock> sort_blocks;
     int64_t sort_max_nv = 0;
@@ -176,6 +178,61 @@ WsLayout ws_layout(const sas_plan *p, int64_t n) {
     L.hist_blocksum = o; o = align_up(o + sizeof(int32_t) * ((hist + kScanTile - 1) / kScanTile));
     L.total = o;
     return L;
+}
+
+PrepBuffers prep_buffers(const WsLayout &L, char *w) {
+    PrepBuffers pb;
+    pb.count = (int32_t *)(w + L.count);
+    pb.blocksum = (int32_t *)(w + L.blocksum);
+    pb.cellid = (int32_t *)(w + L.cellid);
+    pb.rank = (int32_t *)(w + L.rank);
+    pb.sxy = (int2 *)(w + L.sxy);
+    pb.present = (int32_t *)(w + L.present);
+    pb.dt = (int32_t *)(w + L.dt);
+    pb.refine_count = (unsigned long long *)(w + L.refine_count);
+    return pb;
+}
+
+DenseArgs dense_args(const sas_plan *p, const WsLayout &L, char *w, const PrepBuffers &pb,
+                     sas_candidate *cand, int64_t cand_cap, sas_vote_result *res) {
+    DenseArgs a{};
+    a.cat.sxy = pb.sxy;
+    a.cat.off = pb.count;
+    a.cat.dt = pb.dt;
+    a.cat.n_epochs = p->n_epochs;
+    a.cat.ncx = p->ncx;
+    a.cat.ncy = p->ncy;
+    a.cat.cell_log2 = p->cell_log2;
+    a.cat.x0 = p->ext[0];
+    a.cat.x1 = p->ext[1];
+    a.cat.y0 = p->ext[2];
+    a.cat.y1 = p->ext[3];
+    a.log2b = p->log2b;
+    a.coarse_log2 = p->coarse_log2;
+    a.tile_x = p->tile_x;
+    a.tile_y = p->tile_y;
+    a.hx = p->hx;
+    a.hy = p->hy;
+    a.stage_cap = p->stage_cap;
+    a.rows = p->rows;
+    a.max_pairs = p->max_pairs;
+    a.n_min = p->n_min;
+    a.count_sat = p->count_sat;
+    a.mode_epochs = p->mode == SAS_MODE_EPOCHS ? 1 : 0;
+    a.vel = p->d_vel;
+    a.seg = p->d_seg;
+    a.seg_v = p->d_seg_v;
+    a.seg_vel = p->d_seg_vel;
+    a.seg_guard = p->d_seg_guard;
+    a.items = p->d_items;
+    a.n_items = p->n_items;
+    a.refine = (int4 *)(w + L.refine);
+    a.refine_count = pb.refine_count;
+    a.refine_cap = p->dense_mode == kCountRef ? p->refine_cap : 0;
+    a.cand = cand;
+    a.cand_cap = cand_cap;
+    a.res = res;
+    return a;
 }
 
 }  // namespace
@@ -658,6 +715,8 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     if ((st = upload(p.get(), &p->d_seg_vel, seg_vel)) != SAS_OK) goto fail_free;
     if ((st = upload(p.get(), &p->d_seg_guard, seg_guard)) != SAS_OK) goto fail_free;
     if ((st = upload(p.get(), &p->d_items, items)) != SAS_OK) goto fail_free;
+    p->h_items = items;
+    p->footprint_cells = std::max(1.0, area / ((double)cellw * (double)cellw));
     if ((st = upload(p.get(), &p->d_t, p->t)) != SAS_OK) goto fail_free;
     if ((st = upload(p.get(), &p->d_sort_vel, sort_vel)) != SAS_OK) goto fail_free;
     if ((st = upload(p.get(), &p->d_sort_vidx, sort_vidx)) != SAS_OK) goto fail_free;
@@ -730,15 +789,7 @@ sas_status sas_vote(const sas_plan *p, const int32_t *x_q8, const int32_t *y_q8,
         return fail(SAS_E_INVALID, "sas_vote: workspace must be 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)workspace;
-    PrepBuffers pb;
-    pb.count = (int32_t *)(w + L.count);
-    pb.blocksum = (int32_t *)(w + L.blocksum);
-    pb.cellid = (int32_t *)(w + L.cellid);
-    pb.rank = (int32_t *)(w + L.rank);
-    pb.sxy = (int2 *)(w + L.sxy);
-    pb.present = (int32_t *)(w + L.present);
-    pb.dt = (int32_t *)(w + L.dt);
-    pb.refine_count = (unsigned long long *)(w + L.refine_count);
+    const PrepBuffers pb = prep_buffers(L, w);
     hipError_t e = launch_prep(x_q8, y_q8, epoch, n, p->d_t, p->n_epochs, p->ncx, p->ncy,
                                p->cell_log2, p->ext, p->n_cells, pb, res_dev, s);
     if (e != hipSuccess) return hip_fail(e, "sas_vote: preparation launch");
@@ -783,43 +834,7 @@ sas_status sas_vote(const sas_plan *p, const int32_t *x_q8, const int32_t *y_q8,
         return SAS_OK;
     }
 
-    DenseArgs a{};
-    a.cat.sxy = pb.sxy;
-    a.cat.off = pb.count;
-    a.cat.dt = pb.dt;
-    a.cat.n_epochs = p->n_epochs;
-    a.cat.ncx = p->ncx;
-    a.cat.ncy = p->ncy;
-    a.cat.cell_log2 = p->cell_log2;
-    a.cat.x0 = p->ext[0];
-    a.cat.x1 = p->ext[1];
-    a.cat.y0 = p->ext[2];
-    a.cat.y1 = p->ext[3];
-    a.log2b = p->log2b;
-    a.coarse_log2 = p->coarse_log2;
-    a.tile_x = p->tile_x;
-    a.tile_y = p->tile_y;
-    a.hx = p->hx;
-    a.hy = p->hy;
-    a.stage_cap = p->stage_cap;
-    a.rows = p->rows;
-    a.max_pairs = p->max_pairs;
-    a.n_min = p->n_min;
-    a.count_sat = p->count_sat;
-    a.mode_epochs = p->mode == SAS_MODE_EPOCHS ? 1 : 0;
-    a.vel = p->d_vel;
-    a.seg = p->d_seg;
-    a.seg_v = p->d_seg_v;
-    a.seg_vel = p->d_seg_vel;
-    a.seg_guard = p->d_seg_guard;
-    a.items = p->d_items;
-    a.n_items = p->n_items;
-    a.refine = (int4 *)(w + L.refine);
-    a.refine_count = pb.refine_count;
-    a.refine_cap = p->dense_mode == kCountRef ? p->refine_cap : 0;
-    a.cand = cand_dev;
-    a.cand_cap = cand_cap;
-    a.res = res_dev;
+    const DenseArgs a = dense_args(p, L, w, pb, cand_dev, cand_cap, res_dev);
     e = launch_vote_dense(p->dense_mode, p->groups, a, s, p->probe[0], p->probe[1]);
     if (e != hipSuccess) return hip_fail(e, "sas_vote: vote launch");
     return SAS_OK;
@@ -881,6 +896,232 @@ sas_status sas_peaks(const sas_candidate *cand_dev, const sas_vote_result *res_d
     }
     if (k > 0) std::memcpy(out_host, c.data(), sizeof(sas_candidate) * (size_t)k);
     *n_out = k;
+    return SAS_OK;
+}
+
+}  // extern "C"
+
+struct sas_batch {
+    struct Chip {
+        sas_batch_chip b;
+        size_t ws_off = 0;
+        WsLayout L{};
+        DenseArgs args{};
+    };
+    struct Class {
+        int mode = 0, groups = 1;
+        int32_t *d_items5 = nullptr;
+        int64_t n_items = 0;
+        int32_t hist_words_max = 0;
+        size_t lds = 0;
+    };
+    std::vector<Chip> chips;
+    std::vector<Class> classes;
+    DenseArgs *d_args = nullptr;
+    char *ws = nullptr;
+    std::vector<void *> allocs;
+    hipEvent_t probe[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+constexpr int kMaxBatchClasses = 9;  // 3 cell variants x 3 lane-group counts
+
+sas_status batch_layout(const sas_batch_chip *chips, int32_t n_chips, std::vector<size_t> *offs,
+                        size_t *total) {
+    if (n_chips < 1 || !chips) return fail(SAS_E_INVALID, "batch: no chips");
+    size_t o = 0;
+    offs->clear();
+    for (int32_t c = 0; c < n_chips; ++c) {
+        const sas_plan *p = chips[c].plan;
+        if (!p) return fail(SAS_E_INVALID, "batch: null plan");
+        if (p->path != SAS_PATH_DENSE)
+            return fail(SAS_E_INVALID, "batch: every chip needs a dense-path plan");
+        if (chips[c].n < 0 || chips[c].n >= ((int64_t)1 << 31))
+            return fail(SAS_E_INVALID, "batch: chip n must be in [0, 2^31)");
+        offs->push_back(o);
+        o = align_up(o + ws_layout(p, chips[c].n).total);
+    }
+    *total = o;
+    return SAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sas_status sas_batch_workspace_size(const sas_batch_chip *chips, int32_t n_chips, size_t *bytes) {
+    if (!bytes) return fail(SAS_E_INVALID, "sas_batch_workspace_size: null argument");
+    std::vector<size_t> offs;
+    return batch_layout(chips, n_chips, &offs, bytes);
+}
+
+sas_status sas_batch_create(const sas_batch_chip *chips, int32_t n_chips, void *workspace,
+                            size_t ws_bytes, sas_batch **out) {
+    if (!out) return fail(SAS_E_INVALID, "sas_batch_create: null argument");
+    *out = nullptr;
+    std::vector<size_t> offs;
+    size_t total = 0;
+    sas_status st = batch_layout(chips, n_chips, &offs, &total);
+    if (st != SAS_OK) return st;
+    if (!workspace || ws_bytes < total)
+        return fail(SAS_E_WORKSPACE, "sas_batch_create: workspace smaller than "
+                                     "sas_batch_workspace_size()");
+    if (((uintptr_t)workspace & 255) != 0)
+        return fail(SAS_E_INVALID, "sas_batch_create: workspace must be 256-byte aligned");
+    for (int32_t c = 0; c < n_chips; ++c) {
+        const sas_batch_chip &b = chips[c];
+        if (b.n > 0 && (!b.x_q8 || !b.y_q8 || !b.epoch))
+            return fail(SAS_E_INVALID, "sas_batch_create: null catalog array");
+        if (!b.res_dev || b.cand_cap < 0 || (b.cand_cap > 0 && !b.cand_dev))
+            return fail(SAS_E_INVALID, "sas_batch_create: bad output buffers");
+    }
+    std::unique_ptr<sas_batch> bt(new sas_batch());
+    bt->ws = (char *)workspace;
+    std::vector<DenseArgs> args(n_chips);
+    for (int32_t c = 0; c < n_chips; ++c) {
+        sas_batch::Chip ch;
+        ch.b = chips[c];
+        ch.ws_off = offs[c];
+        ch.L = ws_layout(ch.b.plan, ch.b.n);
+        char *w = bt->ws + ch.ws_off;
+        ch.args = dense_args(ch.b.plan, ch.L, w, prep_buffers(ch.L, w), ch.b.cand_dev,
+                             ch.b.cand_cap, ch.b.res_dev);
+        args[c] = ch.args;
+        bt->chips.push_back(ch);
+    }
+    // Merge the chips' items per kernel class: chip-major (largest chips
+    // first), each chip's items in the chip's own L2-friendly order.  Cost of
+    // a chip: its tiles times (expected votes of a tile + a fixed per-tile
+    // cost in vote units).
+    struct It {
+        int32_t v[5];
+    };
+    std::vector<double> chip_cost(n_chips, 0.0);
+    for (int32_t c = 0; c < n_chips; ++c) {
+        const sas_plan *p = chips[c].plan;
+        const double dens = (double)chips[c].n / p->footprint_cells;  // detections per cell
+        chip_cost[c] = (double)p->n_tiles *
+                       ((double)p->tile_x * p->tile_y * dens * (64 / p->groups) + 4096.0);
+    }
+    std::vector<int32_t> chip_order(n_chips);
+    for (int32_t c = 0; c < n_chips; ++c) chip_order[c] = c;
+    std::stable_sort(chip_order.begin(), chip_order.end(),
+                     [&](int32_t u, int32_t w) { return chip_cost[u] > chip_cost[w]; });
+    std::vector<std::vector<It>> per_class(kMaxBatchClasses);
+    for (int32_t c : chip_order) {
+        const sas_plan *p = chips[c].plan;
+        if (chips[c].n == 0 || p->n_items == 0) continue;
+        const int k = p->dense_mode * 3 + (p->groups == 1 ? 0 : p->groups == 2 ? 1 : 2);
+        for (int64_t q = 0; q < p->n_items; ++q) {
+            It it;
+            const int32_t *src = &p->h_items[4 * q];
+            it.v[0] = c;
+            it.v[1] = src[0];
+            it.v[2] = src[1];
+            it.v[3] = src[2];
+            it.v[4] = src[3];
+            per_class[k].push_back(it);
+        }
+    }
+    for (int k = 0; k < kMaxBatchClasses; ++k) {
+        if (per_class[k].empty()) continue;
+        const std::vector<It> &v = per_class[k];
+        sas_batch::Class cl;
+        cl.mode = k / 3;
+        cl.groups = (k % 3 == 0) ? 1 : (k % 3 == 1) ? 2 : 4;
+        std::vector<int32_t> flat;
+        flat.reserve(v.size() * 5);
+        for (const It &it : v) flat.insert(flat.end(), it.v, it.v + 5);
+        for (int32_t c = 0; c < n_chips; ++c) {
+            const sas_plan *p = chips[c].plan;
+            if (p->dense_mode * 3 + (p->groups == 1 ? 0 : p->groups == 2 ? 1 : 2) != k) continue;
+            cl.hist_words_max = std::max(cl.hist_words_max, p->hx * p->hy * (64 / p->groups));
+            cl.lds = std::max(cl.lds, dense_lds_bytes(p->groups, p->hx, p->hy, p->stage_cap,
+                                                      p->max_pairs));
+        }
+        cl.n_items = (int64_t)v.size();
+        void *d = nullptr;
+        hipError_t e = hipMalloc(&d, flat.size() * sizeof(int32_t));
+        if (e != hipSuccess) {
+            for (void *a : bt->allocs) hipFree(a);
+            return fail(SAS_E_NOMEM, "sas_batch_create: item table");
+        }
+        bt->allocs.push_back(d);
+        e = hipMemcpy(d, flat.data(), flat.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            for (void *a : bt->allocs) hipFree(a);
+            return hip_fail(e, "sas_batch_create: item upload");
+        }
+        cl.d_items5 = (int32_t *)d;
+        bt->classes.push_back(cl);
+    }
+    void *d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(DenseArgs) * n_chips);
+    if (e != hipSuccess) {
+        for (void *a : bt->allocs) hipFree(a);
+        return fail(SAS_E_NOMEM, "sas_batch_create: chip table");
+    }
+    bt->allocs.push_back(d);
+    e = hipMemcpy(d, args.data(), sizeof(DenseArgs) * n_chips, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        for (void *a : bt->allocs) hipFree(a);
+        return hip_fail(e, "sas_batch_create: chip table upload");
+    }
+    bt->d_args = (DenseArgs *)d;
+    *out = bt.release();
+    return SAS_OK;
+}
+
+sas_status sas_batch_destroy(sas_batch *b) {
+    if (!b) return SAS_OK;
+    for (void *a : b->allocs) hipFree(a);
+    delete b;
+    return SAS_OK;
+}
+
+sas_status sas_batch_set_probe(sas_batch *b, void *ev_before, void *ev_after) {
+    if (!b) return fail(SAS_E_INVALID, "sas_batch_set_probe: null batch");
+    if ((ev_before == nullptr) != (ev_after == nullptr))
+        return fail(SAS_E_INVALID, "sas_batch_set_probe: give both events or neither");
+    b->probe[0] = (hipEvent_t)ev_before;
+    b->probe[1] = (hipEvent_t)ev_after;
+    return SAS_OK;
+}
+
+sas_status sas_vote_batch(const sas_batch *b, void *stream) {
+    if (!b) return fail(SAS_E_INVALID, "sas_vote_batch: null batch");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    for (const sas_batch::Chip &ch : b->chips) {
+        const sas_plan *p = ch.b.plan;
+        char *w = b->ws + ch.ws_off;
+        e = launch_prep(ch.b.x_q8, ch.b.y_q8, ch.b.epoch, ch.b.n, p->d_t, p->n_epochs, p->ncx,
+                        p->ncy, p->cell_log2, p->ext, p->n_cells, prep_buffers(ch.L, w),
+                        ch.b.res_dev, s);
+        if (e != hipSuccess) return hip_fail(e, "sas_vote_batch: preparation launch");
+    }
+    if (b->probe[0] && (e = hipEventRecord(b->probe[0], s)) != hipSuccess)
+        return hip_fail(e, "sas_vote_batch: probe");
+    int dev = 0, n_cu = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    for (size_t k = 0; k < b->classes.size(); ++k) {
+        const sas_batch::Class &cl = b->classes[k];
+        // persistent: as many workgroups as fit on the device at once
+        const int per_cu = std::max<int>(1, (int)(kLdsPerCU / (cl.lds + dense_static_lds_bytes())));
+        const int grid = (int)std::min<int64_t>(cl.n_items, (int64_t)n_cu * per_cu);
+        e = launch_vote_dense_batch(cl.mode, cl.groups, b->d_args, cl.d_items5, cl.n_items,
+                                    cl.hist_words_max, cl.lds, grid, s);
+        if (e != hipSuccess) return hip_fail(e, "sas_vote_batch: vote launch");
+    }
+    if (b->probe[1] && (e = hipEventRecord(b->probe[1], s)) != hipSuccess)
+        return hip_fail(e, "sas_vote_batch: probe");
+    for (const sas_batch::Chip &ch : b->chips) {
+        if (ch.b.plan->dense_mode != kCountRef || ch.b.n == 0) continue;
+        e = launch_refine(ch.args, s);
+        if (e != hipSuccess) return hip_fail(e, "sas_vote_batch: refinement launch");
+    }
     return SAS_OK;
 }
 

@@ -120,6 +120,13 @@ hipError_t launch_vote_sort_block(const SortArgs &a, const SortBlock &blk, hipSt
 // ev0 / ev1 (optional) are recorded on the stream around the vote kernel.
 hipError_t launch_vote_dense(int mode, int groups, const DenseArgs &a, hipStream_t stream,
                              hipEvent_t ev0, hipEvent_t ev1);
+// One persistent launch over the merged items (chip, segment, ty0, txf,
+// ntiles) of many chips of one kernel class.
+hipError_t launch_vote_dense_batch(int mode, int groups, const DenseArgs *chips_dev,
+                                   const int32_t *items5_dev, int64_t n_items,
+                                   int32_t hist_words_max, size_t lds, int grid,
+                                   hipStream_t stream);
+hipError_t launch_refine(const DenseArgs &a, hipStream_t stream);
 size_t dense_lds_bytes(int groups, int hx, int hy, int stage_cap, int max_pairs);
 size_t dense_static_lds_bytes();
 

@@ -192,12 +192,14 @@ __device__ inline void vote_run(const int2 *st, int32_t n, uint32_t sx, uint32_t
 // Dynamic LDS: histogram [HY][HX][NV] words, then the stage (int2), then the
 // run table of the window index (source offset and exclusive prefix of every
 // (epoch, row) pair).
+// One work item: a segment and a row of ntiles tiles starting at tile column
+// txf (cells), tile row ty0.  The histogram is all zero on entry and on exit;
+// sh.dt holds the catalog's d_e.
 template <int MODE, int G>
-__global__ void __launch_bounds__(T) k_vote_dense(DenseArgs a) {
+__device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t sg, int32_t ty0,
+                          int32_t txf, int32_t ntiles, int &parity) {
     constexpr int NV = 64 / G;
     constexpr int LNV = G == 1 ? 6 : G == 2 ? 5 : 4;
-    extern __shared__ uint4 smem4[];
-    __shared__ Shared sh;
     uint32_t *hist = (uint32_t *)smem4;
     const int hist_words = a.hx * a.hy * NV;
     int2 *stage = (int2 *)(hist + hist_words);
@@ -219,249 +221,288 @@ __global__ void __launch_bounds__(T) k_vote_dense(DenseArgs a) {
     const int np = E * R;  // <= max_pairs
     const int per = (np + T - 1) / T;
     const int p0 = tid * per;
+    const int32_t vx_lo = a.seg[4 * sg], vx_hi = a.seg[4 * sg + 1];
+    const int32_t vy_lo = a.seg[4 * sg + 2], vy_hi = a.seg[4 * sg + 3];
+    __syncthreads();  // the previous item no longer reads the segment tables
+    if (tid < NV) {
+        const int64_t o = (int64_t)sg * NV + tid;
+        sh.sv[tid] = a.seg_v[o];
+        sh.svx[tid] = a.seg_vel[2 * o];
+        sh.svy[tid] = a.seg_vel[2 * o + 1];
+        sh.sg[tid] = a.seg_guard[o];
+    }
+    if (tid < E) {  // shifts of the segment's box edges
+        const int32_t d = sh.dt[tid];
+        sh.es[0][tid] = d >= 0 ? shift_q8(vx_lo, d) : 0;
+        sh.es[1][tid] = d >= 0 ? shift_q8(vx_hi, d) : 0;
+        sh.es[2][tid] = d >= 0 ? shift_q8(vy_lo, d) : 0;
+        sh.es[3][tid] = d >= 0 ? shift_q8(vy_hi, d) : 0;
+    }
+    if (tid == 0) sh.bad = 0;
+    __syncthreads();
+    const int32_t my_vx = sh.svx[j], my_vy = sh.svy[j];
+    const int32_t my_gx = sh.sg[j] & 0xffff, my_gy = sh.sg[j] >> 16;
+    const int32_t oy = ty0 * cellw;
+    // Q8 origin of this lane's histogram row 0: (ty0 - gy) cells
+    const uint32_t oy_lane = (uint32_t)(ty0 - my_gy) * (uint32_t)cellw;
+    const uint32_t lane_addr = (uint32_t)(uintptr_t)(lds_u32 *)hist + (uint32_t)(j * 4);
 
+    // Lane shifts of this wave's epochs e = wave + k NW (k < kEpochRegs),
+    // kept in registers for the whole item.  The window of any tile then
+    // lands inside every lane's histogram (tile independent; checked here).
+    int32_t Sx[kEpochRegs], Sy[kEpochRegs];
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < kEpochRegs; ++k) {
+        const int e = wave + k * NW;
+        Sx[k] = 0;
+        Sy[k] = 0;
+        if (e < E) {
+            const int32_t d = sh.dt[e];
+            if (d >= 0) {
+                Sx[k] = shift_q8(my_vx, d);
+                Sy[k] = shift_q8(my_vy, d);
+                const int64_t gxq = (int64_t)my_gx << kc, gyq = (int64_t)my_gy << kc;
+                const int64_t lx = (int64_t)sh.es[0][e] - Sx[k] - 1 + gxq;
+                const int64_t hx = (int64_t)sh.es[1][e] - Sx[k] + W - 1 + gxq;
+                const int64_t ly = (int64_t)sh.es[2][e] - Sy[k] - 1 + gyq;
+                const int64_t hy = (int64_t)sh.es[3][e] - Sy[k] + H - 1 + gyq;
+                bad |= lx < 0 || ly < 0 || hx >= ((int64_t)a.hx << kc) ||
+                       hy >= ((int64_t)a.hy << kc);
+            }
+        }
+    }
+    for (int e = wave + kEpochRegs * NW; e < E; e += NW) {  // epochs past the registers
+        const int32_t d = sh.dt[e];
+        if (d < 0) continue;
+        const int64_t sxe = shift_q8(my_vx, d), sye = shift_q8(my_vy, d);
+        const int64_t gxq = (int64_t)my_gx << kc, gyq = (int64_t)my_gy << kc;
+        bad |= (int64_t)sh.es[0][e] - sxe - 1 + gxq < 0 ||
+               (int64_t)sh.es[2][e] - sye - 1 + gyq < 0 ||
+               (int64_t)sh.es[1][e] - sxe + W - 1 + gxq >= ((int64_t)a.hx << kc) ||
+               (int64_t)sh.es[3][e] - sye + H - 1 + gyq >= ((int64_t)a.hy << kc);
+    }
+    if (bad) sh.bad = 1;
+    __syncthreads();
+    if (sh.bad) {  // excluded by the planner's guard cells; block uniform
+        if (tid == 0) atomicOr(&a.res->status, SAS_DATA_INTERNAL);
+        return;
+    }
+
+    for (int32_t ti = 0; ti < ntiles; ++ti) {
+        const int32_t tx0 = txf + ti * a.tile_x;
+        const int32_t ox = tx0 * cellw;
+        const uint32_t ox_lane = (uint32_t)(tx0 - my_gx) * (uint32_t)cellw;
+        parity ^= 1;
+
+        // 1. exact windows and run lengths, one thread per (epoch, index row);
+        //    then a block scan lays the runs out (epoch-major)
+        int32_t lsum = 0;
+        for (int k = 0; k < per; ++k) {
+            const int p = p0 + k;
+            if (p >= np) break;
+            const int e = p / R, r = p - e * R;
+            int32_t src = 0, len = 0;
+            if (sh.dt[e] >= 0) {
+                const int32_t xlo = ox + sh.es[0][e], xhi = ox + sh.es[1][e] + W;
+                const int32_t ylo = oy + sh.es[2][e], yhi = oy + sh.es[3][e] + H;
+                int cx0, cx1, cy0, cy1;
+                if (cell_span(xlo, xhi, c.x0, c.x1, c.cell_log2, &cx0, &cx1) &&
+                    cell_span(ylo, yhi, c.y0, c.y1, c.cell_log2, &cy0, &cy1)) {
+                    if (r == 0 && cy1 - cy0 + 1 > R)  // excluded by the planner
+                        atomicOr(&a.res->status, SAS_DATA_INTERNAL);
+                    if (cy0 + r <= cy1) {
+                        const int64_t base = ((int64_t)e * c.ncy + cy0 + r) * c.ncx;
+                        src = c.off[base + cx0];
+                        len = c.off[base + cx1 + 1] - src;
+                    }
+                }
+            }
+            psrc[p] = src;
+            pdst[p] = len;
+            lsum += len;
+        }
+        if (tid < E) sh.ecnt[tid] = 0;
+        int32_t M;
+        int32_t run = scan_block(lsum, &M, sh.wsum[parity]);
+        for (int k = 0; k < per; ++k) {
+            const int p = p0 + k;
+            if (p >= np) break;
+            const int32_t len = pdst[p];
+            pdst[p] = run;
+            run += len;
+        }
+        if (tid == 0) pdst[np] = M;
+        if (M == 0) continue;  // block uniform; nothing to vote, the histogram is clear
+        if (M > a.stage_cap && tid == 0) atomicAdd(&a.res->n_spilled, 1);
+
+        // 2. stage and vote, chunk by chunk
+        for (int32_t c0 = 0; c0 < M; c0 += a.stage_cap) {
+            const int32_t c1 = min(M, c0 + a.stage_cap);
+            if (c0 > 0) {  // the previous chunk is voted: reset its counters
+                __syncthreads();
+                if (tid < E) sh.ecnt[tid] = 0;
+            }
+            __syncthreads();  // run table and counters ready
+            // each thread copies the part of its own runs inside [c0, c1),
+            // keeping the detections inside the exact window
+            for (int k = 0; k < per; ++k) {
+                const int p = p0 + k;
+                if (p >= np) break;
+                const int32_t dst = pdst[p], len = pdst[p + 1] - dst;
+                const int32_t j0 = max(0, c0 - dst), j1 = min(len, c1 - dst);
+                if (j0 >= j1) continue;
+                const int e = p / R;
+                const int32_t src = psrc[p];
+                const int32_t x0 = ox + sh.es[0][e], x1 = ox + sh.es[1][e] + W;
+                const int32_t y0 = oy + sh.es[2][e], y1 = oy + sh.es[3][e] + H;
+                const int32_t b = max(pdst[e * R], c0) - c0;
+                for (int32_t jj = j0; jj < j1; jj += 8) {
+                    int2 q[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (jj + u < j1) q[u] = c.sxy[src + jj + u];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        if (jj + u < j1 && q[u].x >= x0 && q[u].x < x1 && q[u].y >= y0 &&
+                            q[u].y < y1) {
+                            const int32_t slot = atomicAdd(&sh.ecnt[e], 1);
+                            stage[b + slot] = q[u];
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+
+            // vote: wave w takes epochs w, w + NW, ...; their counts and
+            // stage offsets are read once, one per lane
+            int32_t my_n = 0, my_b = 0;
+            {
+                const int e = wave + lane * NW;
+                if (e < E) {
+                    my_n = sh.ecnt[e];
+                    my_b = max(pdst[e * R], c0) - c0;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kEpochRegs; ++k) {
+                const int e = wave + k * NW;
+                if (e >= E) break;
+                const int32_t n = __builtin_amdgcn_readlane(my_n, k);
+                if (n == 0) continue;
+                const int32_t b = __builtin_amdgcn_readlane(my_b, k);
+                vote_run<MODE, G>(stage + b, n, (uint32_t)Sx[k] + ox_lane,
+                                  (uint32_t)Sy[k] + oy_lane, kc, row_bytes, lane_addr,
+                                  MODE == kMask32 ? (1u << e) : 1u, g,
+                                  ox + sh.es[0][e] - 1, oy + sh.es[2][e] - 1);
+            }
+            for (int k = kEpochRegs; wave + k * NW < E; ++k) {
+                const int e = wave + k * NW;
+                const int32_t n = __builtin_amdgcn_readlane(my_n, k);
+                if (n == 0) continue;
+                const int32_t b = __builtin_amdgcn_readlane(my_b, k);
+                const int32_t d = sh.dt[e];
+                vote_run<MODE, G>(stage + b, n, (uint32_t)shift_q8(my_vx, d) + ox_lane,
+                                  (uint32_t)shift_q8(my_vy, d) + oy_lane, kc, row_bytes,
+                                  lane_addr, MODE == kMask32 ? (1u << e) : 1u, g,
+                                  ox + sh.es[0][e] - 1, oy + sh.es[2][e] - 1);
+            }
+        }
+        __syncthreads();
+
+        // 3. read and clear the histogram; emit or queue interior cells
+        for (int w0 = 0; w0 < hist_words / 4; w0 += T) {
+            const int w4 = w0 + tid;
+            uint4 h = make_uint4(0, 0, 0, 0);
+            if (w4 < hist_words / 4) {
+                h = smem4[w4];
+                smem4[w4] = make_uint4(0, 0, 0, 0);
+            }
+            const uint32_t m = max(max(cell_count<MODE>(h.x), cell_count<MODE>(h.y)),
+                                   max(cell_count<MODE>(h.z), cell_count<MODE>(h.w)));
+            if (!__any(m >= nmin)) continue;  // wave uniform
+            const uint32_t hw[4] = {h.x, h.y, h.z, h.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int wi = 4 * w4 + k;
+                const uint32_t cnt = cell_count<MODE>(hw[k]);
+                bool ok = false;
+                uint32_t v = 0;
+                int32_t bx = 0, by = 0;
+                if (cnt >= nmin) {
+                    const int jj = wi & (NV - 1), bin = wi >> LNV;
+                    const int iy = bin / a.hx, ix = bin - iy * a.hx;
+                    const int cx = ix - (sh.sg[jj] & 0xffff), cy = iy - (sh.sg[jj] >> 16);
+                    ok = sh.sv[jj] >= 0 && cx >= 0 && cx < a.tile_x && cy >= 0 &&
+                         cy < a.tile_y;
+                    v = (uint32_t)sh.sv[jj];
+                    bx = tx0 + cx;
+                    by = ty0 + cy;
+                }
+                if (MODE == kCountRef) {
+                    const int64_t idx = wave_append(ok, a.refine_count);
+                    if (ok && idx < a.refine_cap) a.refine[idx] = make_int4((int32_t)v, bx, by, 0);
+                } else {
+                    const int64_t idx = wave_append(ok, (unsigned long long *)&a.res->n_cand);
+                    if (ok && idx < a.cand_cap)
+                        write_cand(a.cand, idx, v, bx, by, cnt, (uint32_t)a.count_sat);
+                }
+            }
+        }
+        // the next write to the histogram comes after several barriers
+    }
+}
+
+// Dynamic LDS: histogram [HY][HX][NV] words, then the stage (int2), then the
+// run table of the window index (source offset and exclusive prefix of every
+// (epoch, row) pair).
+template <int MODE, int G>
+__global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_vote_dense(DenseArgs a) {
+    extern __shared__ uint4 smem4[];
+    __shared__ Shared sh;
+    const int tid = threadIdx.x;
+    const int hist_words = a.hx * a.hy * (64 / G);
     for (int i = tid; i < hist_words / 4; i += T) smem4[i] = make_uint4(0, 0, 0, 0);
-    if (tid < E) sh.dt[tid] = c.dt[tid];
+    if (tid < a.cat.n_epochs) sh.dt[tid] = a.cat.dt[tid];
     int parity = 0;
-
     // Workgroups are dispatched round-robin over the XCDs (each with its own
     // L2); give XCD x the logical indices [x G / 8, (x + 1) G / 8) so that the
     // workgroups resident on one XCD take neighbouring items.
     const int64_t grid = gridDim.x;  // a multiple of kXcds
     const int64_t logical = (int64_t)(blockIdx.x % kXcds) * (grid / kXcds) + blockIdx.x / kXcds;
     for (int64_t item = logical; item < a.n_items; item += grid) {
-        const int32_t sg = a.items[4 * item], ty0 = a.items[4 * item + 1];
-        const int32_t txf = a.items[4 * item + 2], ntiles = a.items[4 * item + 3];
-        const int32_t vx_lo = a.seg[4 * sg], vx_hi = a.seg[4 * sg + 1];
-        const int32_t vy_lo = a.seg[4 * sg + 2], vy_hi = a.seg[4 * sg + 3];
-        __syncthreads();  // the previous item no longer reads the segment tables
-        if (tid < NV) {
-            const int64_t o = (int64_t)sg * NV + tid;
-            sh.sv[tid] = a.seg_v[o];
-            sh.svx[tid] = a.seg_vel[2 * o];
-            sh.svy[tid] = a.seg_vel[2 * o + 1];
-            sh.sg[tid] = a.seg_guard[o];
-        }
-        if (tid < E) {  // shifts of the segment's box edges
-            const int32_t d = sh.dt[tid];
-            sh.es[0][tid] = d >= 0 ? shift_q8(vx_lo, d) : 0;
-            sh.es[1][tid] = d >= 0 ? shift_q8(vx_hi, d) : 0;
-            sh.es[2][tid] = d >= 0 ? shift_q8(vy_lo, d) : 0;
-            sh.es[3][tid] = d >= 0 ? shift_q8(vy_hi, d) : 0;
-        }
-        if (tid == 0) sh.bad = 0;
-        __syncthreads();
-        const int32_t my_vx = sh.svx[j], my_vy = sh.svy[j];
-        const int32_t my_gx = sh.sg[j] & 0xffff, my_gy = sh.sg[j] >> 16;
-        const int32_t oy = ty0 * cellw;
-        // Q8 origin of this lane's histogram row 0: (ty0 - gy) cells
-        const uint32_t oy_lane = (uint32_t)(ty0 - my_gy) * (uint32_t)cellw;
-        const uint32_t lane_addr = (uint32_t)(uintptr_t)(lds_u32 *)hist + (uint32_t)(j * 4);
+        const int32_t *it = a.items + 4 * item;
+        vote_item<MODE, G>(a, sh, smem4, it[0], it[1], it[2], it[3], parity);
+    }
+}
 
-        // Lane shifts of this wave's epochs e = wave + k NW (k < kEpochRegs),
-        // kept in registers for the whole item.  The window of any tile then
-        // lands inside every lane's histogram (tile independent; checked here).
-        int32_t Sx[kEpochRegs], Sy[kEpochRegs];
-        bool bad = false;
-#pragma unroll
-        for (int k = 0; k < kEpochRegs; ++k) {
-            const int e = wave + k * NW;
-            Sx[k] = 0;
-            Sy[k] = 0;
-            if (e < E) {
-                const int32_t d = sh.dt[e];
-                if (d >= 0) {
-                    Sx[k] = shift_q8(my_vx, d);
-                    Sy[k] = shift_q8(my_vy, d);
-                    const int64_t gxq = (int64_t)my_gx << kc, gyq = (int64_t)my_gy << kc;
-                    const int64_t lx = (int64_t)sh.es[0][e] - Sx[k] - 1 + gxq;
-                    const int64_t hx = (int64_t)sh.es[1][e] - Sx[k] + W - 1 + gxq;
-                    const int64_t ly = (int64_t)sh.es[2][e] - Sy[k] - 1 + gyq;
-                    const int64_t hy = (int64_t)sh.es[3][e] - Sy[k] + H - 1 + gyq;
-                    bad |= lx < 0 || ly < 0 || hx >= ((int64_t)a.hx << kc) ||
-                           hy >= ((int64_t)a.hy << kc);
-                }
-            }
+// Many catalogs in one persistent launch (one workgroup per resident slot):
+// the merged items (items5: chip, segment, ty0, txf, ntiles; chip-major, each
+// chip in its own L2-friendly order) are walked like the single-catalog
+// kernel walks its items, and each item reads its chip's parameters from
+// chips[].  Every chip of the launch uses this kernel's cell variant and lane
+// groups; hist_words_max covers the largest histogram among them.
+template <int MODE, int G>
+__global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_vote_dense_batch(const DenseArgs *__restrict__ chips,
+                                                         const int32_t *__restrict__ items5,
+                                                         int64_t n_items, int32_t hist_words_max) {
+    extern __shared__ uint4 smem4[];
+    __shared__ Shared sh;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < hist_words_max / 4; i += T) smem4[i] = make_uint4(0, 0, 0, 0);
+    int parity = 0, chip_now = -1;
+    const int64_t grid = gridDim.x;  // a multiple of kXcds
+    const int64_t logical = (int64_t)(blockIdx.x % kXcds) * (grid / kXcds) + blockIdx.x / kXcds;
+    for (int64_t item = logical; item < n_items; item += grid) {
+        const int32_t *it = items5 + 5 * item;
+        const int chip = it[0];
+        const DenseArgs &a = chips[chip];
+        if (chip != chip_now) {
+            __syncthreads();  // the previous item no longer reads sh.dt
+            if (tid < a.cat.n_epochs) sh.dt[tid] = a.cat.dt[tid];
+            chip_now = chip;
         }
-        for (int e = wave + kEpochRegs * NW; e < E; e += NW) {  // epochs past the registers
-            const int32_t d = sh.dt[e];
-            if (d < 0) continue;
-            const int64_t sxe = shift_q8(my_vx, d), sye = shift_q8(my_vy, d);
-            const int64_t gxq = (int64_t)my_gx << kc, gyq = (int64_t)my_gy << kc;
-            bad |= (int64_t)sh.es[0][e] - sxe - 1 + gxq < 0 ||
-                   (int64_t)sh.es[2][e] - sye - 1 + gyq < 0 ||
-                   (int64_t)sh.es[1][e] - sxe + W - 1 + gxq >= ((int64_t)a.hx << kc) ||
-                   (int64_t)sh.es[3][e] - sye + H - 1 + gyq >= ((int64_t)a.hy << kc);
-        }
-        if (bad) sh.bad = 1;
-        __syncthreads();
-        if (sh.bad) {  // excluded by the planner's guard cells; block uniform
-            if (tid == 0) atomicOr(&a.res->status, SAS_DATA_INTERNAL);
-            continue;
-        }
-
-        for (int32_t ti = 0; ti < ntiles; ++ti) {
-            const int32_t tx0 = txf + ti * a.tile_x;
-            const int32_t ox = tx0 * cellw;
-            const uint32_t ox_lane = (uint32_t)(tx0 - my_gx) * (uint32_t)cellw;
-            parity ^= 1;
-
-            // 1. exact windows and run lengths, one thread per (epoch, index row);
-            //    then a block scan lays the runs out (epoch-major)
-            int32_t lsum = 0;
-            for (int k = 0; k < per; ++k) {
-                const int p = p0 + k;
-                if (p >= np) break;
-                const int e = p / R, r = p - e * R;
-                int32_t src = 0, len = 0;
-                if (sh.dt[e] >= 0) {
-                    const int32_t xlo = ox + sh.es[0][e], xhi = ox + sh.es[1][e] + W;
-                    const int32_t ylo = oy + sh.es[2][e], yhi = oy + sh.es[3][e] + H;
-                    int cx0, cx1, cy0, cy1;
-                    if (cell_span(xlo, xhi, c.x0, c.x1, c.cell_log2, &cx0, &cx1) &&
-                        cell_span(ylo, yhi, c.y0, c.y1, c.cell_log2, &cy0, &cy1)) {
-                        if (r == 0 && cy1 - cy0 + 1 > R)  // excluded by the planner
-                            atomicOr(&a.res->status, SAS_DATA_INTERNAL);
-                        if (cy0 + r <= cy1) {
-                            const int64_t base = ((int64_t)e * c.ncy + cy0 + r) * c.ncx;
-                            src = c.off[base + cx0];
-                            len = c.off[base + cx1 + 1] - src;
-                        }
-                    }
-                }
-                psrc[p] = src;
-                pdst[p] = len;
-                lsum += len;
-            }
-            if (tid < E) sh.ecnt[tid] = 0;
-            int32_t M;
-            int32_t run = scan_block(lsum, &M, sh.wsum[parity]);
-            for (int k = 0; k < per; ++k) {
-                const int p = p0 + k;
-                if (p >= np) break;
-                const int32_t len = pdst[p];
-                pdst[p] = run;
-                run += len;
-            }
-            if (tid == 0) pdst[np] = M;
-            if (M == 0) continue;  // block uniform; nothing to vote, the histogram is clear
-            if (M > a.stage_cap && tid == 0) atomicAdd(&a.res->n_spilled, 1);
-
-            // 2. stage and vote, chunk by chunk
-            for (int32_t c0 = 0; c0 < M; c0 += a.stage_cap) {
-                const int32_t c1 = min(M, c0 + a.stage_cap);
-                if (c0 > 0) {  // the previous chunk is voted: reset its counters
-                    __syncthreads();
-                    if (tid < E) sh.ecnt[tid] = 0;
-                }
-                __syncthreads();  // run table and counters ready
-                // each thread copies the part of its own runs inside [c0, c1),
-                // keeping the detections inside the exact window
-                for (int k = 0; k < per; ++k) {
-                    const int p = p0 + k;
-                    if (p >= np) break;
-                    const int32_t dst = pdst[p], len = pdst[p + 1] - dst;
-                    const int32_t j0 = max(0, c0 - dst), j1 = min(len, c1 - dst);
-                    if (j0 >= j1) continue;
-                    const int e = p / R;
-                    const int32_t src = psrc[p];
-                    const int32_t x0 = ox + sh.es[0][e], x1 = ox + sh.es[1][e] + W;
-                    const int32_t y0 = oy + sh.es[2][e], y1 = oy + sh.es[3][e] + H;
-                    const int32_t b = max(pdst[e * R], c0) - c0;
-                    for (int32_t jj = j0; jj < j1; jj += 8) {
-                        int2 q[8];
-#pragma unroll
-                        for (int u = 0; u < 8; ++u)
-                            if (jj + u < j1) q[u] = c.sxy[src + jj + u];
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) {
-                            if (jj + u < j1 && q[u].x >= x0 && q[u].x < x1 && q[u].y >= y0 &&
-                                q[u].y < y1) {
-                                const int32_t slot = atomicAdd(&sh.ecnt[e], 1);
-                                stage[b + slot] = q[u];
-                            }
-                        }
-                    }
-                }
-                __syncthreads();
-
-                // vote: wave w takes epochs w, w + NW, ...; their counts and
-                // stage offsets are read once, one per lane
-                int32_t my_n = 0, my_b = 0;
-                {
-                    const int e = wave + lane * NW;
-                    if (e < E) {
-                        my_n = sh.ecnt[e];
-                        my_b = max(pdst[e * R], c0) - c0;
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < kEpochRegs; ++k) {
-                    const int e = wave + k * NW;
-                    if (e >= E) break;
-                    const int32_t n = __builtin_amdgcn_readlane(my_n, k);
-                    if (n == 0) continue;
-                    const int32_t b = __builtin_amdgcn_readlane(my_b, k);
-                    vote_run<MODE, G>(stage + b, n, (uint32_t)Sx[k] + ox_lane,
-                                      (uint32_t)Sy[k] + oy_lane, kc, row_bytes, lane_addr,
-                                      MODE == kMask32 ? (1u << e) : 1u, g,
-                                      ox + sh.es[0][e] - 1, oy + sh.es[2][e] - 1);
-                }
-                for (int k = kEpochRegs; wave + k * NW < E; ++k) {
-                    const int e = wave + k * NW;
-                    const int32_t n = __builtin_amdgcn_readlane(my_n, k);
-                    if (n == 0) continue;
-                    const int32_t b = __builtin_amdgcn_readlane(my_b, k);
-                    const int32_t d = sh.dt[e];
-                    vote_run<MODE, G>(stage + b, n, (uint32_t)shift_q8(my_vx, d) + ox_lane,
-                                      (uint32_t)shift_q8(my_vy, d) + oy_lane, kc, row_bytes,
-                                      lane_addr, MODE == kMask32 ? (1u << e) : 1u, g,
-                                      ox + sh.es[0][e] - 1, oy + sh.es[2][e] - 1);
-                }
-            }
-            __syncthreads();
-
-            // 3. read and clear the histogram; emit or queue interior cells
-            for (int w0 = 0; w0 < hist_words / 4; w0 += T) {
-                const int w4 = w0 + tid;
-                uint4 h = make_uint4(0, 0, 0, 0);
-                if (w4 < hist_words / 4) {
-                    h = smem4[w4];
-                    smem4[w4] = make_uint4(0, 0, 0, 0);
-                }
-                const uint32_t m = max(max(cell_count<MODE>(h.x), cell_count<MODE>(h.y)),
-                                       max(cell_count<MODE>(h.z), cell_count<MODE>(h.w)));
-                if (!__any(m >= nmin)) continue;  // wave uniform
-                const uint32_t hw[4] = {h.x, h.y, h.z, h.w};
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int wi = 4 * w4 + k;
-                    const uint32_t cnt = cell_count<MODE>(hw[k]);
-                    bool ok = false;
-                    uint32_t v = 0;
-                    int32_t bx = 0, by = 0;
-                    if (cnt >= nmin) {
-                        const int jj = wi & (NV - 1), bin = wi >> LNV;
-                        const int iy = bin / a.hx, ix = bin - iy * a.hx;
-                        const int cx = ix - (sh.sg[jj] & 0xffff), cy = iy - (sh.sg[jj] >> 16);
-                        ok = sh.sv[jj] >= 0 && cx >= 0 && cx < a.tile_x && cy >= 0 &&
-                             cy < a.tile_y;
-                        v = (uint32_t)sh.sv[jj];
-                        bx = tx0 + cx;
-                        by = ty0 + cy;
-                    }
-                    if (MODE == kCountRef) {
-                        const int64_t idx = wave_append(ok, a.refine_count);
-                        if (ok && idx < a.refine_cap) a.refine[idx] = make_int4((int32_t)v, bx, by, 0);
-                    } else {
-                        const int64_t idx = wave_append(ok, (unsigned long long *)&a.res->n_cand);
-                        if (ok && idx < a.cand_cap)
-                            write_cand(a.cand, idx, v, bx, by, cnt, (uint32_t)a.count_sat);
-                    }
-                }
-            }
-            // the next write to the histogram comes after several barriers
-        }
+        vote_item<MODE, G>(a, sh, smem4, it[1], it[2], it[3], it[4], parity);
     }
 }
 
@@ -536,26 +577,26 @@ __global__ void __launch_bounds__(T) k_refine(DenseArgs a) {
 }
 
 template <int MODE, int G>
+hipError_t set_lds_limit(const void *fn, size_t lds, size_t *lds_set) {
+    if (lds > 65536 && lds > *lds_set) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        *lds_set = lds;
+    }
+    return hipSuccess;
+}
+
+template <int MODE, int G>
 hipError_t launch_mg(const DenseArgs &a, size_t lds, hipStream_t stream, hipEvent_t ev0,
                      hipEvent_t ev1) {
     static size_t lds_set = 0;  // dynamic LDS limit raised so far for this kernel
-    if (lds > 65536 && lds > lds_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_vote_dense<MODE, G>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        lds_set = lds;
-    }
+    hipError_t e = set_lds_limit<MODE, G>((const void *)k_vote_dense<MODE, G>, lds, &lds_set);
+    if (e != hipSuccess) return e;
     const int64_t want = a.n_items < kMaxVoteGrid ? a.n_items : kMaxVoteGrid;
     const dim3 grid((unsigned)((want + kXcds - 1) / kXcds * kXcds)), block(T);
-    if (ev0) {
-        hipError_t e = hipEventRecord(ev0, stream);
-        if (e != hipSuccess) return e;
-    }
+    if (ev0 && (e = hipEventRecord(ev0, stream)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_vote_dense<MODE, G>), grid, block, lds, stream, a);
-    if (ev1) {
-        hipError_t e = hipEventRecord(ev1, stream);
-        if (e != hipSuccess) return e;
-    }
+    if (ev1 && (e = hipEventRecord(ev1, stream)) != hipSuccess) return e;
     if (MODE == kCountRef)
         hipLaunchKernelGGL(k_refine, dim3(kRefineGrid), block, 0, stream, a);
     return hipGetLastError();
@@ -571,6 +612,27 @@ hipError_t launch_m(int groups, const DenseArgs &a, size_t lds, hipStream_t s, h
     }
 }
 
+template <int MODE, int G>
+hipError_t launch_batch_mg(const DenseArgs *chips, const int32_t *items5, int64_t n_items,
+                           int32_t hist_words_max, size_t lds, int grid, hipStream_t stream) {
+    static size_t lds_set = 0;
+    hipError_t e = set_lds_limit<MODE, G>((const void *)k_vote_dense_batch<MODE, G>, lds, &lds_set);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_vote_dense_batch<MODE, G>), dim3(grid), dim3(T), lds, stream, chips,
+                       items5, n_items, hist_words_max);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_batch_m(int groups, const DenseArgs *chips, const int32_t *items5,
+                          int64_t n_items, int32_t hwm, size_t lds, int grid, hipStream_t s) {
+    switch (groups) {
+    case 1: return launch_batch_mg<MODE, 1>(chips, items5, n_items, hwm, lds, grid, s);
+    case 2: return launch_batch_mg<MODE, 2>(chips, items5, n_items, hwm, lds, grid, s);
+    default: return launch_batch_mg<MODE, 4>(chips, items5, n_items, hwm, lds, grid, s);
+    }
+}
+
 }  // namespace
 
 size_t dense_lds_bytes(int groups, int hx, int hy, int stage_cap, int max_pairs) {
@@ -581,6 +643,30 @@ size_t dense_lds_bytes(int groups, int hx, int hy, int stage_cap, int max_pairs)
 }
 
 size_t dense_static_lds_bytes() { return sizeof(Shared); }
+
+hipError_t launch_vote_dense_batch(int mode, int groups, const DenseArgs *chips_dev,
+                                   const int32_t *items5_dev, int64_t n_items,
+                                   int32_t hist_words_max, size_t lds, int grid,
+                                   hipStream_t stream) {
+    if (n_items <= 0) return hipSuccess;
+    grid = (grid + kXcds - 1) / kXcds * kXcds;
+    switch (mode) {
+    case kMask32:
+        return launch_batch_m<kMask32>(groups, chips_dev, items5_dev, n_items, hist_words_max,
+                                       lds, grid, stream);
+    case kCountDet:
+        return launch_batch_m<kCountDet>(groups, chips_dev, items5_dev, n_items, hist_words_max,
+                                         lds, grid, stream);
+    default:
+        return launch_batch_m<kCountRef>(groups, chips_dev, items5_dev, n_items, hist_words_max,
+                                         lds, grid, stream);
+    }
+}
+
+hipError_t launch_refine(const DenseArgs &a, hipStream_t stream) {
+    hipLaunchKernelGGL(k_refine, dim3(kRefineGrid), dim3(T), 0, stream, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_vote_dense(int mode, int groups, const DenseArgs &a, hipStream_t stream,
                              hipEvent_t ev0, hipEvent_t ev1) {

@@ -54,6 +54,12 @@ class Tuning(ctypes.Structure):
                 ("refine_cap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class BatchChip(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("x_q8", ctypes.c_void_p), ("y_q8", ctypes.c_void_p),
+                ("epoch", ctypes.c_void_p), ("n", ctypes.c_int64), ("cand_dev", ctypes.c_void_p),
+                ("cand_cap", ctypes.c_int64), ("res_dev", ctypes.c_void_p)]
+
+
 class PlanDesc(ctypes.Structure):
     _fields_ = [("v_host", ctypes.c_void_p), ("n_v", ctypes.c_int64),
                 ("n_epochs", ctypes.c_int32), ("t_q16", ctypes.c_void_p),
@@ -79,7 +85,9 @@ _lib = None
 
 EXPORTS = ["sas_status_string", "sas_last_error", "sas_version", "sas_grid_spacing",
            "sas_build_grid", "sas_plan_create", "sas_plan_destroy", "sas_plan_get_info",
-           "sas_plan_set_probe", "sas_vote_workspace_size", "sas_vote", "sas_peaks"]
+           "sas_plan_set_probe", "sas_vote_workspace_size", "sas_vote", "sas_peaks",
+           "sas_threshold_n_min", "sas_batch_workspace_size", "sas_batch_create",
+           "sas_batch_destroy", "sas_vote_batch", "sas_batch_set_probe"]
 
 
 def load():
@@ -105,6 +113,13 @@ def load():
         "sas_vote_workspace_size": (I32, [P, I64, P]),
         "sas_vote": (I32, [P, P, P, P, I64, P, I64, P, P, SZ, P]),
         "sas_peaks": (I32, [P, P, I64, I32, I64, P, I64, P, P]),
+        "sas_threshold_n_min": (I32, [I32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      I32, P]),
+        "sas_batch_workspace_size": (I32, [P, I32, P]),
+        "sas_batch_create": (I32, [P, I32, P, SZ, P]),
+        "sas_batch_destroy": (I32, [P]),
+        "sas_vote_batch": (I32, [P, P]),
+        "sas_batch_set_probe": (I32, [P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -156,6 +171,15 @@ def grid_from_spec(spec, binw_q8: int, span_q16: int) -> np.ndarray:
     """Grid of a ``synth.GridSpec``-like object (shape, vmin, vmax, ...)."""
     return build_grid(spec.shape, spec.vmin, spec.vmax, spec.vy_min, spec.vy_max,
                       spec.angle_deg, spec.half_width_deg, binw_q8, span_q16)
+
+
+def threshold_n_min(n_epochs: int, mu: float, n_stacks: float, n_false: float = 100.0,
+                    mode: str = "epochs") -> int:
+    """The threshold rule of Sec. 2.2 (sas_threshold_n_min)."""
+    out = ctypes.c_int32()
+    _check(load().sas_threshold_n_min(int(n_epochs), float(mu), float(n_stacks), float(n_false),
+                                      MODES[mode], ctypes.byref(out)))
+    return out.value
 
 
 # --------------------------------------------------------------------------- plans
@@ -282,3 +306,56 @@ class Search:
         x, y, e = self.upload(x_q8, y_q8, epoch)
         self.vote(x, y, e)
         return self.peaks(order, top_k)
+
+
+class Batch:
+    """Many catalogs voted by one persistent launch per kernel class.
+
+    chips: list of (plan, x, y, epoch) with device tensors; each chip gets
+    its own candidate buffer and result."""
+
+    def __init__(self, chips, cand_cap: int = 1 << 18, device="cuda"):
+        import torch
+        lib = load()
+        self.plans = [c[0] for c in chips]
+        self.tensors = []
+        self.cand = []
+        self.res = []
+        arr = (BatchChip * len(chips))()
+        for k, (plan, x, y, e) in enumerate(chips):
+            cand = torch.empty((max(int(cand_cap), 1), 4), dtype=torch.int32, device=device)
+            res = torch.zeros(4, dtype=torch.int32, device=device)
+            self.tensors.append((x, y, e))
+            self.cand.append(cand)
+            self.res.append(res)
+            arr[k] = BatchChip(plan.handle.value, x.data_ptr(), y.data_ptr(), e.data_ptr(),
+                               int(x.numel()), cand.data_ptr(), cand.shape[0], res.data_ptr())
+        self._arr = arr
+        size = ctypes.c_size_t()
+        _check(lib.sas_batch_workspace_size(ctypes.byref(arr), len(chips), ctypes.byref(size)))
+        self.ws = torch.empty(max(size.value, 256), dtype=torch.uint8, device=device)
+        self._b = ctypes.c_void_p()
+        _check(lib.sas_batch_create(ctypes.byref(arr), len(chips), self.ws.data_ptr(),
+                                    self.ws.numel(), ctypes.byref(self._b)))
+
+    def vote(self, stream=None):
+        _check(load().sas_vote_batch(self._b, _stream_handle(stream)))
+
+    def set_probe(self, ev_before=None, ev_after=None):
+        h0 = ctypes.c_void_p(ev_before.cuda_event) if ev_before is not None else None
+        h1 = ctypes.c_void_p(ev_after.cuda_event) if ev_after is not None else None
+        _check(load().sas_batch_set_probe(self._b, h0, h1))
+
+    def peaks(self, k: int, order="canonical", top_k=0, stream=None):
+        return peaks(self.cand[k], self.res[k], order, top_k, stream)
+
+    def close(self):
+        if self._b:
+            load().sas_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -96,3 +96,36 @@ def _plan_error(**over):
 ])
 def test_plan_argument_errors(over, status):
     assert _plan_error(**over) == status
+
+
+@pytest.mark.parametrize("n_epochs,mu,n_stacks,mode", [
+    (60, 0.0916, 1.23e6 * 32768, "epochs"),
+    (100, 0.0057, 84351 * 524288, "epochs"),
+    (20, 0.02, 441 * 16384, "epochs"),
+    (40, 0.3, 1e9, "epochs"),
+    (120, 0.001, 1e11, "epochs"),
+    (60, 0.0916, 1e10, "detections"),
+    (100, 0.0057, 4.4e10, "detections"),
+])
+def test_threshold_rule_matches_oracle(n_epochs, mu, n_stacks, mode):
+    from oracle import params as oparams
+    assert sas.threshold_n_min(n_epochs, mu, n_stacks, 100.0, mode) == \
+        oparams.choose_n_min(n_epochs, mu, n_stacks, 100.0, mode)
+
+
+def test_threshold_rule_edges():
+    from oracle import params as oparams
+    with pytest.raises(sas.SasError):
+        sas.threshold_n_min(0, 0.1, 1e6)
+    # every count up to E is too frequent: the rule answers E + 1, unreachable
+    assert sas.threshold_n_min(10, 5.0, 1e30) == oparams.choose_n_min(10, 5.0, 1e30) == 11
+    assert sas.threshold_n_min(10, 0.0, 1e30) == 1
+
+
+def test_batch_argument_errors():
+    lib = sas.load()
+    size = ctypes.c_size_t()
+    assert lib.sas_batch_workspace_size(None, 0, ctypes.byref(size)) == sas.SAS_E_INVALID
+    arr = (sas.BatchChip * 1)()
+    assert lib.sas_batch_workspace_size(ctypes.byref(arr), 1, ctypes.byref(size)) == \
+        sas.SAS_E_INVALID  # null plan

@@ -318,3 +318,74 @@ def test_sort_and_dense_agree_on_fast_sample(gpu):
                              path=path, tuning=dict(n_det_hint=wl.n))
     assert len(out["dense"]) > 0
     assert_same(out["sort"], out["dense"])
+
+
+# ---------------------------------------------------------------- batched launch
+
+def _night_chips(n_chips, scale):
+    """Chips of the batched night (sizes scaled down for test time)."""
+    import torch
+    out = []
+    for p in synth.night_chip_params(4, n_chips):
+        p = dict(p)
+        p["n_det"] = max(2000, int(p["n_det"] * scale))
+        wl = synth.make_night_chip(p, synth.FAST_N_MIN)
+        v = _grid(wl)
+        if wl.bin_px > 4:  # fast style: a seeded part of the disk grid keeps the test short
+            v = v[_sampled_velocities(v, 60000, p["chip"])]
+        plan = sas.Plan(v, wl.t_q16, wl.binw_q8, wl.n_min, wl.extent_q8,
+                        tuning=dict(n_det_hint=wl.n))
+        x = torch.as_tensor(wl.x_q8).cuda()
+        y = torch.as_tensor(wl.y_q8).cuda()
+        e = torch.as_tensor(wl.epoch).cuda()
+        out.append((wl, v, plan, x, y, e))
+    return out
+
+
+def test_batch_matches_single_chip_votes(gpu):
+    chips = _night_chips(6, 0.1)
+    styles = {wl.bin_px for wl, *_ in chips}
+    assert len(styles) == 2  # both styles present
+    b = sas.Batch([(plan, x, y, e) for _, _, plan, x, y, e in chips], cand_cap=1 << 20)
+    b.vote()
+    for k, (wl, v, plan, x, y, e) in enumerate(chips):
+        _say(f"batch chip {k} {wl.name} n={wl.n} E={wl.n_epochs} |V|={len(v)}")
+        got = b.peaks(k)
+        s = sas.Search(plan, wl.n, cand_cap=1 << 20)
+        s.vote(x, y, e)
+        assert_same(got, s.peaks())
+        if k < 2:  # and against the oracle on a velocity sample
+            idx = np.union1d(_sampled_velocities(v, 16, 3), np.unique(got["v_idx"])[:16])
+            o = oracle.vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v[idx], wl.binw_q8, wl.n_min,
+                            "epochs", 65535)
+            o["v_idx"] = idx[o["v_idx"]]
+            assert_same(got[np.isin(got["v_idx"], idx)], o)
+    b.close()
+    for c in chips:
+        c[2].close()
+
+
+def test_batch_graph_replays(gpu):
+    import torch
+    chips = _night_chips(4, 0.05)
+    b = sas.Batch([(plan, x, y, e) for _, _, plan, x, y, e in chips], cand_cap=1 << 20)
+    b.vote()
+    eager = [b.peaks(k) for k in range(len(chips))]
+    assert sum(len(r) for r in eager) > 0
+    stream = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=stream):
+        b.vote(stream=torch.cuda.current_stream())
+    for rep in range(3):
+        _say(f"graph replay {rep}")
+        for r in b.res:  # eager work between replays
+            r.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k in range(len(chips)):
+            assert_same(b.peaks(k), eager[k])
+    b.close()
+    for c in chips:
+        c[2].close()
