@@ -7,6 +7,11 @@ canonical order).  Default workload: the wide-field chip (2048x4096 px,
 100 epochs over 4 h, 3000 noise detections per epoch plus 200 movers, 4 px
 bins, sector grid of 84,351 velocities, N_min = 25).
 
+--workload night runs the batched night instead: 64 chips (seeded wide or
+fast style, 5e4-5e5 detections, 40-120 epochs, each with its own grid and
+threshold) voted by one batched launch per kernel class, with launch shapes
+chosen by the autotuner per chip style.
+
 Prints one JSON line (rank 0).  --gpus above 1 is refused: this build
 measures one GPU.
 """
@@ -41,6 +46,96 @@ OPS_PER_VOTE = 6
 VOTE_KERNEL = "k_vote_dense"
 
 
+def _night(n_chips, tune, log):
+    """The batched night: chips with their own plans, thresholds and
+    autotuned launch shapes (one tuning per chip style)."""
+    import torch
+
+    from paper_2509_26279_amd import autotune, sas, synth
+    chips, tuned = [], {}
+    for p in synth.night_chip_params(4, n_chips):
+        wl = synth.make_night_chip(p, 0)
+        v = sas.grid_from_spec(wl.grid, wl.binw_q8, wl.span_q16)
+        n_min = wl.n_min
+        if p["style"] == "fast":  # threshold rule of Sec. 2.2 for this chip
+            area = float(wl.width_px * wl.height_px)
+            mu = wl.n / wl.n_epochs * wl.bin_px ** 2 / area
+            n_min = sas.threshold_n_min(wl.n_epochs, mu, len(v) * area / wl.bin_px ** 2)
+        x = torch.as_tensor(wl.x_q8).cuda()
+        y = torch.as_tensor(wl.y_q8).cuda()
+        e = torch.as_tensor(wl.epoch).cuda()
+        if tune and p["style"] not in tuned:
+            log("tuning the %s style on chip %d" % (p["style"], p["chip"]))
+            r = autotune.tune(v, wl.t_q16, wl.binw_q8, n_min, wl.extent_q8, x, y, e,
+                              cands=[{}, {"groups": 1}, {"groups": 2}, {"groups": 4}],
+                              log=log)
+            tuned[p["style"]] = r["tuning"]
+        tun = dict(tuned.get(p["style"], {}), n_det_hint=wl.n)
+        plan = sas.Plan(v, wl.t_q16, wl.binw_q8, n_min, wl.extent_q8, tuning=tun)
+        chips.append({"wl": wl, "v": v, "plan": plan, "x": x, "y": y, "e": e, "n_min": n_min,
+                      "style": p["style"]})
+    return chips, tuned
+
+
+def run_night(args):
+    import numpy as np
+    import torch
+
+    from paper_2509_26279_amd import sas
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    chips, tuned = _night(args.chips, not args.no_tune, log)
+    b = sas.Batch([(c["plan"], c["x"], c["y"], c["e"]) for c in chips], cand_cap=1 << 21)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        b.vote()
+        for k in range(len(chips)):
+            b.peaks(k)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    for a, z in evs:
+        a.record(stream)
+        z.record(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_cand = 0
+    for k in range(args.steps):
+        b.set_probe(evs[k][0], evs[k][1])
+        b.vote()
+        n_cand = sum(len(b.peaks(c)) for c in range(len(chips)))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    b.set_probe(None, None)
+    kernel_ms = float(np.mean([a.elapsed_time(z) for a, z in evs]))
+    ms_step = wall * 1000.0 / args.steps
+    votes = float(sum(c["wl"].n * len(c["v"]) for c in chips))
+    achieved = OPS_PER_VOTE * votes / (kernel_ms * 1e-3) / 1e12
+    n_fast = sum(c["style"] == "fast" for c in chips)
+    rec = {
+        "metric": "detection-velocity votes/s per chip", "value": votes / (ms_step * 1e-3),
+        "unit": "votes/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "night: %d chips (%d wide-style, %d fast-style), detections "
+                               "log-uniform 5e4-5e5, 40-120 epochs, one batched launch"
+                               % (len(chips), len(chips) - n_fast, n_fast),
+                   "n_detections": int(sum(c["wl"].n for c in chips)),
+                   "votes": votes, "parallelism": "single-gpu"},
+        "candidates_per_s": n_cand / (ms_step * 1e-3), "n_candidates": n_cand,
+        "vote_kernels_ms": kernel_ms, "tuned": tuned,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": INT_PEAK_TOPS,
+                     "unit": "Tops/s", "frac": achieved / INT_PEAK_TOPS, "traffic": None,
+                     "kernel": "k_vote_dense_batch", "ops_per_vote": OPS_PER_VOTE},
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(chips[0]["wl"], chips[0]["v"], args.cpu_seconds,
+                                           chips[0]["n_min"])
+    b.close()
+    for c in chips:
+        c["plan"].close()
+    print(json.dumps(rec), flush=True)
+
+
 def _workload(name):
     from paper_2509_26279_amd import synth
     if name == "wide":
@@ -73,7 +168,7 @@ def _traffic(workload):
     return t.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(wl, v, seconds):
+def cpu_baseline(wl, v, seconds, n_min=None):
     """The oracle as it stands, on the host cores, over a seeded velocity sample."""
     import numpy as np
 
@@ -84,13 +179,14 @@ def cpu_baseline(wl, v, seconds):
     rng = np.random.default_rng(0)
     probe = np.sort(rng.choice(len(v), size=min(threads, len(v)), replace=False))
     t0 = time.perf_counter()
-    oracle.vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v[probe], wl.binw_q8, wl.n_min,
+    n_min = wl.n_min if n_min is None else n_min
+    oracle.vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v[probe], wl.binw_q8, n_min,
                 "epochs", 255, threads=threads)
     dt = time.perf_counter() - t0
     k = int(max(threads, min(len(v), threads * round(seconds / max(dt, 1e-3)))))
     sample = np.sort(rng.choice(len(v), size=k, replace=False))
     t0 = time.perf_counter()
-    c = oracle.vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v[sample], wl.binw_q8, wl.n_min,
+    c = oracle.vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v[sample], wl.binw_q8, n_min,
                     "epochs", 255, threads=threads)
     dt = time.perf_counter() - t0
     return {"value": wl.n * k / dt, "unit": "votes/s", "cores": threads, "kind": "oracle",
@@ -107,11 +203,17 @@ def main():
     ap.add_argument("--workload", default="wide")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--chips", type=int, default=64, help="night workload: number of chips")
+    ap.add_argument("--no-tune", action="store_true", help="night workload: planner defaults")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; --gpus %d is not supported by this build" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "night":
+        run_night(args)
+        return
 
     import numpy as np
     import torch

@@ -129,3 +129,18 @@ def test_batch_argument_errors():
     arr = (sas.BatchChip * 1)()
     assert lib.sas_batch_workspace_size(ctypes.byref(arr), 1, ctypes.byref(size)) == \
         sas.SAS_E_INVALID  # null plan
+
+
+def test_autotune_classes_and_cache(tmp_path):
+    from paper_2509_26279_amd import autotune
+    k1 = autotune.shape_class(1024, 256, 100, 309460, "sector")
+    assert k1 == autotune.shape_class(1024, 256, 127, 300000, "sector")
+    assert k1 != autotune.shape_class(1024, 256, 128, 300000, "sector")
+    assert k1 != autotune.shape_class(4096, 2048, 100, 309460, "disk")
+    cands = autotune.candidates({"n_det_hint": 5})
+    assert {} not in cands and all(c["n_det_hint"] == 5 for c in cands)
+    assert {c.get("groups") for c in cands} == {None, 1, 2, 4}
+    p = str(tmp_path / "tune.json")
+    assert autotune.load_cache(p) == {}
+    autotune.save_cache(p, {k1: {"tuning": {"groups": 1}, "ms": 1.0}})
+    assert autotune.load_cache(p)[k1]["tuning"] == {"groups": 1}

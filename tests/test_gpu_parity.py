@@ -389,3 +389,27 @@ def test_batch_graph_replays(gpu):
     b.close()
     for c in chips:
         c[2].close()
+
+
+# ---------------------------------------------------------------- autotuner
+
+def test_autotuner_keeps_outputs(gpu):
+    """The tuner times several launch shapes of the tiny workload, requires
+    identical candidate lists from all of them, and returns the fastest."""
+    import torch
+    from paper_2509_26279_amd import autotune
+    wl = synth.make_tiny()
+    v = _grid(wl)
+    x = torch.as_tensor(wl.x_q8).cuda()
+    y = torch.as_tensor(wl.y_q8).cuda()
+    e = torch.as_tensor(wl.epoch).cuda()
+    cands = [dict(), dict(groups=1, tile_x=8, tile_y=8), dict(groups=4, tile_x=16, tile_y=12),
+             dict(groups=2, tile_x=12, tile_y=10, stage_cap=64)]
+    r = autotune.tune(v, wl.t_q16, wl.binw_q8, wl.n_min, wl.extent_q8, x, y, e,
+                      count_sat=255, cands=cands)
+    assert r["tuning"] in cands
+    assert all(t["ms"] is not None and t["ms"] >= r["ms"] for t in r["table"])
+    o = oracle.vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v, wl.binw_q8, wl.n_min, "epochs", 255)
+    g = gpu_vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v, wl.binw_q8, wl.n_min, "epochs", 255,
+                 wl.extent_q8, tuning=r["tuning"])
+    assert_same(g, o)
