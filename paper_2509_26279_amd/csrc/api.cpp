@@ -147,7 +147,7 @@ sas_status upload(sas_plan *p, T **dst, const std::vector<T> &src) {
 }
 
 struct WsLayout {
-    size_t count, blocksum, cellid, rank, sxy, present, dt, refine_count, refine;
+    size_t count, blocksum, cellid, rank, sxy, sidx, present, dt, refine_count, refine;
     size_t keys, keys_alt, hist, hist_blocksum;  // sort path
     size_t total;
 };
@@ -163,6 +163,7 @@ WsLayout ws_layout(const sas_plan *p, int64_t n) {
     L.cellid = o; o = align_up(o + sizeof(int32_t) * nn);
     L.rank = o; o = align_up(o + sizeof(int32_t) * nn);
     L.sxy = o; o = align_up(o + 2 * sizeof(int32_t) * nn);
+    L.sidx = o; o = align_up(o + sizeof(int32_t) * nn);
     L.present = o; o = align_up(o + sizeof(int32_t) * kMaxEpochs);
     L.dt = o; o = align_up(o + sizeof(int32_t) * kMaxEpochs);
     L.refine_count = o; o = align_up(o + sizeof(unsigned long long));
@@ -187,6 +188,7 @@ PrepBuffers prep_buffers(const WsLayout &L, char *w) {
     pb.cellid = (int32_t *)(w + L.cellid);
     pb.rank = (int32_t *)(w + L.rank);
     pb.sxy = (int2 *)(w + L.sxy);
+    pb.sidx = (int32_t *)(w + L.sidx);
     pb.present = (int32_t *)(w + L.present);
     pb.dt = (int32_t *)(w + L.dt);
     pb.refine_count = (unsigned long long *)(w + L.refine_count);
@@ -197,6 +199,7 @@ DenseArgs dense_args(const sas_plan *p, const WsLayout &L, char *w, const PrepBu
                      sas_candidate *cand, int64_t cand_cap, sas_vote_result *res) {
     DenseArgs a{};
     a.cat.sxy = pb.sxy;
+    a.cat.sidx = pb.sidx;
     a.cat.off = pb.count;
     a.cat.dt = pb.dt;
     a.cat.n_epochs = p->n_epochs;

@@ -27,6 +27,7 @@ enum DenseMode : int {
 // Catalog after preparation: detections grouped by (epoch, cell row, cell column).
 struct PreparedCatalog {
     const int2 *sxy;      // [n_valid] (x, y), Q8
+    const int32_t *sidx;  // [n_valid] catalog index of each detection
     const int32_t *off;   // [n_cells + 1] CSR offsets; cell = (e * ncy + cy) * ncx + cx
     const int32_t *dt;    // [E] t[e] - t0, Q16 h; -1 for epochs without detections
     int32_t n_epochs;
@@ -67,6 +68,7 @@ struct PrepBuffers {
     int32_t *cellid;    // [n]
     int32_t *rank;      // [n]
     int2 *sxy;          // [n]
+    int32_t *sidx;      // [n] catalog index of each sorted detection
     int32_t *present;   // [E]
     int32_t *dt;        // [E]
     unsigned long long *refine_count;
