@@ -296,6 +296,28 @@ sas_status sas_vote_batch(const sas_batch *batch, void *stream);
 sas_status sas_batch_set_probe(sas_batch *batch, void *ev_before, void *ev_after);
 
 /* ------------------------------------------------------------------------
+ * Learned vetting: candidate features.
+ * ---------------------------------------------------------------------- */
+#define SAS_N_FEATURES 32
+
+/*
+ * sas_features: 32 float features per candidate for vetting (no paper
+ * definition exists; the list is in the library's documentation: coverage,
+ * time extent, longest epoch run, velocity, SNR statistics, residuals of
+ * the projected positions inside the bin with their per-time-slice means
+ * and their slope against time, time-slice fractions, shared epochs).
+ *   workspace: the workspace of the last sas_vote of this plan on this
+ *              catalog (n detections): its window index is read.
+ *   snr_dev:   device [n] float SNR by catalog index, or NULL (zeros).
+ *   cand_dev:  device [n_cand] candidates of this plan (exact bins).
+ *   feat_dev:  device [n_cand][32] float, row-major.
+ * Asynchronous, no allocation.  Errors: SAS_E_INVALID, SAS_E_WORKSPACE.
+ */
+sas_status sas_features(const sas_plan *plan, const void *workspace, size_t ws_bytes, int64_t n,
+                        const float *snr_dev, const sas_candidate *cand_dev, int64_t n_cand,
+                        float *feat_dev, void *stream);
+
+/* ------------------------------------------------------------------------
  * Peaks: collect the candidates of a finished vote in a deterministic order.
  * ---------------------------------------------------------------------- */
 #define SAS_ORDER_CANONICAL 0 /* (v_idx, by, bx) ascending */

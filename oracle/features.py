@@ -49,20 +49,17 @@ def reference_dt(t_q16, epoch, n_epochs):
     return np.where(present, t - t0, -1).astype(np.int64)
 
 
-def _floor_div(a, b):
-    return a // b  # Python integers: floor division
-
-
 def candidate_features(x_q8, y_q8, epoch, snr, t_q16, v_q8, binw_q8, cand, vmax_q8=None):
     """[n_cand, 32] float64 features of the candidates (records with v_idx,
     bx, by), following the definitions above."""
-    x = [int(a) for a in np.asarray(x_q8)]
-    y = [int(a) for a in np.asarray(y_q8)]
-    ep = [int(a) for a in np.asarray(epoch)]
+    xa = np.asarray(x_q8, dtype=np.int64)
+    ya = np.asarray(y_q8, dtype=np.int64)
+    ea = np.asarray(epoch, dtype=np.int64)
     sn = np.asarray(snr, dtype=np.float64)
     t = np.asarray(t_q16, dtype=np.int64)
     E = int(t.shape[0])
-    d = reference_dt(t, ep, E)
+    d = reference_dt(t, ea, E)
+    di_all = d[ea]  # d of each detection
     D = max(int(t.max() - t.min()), 1)
     v = np.asarray(v_q8, dtype=np.int64)
     if vmax_q8 is None:
@@ -73,16 +70,17 @@ def candidate_features(x_q8, y_q8, epoch, snr, t_q16, v_q8, binw_q8, cand, vmax_
     for k, c in enumerate(cand):
         vx, vy = int(v[int(c["v_idx"]), 0]), int(v[int(c["v_idx"]), 1])
         bx, by = int(c["bx"]), int(c["by"])
+        # exact bins of every detection (int64 holds 65536 x - v d exactly;
+        # // is floor division), then the contributors one by one
+        nx_all = 65536 * xa - vx * di_all
+        ny_all = 65536 * ya - vy * di_all
+        hit = np.nonzero((nx_all // (65536 * b) == bx) & (ny_all // (65536 * b) == by))[0]
         rows = []  # (epoch, d, r_x, r_y, snr)
-        for i in range(len(x)):
-            di = int(d[ep[i]])
-            nx = 65536 * x[i] - vx * di
-            ny = 65536 * y[i] - vy * di
-            if _floor_div(nx, 65536 * b) != bx or _floor_div(ny, 65536 * b) != by:
-                continue
+        for i in hit:
+            nx, ny = int(nx_all[i]), int(ny_all[i])
             rx = nx / (65536.0 * b) - bx - 0.5
             ry = ny / (65536.0 * b) - by - 0.5
-            rows.append((ep[i], di, rx, ry, float(sn[i])))
+            rows.append((int(ea[i]), int(di_all[i]), rx, ry, float(sn[i])))
         f = out[k]
         n = len(rows)
         if n == 0:
@@ -116,7 +114,7 @@ def candidate_features(x_q8, y_q8, epoch, snr, t_q16, v_q8, binw_q8, cand, vmax_
         tau = [r[1] / D for r in rows]
         mt = sum(tau) / n
         stt = sum((a - mt) ** 2 for a in tau)
-        if stt > 0:
+        if len({r[1] for r in rows}) > 1:  # not all d equal (exact, on the integers)
             f[16] = sum((a - mt) * (bq - mx) for a, bq in zip(tau, rx)) / stt
             f[17] = sum((a - mt) * (bq - my) for a, bq in zip(tau, ry)) / stt
         for sl in range(4):

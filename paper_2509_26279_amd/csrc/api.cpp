@@ -119,6 +119,7 @@ struct sas_plan {
     int32_t *d_seg_guard = nullptr, *d_items = nullptr;
     std::vector<int32_t> h_items;  // host copy of the work items
     double footprint_cells = 1.0;  // cells of the footprint (batch cost estimates)
+    double vmax = 0.0;             // largest |v| of the grid, Q8 px/h
     // sort path
     std::vector<SortBlock> sort_blocks;
     int64_t sort_max_nv = 0;
@@ -719,6 +720,9 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     if ((st = upload(p.get(), &p->d_seg_guard, seg_guard)) != SAS_OK) goto fail_free;
     if ((st = upload(p.get(), &p->d_items, items)) != SAS_OK) goto fail_free;
     p->h_items = items;
+    for (int64_t j = 0; j < n_v; ++j)
+        p->vmax = std::max(p->vmax, std::sqrt((double)V[2 * j] * V[2 * j] +
+                                              (double)V[2 * j + 1] * V[2 * j + 1]));
     p->footprint_cells = std::max(1.0, area / ((double)cellw * (double)cellw));
     if ((st = upload(p.get(), &p->d_t, p->t)) != SAS_OK) goto fail_free;
     if ((st = upload(p.get(), &p->d_sort_vel, sort_vel)) != SAS_OK) goto fail_free;
@@ -1129,3 +1133,31 @@ sas_status sas_vote_batch(const sas_batch *b, void *stream) {
 }
 
 }  // extern "C"
+
+extern "C" sas_status sas_features(const sas_plan *p, const void *workspace, size_t ws_bytes,
+                                   int64_t n, const float *snr_dev, const sas_candidate *cand_dev,
+                                   int64_t n_cand, float *feat_dev, void *stream) {
+    if (!p || n < 0 || n_cand < 0 || (n_cand > 0 && (!cand_dev || !feat_dev)))
+        return fail(SAS_E_INVALID, "sas_features: bad argument");
+    if (p->path != SAS_PATH_DENSE)
+        return fail(SAS_E_INVALID, "sas_features: needs the window index of a dense-path plan");
+    const WsLayout L = ws_layout(p, n);
+    if (!workspace || ws_bytes < L.total)
+        return fail(SAS_E_WORKSPACE, "sas_features: workspace smaller than sas_vote_workspace_size()");
+    if (n_cand == 0 || n == 0) return SAS_OK;
+    char *w = (char *)workspace;
+    const PrepBuffers pb = prep_buffers(L, w);
+    FeatureArgs a{};
+    a.cat = dense_args(p, L, w, pb, nullptr, 0, nullptr).cat;
+    a.log2b = p->log2b;
+    a.span = std::max<int64_t>(p->span, 1);
+    a.vmax = p->vmax;
+    a.vel = p->d_vel;
+    a.snr = snr_dev;
+    a.cand = cand_dev;
+    a.n_cand = n_cand;
+    a.feat = feat_dev;
+    hipError_t e = launch_features(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "sas_features: launch");
+    return SAS_OK;
+}

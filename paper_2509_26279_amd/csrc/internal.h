@@ -118,6 +118,21 @@ constexpr int kSortKeysPerTile = 4096;  // radix tile: 256 threads x 16 keys
 // Keys, radix sort and count of one sort block (blk: host copy of its table row).
 hipError_t launch_vote_sort_block(const SortArgs &a, const SortBlock &blk, hipStream_t stream);
 
+// Candidate features for learned vetting.
+constexpr int kFeatures = 32;
+struct FeatureArgs {
+    PreparedCatalog cat;       // window index of the voted catalog
+    int32_t log2b;
+    int64_t span;              // Delta t of the plan, Q16 h (>= 1)
+    double vmax;               // largest |v| of the plan's grid, Q8 px/h
+    const int32_t *vel;        // [n_v][2]
+    const float *snr;          // [n] by catalog index, or null
+    const sas_candidate *cand;
+    int64_t n_cand;
+    float *feat;               // [n_cand][kFeatures]
+};
+hipError_t launch_features(const FeatureArgs &a, hipStream_t stream);
+
 // groups: lane groups G (1, 2 or 4); segments hold 64 / G velocities.
 // ev0 / ev1 (optional) are recorded on the stream around the vote kernel.
 hipError_t launch_vote_dense(int mode, int groups, const DenseArgs &a, hipStream_t stream,

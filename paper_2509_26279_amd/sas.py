@@ -27,6 +27,7 @@ MODES = {"epochs": 0, "detections": 1}
 PATHS = {"auto": 0, "dense": 1, "sort": 2}
 ORDERS = {"canonical": 0, "by_count": 1}
 
+N_FEATURES = 32
 CAND_DTYPE = np.dtype([("v_idx", "<u4"), ("bx", "<i4"), ("by", "<i4"),
                        ("count", "<u2"), ("flags", "<u2")])
 
@@ -87,7 +88,7 @@ EXPORTS = ["sas_status_string", "sas_last_error", "sas_version", "sas_grid_spaci
            "sas_build_grid", "sas_plan_create", "sas_plan_destroy", "sas_plan_get_info",
            "sas_plan_set_probe", "sas_vote_workspace_size", "sas_vote", "sas_peaks",
            "sas_threshold_n_min", "sas_batch_workspace_size", "sas_batch_create",
-           "sas_batch_destroy", "sas_vote_batch", "sas_batch_set_probe"]
+           "sas_batch_destroy", "sas_vote_batch", "sas_batch_set_probe", "sas_features"]
 
 
 def load():
@@ -120,6 +121,7 @@ def load():
         "sas_batch_destroy": (I32, [P]),
         "sas_vote_batch": (I32, [P, P]),
         "sas_batch_set_probe": (I32, [P, P, P]),
+        "sas_features": (I32, [P, P, SZ, I64, P, P, I64, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -301,6 +303,22 @@ class Search:
         r = self.res.cpu().numpy().view(np.int32)
         n_cand = int(r[0].astype(np.int64) | (r[1].astype(np.int64) << 32))
         return {"n_cand": n_cand, "status": int(r[2]), "n_spilled": int(r[3])}
+
+    def features(self, n: int, snr=None, stream=None):
+        """Features of the candidates left in the device buffer by the last
+        vote of an n-detection catalog: (records as CAND_DTYPE in buffer
+        order, float32 [n_cand, 32]).  snr: device float tensor [n] or None."""
+        import torch
+        r = self.result()
+        k = min(r["n_cand"], self.cand.shape[0])
+        feat = torch.empty((max(k, 1), N_FEATURES), dtype=torch.float32, device=self.cand.device)
+        _check(load().sas_features(self.plan.handle, self.ws.data_ptr(),
+                                   self.ws.numel() * self.ws.element_size(), int(n),
+                                   snr.data_ptr() if snr is not None else None,
+                                   self.cand.data_ptr(), k, feat.data_ptr(),
+                                   _stream_handle(stream)))
+        recs = self.cand[:k].cpu().numpy().view(CAND_DTYPE).reshape(-1)
+        return recs.copy(), feat[:k].cpu().numpy()
 
     def run(self, x_q8, y_q8, epoch, order="canonical", top_k=0):
         x, y, e = self.upload(x_q8, y_q8, epoch)

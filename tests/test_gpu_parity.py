@@ -413,3 +413,44 @@ def test_autotuner_keeps_outputs(gpu):
     g = gpu_vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v, wl.binw_q8, wl.n_min, "epochs", 255,
                  wl.extent_q8, tuning=r["tuning"])
     assert_same(g, o)
+
+
+# ---------------------------------------------------------------- candidate features
+
+def _features_case(wl, v, n_min, tuning=None, sample=None, seed=0):
+    import torch
+    from oracle import features as of
+    plan = sas.Plan(v, wl.t_q16, wl.binw_q8, n_min, wl.extent_q8, tuning=tuning)
+    s = sas.Search(plan, wl.n, cand_cap=1 << 20)
+    x, y, e = s.upload(wl.x_q8, wl.y_q8, wl.epoch)
+    snr = torch.as_tensor(wl.snr).cuda()
+    s.vote(x, y, e)
+    s.peaks()
+    recs, feat = s.features(wl.n, snr)
+    plan.close()
+    assert len(recs) > 0
+    idx = np.arange(len(recs))
+    if sample is not None and len(recs) > sample:
+        idx = np.sort(np.random.default_rng(seed).choice(len(recs), sample, replace=False))
+    vmax = float(np.sqrt((v.astype(np.float64) ** 2).sum(axis=1)).max())
+    ref = of.candidate_features(wl.x_q8, wl.y_q8, wl.epoch, wl.snr, wl.t_q16, v, wl.binw_q8,
+                                recs[idx], vmax)
+    np.testing.assert_allclose(feat[idx], ref, rtol=1e-5, atol=2e-6)
+    return recs, feat
+
+
+def test_features_tiny(gpu):
+    wl = synth.make_tiny()
+    v = _grid(wl)
+    for n_min in (12, 5):
+        _say(f"features tiny n_min={n_min}")
+        _features_case(wl, v, n_min)
+
+
+def test_features_wide_subset_coarse_cells(gpu):
+    """Candidates that came through the coarse-cell filter and refinement."""
+    wl = synth.make_wide()
+    v = _grid(wl)
+    v = v[_sampled_velocities(v, 3000, 41)]
+    _say(f"features wide subset |V|={len(v)}")
+    _features_case(wl, v, 14, tuning=dict(n_det_hint=wl.n), sample=150)
