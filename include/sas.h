@@ -317,6 +317,42 @@ sas_status sas_features(const sas_plan *plan, const void *workspace, size_t ws_b
                         const float *snr_dev, const sas_candidate *cand_dev, int64_t n_cand,
                         float *feat_dev, void *stream);
 
+/*
+ * Vetting MLP 32 -> 128 -> 128 -> 1 (ReLU), bf16 operands on the matrix
+ * cores with FP32 accumulation, FP32 master weights.  Parameters are packed
+ * W1 (32 x 128, row-major), b1 (128), W2 (128 x 128), b2 (128), W3 (128),
+ * b3 (1): 20865 floats.  Inputs are [n][32] float rows on the device,
+ * standardised inside as (x - mean) / std (std 0 counts as 1).  The loss is
+ * the batch mean of binary cross-entropy with logits, positives weighted by
+ * pos_weight; weight gradients are reduced over the batch in a fixed order,
+ * so they are identical from run to run.  The optimiser is AdamW with
+ * decoupled weight decay on every parameter.
+ */
+typedef struct sas_mlp sas_mlp;
+#define SAS_MLP_PARAMS 20865
+
+/* Allocate the network for batches of up to max_batch rows; He-uniform
+ * weights (bound sqrt(6 / fan_in)) and zero biases from `seed`. */
+sas_status sas_mlp_create(int64_t max_batch, uint64_t seed, sas_mlp **mlp_out);
+sas_status sas_mlp_destroy(sas_mlp *mlp);
+/* Host mean[32] and std[32] of the input standardisation (synchronous). */
+sas_status sas_mlp_set_norm(sas_mlp *mlp, const float *mean_host, const float *std_host);
+/* Copy the FP32 parameters out (cap >= 20865; *n_out = 20865), or in
+ * (n = 20865; resets the optimiser state).  Synchronous. */
+sas_status sas_mlp_get_params(const sas_mlp *mlp, float *host, int64_t cap, int64_t *n_out);
+sas_status sas_mlp_set_params(sas_mlp *mlp, const float *host, int64_t n);
+/* Logits of n rows (any n; processed max_batch rows at a time). */
+sas_status sas_mlp_forward(const sas_mlp *mlp, const float *x_dev, int64_t n, float *logits_dev,
+                           void *stream);
+/* Mean loss (device float) and gradient (device [20865] float) of one batch
+ * (1 <= batch <= max_batch), without updating the parameters. */
+sas_status sas_mlp_grad(const sas_mlp *mlp, const float *x_dev, const float *y_dev, int64_t batch,
+                        float pos_weight, float *loss_dev, float *grad_dev, void *stream);
+/* One AdamW training step on a batch; *loss_dev receives its mean loss. */
+sas_status sas_mlp_train_step(sas_mlp *mlp, const float *x_dev, const float *y_dev, int64_t batch,
+                              float pos_weight, float lr, float beta1, float beta2, float eps,
+                              float weight_decay, float *loss_dev, void *stream);
+
 /* ------------------------------------------------------------------------
  * Peaks: collect the candidates of a finished vote in a deterministic order.
  * ---------------------------------------------------------------------- */

@@ -133,6 +133,46 @@ struct FeatureArgs {
 };
 hipError_t launch_features(const FeatureArgs &a, hipStream_t stream);
 
+// Vetting MLP 32 -> 128 -> 128 -> 1; parameters packed W1 (32 x 128),
+// b1, W2 (128 x 128), b2, W3 (128), b3.
+constexpr int kMlpIn = 32, kMlpHidden = 128;
+constexpr int kMlpOffW1 = 0;
+constexpr int kMlpOffB1 = kMlpOffW1 + kMlpIn * kMlpHidden;
+constexpr int kMlpOffW2 = kMlpOffB1 + kMlpHidden;
+constexpr int kMlpOffB2 = kMlpOffW2 + kMlpHidden * kMlpHidden;
+constexpr int kMlpOffW3 = kMlpOffB2 + kMlpHidden;
+constexpr int kMlpOffB3 = kMlpOffW3 + kMlpHidden;
+constexpr int kMlpParams = kMlpOffB3 + 1;  // 20865
+constexpr int kMlpSplitK = 512;            // batch rows per weight-gradient partial
+
+struct MlpWeights {        // bf16 working copies of the weights
+    uint16_t *w1;          // [32][128]
+    uint16_t *w2;          // [128][128]
+    uint16_t *w3;          // [128][16], column 0 = W3, the rest 0
+    float *b3pad;          // [16], element 0 = b3, the rest 0
+};
+
+struct MlpBuffers {
+    float *p, *m, *v, *grad;   // FP32 master parameters, AdamW moments, gradient
+    MlpWeights w;
+    float *mu, *sd;            // [32] input standardisation
+    uint16_t *a0;              // [max_batch][32]
+    uint16_t *h1, *h2;         // [max_batch][128]
+    uint16_t *d1, *d2;         // [max_batch][128]
+    float *z16;                // [max_batch][16], column 0 = logits
+    uint16_t *g3;              // [max_batch][16]
+    float *row_loss;           // [max_batch]
+    float *part;               // [max_batch / kMlpSplitK + 1][128][128]
+};
+
+hipError_t mlp_forward(const MlpBuffers &b, const float *x, int64_t n, hipStream_t s);
+hipError_t mlp_logits(const MlpBuffers &b, const float *x, int64_t n, float *out, hipStream_t s);
+hipError_t mlp_grad(const MlpBuffers &b, const float *x, const float *y, int64_t B, float pw,
+                    float *loss, float *grad, hipStream_t s);
+hipError_t mlp_adamw(const MlpBuffers &b, const float *grad, float lr, float b1, float b2,
+                     float eps, float wd, float c1, float c2, hipStream_t s);
+hipError_t mlp_refresh(const MlpBuffers &b, hipStream_t s);
+
 // groups: lane groups G (1, 2 or 4); segments hold 64 / G velocities.
 // ev0 / ev1 (optional) are recorded on the stream around the vote kernel.
 hipError_t launch_vote_dense(int mode, int groups, const DenseArgs &a, hipStream_t stream,

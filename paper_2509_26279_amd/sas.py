@@ -88,7 +88,9 @@ EXPORTS = ["sas_status_string", "sas_last_error", "sas_version", "sas_grid_spaci
            "sas_build_grid", "sas_plan_create", "sas_plan_destroy", "sas_plan_get_info",
            "sas_plan_set_probe", "sas_vote_workspace_size", "sas_vote", "sas_peaks",
            "sas_threshold_n_min", "sas_batch_workspace_size", "sas_batch_create",
-           "sas_batch_destroy", "sas_vote_batch", "sas_batch_set_probe", "sas_features"]
+           "sas_batch_destroy", "sas_vote_batch", "sas_batch_set_probe", "sas_features",
+           "sas_mlp_create", "sas_mlp_destroy", "sas_mlp_set_norm", "sas_mlp_get_params",
+           "sas_mlp_set_params", "sas_mlp_forward", "sas_mlp_grad", "sas_mlp_train_step"]
 
 
 def load():
@@ -122,6 +124,16 @@ def load():
         "sas_vote_batch": (I32, [P, P]),
         "sas_batch_set_probe": (I32, [P, P, P]),
         "sas_features": (I32, [P, P, SZ, I64, P, P, I64, P, P]),
+        "sas_mlp_create": (I32, [I64, ctypes.c_uint64, P]),
+        "sas_mlp_destroy": (I32, [P]),
+        "sas_mlp_set_norm": (I32, [P, P, P]),
+        "sas_mlp_get_params": (I32, [P, P, I64, P]),
+        "sas_mlp_set_params": (I32, [P, P, I64]),
+        "sas_mlp_forward": (I32, [P, P, I64, P, P]),
+        "sas_mlp_grad": (I32, [P, P, P, I64, ctypes.c_float, P, P, P]),
+        "sas_mlp_train_step": (I32, [P, P, P, I64, ctypes.c_float, ctypes.c_float,
+                                     ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                     ctypes.c_float, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -371,6 +383,70 @@ class Batch:
         if self._b:
             load().sas_batch_destroy(self._b)
             self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+MLP_PARAMS = 20865
+
+
+class MLP:
+    """The vetting network (sas_mlp_*): 32 -> 128 -> 128 -> 1 on bf16 MFMA."""
+
+    def __init__(self, max_batch: int = 4096, seed: int = 0, device="cuda"):
+        import torch
+        self.device = device
+        self.max_batch = int(max_batch)
+        self._m = ctypes.c_void_p()
+        _check(load().sas_mlp_create(self.max_batch, ctypes.c_uint64(seed), ctypes.byref(self._m)))
+        self._loss = torch.zeros(1, dtype=torch.float32, device=device)
+
+    def set_norm(self, mean, std):
+        m = np.ascontiguousarray(mean, dtype=np.float32)
+        s = np.ascontiguousarray(std, dtype=np.float32)
+        _check(load().sas_mlp_set_norm(self._m, m.ctypes.data, s.ctypes.data))
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(MLP_PARAMS, dtype=np.float32)
+        n = ctypes.c_int64()
+        _check(load().sas_mlp_get_params(self._m, out.ctypes.data, MLP_PARAMS, ctypes.byref(n)))
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        _check(load().sas_mlp_set_params(self._m, p.ctypes.data, p.shape[0]))
+
+    def forward(self, x, stream=None):
+        import torch
+        out = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        _check(load().sas_mlp_forward(self._m, x.data_ptr(), x.shape[0], out.data_ptr(),
+                                      _stream_handle(stream)))
+        return out
+
+    def grad(self, x, y, pos_weight=1.0, stream=None):
+        import torch
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
+        _check(load().sas_mlp_grad(self._m, x.data_ptr(), y.data_ptr(), x.shape[0],
+                                   float(pos_weight), self._loss.data_ptr(), g.data_ptr(),
+                                   _stream_handle(stream)))
+        return self._loss, g
+
+    def train_step(self, x, y, pos_weight=1.0, lr=1e-3, betas=(0.9, 0.999), eps=1e-8,
+                   weight_decay=0.01, stream=None):
+        _check(load().sas_mlp_train_step(self._m, x.data_ptr(), y.data_ptr(), x.shape[0],
+                                         float(pos_weight), float(lr), float(betas[0]),
+                                         float(betas[1]), float(eps), float(weight_decay),
+                                         self._loss.data_ptr(), _stream_handle(stream)))
+        return self._loss
+
+    def close(self):
+        if self._m:
+            load().sas_mlp_destroy(self._m)
+            self._m = ctypes.c_void_p()
 
     def __del__(self):
         try:

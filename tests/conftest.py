@@ -18,3 +18,13 @@ def oracle_lib():
     import oracle
     oracle.build()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def gpu():
+    """torch with a visible GPU and the HIP library loaded (no fallback)."""
+    import torch
+    assert torch.cuda.is_available(), "no GPU"
+    from paper_2509_26279_amd import sas
+    sas.load()
+    return torch

@@ -19,14 +19,6 @@ def _say(msg):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def gpu():
-    import torch
-    assert torch.cuda.is_available(), "no GPU"
-    sas.load()
-    return torch
-
-
 def _extent(x, y):
     return (int(x.min()), int(x.max()) + 1, int(y.min()), int(y.max()) + 1)
 
