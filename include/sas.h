@@ -304,8 +304,9 @@ sas_status sas_batch_set_probe(sas_batch *batch, void *ev_before, void *ev_after
  * sas_features: 32 float features per candidate for vetting (no paper
  * definition exists; the list is in the library's documentation: coverage,
  * time extent, longest epoch run, velocity, SNR statistics, residuals of
- * the projected positions inside the bin with their per-time-slice means
- * and their slope against time, time-slice fractions, shared epochs).
+ * the projected positions inside the bin with their per-time-slice means,
+ * their slope against time and their scatter about the fitted line,
+ * time-slice fractions, shared epochs).
  *   workspace: the workspace of the last sas_vote of this plan on this
  *              catalog (n detections): its window index is read.
  *   snr_dev:   device [n] float SNR by catalog index, or NULL (zeros).

@@ -28,7 +28,9 @@ largest |v| of the grid, P the distinct epochs and C the detections
            (0 when the slice is empty), s = 0..3
   f26 + s  fraction of C in slice s
   f30 (n - c) / n   (detections sharing an epoch)
-  f31 0 (reserved)
+  f31 root mean square of r_x and r_y about their least-squares lines
+      against d / D (the linear trajectory fit of Sec. 2.1, Step 4, on the
+      candidate's own detections): sqrt((SSE_x + SSE_y) / (2 n))
 """
 from __future__ import annotations
 
@@ -117,6 +119,9 @@ def candidate_features(x_q8, y_q8, epoch, snr, t_q16, v_q8, binw_q8, cand, vmax_
         if len({r[1] for r in rows}) > 1:  # not all d equal (exact, on the integers)
             f[16] = sum((a - mt) * (bq - mx) for a, bq in zip(tau, rx)) / stt
             f[17] = sum((a - mt) * (bq - my) for a, bq in zip(tau, ry)) / stt
+        sse = sum((bq - mx - f[16] * (a - mt)) ** 2 for a, bq in zip(tau, rx)) + \
+            sum((bq - my - f[17] * (a - mt)) ** 2 for a, bq in zip(tau, ry))
+        f[31] = math.sqrt(sse / (2 * n))
         for sl in range(4):
             idx = [j for j in range(n) if min(3, (4 * rows[j][1]) // D) == sl]
             if idx:

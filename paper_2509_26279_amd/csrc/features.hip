@@ -14,7 +14,7 @@
 //   f10 min snr - 3  f11 mean snr - 3  f12, f13 mean r  f14, f15 std r
 //   f16, f17 least-squares slope of r against tau (0 if all d equal)
 //   f18..f25 per-slice mean r_x, r_y  f26..f29 slice fractions
-//   f30 (n - c)/n  f31 0
+//   f30 (n - c)/n  f31 RMS of r about the least-squares lines (x and y)
 // with r_x = (65536 x - vx d) / (65536 b) - bx - 1/2.
 #include "internal.h"
 
@@ -195,11 +195,16 @@ __global__ void __launch_bounds__(FT) k_features(FeatureArgs a) {
             f[13] = (float)my;
             f[14] = (float)sqrt(fmax(rxx / n - mx * mx, 0.0));
             f[15] = (float)sqrt(fmax(ryy / n - my * my, 0.0));
+            const double sxx = rxx - n * mx * mx, syy = ryy - n * my * my;
+            double sse = sxx + syy;  // about the means, then about the fitted lines
             if (dmax > dmin) {
                 const double mt = ts / n, stt = tts - n * mt * mt;
-                f[16] = (float)((txs - n * mt * mx) / stt);
-                f[17] = (float)((tys - n * mt * my) / stt);
+                const double sxt = txs - n * mt * mx, syt = tys - n * mt * my;
+                f[16] = (float)(sxt / stt);
+                f[17] = (float)(syt / stt);
+                sse -= (sxt * sxt + syt * syt) / stt;
             }
+            f[31] = (float)sqrt(fmax(sse, 0.0) / (2.0 * n));
             for (int q = 0; q < 4; ++q) {
                 if (sn[q] > 0) {
                     f[18 + 2 * q] = (float)(sx[q] / sn[q]);
