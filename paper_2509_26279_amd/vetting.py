@@ -100,6 +100,9 @@ def candidate_pool(wl, v, n_pool, tuning=None, cand_cap=1 << 23):
         recs, feat = s.features(wl.n, snr)
     finally:
         plan.close()
+    # canonical order (the device appends candidates in no fixed order)
+    order = np.lexsort((recs["bx"], recs["by"], recs["v_idx"]))
+    recs, feat = recs[order], feat[order]
     present = np.zeros(wl.n_epochs, dtype=bool)
     present[np.asarray(wl.epoch, dtype=np.int64)] = True
     t0 = int(np.asarray(wl.t_q16)[present].min())
