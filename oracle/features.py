@@ -20,7 +20,16 @@ largest |v| of the grid, P the distinct epochs and C the detections
   f2 min_P d / D             f3 (max_P d - min_P d) / D
   f4 longest run of consecutive epoch indices in P, / E
   f5 vx / vmax   f6 vy / vmax   f7 |v| / vmax
-  f8 sum(snr) / E   f9 max(snr) - 3   f10 min(snr) - 3   f11 mean(snr) - 3
+  f8 sum(snr) / E   f11 mean(snr) - 3
+  f9  number of neighbouring candidates / 80
+  f10 largest count among neighbouring candidates / own count (0: none)
+      Neighbours are the other candidates of the same list whose lattice
+      velocity index (v / s rounded half up, s the grid spacing) differs by
+      at most 1 in each component and whose bin differs by at most 1 in
+      each axis (a real mover's stack spreads over neighbouring velocities
+      and bins; a noise stack stands alone).  Counts are capped at 4095.
+      Candidates whose lattice index or bin falls outside +-1022 / +-16382
+      get no neighbours.
   f12, f13 mean r_x, mean r_y      f14, f15 population std of r_x, r_y
   f16, f17 least-squares slope of r_x, r_y against d / D (bins per span;
            0 when all d are equal)
@@ -51,9 +60,54 @@ def reference_dt(t_q16, epoch, n_epochs):
     return np.where(present, t - t0, -1).astype(np.int64)
 
 
-def candidate_features(x_q8, y_q8, epoch, snr, t_q16, v_q8, binw_q8, cand, vmax_q8=None):
+def _lattice(v, s):
+    return (2 * int(v) + s) // (2 * s)  # v / s rounded half up
+
+
+def _packable(ix, iy, bx, by):
+    return abs(ix) <= 1022 and abs(iy) <= 1022 and abs(bx) <= 16382 and abs(by) <= 16382
+
+
+def neighbour_features(cand, v_q8, spacing_q8):
+    """(f9, f10) of every candidate of the list (definitions above)."""
+    n = len(cand)
+    out = np.zeros((n, 2), dtype=np.float64)
+    if not spacing_q8 or n == 0:
+        return out
+    v = np.asarray(v_q8, dtype=np.int64)
+    keyed = {}
+    keys = []
+    for i, c in enumerate(cand):
+        vx, vy = v[int(c["v_idx"])]
+        k = (_lattice(vx, spacing_q8), _lattice(vy, spacing_q8), int(c["bx"]), int(c["by"]))
+        keys.append(k)
+        if _packable(*k):
+            keyed[k] = min(int(c["count"]), 4095)
+    for i, k in enumerate(keys):
+        if not _packable(*k):
+            continue
+        own = min(int(cand[i]["count"]), 4095)
+        cnt, best = 0, 0
+        for a in (-1, 0, 1):
+            for b in (-1, 0, 1):
+                for cx in (-1, 0, 1):
+                    for cy in (-1, 0, 1):
+                        if a == b == cx == cy == 0:
+                            continue
+                        q = keyed.get((k[0] + a, k[1] + b, k[2] + cx, k[3] + cy))
+                        if q is not None:
+                            cnt += 1
+                            best = max(best, q)
+        out[i, 0] = cnt / 80.0
+        out[i, 1] = best / own if cnt and own else 0.0
+    return out
+
+
+def candidate_features(x_q8, y_q8, epoch, snr, t_q16, v_q8, binw_q8, cand, vmax_q8=None,
+                       spacing_q8=0):
     """[n_cand, 32] float64 features of the candidates (records with v_idx,
-    bx, by), following the definitions above."""
+    bx, by, count), following the definitions above; the neighbour features
+    look among the candidates of `cand` (zeros when spacing_q8 is 0)."""
     xa = np.asarray(x_q8, dtype=np.int64)
     ya = np.asarray(y_q8, dtype=np.int64)
     ea = np.asarray(epoch, dtype=np.int64)
@@ -104,8 +158,6 @@ def candidate_features(x_q8, y_q8, epoch, snr, t_q16, v_q8, binw_q8, cand, vmax_
         f[7] = math.hypot(vx, vy) / vmax
         s = [r[4] for r in rows]
         f[8] = sum(s) / E
-        f[9] = max(s) - 3.0
-        f[10] = min(s) - 3.0
         f[11] = sum(s) / n - 3.0
         rx = [r[2] for r in rows]
         ry = [r[3] for r in rows]
@@ -129,6 +181,7 @@ def candidate_features(x_q8, y_q8, epoch, snr, t_q16, v_q8, binw_q8, cand, vmax_
                 f[19 + 2 * sl] = sum(ry[j] for j in idx) / len(idx)
             f[26 + sl] = len(idx) / n
         f[30] = (n - cnum) / n
+    out[:, 9:11] = neighbour_features(cand, v, spacing_q8)
     return out
 
 

@@ -114,3 +114,15 @@ def test_labels_follow_the_injected_track():
     cand[2] = (1, bx, by, 0, 0)         # wrong velocity: leaves the track
     lab = of.label_candidates(cand, v, b, t, int(t[0]), truth, 4.0)
     assert list(lab) == [1, 0, 0]
+
+
+def test_neighbour_features_by_hand():
+    """Three candidates: two adjacent (one lattice step, one bin apart), one far."""
+    v = np.array([[0, 0], [256, 0], [256 * 40, 0]], np.int32)      # spacing 256
+    cand = np.zeros(3, CAND_DTYPE)
+    cand[0] = (0, 10, 10, 20, 0)
+    cand[1] = (1, 11, 9, 30, 0)
+    cand[2] = (2, 10, 10, 25, 0)
+    nf = of.neighbour_features(cand, v, 256)
+    np.testing.assert_allclose(nf, [[1 / 80, 30 / 20], [1 / 80, 20 / 30], [0, 0]])
+    assert np.all(of.neighbour_features(cand, v, 0) == 0)
