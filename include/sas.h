@@ -303,20 +303,33 @@ sas_status sas_batch_set_probe(sas_batch *batch, void *ev_before, void *ev_after
 /*
  * sas_features: 32 float features per candidate for vetting (no paper
  * definition exists; the list is in the library's documentation: coverage,
- * time extent, longest epoch run, velocity, SNR statistics, residuals of
- * the projected positions inside the bin with their per-time-slice means,
- * their slope against time and their scatter about the fitted line,
- * time-slice fractions, shared epochs).
- *   workspace: the workspace of the last sas_vote of this plan on this
- *              catalog (n detections): its window index is read.
- *   snr_dev:   device [n] float SNR by catalog index, or NULL (zeros).
- *   cand_dev:  device [n_cand] candidates of this plan (exact bins).
- *   feat_dev:  device [n_cand][32] float, row-major.
- * Asynchronous, no allocation.  Errors: SAS_E_INVALID, SAS_E_WORKSPACE.
+ * time extent, longest epoch run, velocity, SNR statistics, neighbouring
+ * candidates in (velocity, bin), residuals of the projected positions inside
+ * the bin with their per-time-slice means, their slope against time and
+ * their scatter about the fitted line, time-slice fractions, shared epochs).
+ *   workspace:  the workspace of the last sas_vote of this plan on this
+ *               catalog (n detections): its window index is read.
+ *   snr_dev:    device [n] float SNR by catalog index, or NULL (zeros).
+ *   cand_dev:   device [n_cand] candidates of this plan (exact bins).
+ *   spacing_q8: lattice spacing of the velocity grid (Q8 px/h; the
+ *               sas_grid_spec spacing).  Velocities are placed on the lattice
+ *               by rounding v / spacing half up; two candidates are
+ *               neighbours when those indices and their bins differ by at
+ *               most 1 per component.  0 leaves features 9 and 10 at zero.
+ *   scratch:    device memory of sas_features_scratch_size(n_cand) bytes or
+ *               more (neighbour keys and their sort); unused when
+ *               spacing_q8 is 0 (may then be NULL).
+ *   feat_dev:   device [n_cand][32] float, row-major.
+ * Asynchronous, no allocation.  Errors: SAS_E_INVALID (n_cand >= 2^31,
+ * negative spacing), SAS_E_WORKSPACE (workspace or scratch too small).
  */
 sas_status sas_features(const sas_plan *plan, const void *workspace, size_t ws_bytes, int64_t n,
                         const float *snr_dev, const sas_candidate *cand_dev, int64_t n_cand,
+                        int32_t spacing_q8, void *scratch, size_t scratch_bytes,
                         float *feat_dev, void *stream);
+
+/* Bytes of scratch sas_features needs for n_cand candidates. */
+sas_status sas_features_scratch_size(int64_t n_cand, size_t *bytes);
 
 /*
  * Vetting MLP 32 -> 128 -> 128 -> 1 (ReLU), bf16 operands on the matrix

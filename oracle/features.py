@@ -27,7 +27,9 @@ largest |v| of the grid, P the distinct epochs and C the detections
       velocity index (v / s rounded half up, s the grid spacing) differs by
       at most 1 in each component and whose bin differs by at most 1 in
       each axis (a real mover's stack spreads over neighbouring velocities
-      and bins; a noise stack stands alone).  Counts are capped at 4095.
+      and bins; a noise stack stands alone).  Counts are capped at 4095;
+      candidates that share a lattice index and bin count as one, with
+      the largest of their counts.
       Candidates whose lattice index or bin falls outside +-1022 / +-16382
       get no neighbours.
   f12, f13 mean r_x, mean r_y      f14, f15 population std of r_x, r_y
@@ -68,10 +70,12 @@ def _packable(ix, iy, bx, by):
     return abs(ix) <= 1022 and abs(iy) <= 1022 and abs(bx) <= 16382 and abs(by) <= 16382
 
 
-def neighbour_features(cand, v_q8, spacing_q8):
-    """(f9, f10) of every candidate of the list (definitions above)."""
+def neighbour_features(cand, v_q8, spacing_q8, rows=None):
+    """(f9, f10) of the candidates `rows` (default: all) of the list, their
+    neighbours taken among the whole list (definitions above)."""
     n = len(cand)
-    out = np.zeros((n, 2), dtype=np.float64)
+    rows = np.arange(n) if rows is None else np.asarray(rows, dtype=np.int64)
+    out = np.zeros((len(rows), 2), dtype=np.float64)
     if not spacing_q8 or n == 0:
         return out
     v = np.asarray(v_q8, dtype=np.int64)
@@ -81,9 +85,10 @@ def neighbour_features(cand, v_q8, spacing_q8):
         vx, vy = v[int(c["v_idx"])]
         k = (_lattice(vx, spacing_q8), _lattice(vy, spacing_q8), int(c["bx"]), int(c["by"]))
         keys.append(k)
-        if _packable(*k):
-            keyed[k] = min(int(c["count"]), 4095)
-    for i, k in enumerate(keys):
+        if _packable(*k):  # candidates sharing a key: the largest count stands for them
+            keyed[k] = max(keyed.get(k, 0), min(int(c["count"]), 4095))
+    for r, i in enumerate(rows):
+        k = keys[i]
         if not _packable(*k):
             continue
         own = min(int(cand[i]["count"]), 4095)
@@ -98,8 +103,8 @@ def neighbour_features(cand, v_q8, spacing_q8):
                         if q is not None:
                             cnt += 1
                             best = max(best, q)
-        out[i, 0] = cnt / 80.0
-        out[i, 1] = best / own if cnt and own else 0.0
+        out[r, 0] = cnt / 80.0
+        out[r, 1] = best / own if cnt and own else 0.0
     return out
 
 

@@ -1134,16 +1134,51 @@ sas_status sas_vote_batch(const sas_batch *b, void *stream) {
 
 }  // extern "C"
 
+namespace {
+
+struct FeatScratch {
+    size_t keys, keys_alt, hist, hist_blocksum, total;
+};
+
+FeatScratch feat_scratch_layout(int64_t n_cand) {
+    FeatScratch L{};
+    const int64_t tiles = (n_cand + kSortKeysPerTile - 1) / kSortKeysPerTile;
+    const int64_t hist = 256 * tiles;
+    size_t o = 0;
+    L.keys = o; o = align_up(o + sizeof(uint64_t) * n_cand);
+    L.keys_alt = o; o = align_up(o + sizeof(uint64_t) * n_cand);
+    L.hist = o; o = align_up(o + sizeof(int32_t) * hist);
+    L.hist_blocksum = o; o = align_up(o + sizeof(int32_t) * ((hist + kScanTile - 1) / kScanTile));
+    L.total = o;
+    return L;
+}
+
+constexpr int64_t kMaxFeatureCands = (int64_t)1 << 31;
+
+}  // namespace
+
+extern "C" sas_status sas_features_scratch_size(int64_t n_cand, size_t *bytes) {
+    if (!bytes || n_cand < 0 || n_cand >= kMaxFeatureCands)
+        return fail(SAS_E_INVALID, "sas_features_scratch_size: bad argument");
+    *bytes = feat_scratch_layout(n_cand).total;
+    return SAS_OK;
+}
+
 extern "C" sas_status sas_features(const sas_plan *p, const void *workspace, size_t ws_bytes,
                                    int64_t n, const float *snr_dev, const sas_candidate *cand_dev,
-                                   int64_t n_cand, float *feat_dev, void *stream) {
-    if (!p || n < 0 || n_cand < 0 || (n_cand > 0 && (!cand_dev || !feat_dev)))
+                                   int64_t n_cand, int32_t spacing_q8, void *scratch,
+                                   size_t scratch_bytes, float *feat_dev, void *stream) {
+    if (!p || n < 0 || n_cand < 0 || n_cand >= kMaxFeatureCands || spacing_q8 < 0 ||
+        (n_cand > 0 && (!cand_dev || !feat_dev)))
         return fail(SAS_E_INVALID, "sas_features: bad argument");
     if (p->path != SAS_PATH_DENSE)
         return fail(SAS_E_INVALID, "sas_features: needs the window index of a dense-path plan");
     const WsLayout L = ws_layout(p, n);
     if (!workspace || ws_bytes < L.total)
         return fail(SAS_E_WORKSPACE, "sas_features: workspace smaller than sas_vote_workspace_size()");
+    const FeatScratch S = feat_scratch_layout(n_cand);
+    if (spacing_q8 > 0 && n_cand > 0 && (!scratch || scratch_bytes < S.total))
+        return fail(SAS_E_WORKSPACE, "sas_features: scratch smaller than sas_features_scratch_size()");
     if (n_cand == 0 || n == 0) return SAS_OK;
     char *w = (char *)workspace;
     const PrepBuffers pb = prep_buffers(L, w);
@@ -1157,6 +1192,14 @@ extern "C" sas_status sas_features(const sas_plan *p, const void *workspace, siz
     a.cand = cand_dev;
     a.n_cand = n_cand;
     a.feat = feat_dev;
+    a.spacing = spacing_q8;
+    if (spacing_q8 > 0) {
+        char *s = (char *)scratch;
+        a.keys = (uint64_t *)(s + S.keys);
+        a.keys_alt = (uint64_t *)(s + S.keys_alt);
+        a.hist = (int32_t *)(s + S.hist);
+        a.hist_blocksum = (int32_t *)(s + S.hist_blocksum);
+    }
     hipError_t e = launch_features(a, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "sas_features: launch");
     return SAS_OK;

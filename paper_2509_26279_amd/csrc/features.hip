@@ -27,6 +27,51 @@ __device__ inline int32_t shift_q8(int32_t v, int32_t d) {
     return (int32_t)(((int64_t)v * (int64_t)d + 65535) >> 16);
 }
 
+// Neighbour key of a candidate: lattice velocity index (v / s rounded half
+// up) and bin, packed 11 + 11 + 15 + 15 bits above a 12-bit count; all ones
+// when a component is out of range (such a candidate has no neighbours).
+constexpr uint64_t kNoNeighbourKey = ~(uint64_t)0;
+
+__device__ inline int64_t lattice_index(int32_t v, int32_t s) {
+    const int64_t n = 2 * (int64_t)v + s, d = 2 * (int64_t)s;
+    return n >= 0 ? n / d : -((-n + d - 1) / d);  // floor
+}
+
+__device__ inline bool packable(int64_t ix, int64_t iy, int64_t bx, int64_t by) {
+    return ix >= -1022 && ix <= 1022 && iy >= -1022 && iy <= 1022 && bx >= -16382 &&
+           bx <= 16382 && by >= -16382 && by <= 16382;
+}
+
+__device__ inline uint64_t pack_key(int64_t ix, int64_t iy, int64_t bx, int64_t by) {
+    return ((uint64_t)(ix + 1024) << 53) | ((uint64_t)(iy + 1024) << 42) |
+           ((uint64_t)(bx + 16384) << 27) | ((uint64_t)(by + 16384) << 12);
+}
+
+__global__ void k_neighbour_keys(FeatureArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n_cand) return;
+    const sas_candidate cd = a.cand[i];
+    const int64_t ix = lattice_index(a.vel[2 * (int64_t)cd.v_idx], a.spacing);
+    const int64_t iy = lattice_index(a.vel[2 * (int64_t)cd.v_idx + 1], a.spacing);
+    a.keys[i] = packable(ix, iy, cd.bx, cd.by)
+                    ? pack_key(ix, iy, cd.bx, cd.by) | (uint64_t)min((int)cd.count, 4095)
+                    : kNoNeighbourKey;
+}
+
+// Largest count among the candidates with packed key `want` (count bits
+// clear), or -1 when there is none.
+__device__ inline int find_key(const uint64_t *keys, int64_t n, uint64_t want) {
+    const uint64_t w = want >> 12;
+    int64_t lo = 0, hi = n;  // first key whose upper bits are >= w
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((keys[mid] >> 12) < w) lo = mid + 1; else hi = mid;
+    }
+    int best = -1;
+    for (; lo < n && (keys[lo] >> 12) == w; ++lo) best = max(best, (int)(keys[lo] & 4095));
+    return best;
+}
+
 __device__ inline double wsum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -35,11 +80,6 @@ __device__ inline double wsum(double v) {
 __device__ inline double wmax(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ inline double wmin(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
     return v;
 }
 __device__ inline int64_t wmin_i(int64_t v) {
@@ -59,7 +99,7 @@ __device__ inline int64_t wmax_i(int64_t v) {
     return v;
 }
 
-__global__ void __launch_bounds__(FT) k_features(FeatureArgs a) {
+__global__ void __launch_bounds__(FT) k_features(FeatureArgs a, const uint64_t *nkeys) {
     const int lane = __lane_id();
     const int64_t wave_id = ((int64_t)blockIdx.x * FT + threadIdx.x) >> 6;
     const int64_t n_waves = ((int64_t)gridDim.x * FT) >> 6;
@@ -71,7 +111,7 @@ __global__ void __launch_bounds__(FT) k_features(FeatureArgs a) {
     for (int64_t k = wave_id; k < a.n_cand; k += n_waves) {
         const sas_candidate cd = a.cand[k];
         const int32_t vx = a.vel[2 * (int64_t)cd.v_idx], vy = a.vel[2 * (int64_t)cd.v_idx + 1];
-        double n = 0, ssum = 0, smax = -1e300, smin = 1e300, rxs = 0, rys = 0, rxx = 0, ryy = 0;
+        double n = 0, ssum = 0, rxs = 0, rys = 0, rxx = 0, ryy = 0;
         double ts = 0, tts = 0, txs = 0, tys = 0;
         double sn[4] = {0, 0, 0, 0}, sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0};
         int64_t dmin = INT64_MAX, dmax = INT64_MIN, dpmin = INT64_MAX, dpmax = INT64_MIN;
@@ -108,8 +148,6 @@ __global__ void __launch_bounds__(FT) k_features(FeatureArgs a) {
                                 has = true;
                                 n += 1;
                                 ssum += s;
-                                smax = fmax(smax, s);
-                                smin = fmin(smin, s);
                                 rxs += rx;
                                 rys += ry;
                                 rxx += rx * rx;
@@ -148,8 +186,6 @@ __global__ void __launch_bounds__(FT) k_features(FeatureArgs a) {
         for (int q = 0; q < kFeatures; ++q) f[q] = 0.0f;
         // every lane holds the wave totals after the reductions
         ssum = wsum(ssum);
-        smax = wmax(smax);
-        smin = wmin(smin);
         rxs = wsum(rxs);
         rys = wsum(rys);
         rxx = wsum(rxx);
@@ -188,8 +224,6 @@ __global__ void __launch_bounds__(FT) k_features(FeatureArgs a) {
             f[6] = (float)(vy / vmax);
             f[7] = (float)(sqrt((double)vx * vx + (double)vy * vy) / vmax);
             f[8] = (float)(ssum / E);
-            f[9] = (float)(smax - 3.0);
-            f[10] = (float)(smin - 3.0);
             f[11] = (float)(ssum / n - 3.0);
             f[12] = (float)mx;
             f[13] = (float)my;
@@ -214,6 +248,33 @@ __global__ void __launch_bounds__(FT) k_features(FeatureArgs a) {
             }
             f[30] = (float)((n - cnt) / n);
         }
+        // neighbouring candidates: lane q < 81 takes offset q (base 3 digits - 1)
+        {
+            double ncnt = 0.0, nbest = 0.0;
+            if (a.spacing > 0 && nkeys) {
+                const int64_t ix = lattice_index(vx, a.spacing), iy = lattice_index(vy, a.spacing);
+                for (int q = lane; q < 81; q += 64) {
+                    if (q == 40) continue;  // the candidate itself
+                    const int64_t dx = q % 3 - 1, dy = (q / 3) % 3 - 1;
+                    const int64_t ex = (q / 9) % 3 - 1, ey = q / 27 - 1;
+                    if (!packable(ix, iy, cd.bx, cd.by) ||
+                        !packable(ix + dx, iy + dy, (int64_t)cd.bx + ex, (int64_t)cd.by + ey))
+                        continue;
+                    const int c = find_key(nkeys, a.n_cand,
+                                           pack_key(ix + dx, iy + dy, (int64_t)cd.bx + ex,
+                                                    (int64_t)cd.by + ey));
+                    if (c >= 0) {
+                        ncnt += 1.0;
+                        nbest = fmax(nbest, (double)c);
+                    }
+                }
+            }
+            ncnt = wsum(ncnt);
+            nbest = wmax(nbest);
+            const double own = (double)min((int)cd.count, 4095);
+            f[9] = (float)(ncnt / 80.0);
+            f[10] = (float)(ncnt > 0 && own > 0 ? nbest / own : 0.0);
+        }
         if (lane < kFeatures) {
             float mine = 0.0f;
 #pragma unroll
@@ -227,9 +288,17 @@ __global__ void __launch_bounds__(FT) k_features(FeatureArgs a) {
 
 hipError_t launch_features(const FeatureArgs &a, hipStream_t stream) {
     if (a.n_cand <= 0) return hipSuccess;
+    uint64_t *sorted = nullptr;
+    if (a.spacing > 0) {
+        hipLaunchKernelGGL(k_neighbour_keys, dim3((unsigned)((a.n_cand + 255) / 256)), dim3(256), 0,
+                           stream, a);
+        hipError_t e = launch_radix_sort_u64(a.keys, a.keys_alt, a.n_cand, 12, 64, a.hist,
+                                             a.hist_blocksum, stream, &sorted);
+        if (e != hipSuccess) return e;
+    }
     const int64_t blocks = (a.n_cand + FT / 64 - 1) / (FT / 64);
     hipLaunchKernelGGL(k_features, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(FT), 0,
-                       stream, a);
+                       stream, a, (const uint64_t *)sorted);
     return hipGetLastError();
 }
 

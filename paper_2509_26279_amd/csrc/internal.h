@@ -115,6 +115,12 @@ struct SortArgs {
 
 constexpr int kSortKeysPerTile = 4096;  // radix tile: 256 threads x 16 keys
 
+// Stable LSD radix sort of m keys on bits [lo_bit, hi_bit) (8-bit digits);
+// *sorted is keys or alt, whichever holds the result.  hist: 256 x tiles.
+hipError_t launch_radix_sort_u64(uint64_t *keys, uint64_t *alt, int64_t m, int lo_bit, int hi_bit,
+                                 int32_t *hist, int32_t *hist_blocksum, hipStream_t stream,
+                                 uint64_t **sorted);
+
 // Keys, radix sort and count of one sort block (blk: host copy of its table row).
 hipError_t launch_vote_sort_block(const SortArgs &a, const SortBlock &blk, hipStream_t stream);
 
@@ -130,7 +136,11 @@ struct FeatureArgs {
     const sas_candidate *cand;
     int64_t n_cand;
     float *feat;               // [n_cand][kFeatures]
+    int32_t spacing;           // lattice spacing of the grid (0: no neighbour features)
+    uint64_t *keys, *keys_alt; // [n_cand] neighbour keys (scratch)
+    int32_t *hist, *hist_blocksum;
 };
+// Neighbour keys of the candidates, their sort, then the features.
 hipError_t launch_features(const FeatureArgs &a, hipStream_t stream);
 
 // Vetting MLP 32 -> 128 -> 128 -> 1; parameters packed W1 (32 x 128),

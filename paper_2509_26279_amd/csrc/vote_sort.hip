@@ -181,23 +181,34 @@ inline unsigned grid_for(int64_t n, int64_t cap) {
 
 }  // namespace
 
-hipError_t launch_vote_sort_block(const SortArgs &a, const SortBlock &blk, hipStream_t stream) {
-    const int64_t m = (int64_t)blk.nv * a.n;
-    if (m <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sort_keygen, dim3(grid_for(m, 1 << 16)), dim3(T), 0, stream, a, blk);
+hipError_t launch_radix_sort_u64(uint64_t *keys, uint64_t *alt, int64_t m, int lo_bit, int hi_bit,
+                                 int32_t *hist, int32_t *hist_blocksum, hipStream_t stream,
+                                 uint64_t **sorted) {
     const int64_t n_tiles = (m + kSortKeysPerTile - 1) / kSortKeysPerTile;
-    uint64_t *in = a.keys, *out = a.keys_alt;
-    for (int shift = 8; shift < 8 + blk.key_bits; shift += 8) {
+    uint64_t *in = keys, *out = alt;
+    for (int shift = lo_bit; shift < hi_bit && m > 0; shift += 8) {
         hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)n_tiles), dim3(T), 0, stream, in, m, shift,
-                           a.hist, n_tiles);
-        hipError_t e = launch_scan_exclusive(a.hist, 256 * n_tiles, a.hist_blocksum, stream);
+                           hist, n_tiles);
+        hipError_t e = launch_scan_exclusive(hist, 256 * n_tiles, hist_blocksum, stream);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)n_tiles), dim3(T), 0, stream, in, out, m,
-                           shift, a.hist, n_tiles);
+                           shift, hist, n_tiles);
         uint64_t *tmp = in;
         in = out;
         out = tmp;
     }
+    *sorted = in;
+    return hipGetLastError();
+}
+
+hipError_t launch_vote_sort_block(const SortArgs &a, const SortBlock &blk, hipStream_t stream) {
+    const int64_t m = (int64_t)blk.nv * a.n;
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sort_keygen, dim3(grid_for(m, 1 << 16)), dim3(T), 0, stream, a, blk);
+    uint64_t *in = nullptr;
+    hipError_t e = launch_radix_sort_u64(a.keys, a.keys_alt, m, 8, 8 + blk.key_bits, a.hist,
+                                         a.hist_blocksum, stream, &in);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sort_count, dim3(grid_for(m, 1 << 15)), dim3(T), 0, stream, a, blk,
                        (const uint64_t *)in, m);
     return hipGetLastError();

@@ -89,6 +89,7 @@ EXPORTS = ["sas_status_string", "sas_last_error", "sas_version", "sas_grid_spaci
            "sas_plan_set_probe", "sas_vote_workspace_size", "sas_vote", "sas_peaks",
            "sas_threshold_n_min", "sas_batch_workspace_size", "sas_batch_create",
            "sas_batch_destroy", "sas_vote_batch", "sas_batch_set_probe", "sas_features",
+           "sas_features_scratch_size",
            "sas_mlp_create", "sas_mlp_destroy", "sas_mlp_set_norm", "sas_mlp_get_params",
            "sas_mlp_set_params", "sas_mlp_forward", "sas_mlp_grad", "sas_mlp_train_step"]
 
@@ -123,7 +124,8 @@ def load():
         "sas_batch_destroy": (I32, [P]),
         "sas_vote_batch": (I32, [P, P]),
         "sas_batch_set_probe": (I32, [P, P, P]),
-        "sas_features": (I32, [P, P, SZ, I64, P, P, I64, P, P]),
+        "sas_features": (I32, [P, P, SZ, I64, P, P, I64, I32, P, SZ, P, P]),
+        "sas_features_scratch_size": (I32, [I64, ctypes.POINTER(ctypes.c_size_t)]),
         "sas_mlp_create": (I32, [I64, ctypes.c_uint64, P]),
         "sas_mlp_destroy": (I32, [P]),
         "sas_mlp_set_norm": (I32, [P, P, P]),
@@ -282,6 +284,13 @@ def peaks(cand, res, order="canonical", top_k=0, stream=None):
     return out[:n.value].copy()
 
 
+def features_scratch_size(n_cand: int) -> int:
+    """Device scratch bytes sas_features needs for n_cand candidates."""
+    out = ctypes.c_size_t(0)
+    _check(load().sas_features_scratch_size(int(n_cand), ctypes.byref(out)))
+    return int(out.value)
+
+
 class Search:
     """Device buffers for repeated searches of catalogs with one plan."""
 
@@ -316,18 +325,23 @@ class Search:
         n_cand = int(r[0].astype(np.int64) | (r[1].astype(np.int64) << 32))
         return {"n_cand": n_cand, "status": int(r[2]), "n_spilled": int(r[3])}
 
-    def features(self, n: int, snr=None, stream=None):
+    def features(self, n: int, snr=None, spacing_q8: int = 0, stream=None):
         """Features of the candidates left in the device buffer by the last
         vote of an n-detection catalog: (records as CAND_DTYPE in buffer
-        order, float32 [n_cand, 32]).  snr: device float tensor [n] or None."""
+        order, float32 [n_cand, 32]).  snr: device float tensor [n] or None;
+        spacing_q8: the velocity grid's lattice spacing (0: no neighbour
+        features)."""
         import torch
         r = self.result()
         k = min(r["n_cand"], self.cand.shape[0])
         feat = torch.empty((max(k, 1), N_FEATURES), dtype=torch.float32, device=self.cand.device)
+        nb = features_scratch_size(k) if spacing_q8 else 0
+        scratch = torch.empty(max(nb, 1), dtype=torch.uint8, device=self.cand.device)
         _check(load().sas_features(self.plan.handle, self.ws.data_ptr(),
                                    self.ws.numel() * self.ws.element_size(), int(n),
                                    snr.data_ptr() if snr is not None else None,
-                                   self.cand.data_ptr(), k, feat.data_ptr(),
+                                   self.cand.data_ptr(), k, int(spacing_q8),
+                                   scratch.data_ptr(), nb, feat.data_ptr(),
                                    _stream_handle(stream)))
         recs = self.cand[:k].cpu().numpy().view(CAND_DTYPE).reshape(-1)
         return recs.copy(), feat[:k].cpu().numpy()

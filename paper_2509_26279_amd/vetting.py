@@ -10,10 +10,19 @@ used with fewer false candidates:
   * labels: a candidate is positive when its track (bin centre moved with
     its trial velocity) stays within one bin width of an injected mover in
     at least half of the epochs;
-  * training: the MLP of sas_mlp_* on standardised features, binary
-    cross-entropy with positives weighted by min(n_neg / n_pos, 100), AdamW;
-  * operating point: the score threshold tau is the largest one whose
-    recall on validation catalogs reaches the plain threshold's recall there.
+  * training: an ensemble of MLPs (sas_mlp_*, different seeds) on
+    standardised features, binary cross-entropy with positives weighted by
+    min(n_neg / n_pos, 100), AdamW; at most `cap` candidates per mover are
+    kept for training, so that slow movers with hundreds of ghost stacks do
+    not drown the hard ones;
+  * score: the mean logit of the members;
+  * operating point, on validation catalogs: the lower of (a) the largest
+    threshold that keeps every findable mover the plain threshold finds
+    there (so the validation recall is at least the plain threshold's,
+    mover by mover) and (b) the lowest threshold whose false positives stay
+    within a budget, by default a tenth of the plain threshold's.  (b) spends
+    part of the gain on a margin: (a) alone is set by the single hardest
+    validation mover and misses test movers just below it.
 
 Recall counts findable movers (at least N_min epochs on the chip) with at
 least one selected candidate matched to them; false positives are selected
@@ -97,7 +106,7 @@ def candidate_pool(wl, v, n_pool, tuning=None, cand_cap=1 << 23):
         s.vote(x, y, e)
         s.peaks()  # checks the result (overflow, data errors)
         snr = torch.as_tensor(np.ascontiguousarray(wl.snr, dtype=np.float32)).cuda()
-        recs, feat = s.features(wl.n, snr)
+        recs, feat = s.features(wl.n, snr, spacing_q8=sas.grid_spacing(wl.binw_q8, wl.span_q16))
     finally:
         plan.close()
     # canonical order (the device appends candidates in no fixed order)
@@ -109,42 +118,86 @@ def candidate_pool(wl, v, n_pool, tuning=None, cand_cap=1 << 23):
     return recs, feat, recs["count"].astype(np.int32), t0
 
 
-class Vetter:
-    """Train and apply the vetting network."""
+def balance(matched, cap, seed=0):
+    """Mask keeping every negative and at most `cap` (random) candidates of
+    each mover; cap 0 keeps everything."""
+    m = np.asarray(matched)
+    keep = np.ones(len(m), dtype=bool)
+    if cap <= 0:
+        return keep
+    rng = np.random.default_rng(seed)
+    for k in np.unique(m[m >= 0]):
+        ids = np.nonzero(m == k)[0]
+        if len(ids) > cap:
+            keep[rng.choice(ids, len(ids) - cap, replace=False)] = False
+    return keep
 
-    def __init__(self, seed=0, max_batch=4096):
-        self.net = sas.MLP(max_batch=max_batch, seed=seed)
+
+def superset_tau(scores, matched, findable_mask, plain_selected):
+    """Largest threshold that keeps every findable mover found by the plain
+    selection: the smallest, over those movers, of their best score (inf
+    when there are none)."""
+    sc = np.asarray(scores)
+    m = np.asarray(matched)
+    fmask = np.asarray(findable_mask, dtype=bool)
+    sel = np.asarray(plain_selected, dtype=bool)
+    movers = np.unique(m[sel & (m >= 0)])
+    movers = movers[fmask[movers]]
+    if len(movers) == 0:
+        return float("inf")
+    order = np.argsort(m, kind="stable")
+    ms = m[order]
+    best = np.full(len(fmask), -np.inf)
+    pos = ms >= 0
+    np.maximum.at(best, ms[pos], sc[order][pos])
+    return float(best[movers].min())
+
+
+def budget_tau(scores, matched, n_fp):
+    """Lowest threshold with at most n_fp unmatched candidates at or above
+    it (-inf when there are no more than n_fp of them)."""
+    neg = np.sort(np.asarray(scores, dtype=np.float32)[np.asarray(matched) < 0])[::-1]
+    n_fp = int(n_fp)
+    if n_fp >= len(neg):
+        return float("-inf")
+    return float(np.nextafter(neg[n_fp], np.float32(np.inf)))
+
+
+class Vetter:
+    """Train and apply the vetting ensemble."""
+
+    def __init__(self, members=5, seed=0, max_batch=4096):
+        self.nets = [sas.MLP(max_batch=max_batch, seed=seed + k) for k in range(members)]
+        self.seed = seed
         self.max_batch = max_batch
         self.mean = None
         self.std = None
         self.tau = None
 
-    def fit(self, feats, labels, epochs=6, lr=1e-3, weight_decay=0.01, seed=0, log=None):
+    def fit(self, feats, labels, epochs=60, lr=1e-3, weight_decay=0.01, log=None):
         import torch
         x = np.ascontiguousarray(feats, dtype=np.float32)
         y = np.ascontiguousarray(labels, dtype=np.float32)
         self.mean = x.mean(axis=0)
         self.std = x.std(axis=0)
-        self.net.set_norm(self.mean, self.std)
         n_pos = max(float(y.sum()), 1.0)
         pw = min((len(y) - n_pos) / n_pos, 100.0)
         xt = torch.as_tensor(x).cuda()
         yt = torch.as_tensor(y).cuda()
-        rng = np.random.default_rng(seed)
         B = self.max_batch
-        for ep in range(epochs):
-            perm = torch.as_tensor(rng.permutation(len(y))).cuda()
-            xs, ys = xt[perm].contiguous(), yt[perm].contiguous()
-            tot = 0.0
-            nb = 0
-            for b in range(0, len(y) - B + 1 if len(y) >= B else 1, B):
-                xb, yb = xs[b:b + B], ys[b:b + B]
-                loss = self.net.train_step(xb, yb, pw, lr=lr, weight_decay=weight_decay)
-                nb += 1
-                if nb % 50 == 0 or b + 2 * B > len(y):
-                    tot = float(loss.cpu())
-            if log:
-                log("epoch %d  loss %.4f  (pos_weight %.1f, %d rows)" % (ep, tot, pw, len(y)))
+        for k, net in enumerate(self.nets):
+            net.set_norm(self.mean, self.std)
+            rng = np.random.default_rng(self.seed + 1000 + k)
+            for ep in range(epochs):
+                perm = torch.as_tensor(rng.permutation(len(y))).cuda()
+                xs, ys = xt[perm].contiguous(), yt[perm].contiguous()
+                loss = None
+                for b in range(0, len(y) - B + 1 if len(y) >= B else 1, B):
+                    loss = net.train_step(xs[b:b + B], ys[b:b + B], pw, lr=lr,
+                                          weight_decay=weight_decay)
+                if log and loss is not None and (ep == epochs - 1 or ep % 20 == 0):
+                    log("member %d epoch %d  loss %.4f  (pos_weight %.1f, %d rows)"
+                        % (k, ep, float(loss.cpu()), pw, len(y)))
         return self
 
     def score(self, feats):
@@ -152,22 +205,100 @@ class Vetter:
         x = torch.as_tensor(np.ascontiguousarray(feats, dtype=np.float32)).cuda()
         if x.shape[0] == 0:
             return np.zeros(0, dtype=np.float32)
-        return self.net.forward(x).cpu().numpy()
+        out = None
+        B = self.max_batch
+        for net in self.nets:
+            z = torch.cat([net.forward(x[b:b + B]) for b in range(0, x.shape[0], B)])
+            out = z if out is None else out + z
+        return (out / len(self.nets)).cpu().numpy()
 
-    def choose_tau(self, scores, matched, findable_mask, target_recall):
-        """Largest threshold whose recall reaches target_recall."""
-        order = np.argsort(-scores)
-        taus = np.unique(scores)[::-1]
-        best = float(taus[-1]) if len(taus) else 0.0
-        # scan thresholds from high to low; recall is monotone in tau
-        lo, hi = 0, len(taus) - 1
-        while lo <= hi:
-            mid = (lo + hi) // 2
-            r, _ = recall_fp(scores >= taus[mid], matched, findable_mask)
-            if r >= target_recall:
-                best = float(taus[mid])
-                hi = mid - 1
-            else:
-                lo = mid + 1
-        self.tau = best
-        return best
+    def choose_tau(self, scores, matched, findable_mask, plain_selected, fp_budget=0.1):
+        """Operating point on validation: min(superset_tau, budget_tau with
+        fp_budget times the plain selection's false positives)."""
+        plain_fp = recall_fp(plain_selected, matched, findable_mask)[1]
+        self.tau = min(superset_tau(scores, matched, findable_mask, plain_selected),
+                       budget_tau(scores, matched, int(fp_budget * plain_fp)))
+        return self.tau
+
+    def close(self):
+        for net in self.nets:
+            net.close()
+        self.nets = []
+
+
+def pools(seeds, n_pool, n_min, make, log=None):
+    """Candidate pools of the catalogs make(seed): features, labels (matched
+    mover, or -1, with movers numbered across the catalogs), counts and the
+    findable mask of those movers."""
+    F, M, C, FIND = [], [], [], []
+    off = 0
+    for sd in seeds:
+        wl = make(sd)
+        v = sas.grid_from_spec(wl.grid, wl.binw_q8, wl.span_q16)
+        recs, feat, cnt, t0 = candidate_pool(wl, v, n_pool)
+        m = match_movers(recs, v, wl.binw_q8, wl.t_q16, t0, wl.truth, wl.bin_px)
+        fnd = findable(wl.truth, n_min)
+        if log:
+            log("seed %d: pool %d, matched %d, findable movers %d"
+                % (sd, len(recs), int((m >= 0).sum()), int(fnd.sum())))
+        F.append(feat)
+        M.append(np.where(m >= 0, m + off, -1))
+        C.append(cnt)
+        FIND.append(fnd)
+        off += len(fnd)
+    return (np.concatenate(F), np.concatenate(M), np.concatenate(C), np.concatenate(FIND))
+
+
+def evaluate(train_seeds, val_seeds, test_seeds, n_pool, n_min, make, members=5, cap=8,
+             epochs=60, seed=0, fp_budget=0.1, log=None):
+    """The vetting protocol: pools at n_pool, training on balanced train
+    pools, tau on validation, recall and false positives on test for the
+    plain threshold n_min and for the learned selection."""
+    tr = pools(train_seeds, n_pool, n_min, make, log)
+    va = pools(val_seeds, n_pool, n_min, make, log)
+    te = pools(test_seeds, n_pool, n_min, make, log)
+    keep = balance(tr[1], cap, seed)
+    vet = Vetter(members=members, seed=seed)
+    try:
+        vet.fit(tr[0][keep], (tr[1][keep] >= 0).astype(np.float32), epochs=epochs, log=log)
+        tau = vet.choose_tau(vet.score(va[0]), va[1], va[3], va[2] >= n_min, fp_budget)
+        st = vet.score(te[0])
+    finally:
+        vet.close()
+    plain = recall_fp(te[2] >= n_min, te[1], te[3])
+    learned = recall_fp(st >= tau, te[1], te[3])
+    curve = {int(k): recall_fp(te[2] >= k, te[1], te[3]) for k in range(n_pool, n_min + 5)}
+    return {"plain": plain, "learned": learned, "tau": tau, "n_min": n_min, "n_pool": n_pool,
+            "pool_test": int(len(te[2])), "findable_test": int(te[3].sum()),
+            "train_rows": int(keep.sum()), "members": members, "epochs": epochs,
+            "plain_curve": curve}
+
+
+# Seeds of the fast-style vetting protocol (train / validation / test chips).
+TRAIN_SEEDS = tuple(range(100, 136))
+VAL_SEEDS = tuple(range(200, 212))
+TEST_SEEDS = tuple(range(300, 312))
+POOL_N_MIN = 19
+
+
+def fast_protocol(members=5, epochs=60, log=None, train=TRAIN_SEEDS, val=VAL_SEEDS,
+                  test=TEST_SEEDS):
+    """The protocol on fast-style chips: pool at N_pool = 19, plain threshold
+    from the threshold rule (Sec. 2.2) for the fast style."""
+    from . import synth
+    return evaluate(train, val, test, POOL_N_MIN, synth.FAST_N_MIN, synth.make_fast,
+                    members=members, epochs=epochs, log=log)
+
+
+if __name__ == "__main__":
+    import json
+    import sys
+    import time
+    t_start = time.time()
+
+    def _log(msg):
+        print("%7.1fs %s" % (time.time() - t_start, msg), file=sys.stderr, flush=True)
+
+    out = fast_protocol(log=_log)
+    out["plain_curve"] = {str(k): v for k, v in out["plain_curve"].items()}
+    print(json.dumps(out), flush=True)

@@ -418,7 +418,8 @@ def _features_case(wl, v, n_min, tuning=None, sample=None, seed=0):
     snr = torch.as_tensor(wl.snr).cuda()
     s.vote(x, y, e)
     s.peaks()
-    recs, feat = s.features(wl.n, snr)
+    spacing = ogrid.spacing_q8(wl.binw_q8, wl.span_q16)
+    recs, feat = s.features(wl.n, snr, spacing_q8=spacing)
     plan.close()
     assert len(recs) > 0
     idx = np.arange(len(recs))
@@ -427,6 +428,8 @@ def _features_case(wl, v, n_min, tuning=None, sample=None, seed=0):
     vmax = float(np.sqrt((v.astype(np.float64) ** 2).sum(axis=1)).max())
     ref = of.candidate_features(wl.x_q8, wl.y_q8, wl.epoch, wl.snr, wl.t_q16, v, wl.binw_q8,
                                 recs[idx], vmax)
+    # neighbours are looked up among the whole candidate list
+    ref[:, 9:11] = of.neighbour_features(recs, v, spacing, rows=idx)
     np.testing.assert_allclose(feat[idx], ref, rtol=1e-5, atol=2e-6)
     return recs, feat
 

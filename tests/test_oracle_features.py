@@ -126,3 +126,28 @@ def test_neighbour_features_by_hand():
     nf = of.neighbour_features(cand, v, 256)
     np.testing.assert_allclose(nf, [[1 / 80, 30 / 20], [1 / 80, 20 / 30], [0, 0]])
     assert np.all(of.neighbour_features(cand, v, 0) == 0)
+
+
+def test_neighbour_features_rounding_sharing_and_rows():
+    """Lattice rounding half up (v = 1.5 s lands on index 2, -1.5 s on -1),
+    two candidates on one lattice index and bin counted once with the larger
+    count, the 4095 cap, and rows looked up against the whole list."""
+    s = 100
+    v = np.array([[150, 0], [200, 0], [-150, 0], [0, 0], [210, 0]], np.int32)
+    cand = np.zeros(5, CAND_DTYPE)
+    cand[0] = (0, 0, 0, 9000, 0)   # index (2, 0), count capped to 4095
+    cand[1] = (3, 1, 1, 50, 0)     # index (0, 0): two lattice steps from 0, no neighbour of it
+    cand[2] = (2, 5, 5, 40, 0)     # index (-1, 0), alone
+    cand[3] = (1, 1, 1, 60, 0)     # index (2, 0), bin (1, 1): next to cand 0
+    cand[4] = (4, 1, 1, 70, 0)     # v = 2.1 s -> index (2, 0), same key as cand 3
+    nf = of.neighbour_features(cand, v, s)
+    # cand 0 sees the shared key (2, 0, 1, 1) once, with count 70
+    np.testing.assert_allclose(nf[0], [1 / 80, 70 / 4095])
+    # cand 1 at (0, 0, 1, 1): nothing at lattice index -1..1 except itself
+    np.testing.assert_allclose(nf[1], [0, 0])
+    np.testing.assert_allclose(nf[2], [0, 0])
+    # cands 3 and 4 share a key: each sees cand 0 only (the shared key is its own)
+    np.testing.assert_allclose(nf[3], [1 / 80, 4095 / 60])
+    np.testing.assert_allclose(nf[4], [1 / 80, 4095 / 70])
+    sub = of.neighbour_features(cand, v, s, rows=[4, 0])
+    np.testing.assert_allclose(sub, nf[[4, 0]])
