@@ -102,6 +102,11 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libsas.so is not built (%s); run python -m paper_2509_26279_amd.build"
                            % LIB_PATH)
+    # torch ships its own HIP runtime; importing it first makes the library
+    # bind to that same runtime (one runtime per process, so torch's device
+    # memory and streams are the library's too).  Loaded the other way round,
+    # torch finds the system runtime already initialised and no device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     sig = {
