@@ -111,7 +111,8 @@ struct sas_plan {
     int64_t n_v = 0;
     int dense_mode = 0;
     int32_t tile_x = 16, tile_y = 16, vbx = 8, vby = 8, groups = 1, cell_log2 = 11;
-    int32_t coarse_log2 = 0, hx = 0, hy = 0, stage_cap = 0, rows = 0, max_pairs = 0;
+    int32_t coarse_log2 = 0, hx = 0, hy = 0, stage_cap = 0, rows = 0, rows_log2 = 0;
+    int32_t max_pairs = 0;
     int32_t ncx = 1, ncy = 1;
     int64_t n_cells = 0, n_items = 0, n_segments = 0, n_tiles = 0, refine_cap = 0;
     size_t lds_bytes = 0;
@@ -219,6 +220,7 @@ DenseArgs dense_args(const sas_plan *p, const WsLayout &L, char *w, const PrepBu
     a.hy = p->hy;
     a.stage_cap = p->stage_cap;
     a.rows = p->rows;
+    a.rows_log2 = p->rows_log2;
     a.max_pairs = p->max_pairs;
     a.n_min = p->n_min;
     a.count_sat = p->count_sat;
@@ -463,6 +465,11 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     auto rows_bound = [&](int c, int64_t ty) {  // index rows one tile's window can touch
         return (int64_t)((ty * cellw + spread_y_max - 1) >> c) + 2;
     };
+    auto log2_ceil = [](int64_t v) {
+        int l = 0;
+        while (((int64_t)1 << l) < v) ++l;
+        return l;
+    };
     // tile shape: the largest interior under the histogram budget with the
     // best ratio of interior to window area (exact windows: the window adds
     // the average spread of a block to each side length)
@@ -495,14 +502,15 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     const int64_t HX = TX + guard_x, HY = TY + guard_y;
     if (!cl) cl = kc + 1;  // window-index cells of 2 x 2 histogram cells
     while (ncells_of(cl, ex[0], ex[1]) > 32767 || ncells_of(cl, ex[2], ex[3]) > 32767 ||
-           (int64_t)d->n_epochs * rows_bound(cl, TY) > 2048)
+           ((int64_t)d->n_epochs << log2_ceil(rows_bound(cl, TY))) > kMaxWindowPairs)
         ++cl;
     if (cl > 30) return fail(SAS_E_UNSUPPORTED, "sas_plan_create: footprint too large");
     const int64_t ncx = ncells_of(cl, ex[0], ex[1]), ncy = ncells_of(cl, ex[2], ex[3]);
     const int64_t n_cells = (int64_t)d->n_epochs * ncx * ncy;
     if (n_cells >= ((int64_t)1 << 30))
         return fail(SAS_E_INVALID, "sas_plan_create: window index too large; raise cell_log2");
-    const int64_t max_pairs = (int64_t)d->n_epochs * rows_bound(cl, TY);
+    const int rows_log2 = log2_ceil(rows_bound(cl, TY));
+    const int64_t max_pairs = (int64_t)d->n_epochs << rows_log2;
     const size_t hist_bytes = (size_t)HX * HY * NV * 4;
     int64_t stage_cap = tu.stage_cap;
     if (!stage_cap) {
@@ -571,6 +579,7 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     p->stage_cap = (int32_t)stage_cap;
     p->max_pairs = (int32_t)max_pairs;
     p->rows = (int32_t)rows_bound(cl, TY);
+    p->rows_log2 = rows_log2;
     p->lds_bytes = lds + lds_static;
     p->cell_log2 = cl;
     p->ncx = (int32_t)ncx;

@@ -10,6 +10,8 @@ namespace sas {
 
 constexpr int kMaxEpochs = 256;
 constexpr int kVoteThreads = 512;          // threads per vote workgroup (8 waves)
+constexpr int kMaxWindowPairs = 2048;      // (epoch, index row) pairs of one tile's windows
+constexpr int kPairsPerThread = kMaxWindowPairs / kVoteThreads;
 constexpr int kSlotWords = kMaxEpochs / 32;
 constexpr int64_t kMaxVoteGrid = 1 << 16;  // workgroups of one vote launch (grid-stride)
 constexpr int kLdsPerCU = 160 * 1024;      // gfx950
@@ -43,7 +45,8 @@ struct DenseArgs {
     int32_t hx, hy;           // histogram cells per tile, guards included
     int32_t stage_cap;        // detections staged in LDS at a time
     int32_t rows;             // index rows a tile window can touch (planner bound)
-    int32_t max_pairs;        // capacity of the run table: E x rows
+    int32_t rows_log2;        // run table rows per epoch: 2^rows_log2 >= rows
+    int32_t max_pairs;        // capacity of the run table: E << rows_log2
     int32_t n_min, count_sat;
     int32_t mode_epochs;      // 1: count distinct epochs, 0: count detections
     const int32_t *vel;       // [n_v][2] velocities, Q8 px/h

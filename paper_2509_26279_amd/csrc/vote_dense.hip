@@ -52,7 +52,7 @@ struct Shared {
 };
 
 // Epochs per wave whose lane shifts stay in registers over a work item.
-constexpr int kEpochRegs = 16;
+constexpr int kEpochRegs = 10;
 
 // ceil(v * d / 65536) for d >= 0: the shift v (t_e - t0) in Q8 pixels,
 // rounded so that the floor of the shifted position is exact.
@@ -152,40 +152,118 @@ __device__ inline void lds_vote(uint32_t addr, uint32_t val) {
         __hip_atomic_fetch_add(p, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// U consecutive votes of lane group g: detections st[g], st[g + G], ...,
+// st[g + (U - 1) G]; (sx, sy) is the lane's shift plus its histogram origin.
+template <int MODE, int G, int U>
+__device__ __attribute__((always_inline)) inline void vote_block(
+    const int2 *st, int g, uint32_t sx, uint32_t sy, int kc, uint32_t row_bytes,
+    uint32_t lane_addr, uint32_t val) {
+    constexpr int LNV = G == 1 ? 6 : G == 2 ? 5 : 4;
+    int2 q[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) q[u] = st[u * G + g];
+    uint32_t addr[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint32_t ix = ((uint32_t)q[u].x - sx) >> kc;
+        const uint32_t iy = ((uint32_t)q[u].y - sy) >> kc;
+        addr[u] = hist_addr(ix, iy, row_bytes, LNV + 2, lane_addr);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) lds_vote<MODE>(addr[u], val);
+}
+
 // Votes of n staged detections st[0, n) of one epoch: lane (g, j) takes
-// detections g, g + G, ...; (sx, sy) is the lane's shift plus its histogram
-// origin.  A group past the end votes (nx, ny), which lands in a guard cell
-// of every lane.
+// detections g, g + G, ...  Blocks of 4 G, then 2 G and G detections while
+// they last (block-uniform branches, no wasted votes); with G > 1 the last
+// partial round is voted by the groups g < n mod G only.
 template <int MODE, int G>
 __device__ inline void vote_run(const int2 *st, int32_t n, uint32_t sx, uint32_t sy, int kc,
-                                uint32_t row_bytes, uint32_t lane_addr, uint32_t val, int g,
-                                int32_t nx, int32_t ny) {
-    constexpr int LNV = G == 1 ? 6 : G == 2 ? 5 : 4;
-    constexpr int U = G == 1 ? 4 : 2;
+                                uint32_t row_bytes, uint32_t lane_addr, uint32_t val, int g) {
     int32_t i = 0;
-    for (; i + G * U <= n; i += G * U) {
-        int2 q[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) q[u] = st[i + u * G + g];
-        uint32_t addr[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint32_t ix = ((uint32_t)q[u].x - sx) >> kc;
-            const uint32_t iy = ((uint32_t)q[u].y - sy) >> kc;
-            addr[u] = hist_addr(ix, iy, row_bytes, LNV + 2, lane_addr);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) lds_vote<MODE>(addr[u], val);
+    for (; i + 4 * G <= n; i += 4 * G)
+        vote_block<MODE, G, 4>(st + i, g, sx, sy, kc, row_bytes, lane_addr, val);
+    if (i + 2 * G <= n) {
+        vote_block<MODE, G, 2>(st + i, g, sx, sy, kc, row_bytes, lane_addr, val);
+        i += 2 * G;
     }
-    for (; i < n; i += G) {
-        int2 q = st[min(i + g, n - 1)];
-        if (G > 1 && i + g >= n) {
-            q.x = nx;
-            q.y = ny;
+    if (i + G <= n) {
+        vote_block<MODE, G, 1>(st + i, g, sx, sy, kc, row_bytes, lane_addr, val);
+        i += G;
+    }
+    if (G > 1 && i + g < n)
+        vote_block<MODE, G, 1>(st + i, g, sx, sy, kc, row_bytes, lane_addr, val);
+}
+
+constexpr int kCopyAhead = 4;  // detections of a run loaded at once
+
+// Run of window-index row r of epoch e for the tile whose Q8 origin is
+// (oxw, oy): source offset and end offset (0, 0 when the window misses the
+// footprint or has fewer rows).
+__device__ __attribute__((always_inline)) inline void window_run(
+    const DenseArgs &a, const Shared &sh, int e, int r, int32_t oxw, int32_t oy, int32_t W,
+    int32_t H, int32_t &src, int32_t &end) {
+    const PreparedCatalog &c = a.cat;
+    src = 0;
+    end = 0;
+    if (sh.dt[e] < 0) return;
+    const int32_t xlo = oxw + sh.es[0][e], xhi = oxw + sh.es[1][e] + W;
+    const int32_t ylo = oy + sh.es[2][e], yhi = oy + sh.es[3][e] + H;
+    int cx0, cx1, cy0, cy1;
+    if (!cell_span(xlo, xhi, c.x0, c.x1, c.cell_log2, &cx0, &cx1) ||
+        !cell_span(ylo, yhi, c.y0, c.y1, c.cell_log2, &cy0, &cy1))
+        return;
+    if (r == 0 && cy1 - cy0 + 1 > a.rows)  // excluded by the planner
+        atomicOr(&a.res->status, SAS_DATA_INTERNAL);
+    if (cy0 + r > cy1) return;
+    const int64_t base = ((int64_t)e * c.ncy + cy0 + r) * c.ncx;
+    src = c.off[base + cx0];
+    end = c.off[base + cx1 + 1];
+}
+
+// First loads of the part [jb, je) of a run (stage positions dst .. dst +
+// len, source src) that falls in the chunk [c0, c1) of the tile's runs.
+__device__ __attribute__((always_inline)) inline void copy_issue(
+    const PreparedCatalog &c, int32_t c0, int32_t c1, int32_t dst, int32_t len, int32_t src,
+    int2 (&q)[kCopyAhead], int32_t &jb, int32_t &je, int32_t &sr) {
+    jb = max(0, c0 - dst);
+    je = max(jb, min(len, c1 - dst));
+    sr = src;
+#pragma unroll
+    for (int u = 0; u < kCopyAhead; ++u)
+        if (jb + u < je) q[u] = c.sxy[src + jb + u];
+}
+
+// Keeps the detections of the issued run part inside the exact window of
+// epoch e and appends them to the epoch's part of the stage (one atomic per
+// kCopyAhead detections); loads the rest of a longer part on the way.
+__device__ __attribute__((always_inline)) inline void copy_complete(
+    const PreparedCatalog &c, Shared &sh, int2 *stage, const int32_t *pdst, int e, int LR,
+    int32_t c0, int32_t oxw, int32_t oy, int32_t W, int32_t H, int2 (&q)[kCopyAhead],
+    int32_t jb, int32_t je, int32_t sr) {
+    if (jb >= je) return;
+    const int32_t x0 = oxw + sh.es[0][e], x1 = oxw + sh.es[1][e] + W;
+    const int32_t y0 = oy + sh.es[2][e], y1 = oy + sh.es[3][e] + H;
+    const int32_t b = max(pdst[e << LR], c0) - c0;
+    for (int32_t jj = jb; jj < je; jj += kCopyAhead) {
+        if (jj > jb) {
+#pragma unroll
+            for (int u = 0; u < kCopyAhead; ++u)
+                if (jj + u < je) q[u] = c.sxy[sr + jj + u];
         }
-        const uint32_t ix = ((uint32_t)q.x - sx) >> kc;
-        const uint32_t iy = ((uint32_t)q.y - sy) >> kc;
-        lds_vote<MODE>(hist_addr(ix, iy, row_bytes, LNV + 2, lane_addr), val);
+        bool keep[kCopyAhead];
+        int32_t nk = 0;
+#pragma unroll
+        for (int u = 0; u < kCopyAhead; ++u) {
+            keep[u] = jj + u < je && q[u].x >= x0 && q[u].x < x1 && q[u].y >= y0 && q[u].y < y1;
+            nk += keep[u];
+        }
+        if (nk > 0) {
+            int32_t slot = b + atomicAdd(&sh.ecnt[e], nk);
+#pragma unroll
+            for (int u = 0; u < kCopyAhead; ++u)
+                if (keep[u]) stage[slot++] = q[u];
+        }
     }
 }
 
@@ -209,16 +287,17 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
     const PreparedCatalog &c = a.cat;
     const int E = c.n_epochs;
     const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
-    const int g = lane >> LNV, j = lane & (NV - 1);
+    const int g = G == 1 ? 0 : lane >> LNV, j = lane & (NV - 1);
     const int kc = a.log2b + a.coarse_log2;
     const int32_t cellw = (int32_t)1 << kc;
     const int32_t W = a.tile_x << kc, H = a.tile_y << kc;  // tile size, Q8
     const uint32_t nmin = (uint32_t)a.n_min;
     const uint32_t row_bytes = (uint32_t)(a.hx * NV * 4);
-    // run table: pairs (epoch, index row r < R), epoch-major; thread tid owns
-    // pairs [p0, p0 + per)
-    const int R = a.rows;
-    const int np = E * R;  // <= max_pairs
+    // run table: pairs p = (e << LR) + r of epoch e and index row r < 2^LR
+    // (rows past the window's are empty), epoch-major; thread tid owns pairs
+    // [p0, p0 + per)
+    const int LR = a.rows_log2;
+    const int np = E << LR;  // == max_pairs
     const int per = (np + T - 1) / T;
     const int p0 = tid * per;
     const int32_t vx_lo = a.seg[4 * sg], vx_hi = a.seg[4 * sg + 1];
@@ -288,92 +367,94 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         if (tid == 0) atomicOr(&a.res->status, SAS_DATA_INTERNAL);
         return;
     }
+    // from here on Sx, Sy hold the shift plus the Q8 origin of the lane's
+    // histogram for the current tile: row 0 at ty0 - gy cells, column 0 at
+    // tx0 - gx cells
+#pragma unroll
+    for (int k = 0; k < kEpochRegs; ++k) {
+        Sx[k] += (int32_t)((uint32_t)(txf - my_gx) * (uint32_t)cellw);
+        Sy[k] += (int32_t)oy_lane;
+    }
+
+    // Run of each of this thread's (epoch, index row) pairs p0 + k: the
+    // windows of a tile are laid out epoch-major (psrc, pdst), and the
+    // ecnt of every epoch is reset.  Returns the total M (block uniform).
+    const auto lay_out = [&](const int32_t (&src)[kPairsPerThread],
+                             const int32_t (&len)[kPairsPerThread],
+                             int32_t (&dst)[kPairsPerThread]) __attribute__((always_inline)) {
+        int32_t lsum = 0;
+#pragma unroll
+        for (int k = 0; k < kPairsPerThread; ++k) {
+            if (k < per && p0 + k < np) psrc[p0 + k] = src[k];
+            lsum += len[k];
+        }
+        if (tid < E) sh.ecnt[tid] = 0;
+        parity ^= 1;
+        int32_t total;
+        int32_t run = scan_block(lsum, &total, sh.wsum[parity]);
+#pragma unroll
+        for (int k = 0; k < kPairsPerThread; ++k) {
+            dst[k] = run;
+            if (k < per && p0 + k < np) pdst[p0 + k] = run;
+            run += len[k];
+        }
+        if (tid == 0) pdst[np] = total;
+        return total;
+    };
+    // Stages the chunk [c0, c1) of the tile at oxw for the pairs k >= k0,
+    // two at a time, reading the run table (after a barrier).
+    const auto copy_rest = [&](int k0, int32_t c0, int32_t c1, int32_t oxw)
+                               __attribute__((always_inline)) {
+        for (int k = k0; k < per; k += 2) {
+            const int pa = p0 + k, pb = pa + 1;
+            int2 qa[kCopyAhead], qb[kCopyAhead];
+            int32_t jba = 0, jea = 0, sra = 0, jbb = 0, jeb = 0, srb = 0;
+            if (pa < np)
+                copy_issue(c, c0, c1, pdst[pa], pdst[pa + 1] - pdst[pa], psrc[pa], qa, jba, jea,
+                           sra);
+            if (k + 1 < per && pb < np)
+                copy_issue(c, c0, c1, pdst[pb], pdst[pb + 1] - pdst[pb], psrc[pb], qb, jbb, jeb,
+                           srb);
+            copy_complete(c, sh, stage, pdst, pa >> LR, LR, c0, oxw, oy, W, H, qa, jba, jea, sra);
+            copy_complete(c, sh, stage, pdst, pb >> LR, LR, c0, oxw, oy, W, H, qb, jbb, jeb, srb);
+        }
+    };
+
+    // Tile 0: windows, run table and its first chunk.
+    int32_t M;
+    {
+        int32_t src[kPairsPerThread], len[kPairsPerThread], dst[kPairsPerThread];
+#pragma unroll
+        for (int k = 0; k < kPairsPerThread; ++k) {
+            int32_t end = 0;
+            src[k] = 0;
+            if (k < per && p0 + k < np)
+                window_run(a, sh, (p0 + k) >> LR, (p0 + k) & ((1 << LR) - 1), txf * cellw, oy, W, H, src[k], end);
+            len[k] = end - src[k];
+        }
+        M = lay_out(src, len, dst);
+        __syncthreads();  // run table visible
+        copy_rest(0, 0, min(M, a.stage_cap), txf * cellw);
+        __syncthreads();  // stage ready
+    }
 
     for (int32_t ti = 0; ti < ntiles; ++ti) {
         const int32_t tx0 = txf + ti * a.tile_x;
         const int32_t ox = tx0 * cellw;
         const uint32_t ox_lane = (uint32_t)(tx0 - my_gx) * (uint32_t)cellw;
-        parity ^= 1;
+        const bool next = ti + 1 < ntiles;  // block uniform
+        const int32_t oxn = ox + a.tile_x * cellw;
 
-        // 1. exact windows and run lengths, one thread per (epoch, index row);
-        //    then a block scan lays the runs out (epoch-major)
-        int32_t lsum = 0;
-        for (int k = 0; k < per; ++k) {
-            const int p = p0 + k;
-            if (p >= np) break;
-            const int e = p / R, r = p - e * R;
-            int32_t src = 0, len = 0;
-            if (sh.dt[e] >= 0) {
-                const int32_t xlo = ox + sh.es[0][e], xhi = ox + sh.es[1][e] + W;
-                const int32_t ylo = oy + sh.es[2][e], yhi = oy + sh.es[3][e] + H;
-                int cx0, cx1, cy0, cy1;
-                if (cell_span(xlo, xhi, c.x0, c.x1, c.cell_log2, &cx0, &cx1) &&
-                    cell_span(ylo, yhi, c.y0, c.y1, c.cell_log2, &cy0, &cy1)) {
-                    if (r == 0 && cy1 - cy0 + 1 > R)  // excluded by the planner
-                        atomicOr(&a.res->status, SAS_DATA_INTERNAL);
-                    if (cy0 + r <= cy1) {
-                        const int64_t base = ((int64_t)e * c.ncy + cy0 + r) * c.ncx;
-                        src = c.off[base + cx0];
-                        len = c.off[base + cx1 + 1] - src;
-                    }
-                }
-            }
-            psrc[p] = src;
-            pdst[p] = len;
-            lsum += len;
-        }
-        if (tid < E) sh.ecnt[tid] = 0;
-        int32_t M;
-        int32_t run = scan_block(lsum, &M, sh.wsum[parity]);
-        for (int k = 0; k < per; ++k) {
-            const int p = p0 + k;
-            if (p >= np) break;
-            const int32_t len = pdst[p];
-            pdst[p] = run;
-            run += len;
-        }
-        if (tid == 0) pdst[np] = M;
-        if (M == 0) continue;  // block uniform; nothing to vote, the histogram is clear
+        // 2. vote, chunk by chunk (the first chunk is staged)
         if (M > a.stage_cap && tid == 0) atomicAdd(&a.res->n_spilled, 1);
-
-        // 2. stage and vote, chunk by chunk
         for (int32_t c0 = 0; c0 < M; c0 += a.stage_cap) {
-            const int32_t c1 = min(M, c0 + a.stage_cap);
-            if (c0 > 0) {  // the previous chunk is voted: reset its counters
+            if (c0 > 0) {  // the previous chunk is voted: stage the next one
                 __syncthreads();
                 if (tid < E) sh.ecnt[tid] = 0;
+                __syncthreads();
+                copy_rest(0, c0, min(M, c0 + a.stage_cap), ox);
+                __syncthreads();
             }
-            __syncthreads();  // run table and counters ready
-            // each thread copies the part of its own runs inside [c0, c1),
-            // keeping the detections inside the exact window
-            for (int k = 0; k < per; ++k) {
-                const int p = p0 + k;
-                if (p >= np) break;
-                const int32_t dst = pdst[p], len = pdst[p + 1] - dst;
-                const int32_t j0 = max(0, c0 - dst), j1 = min(len, c1 - dst);
-                if (j0 >= j1) continue;
-                const int e = p / R;
-                const int32_t src = psrc[p];
-                const int32_t x0 = ox + sh.es[0][e], x1 = ox + sh.es[1][e] + W;
-                const int32_t y0 = oy + sh.es[2][e], y1 = oy + sh.es[3][e] + H;
-                const int32_t b = max(pdst[e * R], c0) - c0;
-                for (int32_t jj = j0; jj < j1; jj += 8) {
-                    int2 q[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u)
-                        if (jj + u < j1) q[u] = c.sxy[src + jj + u];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        if (jj + u < j1 && q[u].x >= x0 && q[u].x < x1 && q[u].y >= y0 &&
-                            q[u].y < y1) {
-                            const int32_t slot = atomicAdd(&sh.ecnt[e], 1);
-                            stage[b + slot] = q[u];
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-
             // vote: wave w takes epochs w, w + NW, ...; their counts and
             // stage offsets are read once, one per lane
             int32_t my_n = 0, my_b = 0;
@@ -381,7 +462,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                 const int e = wave + lane * NW;
                 if (e < E) {
                     my_n = sh.ecnt[e];
-                    my_b = max(pdst[e * R], c0) - c0;
+                    my_b = max(pdst[e << LR], c0) - c0;
                 }
             }
 #pragma unroll
@@ -391,10 +472,8 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                 const int32_t n = __builtin_amdgcn_readlane(my_n, k);
                 if (n == 0) continue;
                 const int32_t b = __builtin_amdgcn_readlane(my_b, k);
-                vote_run<MODE, G>(stage + b, n, (uint32_t)Sx[k] + ox_lane,
-                                  (uint32_t)Sy[k] + oy_lane, kc, row_bytes, lane_addr,
-                                  MODE == kMask32 ? (1u << e) : 1u, g,
-                                  ox + sh.es[0][e] - 1, oy + sh.es[2][e] - 1);
+                vote_run<MODE, G>(stage + b, n, (uint32_t)Sx[k], (uint32_t)Sy[k], kc, row_bytes,
+                                  lane_addr, MODE == kMask32 ? (1u << e) : 1u, g);
             }
             for (int k = kEpochRegs; wave + k * NW < E; ++k) {
                 const int e = wave + k * NW;
@@ -404,52 +483,87 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                 const int32_t d = sh.dt[e];
                 vote_run<MODE, G>(stage + b, n, (uint32_t)shift_q8(my_vx, d) + ox_lane,
                                   (uint32_t)shift_q8(my_vy, d) + oy_lane, kc, row_bytes,
-                                  lane_addr, MODE == kMask32 ? (1u << e) : 1u, g,
-                                  ox + sh.es[0][e] - 1, oy + sh.es[2][e] - 1);
+                                  lane_addr, MODE == kMask32 ? (1u << e) : 1u, g);
             }
         }
-        __syncthreads();
+        __syncthreads();  // votes done: stage, counters and run table are free
+
+        // the next tile's run table, and the loads of its first chunk, in
+        // flight over the scan and clear of this tile
+        int32_t Mn = 0;
+        int2 q0[kCopyAhead], q1[kCopyAhead];
+        int32_t jb0 = 0, je0 = 0, sr0 = 0, jb1 = 0, je1 = 0, sr1 = 0;
+        if (next) {
+            int32_t src[kPairsPerThread], len[kPairsPerThread], dst[kPairsPerThread];
+#pragma unroll
+            for (int k = 0; k < kPairsPerThread; ++k) {
+                int32_t end = 0;
+                src[k] = 0;
+                if (k < per && p0 + k < np)
+                    window_run(a, sh, (p0 + k) >> LR, (p0 + k) & ((1 << LR) - 1), oxn, oy, W, H, src[k], end);
+                len[k] = end - src[k];
+            }
+            Mn = lay_out(src, len, dst);
+            const int32_t c1 = min(Mn, a.stage_cap);
+            copy_issue(c, 0, c1, dst[0], len[0], src[0], q0, jb0, je0, sr0);
+            copy_issue(c, 0, c1, dst[1], len[1], src[1], q1, jb1, je1, sr1);
+        }
 
         // 3. read and clear the histogram; emit or queue interior cells
-        for (int w0 = 0; w0 < hist_words / 4; w0 += T) {
-            const int w4 = w0 + tid;
-            uint4 h = make_uint4(0, 0, 0, 0);
-            if (w4 < hist_words / 4) {
-                h = smem4[w4];
-                smem4[w4] = make_uint4(0, 0, 0, 0);
-            }
-            const uint32_t m = max(max(cell_count<MODE>(h.x), cell_count<MODE>(h.y)),
-                                   max(cell_count<MODE>(h.z), cell_count<MODE>(h.w)));
-            if (!__any(m >= nmin)) continue;  // wave uniform
-            const uint32_t hw[4] = {h.x, h.y, h.z, h.w};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int wi = 4 * w4 + k;
-                const uint32_t cnt = cell_count<MODE>(hw[k]);
-                bool ok = false;
-                uint32_t v = 0;
-                int32_t bx = 0, by = 0;
-                if (cnt >= nmin) {
-                    const int jj = wi & (NV - 1), bin = wi >> LNV;
-                    const int iy = bin / a.hx, ix = bin - iy * a.hx;
-                    const int cx = ix - (sh.sg[jj] & 0xffff), cy = iy - (sh.sg[jj] >> 16);
-                    ok = sh.sv[jj] >= 0 && cx >= 0 && cx < a.tile_x && cy >= 0 &&
-                         cy < a.tile_y;
-                    v = (uint32_t)sh.sv[jj];
-                    bx = tx0 + cx;
-                    by = ty0 + cy;
+        if (M > 0) {
+            for (int w0 = 0; w0 < hist_words / 4; w0 += T) {
+                const int w4 = w0 + tid;
+                uint4 h = make_uint4(0, 0, 0, 0);
+                if (w4 < hist_words / 4) {
+                    h = smem4[w4];
+                    smem4[w4] = make_uint4(0, 0, 0, 0);
                 }
-                if (MODE == kCountRef) {
-                    const int64_t idx = wave_append(ok, a.refine_count);
-                    if (ok && idx < a.refine_cap) a.refine[idx] = make_int4((int32_t)v, bx, by, 0);
-                } else {
-                    const int64_t idx = wave_append(ok, (unsigned long long *)&a.res->n_cand);
-                    if (ok && idx < a.cand_cap)
-                        write_cand(a.cand, idx, v, bx, by, cnt, (uint32_t)a.count_sat);
+                const uint32_t m = max(max(cell_count<MODE>(h.x), cell_count<MODE>(h.y)),
+                                       max(cell_count<MODE>(h.z), cell_count<MODE>(h.w)));
+                if (!__any(m >= nmin)) continue;  // wave uniform
+                const uint32_t hw[4] = {h.x, h.y, h.z, h.w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int wi = 4 * w4 + k;
+                    const uint32_t cnt = cell_count<MODE>(hw[k]);
+                    bool ok = false;
+                    uint32_t v = 0;
+                    int32_t bx = 0, by = 0;
+                    if (cnt >= nmin) {
+                        const int jj = wi & (NV - 1), bin = wi >> LNV;
+                        const int iy = bin / a.hx, ix = bin - iy * a.hx;
+                        const int cx = ix - (sh.sg[jj] & 0xffff), cy = iy - (sh.sg[jj] >> 16);
+                        ok = sh.sv[jj] >= 0 && cx >= 0 && cx < a.tile_x && cy >= 0 &&
+                             cy < a.tile_y;
+                        v = (uint32_t)sh.sv[jj];
+                        bx = tx0 + cx;
+                        by = ty0 + cy;
+                    }
+                    if (MODE == kCountRef) {
+                        const int64_t idx = wave_append(ok, a.refine_count);
+                        if (ok && idx < a.refine_cap)
+                            a.refine[idx] = make_int4((int32_t)v, bx, by, 0);
+                    } else {
+                        const int64_t idx =
+                            wave_append(ok, (unsigned long long *)&a.res->n_cand);
+                        if (ok && idx < a.cand_cap)
+                            write_cand(a.cand, idx, v, bx, by, cnt, (uint32_t)a.count_sat);
+                    }
                 }
             }
         }
-        // the next write to the histogram comes after several barriers
+
+        if (next) {
+            __syncthreads();  // the next tile's run table is visible
+            copy_complete(c, sh, stage, pdst, p0 >> LR, LR, 0, oxn, oy, W, H, q0, jb0, je0, sr0);
+            copy_complete(c, sh, stage, pdst, (p0 + 1) >> LR, LR, 0, oxn, oy, W, H, q1, jb1, je1,
+                          sr1);
+            copy_rest(2, 0, min(Mn, a.stage_cap), oxn);
+            __syncthreads();  // stage ready; the histogram is clear
+        }
+        M = Mn;
+#pragma unroll
+        for (int k = 0; k < kEpochRegs; ++k) Sx[k] += a.tile_x * cellw;
     }
 }
 
