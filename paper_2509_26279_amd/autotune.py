@@ -35,6 +35,8 @@ def candidates(base: dict) -> list:
     out = [dict()]
     for g in (1, 2, 4):
         out.append({"groups": g})
+        for cl in (-1, 1):  # window-index cells one step finer or coarser than the planner's
+            out.append({"groups": g, "cell_log2_step": cl})
         for tx, ty in ((8, 8), (12, 10), (16, 12), (24, 16), (16, 24)):
             out.append({"groups": g, "tile_x": tx, "tile_y": ty})
     return [dict(base, **c) for c in out]
@@ -71,6 +73,13 @@ def tune(v, t_q16, binw_q8, n_min, extent_q8, x, y, e, mode="epochs", count_sat=
     table = []
     for tun in (cands or candidates(base)):
         try:
+            if "cell_log2_step" in tun:  # relative to the planner's window-index cells
+                tun = dict(tun)
+                step = tun.pop("cell_log2_step")
+                probe = sas.Plan(v, t_q16, binw_q8, n_min, extent_q8, mode=mode,
+                                 count_sat=count_sat, tuning=tun)
+                tun["cell_log2"] = probe.info()["cell_log2"] + step
+                probe.close()
             plan = sas.Plan(v, t_q16, binw_q8, n_min, extent_q8, mode=mode,
                             count_sat=count_sat, tuning=tun)
         except sas.SasError as err:  # shape does not fit (LDS, guard cells)
