@@ -112,7 +112,6 @@ struct sas_plan {
     int dense_mode = 0;
     int32_t tile_x = 16, tile_y = 16, vbx = 8, vby = 8, groups = 1, cell_log2 = 11;
     int32_t coarse_log2 = 0, hx = 0, hy = 0, stage_cap = 0, rows = 0, rows_log2 = 0;
-    int32_t max_pairs = 0;
     int32_t ncx = 1, ncy = 1;
     int64_t n_cells = 0, n_items = 0, n_segments = 0, n_tiles = 0, refine_cap = 0;
     size_t lds_bytes = 0;
@@ -221,7 +220,6 @@ DenseArgs dense_args(const sas_plan *p, const WsLayout &L, char *w, const PrepBu
     a.stage_cap = p->stage_cap;
     a.rows = p->rows;
     a.rows_log2 = p->rows_log2;
-    a.max_pairs = p->max_pairs;
     a.n_min = p->n_min;
     a.count_sat = p->count_sat;
     a.mode_epochs = p->mode == SAS_MODE_EPOCHS ? 1 : 0;
@@ -505,7 +503,7 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
         while (cl < 30 && (((int64_t)TY << kc) >> (cl + 1)) >= 4) ++cl;
     }
     while (ncells_of(cl, ex[0], ex[1]) > 32767 || ncells_of(cl, ex[2], ex[3]) > 32767 ||
-           ((int64_t)d->n_epochs << log2_ceil(rows_bound(cl, TY))) > kMaxWindowPairs)
+           ((((int64_t)d->n_epochs + 7) / 8) << log2_ceil(rows_bound(cl, TY))) > kMaxWavePairs)
         ++cl;
     if (cl > 30) return fail(SAS_E_UNSUPPORTED, "sas_plan_create: footprint too large");
     const int64_t ncx = ncells_of(cl, ex[0], ex[1]), ncy = ncells_of(cl, ex[2], ex[3]);
@@ -513,11 +511,10 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     if (n_cells >= ((int64_t)1 << 30))
         return fail(SAS_E_INVALID, "sas_plan_create: window index too large; raise cell_log2");
     const int rows_log2 = log2_ceil(rows_bound(cl, TY));
-    const int64_t max_pairs = (int64_t)d->n_epochs << rows_log2;
     const size_t hist_bytes = (size_t)HX * HY * NV * 4;
     int64_t stage_cap = tu.stage_cap;
     if (!stage_cap) {
-        const size_t fixed = dense_lds_bytes(G, (int)HX, (int)HY, 0, (int)max_pairs);
+        const size_t fixed = dense_lds_bytes(G, (int)HX, (int)HY, 0);
         const size_t room = lds_target > fixed ? (lds_target - fixed) / sizeof(int2) : 0;
         int64_t want = (int64_t)room;
         if (tu.n_det_hint > 0) {
@@ -527,8 +524,10 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
         }
         stage_cap = std::max<int64_t>(want, 256);
     }
-    stage_cap = (stage_cap + 1) & ~(int64_t)1;
-    const size_t lds = dense_lds_bytes(G, (int)HX, (int)HY, (int)stage_cap, (int)max_pairs);
+    // one part per wave of the workgroup, at least two detections each
+    stage_cap = std::max<int64_t>((stage_cap + kVoteWaves - 1) / kVoteWaves * kVoteWaves,
+                                  2 * kVoteWaves);
+    const size_t lds = dense_lds_bytes(G, (int)HX, (int)HY, (int)stage_cap);
     if (HX > 65535 || HY > 65535 || hist_bytes > lds_cap || lds > lds_cap)
         return fail(SAS_E_INVALID, "sas_plan_create: tile + guard cells + stage exceed the LDS of "
                                    "a workgroup; lower tile_x, tile_y, stage_cap or vblock");
@@ -580,7 +579,6 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     p->hx = (int32_t)HX;
     p->hy = (int32_t)HY;
     p->stage_cap = (int32_t)stage_cap;
-    p->max_pairs = (int32_t)max_pairs;
     p->rows = (int32_t)rows_bound(cl, TY);
     p->rows_log2 = rows_log2;
     p->lds_bytes = lds + lds_static;
@@ -1056,8 +1054,7 @@ sas_status sas_batch_create(const sas_batch_chip *chips, int32_t n_chips, void *
             const sas_plan *p = chips[c].plan;
             if (p->dense_mode * 3 + (p->groups == 1 ? 0 : p->groups == 2 ? 1 : 2) != k) continue;
             cl.hist_words_max = std::max(cl.hist_words_max, p->hx * p->hy * (64 / p->groups));
-            cl.lds = std::max(cl.lds, dense_lds_bytes(p->groups, p->hx, p->hy, p->stage_cap,
-                                                      p->max_pairs));
+            cl.lds = std::max(cl.lds, dense_lds_bytes(p->groups, p->hx, p->hy, p->stage_cap));
         }
         cl.n_items = (int64_t)v.size();
         void *d = nullptr;

@@ -9,9 +9,9 @@
 namespace sas {
 
 constexpr int kMaxEpochs = 256;
-constexpr int kVoteThreads = 512;          // threads per vote workgroup (8 waves)
-constexpr int kMaxWindowPairs = 2048;      // (epoch, index row) pairs of one tile's windows
-constexpr int kPairsPerThread = kMaxWindowPairs / kVoteThreads;
+constexpr int kVoteThreads = 512;          // threads per vote workgroup
+constexpr int kVoteWaves = kVoteThreads / 64;
+constexpr int kMaxWavePairs = 128;         // (epoch, index row) pairs of one wave's windows
 constexpr int kSlotWords = kMaxEpochs / 32;
 constexpr int64_t kMaxVoteGrid = 1 << 16;  // workgroups of one vote launch (grid-stride)
 constexpr int kLdsPerCU = 160 * 1024;      // gfx950
@@ -45,8 +45,7 @@ struct DenseArgs {
     int32_t hx, hy;           // histogram cells per tile, guards included
     int32_t stage_cap;        // detections staged in LDS at a time
     int32_t rows;             // index rows a tile window can touch (planner bound)
-    int32_t rows_log2;        // run table rows per epoch: 2^rows_log2 >= rows
-    int32_t max_pairs;        // capacity of the run table: E << rows_log2
+    int32_t rows_log2;        // run rows per epoch: 2^rows_log2 >= rows
     int32_t n_min, count_sat;
     int32_t mode_epochs;      // 1: count distinct epochs, 0: count detections
     const int32_t *vel;       // [n_v][2] velocities, Q8 px/h
@@ -197,7 +196,7 @@ hipError_t launch_vote_dense_batch(int mode, int groups, const DenseArgs *chips_
                                    int32_t hist_words_max, size_t lds, int grid,
                                    hipStream_t stream);
 hipError_t launch_refine(const DenseArgs &a, hipStream_t stream);
-size_t dense_lds_bytes(int groups, int hx, int hy, int stage_cap, int max_pairs);
+size_t dense_lds_bytes(int groups, int hx, int hy, int stage_cap);
 size_t dense_static_lds_bytes();
 
 }  // namespace sas

@@ -43,8 +43,7 @@ constexpr int NW = T / 64;
 struct Shared {
     int32_t dt[kMaxEpochs];
     int32_t es[4][kMaxEpochs];  // per epoch: S(vx_lo), S(vx_hi), S(vy_lo), S(vy_hi) of the segment
-    int32_t ecnt[kMaxEpochs];   // staged detections of the epoch in the current chunk
-    int32_t wsum[2][NW];        // block scan partials (alternating per tile)
+    int32_t voted[3];           // tile t % 3 has staged detections (set before it is voted)
     int32_t sv[64];             // segment: v_idx of each velocity lane (-1: unused)
     int32_t svx[64], svy[64];   // segment: velocity of each lane
     int32_t sg[64];             // segment: left guard cells of each lane, gx | gy << 16
@@ -81,31 +80,6 @@ __device__ inline int64_t wave_append(bool ok, unsigned long long *counter) {
     const uint32_t pre = __builtin_amdgcn_mbcnt_hi(
         (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
     return (int64_t)base + pre;
-}
-
-// Exclusive scan over the T threads of the block; *total gets the sum.
-// wsum[NW] must not be read by an earlier call that some thread may still
-// be in (alternate two arrays).
-__device__ inline int32_t scan_block(int32_t v, int32_t *total, int32_t *wsum) {
-    const int lane = __lane_id();
-    const int wave = threadIdx.x >> 6;
-    int32_t incl = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int32_t o = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += o;
-    }
-    if (lane == 63) wsum[wave] = incl;
-    __syncthreads();
-    int32_t off = 0, tot = 0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-        const int32_t s = wsum[w];
-        off += (w < wave) ? s : 0;
-        tot += s;
-    }
-    *total = tot;
-    return off + incl - v;
 }
 
 // Cell rows/columns of the window index that an axis interval [lo, hi) of
@@ -221,68 +195,71 @@ __device__ __attribute__((always_inline)) inline void window_run(
     end = c.off[base + cx1 + 1];
 }
 
-// First loads of the part [jb, je) of a run (stage positions dst .. dst +
-// len, source src) that falls in the chunk [c0, c1) of the tile's runs.
-__device__ __attribute__((always_inline)) inline void copy_issue(
-    const PreparedCatalog &c, int32_t c0, int32_t c1, int32_t dst, int32_t len, int32_t src,
-    int2 (&q)[kCopyAhead], int32_t &jb, int32_t &je, int32_t &sr) {
-    jb = max(0, c0 - dst);
-    je = max(jb, min(len, c1 - dst));
-    sr = src;
+// Exclusive scan over the 64 lanes of a wave; *total gets the sum.
+__device__ __attribute__((always_inline)) inline int32_t wave_scan(int32_t v, int32_t *total) {
+    const int lane = __lane_id();
+    int32_t incl = v;
 #pragma unroll
-    for (int u = 0; u < kCopyAhead; ++u)
-        if (jb + u < je) q[u] = c.sxy[src + jb + u];
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    *total = __shfl(incl, 63, 64);
+    return incl - v;
 }
 
-// Keeps the detections of the issued run part inside the exact window of
-// epoch e and appends them to the epoch's part of the stage (one atomic per
-// kCopyAhead detections); loads the rest of a longer part on the way.
-__device__ __attribute__((always_inline)) inline void copy_complete(
-    const PreparedCatalog &c, Shared &sh, int2 *stage, const int32_t *pdst, int e, int LR,
-    int32_t c0, int32_t oxw, int32_t oy, int32_t W, int32_t H, int2 (&q)[kCopyAhead],
-    int32_t jb, int32_t je, int32_t sr) {
-    if (jb >= je) return;
-    const int32_t x0 = oxw + sh.es[0][e], x1 = oxw + sh.es[1][e] + W;
-    const int32_t y0 = oy + sh.es[2][e], y1 = oy + sh.es[3][e] + H;
-    const int32_t b = max(pdst[e << LR], c0) - c0;
+// Exact window of epoch e for the tile whose Q8 origin is (oxw, oy).
+struct Window {
+    int32_t x0, x1, y0, y1;
+    __device__ bool holds(int2 q) const {
+        return (uint32_t)(q.x - x0) < (uint32_t)(x1 - x0) &&
+               (uint32_t)(q.y - y0) < (uint32_t)(y1 - y0);
+    }
+};
+
+__device__ __attribute__((always_inline)) inline Window window_of(const Shared &sh, int e,
+                                                                 int32_t oxw, int32_t oy,
+                                                                 int32_t W, int32_t H) {
+    return Window{oxw + sh.es[0][e], oxw + sh.es[1][e] + W, oy + sh.es[2][e],
+                  oy + sh.es[3][e] + H};
+}
+
+// One lane's part [jb, je) of a window-index run (source src): the
+// detections inside the window w, counted (write = false) or appended at
+// dst (write = true).  kCopyAhead loads at a time.
+template <bool WRITE>
+__device__ __attribute__((always_inline)) inline int32_t run_part(
+    const PreparedCatalog &c, int32_t src, int32_t jb, int32_t je, Window w, int2 *dst) {
+    int32_t n = 0;
     for (int32_t jj = jb; jj < je; jj += kCopyAhead) {
-        if (jj > jb) {
+        int2 q[kCopyAhead];
 #pragma unroll
-            for (int u = 0; u < kCopyAhead; ++u)
-                if (jj + u < je) q[u] = c.sxy[sr + jj + u];
-        }
-        bool keep[kCopyAhead];
-        int32_t nk = 0;
+        for (int u = 0; u < kCopyAhead; ++u)
+            if (jj + u < je) q[u] = c.sxy[src + jj + u];
 #pragma unroll
         for (int u = 0; u < kCopyAhead; ++u) {
-            keep[u] = jj + u < je && q[u].x >= x0 && q[u].x < x1 && q[u].y >= y0 && q[u].y < y1;
-            nk += keep[u];
-        }
-        if (nk > 0) {
-            int32_t slot = b + atomicAdd(&sh.ecnt[e], nk);
-#pragma unroll
-            for (int u = 0; u < kCopyAhead; ++u)
-                if (keep[u]) stage[slot++] = q[u];
+            if (jj + u < je && w.holds(q[u])) {
+                if (WRITE) dst[n] = q[u];
+                ++n;
+            }
         }
     }
+    return n;
 }
 
-// Dynamic LDS: histogram [HY][HX][NV] words, then the stage (int2), then the
-// run table of the window index (source offset and exclusive prefix of every
-// (epoch, row) pair).
+// Dynamic LDS: histogram [HY][HX][NV] words, then the stage (int2), one
+// part of stage_cap / NW detections per wave.
 // One work item: a segment and a row of ntiles tiles starting at tile column
 // txf (cells), tile row ty0.  The histogram is all zero on entry and on exit;
 // sh.dt holds the catalog's d_e.
 template <int MODE, int G>
 __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t sg, int32_t ty0,
-                          int32_t txf, int32_t ntiles, int &parity) {
+                          int32_t txf, int32_t ntiles, int32_t &tseq) {
     constexpr int NV = 64 / G;
     constexpr int LNV = G == 1 ? 6 : G == 2 ? 5 : 4;
     uint32_t *hist = (uint32_t *)smem4;
     const int hist_words = a.hx * a.hy * NV;
     int2 *stage = (int2 *)(hist + hist_words);
-    int32_t *psrc = (int32_t *)(stage + a.stage_cap);
-    int32_t *pdst = psrc + a.max_pairs;
 
     const PreparedCatalog &c = a.cat;
     const int E = c.n_epochs;
@@ -293,13 +270,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
     const int32_t W = a.tile_x << kc, H = a.tile_y << kc;  // tile size, Q8
     const uint32_t nmin = (uint32_t)a.n_min;
     const uint32_t row_bytes = (uint32_t)(a.hx * NV * 4);
-    // run table: pairs p = (e << LR) + r of epoch e and index row r < 2^LR
-    // (rows past the window's are empty), epoch-major; thread tid owns pairs
-    // [p0, p0 + per)
-    const int LR = a.rows_log2;
-    const int np = E << LR;  // == max_pairs
-    const int per = (np + T - 1) / T;
-    const int p0 = tid * per;
+    const int LR = a.rows_log2;  // run rows per epoch: 2^LR
     const int32_t vx_lo = a.seg[4 * sg], vx_hi = a.seg[4 * sg + 1];
     const int32_t vy_lo = a.seg[4 * sg + 2], vy_hi = a.seg[4 * sg + 3];
     __syncthreads();  // the previous item no longer reads the segment tables
@@ -376,95 +347,101 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         Sy[k] += (int32_t)oy_lane;
     }
 
-    // Run of each of this thread's (epoch, index row) pairs p0 + k: the
-    // windows of a tile are laid out epoch-major (psrc, pdst), and the
-    // ecnt of every epoch is reset.  Returns the total M (block uniform).
-    const auto lay_out = [&](const int32_t (&src)[kPairsPerThread],
-                             const int32_t (&len)[kPairsPerThread],
-                             int32_t (&dst)[kPairsPerThread]) __attribute__((always_inline)) {
-        int32_t lsum = 0;
+    // Each wave stages and votes its own epochs e = wave + NW k (k < KW)
+    // without waiting for the others: its (epoch, index row) pairs
+    // q = (k << LR) + r sit in two slots of its lanes (q = lane, 64 + lane),
+    // their runs are laid out by wave scans, and the detections inside the
+    // exact windows are packed epoch-major into the wave's part of the stage.
+    const int KW = E > wave ? (E - wave + NW - 1) / NW : 0;
+    const int nq = KW << LR;  // <= 128 (planner)
+    const int32_t wcap = a.stage_cap / NW;
+    int2 *wst = stage + wave * wcap;
+    int32_t rsrc[2], rlen[2], rpre[2];
+    int32_t Mw = 0;              // this wave's window-index entries of the tile (wave uniform)
+    int32_t my_b = 0, my_n = 0;  // lane k < KW: stage start and count of epoch k
+
+    const auto runs = [&](int32_t oxw) __attribute__((always_inline)) {
+        int32_t end[2];
 #pragma unroll
-        for (int k = 0; k < kPairsPerThread; ++k) {
-            if (k < per && p0 + k < np) psrc[p0 + k] = src[k];
-            lsum += len[k];
+        for (int s2 = 0; s2 < 2; ++s2) {
+            const int q = s2 * 64 + lane;
+            rsrc[s2] = 0;
+            end[s2] = 0;
+            if (q < nq)
+                window_run(a, sh, wave + NW * (q >> LR), q & ((1 << LR) - 1), oxw, oy, W, H,
+                           rsrc[s2], end[s2]);
         }
-        if (tid < E) sh.ecnt[tid] = 0;
-        parity ^= 1;
-        int32_t total;
-        int32_t run = scan_block(lsum, &total, sh.wsum[parity]);
-#pragma unroll
-        for (int k = 0; k < kPairsPerThread; ++k) {
-            dst[k] = run;
-            if (k < per && p0 + k < np) pdst[p0 + k] = run;
-            run += len[k];
-        }
-        if (tid == 0) pdst[np] = total;
-        return total;
+        int32_t t0, t1;
+        rlen[0] = end[0] - rsrc[0];
+        rlen[1] = end[1] - rsrc[1];
+        rpre[0] = wave_scan(rlen[0], &t0);
+        rpre[1] = t0 + wave_scan(rlen[1], &t1);
+        Mw = t0 + t1;
     };
-    // Stages the chunk [c0, c1) of the tile at oxw for the pairs k >= k0,
-    // two at a time, reading the run table (after a barrier).
-    const auto copy_rest = [&](int k0, int32_t c0, int32_t c1, int32_t oxw)
-                               __attribute__((always_inline)) {
-        for (int k = k0; k < per; k += 2) {
-            const int pa = p0 + k, pb = pa + 1;
-            int2 qa[kCopyAhead], qb[kCopyAhead];
-            int32_t jba = 0, jea = 0, sra = 0, jbb = 0, jeb = 0, srb = 0;
-            if (pa < np)
-                copy_issue(c, c0, c1, pdst[pa], pdst[pa + 1] - pdst[pa], psrc[pa], qa, jba, jea,
-                           sra);
-            if (k + 1 < per && pb < np)
-                copy_issue(c, c0, c1, pdst[pb], pdst[pb + 1] - pdst[pb], psrc[pb], qb, jbb, jeb,
-                           srb);
-            copy_complete(c, sh, stage, pdst, pa >> LR, LR, c0, oxw, oy, W, H, qa, jba, jea, sra);
-            copy_complete(c, sh, stage, pdst, pb >> LR, LR, c0, oxw, oy, W, H, qb, jbb, jeb, srb);
+    // the entries [c0, c0 + wcap) of the wave's runs (in pair order) that lie
+    // in their epoch's exact window, packed into the wave's stage
+    const auto stage_chunk = [&](int32_t oxw, int32_t c0) __attribute__((always_inline)) {
+        const int32_t c1 = c0 + wcap;
+        int32_t jb[2], je[2], nk[2];
+        Window w[2];
+        int2 q[2][kCopyAhead];
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+            jb[s2] = max(0, c0 - rpre[s2]);
+            je[s2] = max(jb[s2], min(rlen[s2], c1 - rpre[s2]));
+#pragma unroll
+            for (int u = 0; u < kCopyAhead; ++u)
+                if (jb[s2] + u < je[s2]) q[s2][u] = c.sxy[rsrc[s2] + jb[s2] + u];
         }
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+            const int k = min((s2 * 64 + lane) >> LR, max(KW - 1, 0));
+            w[s2] = window_of(sh, wave + NW * k, oxw, oy, W, H);
+            nk[s2] = 0;
+#pragma unroll
+            for (int u = 0; u < kCopyAhead; ++u) nk[s2] += jb[s2] + u < je[s2] && w[s2].holds(q[s2][u]);
+            nk[s2] += run_part<false>(c, rsrc[s2], jb[s2] + kCopyAhead, je[s2], w[s2], nullptr);
+        }
+        int32_t t0, t1;
+        int32_t start[2];  // packed position of the lane's first kept detection, per slot
+        start[0] = wave_scan(nk[0], &t0);
+        start[1] = t0 + wave_scan(nk[1], &t1);
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+            int32_t at = start[s2];
+#pragma unroll
+            for (int u = 0; u < kCopyAhead; ++u)
+                if (jb[s2] + u < je[s2] && w[s2].holds(q[s2][u])) wst[at++] = q[s2][u];
+            run_part<true>(c, rsrc[s2], jb[s2] + kCopyAhead, je[s2], w[s2], wst + at);
+        }
+        // lane k < KW: the packed start of epoch k is the kept prefix at pair k << LR
+        const int qk = min(lane, 31) << LR;
+        const int32_t b0 = __shfl(start[0], qk & 63, 64);
+        const int32_t b1 = __shfl(start[1], qk & 63, 64);
+        my_b = lane < KW ? (qk < 64 ? b0 : b1) : t0 + t1;
+        const int32_t nb = __shfl(my_b, min(lane + 1, 63), 64);
+        my_n = lane < KW ? nb - my_b : 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     };
 
-    // Tile 0: windows, run table and its first chunk.
-    int32_t M;
-    {
-        int32_t src[kPairsPerThread], len[kPairsPerThread], dst[kPairsPerThread];
-#pragma unroll
-        for (int k = 0; k < kPairsPerThread; ++k) {
-            int32_t end = 0;
-            src[k] = 0;
-            if (k < per && p0 + k < np)
-                window_run(a, sh, (p0 + k) >> LR, (p0 + k) & ((1 << LR) - 1), txf * cellw, oy, W, H, src[k], end);
-            len[k] = end - src[k];
-        }
-        M = lay_out(src, len, dst);
-        __syncthreads();  // run table visible
-        copy_rest(0, 0, min(M, a.stage_cap), txf * cellw);
-        __syncthreads();  // stage ready
+    runs(txf * cellw);
+    if (Mw > 0) {
+        stage_chunk(txf * cellw, 0);
+        if (lane == 0) sh.voted[tseq % 3] = 1;
     }
-
-    for (int32_t ti = 0; ti < ntiles; ++ti) {
+    for (int32_t ti = 0; ti < ntiles; ++ti, ++tseq) {
         const int32_t tx0 = txf + ti * a.tile_x;
         const int32_t ox = tx0 * cellw;
         const uint32_t ox_lane = (uint32_t)(tx0 - my_gx) * (uint32_t)cellw;
         const bool next = ti + 1 < ntiles;  // block uniform
         const int32_t oxn = ox + a.tile_x * cellw;
 
-        // 2. vote, chunk by chunk (the first chunk is staged)
-        if (M > a.stage_cap && tid == 0) atomicAdd(&a.res->n_spilled, 1);
-        for (int32_t c0 = 0; c0 < M; c0 += a.stage_cap) {
-            if (c0 > 0) {  // the previous chunk is voted: stage the next one
-                __syncthreads();
-                if (tid < E) sh.ecnt[tid] = 0;
-                __syncthreads();
-                copy_rest(0, c0, min(M, c0 + a.stage_cap), ox);
-                __syncthreads();
-            }
-            // vote: wave w takes epochs w, w + NW, ...; their counts and
-            // stage offsets are read once, one per lane
-            int32_t my_n = 0, my_b = 0;
-            {
-                const int e = wave + lane * NW;
-                if (e < E) {
-                    my_n = sh.ecnt[e];
-                    my_b = max(pdst[e << LR], c0) - c0;
-                }
-            }
+        // 2. vote this wave's entries, chunk by chunk (the first is staged)
+        if (Mw > wcap && lane == 0) atomicAdd(&a.res->n_spilled, 1);
+        for (int32_t c0 = 0; c0 < Mw; c0 += wcap) {
+            if (c0 > 0) stage_chunk(ox, c0);
 #pragma unroll
             for (int k = 0; k < kEpochRegs; ++k) {
                 const int e = wave + k * NW;
@@ -472,7 +449,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                 const int32_t n = __builtin_amdgcn_readlane(my_n, k);
                 if (n == 0) continue;
                 const int32_t b = __builtin_amdgcn_readlane(my_b, k);
-                vote_run<MODE, G>(stage + b, n, (uint32_t)Sx[k], (uint32_t)Sy[k], kc, row_bytes,
+                vote_run<MODE, G>(wst + b, n, (uint32_t)Sx[k], (uint32_t)Sy[k], kc, row_bytes,
                                   lane_addr, MODE == kMask32 ? (1u << e) : 1u, g);
             }
             for (int k = kEpochRegs; wave + k * NW < E; ++k) {
@@ -481,36 +458,29 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                 if (n == 0) continue;
                 const int32_t b = __builtin_amdgcn_readlane(my_b, k);
                 const int32_t d = sh.dt[e];
-                vote_run<MODE, G>(stage + b, n, (uint32_t)shift_q8(my_vx, d) + ox_lane,
+                vote_run<MODE, G>(wst + b, n, (uint32_t)shift_q8(my_vx, d) + ox_lane,
                                   (uint32_t)shift_q8(my_vy, d) + oy_lane, kc, row_bytes,
                                   lane_addr, MODE == kMask32 ? (1u << e) : 1u, g);
             }
+            __builtin_amdgcn_wave_barrier();  // the stage is read before it is refilled
         }
-        __syncthreads();  // votes done: stage, counters and run table are free
-
-        // the next tile's run table, and the loads of its first chunk, in
-        // flight over the scan and clear of this tile
-        int32_t Mn = 0;
-        int2 q0[kCopyAhead], q1[kCopyAhead];
-        int32_t jb0 = 0, je0 = 0, sr0 = 0, jb1 = 0, je1 = 0, sr1 = 0;
+        // the next tile's runs and first chunk, while other waves still vote
         if (next) {
-            int32_t src[kPairsPerThread], len[kPairsPerThread], dst[kPairsPerThread];
-#pragma unroll
-            for (int k = 0; k < kPairsPerThread; ++k) {
-                int32_t end = 0;
-                src[k] = 0;
-                if (k < per && p0 + k < np)
-                    window_run(a, sh, (p0 + k) >> LR, (p0 + k) & ((1 << LR) - 1), oxn, oy, W, H, src[k], end);
-                len[k] = end - src[k];
+            runs(oxn);
+            if (Mw > 0) {
+                stage_chunk(oxn, 0);
+                if (lane == 0) sh.voted[(tseq + 1) % 3] = 1;
             }
-            Mn = lay_out(src, len, dst);
-            const int32_t c1 = min(Mn, a.stage_cap);
-            copy_issue(c, 0, c1, dst[0], len[0], src[0], q0, jb0, je0, sr0);
-            copy_issue(c, 0, c1, dst[1], len[1], src[1], q1, jb1, je1, sr1);
         }
+        __syncthreads();  // every vote of this tile is in the histogram
+        // The flag of tile t is set after the barrier that ends tile t - 2 and
+        // read between the two barriers of tile t; it is cleared here for
+        // tile t + 2, whose flag was last read before this tile's first barrier.
+        const bool any = sh.voted[tseq % 3] != 0;  // block uniform
+        if (tid == 0) sh.voted[(tseq + 2) % 3] = 0;
 
         // 3. read and clear the histogram; emit or queue interior cells
-        if (M > 0) {
+        if (any) {
             for (int w0 = 0; w0 < hist_words / 4; w0 += T) {
                 const int w4 = w0 + tid;
                 uint4 h = make_uint4(0, 0, 0, 0);
@@ -552,24 +522,14 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                 }
             }
         }
-
-        if (next) {
-            __syncthreads();  // the next tile's run table is visible
-            copy_complete(c, sh, stage, pdst, p0 >> LR, LR, 0, oxn, oy, W, H, q0, jb0, je0, sr0);
-            copy_complete(c, sh, stage, pdst, (p0 + 1) >> LR, LR, 0, oxn, oy, W, H, q1, jb1, je1,
-                          sr1);
-            copy_rest(2, 0, min(Mn, a.stage_cap), oxn);
-            __syncthreads();  // stage ready; the histogram is clear
-        }
-        M = Mn;
+        __syncthreads();  // the histogram is clear before the next tile's votes
 #pragma unroll
         for (int k = 0; k < kEpochRegs; ++k) Sx[k] += a.tile_x * cellw;
     }
 }
 
-// Dynamic LDS: histogram [HY][HX][NV] words, then the stage (int2), then the
-// run table of the window index (source offset and exclusive prefix of every
-// (epoch, row) pair).
+// Dynamic LDS: histogram [HY][HX][NV] words, then the stage (int2), one
+// part of stage_cap / NW detections per wave.
 template <int MODE, int G>
 __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_vote_dense(DenseArgs a) {
     extern __shared__ uint4 smem4[];
@@ -578,7 +538,8 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
     const int hist_words = a.hx * a.hy * (64 / G);
     for (int i = tid; i < hist_words / 4; i += T) smem4[i] = make_uint4(0, 0, 0, 0);
     if (tid < a.cat.n_epochs) sh.dt[tid] = a.cat.dt[tid];
-    int parity = 0;
+    int32_t tseq = 0;  // tiles done by this workgroup (flag ring of sh.voted)
+    if (tid < 3) sh.voted[tid] = 0;
     // Workgroups are dispatched round-robin over the XCDs (each with its own
     // L2); give XCD x the logical indices [x G / 8, (x + 1) G / 8) so that the
     // workgroups resident on one XCD take neighbouring items.
@@ -586,7 +547,7 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
     const int64_t logical = (int64_t)(blockIdx.x % kXcds) * (grid / kXcds) + blockIdx.x / kXcds;
     for (int64_t item = logical; item < a.n_items; item += grid) {
         const int32_t *it = a.items + 4 * item;
-        vote_item<MODE, G>(a, sh, smem4, it[0], it[1], it[2], it[3], parity);
+        vote_item<MODE, G>(a, sh, smem4, it[0], it[1], it[2], it[3], tseq);
     }
 }
 
@@ -604,7 +565,8 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
     __shared__ Shared sh;
     const int tid = threadIdx.x;
     for (int i = tid; i < hist_words_max / 4; i += T) smem4[i] = make_uint4(0, 0, 0, 0);
-    int parity = 0, chip_now = -1;
+    int32_t tseq = 0, chip_now = -1;  // tseq: tiles done by this workgroup
+    if (tid < 3) sh.voted[tid] = 0;
     const int64_t grid = gridDim.x;  // a multiple of kXcds
     const int64_t logical = (int64_t)(blockIdx.x % kXcds) * (grid / kXcds) + blockIdx.x / kXcds;
     for (int64_t item = logical; item < n_items; item += grid) {
@@ -612,11 +574,14 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
         const int chip = it[0];
         const DenseArgs &a = chips[chip];
         if (chip != chip_now) {
-            __syncthreads();  // the previous item no longer reads sh.dt
+            __syncthreads();  // the previous item no longer reads sh.dt or the stage
             if (tid < a.cat.n_epochs) sh.dt[tid] = a.cat.dt[tid];
+            // this chip's histogram may cover what was the previous chip's stage
+            const int hw = a.hx * a.hy * (64 / G);
+            for (int i = tid; i < hw / 4; i += T) smem4[i] = make_uint4(0, 0, 0, 0);
             chip_now = chip;
         }
-        vote_item<MODE, G>(a, sh, smem4, it[1], it[2], it[3], it[4], parity);
+        vote_item<MODE, G>(a, sh, smem4, it[1], it[2], it[3], it[4], tseq);
     }
 }
 
@@ -749,10 +714,9 @@ hipError_t launch_batch_m(int groups, const DenseArgs *chips, const int32_t *ite
 
 }  // namespace
 
-size_t dense_lds_bytes(int groups, int hx, int hy, int stage_cap, int max_pairs) {
+size_t dense_lds_bytes(int groups, int hx, int hy, int stage_cap) {
     size_t b = (size_t)hx * hy * (64 / groups) * sizeof(uint32_t);  // histogram
-    b += (size_t)stage_cap * sizeof(int2);                            // stage
-    b += (size_t)(2 * max_pairs + 1) * sizeof(int32_t);               // run table
+    b += (size_t)stage_cap * sizeof(int2);                            // stage (NW parts)
     return (b + 15) & ~(size_t)15;
 }
 
@@ -785,7 +749,7 @@ hipError_t launch_refine(const DenseArgs &a, hipStream_t stream) {
 hipError_t launch_vote_dense(int mode, int groups, const DenseArgs &a, hipStream_t stream,
                              hipEvent_t ev0, hipEvent_t ev1) {
     if (a.n_items <= 0) return hipSuccess;
-    const size_t lds = dense_lds_bytes(groups, a.hx, a.hy, a.stage_cap, a.max_pairs);
+    const size_t lds = dense_lds_bytes(groups, a.hx, a.hy, a.stage_cap);
     switch (mode) {
     case kMask32: return launch_m<kMask32>(groups, a, lds, stream, ev0, ev1);
     case kCountDet: return launch_m<kCountDet>(groups, a, lds, stream, ev0, ev1);
