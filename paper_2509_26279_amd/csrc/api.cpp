@@ -473,7 +473,7 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     // the average spread of a block to each side length)
     int32_t TX = tu.tile_x, TY = tu.tile_y;
     if (!TX || !TY) {
-        const size_t hist_budget = lds_target * 2 / 3;
+        const size_t hist_budget = lds_target * 3 / 4;
         double best = -1.0;
         for (int ty = 1; ty <= 128; ++ty)
             for (int tx = 1; tx <= 128; ++tx) {
@@ -498,10 +498,7 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     if (TX < 1 || TY < 1 || TX > 4096 || TY > 4096)
         return fail(SAS_E_INVALID, "sas_plan_create: tile_x and tile_y must be in [1, 4096]");
     const int64_t HX = TX + guard_x, HY = TY + guard_y;
-    if (!cl) {  // window-index cells of 2 x 2 histogram cells or more, with >= 4 per tile height
-        cl = kc + 1;
-        while (cl < 30 && (((int64_t)TY << kc) >> (cl + 1)) >= 4) ++cl;
-    }
+    if (!cl) cl = kc + 1;  // window-index cells of 2 x 2 histogram cells
     while (ncells_of(cl, ex[0], ex[1]) > 32767 || ncells_of(cl, ex[2], ex[3]) > 32767 ||
            ((((int64_t)d->n_epochs + 7) / 8) << log2_ceil(rows_bound(cl, TY))) > kMaxWavePairs)
         ++cl;

@@ -171,28 +171,36 @@ __device__ inline void vote_run(const int2 *st, int32_t n, uint32_t sx, uint32_t
 
 constexpr int kCopyAhead = 4;  // detections of a run loaded at once
 
-// Run of window-index row r of epoch e for the tile whose Q8 origin is
-// (oxw, oy): source offset and end offset (0, 0 when the window misses the
-// footprint or has fewer rows).
-__device__ __attribute__((always_inline)) inline void window_run(
-    const DenseArgs &a, const Shared &sh, int e, int r, int32_t oxw, int32_t oy, int32_t W,
-    int32_t H, int32_t &src, int32_t &end) {
+// Window-index row r of epoch e for the item's tile row at oy: the index of
+// its cell column 0, or -1 when the epoch's window misses the footprint in y
+// or touches fewer rows (tile independent).
+__device__ __attribute__((always_inline)) inline int32_t window_row(
+    const DenseArgs &a, const Shared &sh, int e, int r, int32_t oy, int32_t H) {
     const PreparedCatalog &c = a.cat;
-    src = 0;
-    end = 0;
-    if (sh.dt[e] < 0) return;
-    const int32_t xlo = oxw + sh.es[0][e], xhi = oxw + sh.es[1][e] + W;
+    if (sh.dt[e] < 0) return -1;
     const int32_t ylo = oy + sh.es[2][e], yhi = oy + sh.es[3][e] + H;
-    int cx0, cx1, cy0, cy1;
-    if (!cell_span(xlo, xhi, c.x0, c.x1, c.cell_log2, &cx0, &cx1) ||
-        !cell_span(ylo, yhi, c.y0, c.y1, c.cell_log2, &cy0, &cy1))
-        return;
+    int cy0, cy1;
+    if (!cell_span(ylo, yhi, c.y0, c.y1, c.cell_log2, &cy0, &cy1)) return -1;
     if (r == 0 && cy1 - cy0 + 1 > a.rows)  // excluded by the planner
         atomicOr(&a.res->status, SAS_DATA_INTERNAL);
-    if (cy0 + r > cy1) return;
-    const int64_t base = ((int64_t)e * c.ncy + cy0 + r) * c.ncx;
-    src = c.off[base + cx0];
-    end = c.off[base + cx1 + 1];
+    if (cy0 + r > cy1) return -1;
+    return (e * c.ncy + cy0 + r) * c.ncx;  // < 2^30 cells (planner)
+}
+
+// Run of that row for the tile whose Q8 x origin is oxw: source offset and
+// end offset in the window index (0, 0 when the window misses in x).
+__device__ __attribute__((always_inline)) inline void window_run(
+    const PreparedCatalog &c, const Shared &sh, int e, int32_t row, int32_t oxw, int32_t W,
+    int32_t &src, int32_t &end) {
+    src = 0;
+    end = 0;
+    if (row < 0) return;
+    int cx0, cx1;
+    if (!cell_span(oxw + sh.es[0][e], oxw + sh.es[1][e] + W, c.x0, c.x1, c.cell_log2, &cx0,
+                   &cx1))
+        return;
+    src = c.off[row + cx0];
+    end = c.off[row + cx1 + 1];
 }
 
 // Exclusive scan over the 64 lanes of a wave; *total gets the sum.
@@ -359,18 +367,19 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
     int32_t rsrc[2], rlen[2], rpre[2];
     int32_t Mw = 0;              // this wave's window-index entries of the tile (wave uniform)
     int32_t my_b = 0, my_n = 0;  // lane k < KW: stage start and count of epoch k
+    int32_t rowb[2];             // window-index row of each slot's pair (-1: none)
+    int qe[2];                   // epoch of each slot's pair (clamped for empty slots)
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+        const int q = s2 * 64 + lane;
+        qe[s2] = wave + NW * min(q >> LR, max(KW - 1, 0));
+        rowb[s2] = q < nq ? window_row(a, sh, qe[s2], q & ((1 << LR) - 1), oy, H) : -1;
+    }
 
     const auto runs = [&](int32_t oxw) __attribute__((always_inline)) {
         int32_t end[2];
 #pragma unroll
-        for (int s2 = 0; s2 < 2; ++s2) {
-            const int q = s2 * 64 + lane;
-            rsrc[s2] = 0;
-            end[s2] = 0;
-            if (q < nq)
-                window_run(a, sh, wave + NW * (q >> LR), q & ((1 << LR) - 1), oxw, oy, W, H,
-                           rsrc[s2], end[s2]);
-        }
+        for (int s2 = 0; s2 < 2; ++s2) window_run(c, sh, qe[s2], rowb[s2], oxw, W, rsrc[s2], end[s2]);
         int32_t t0, t1;
         rlen[0] = end[0] - rsrc[0];
         rlen[1] = end[1] - rsrc[1];
@@ -395,8 +404,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         }
 #pragma unroll
         for (int s2 = 0; s2 < 2; ++s2) {
-            const int k = min((s2 * 64 + lane) >> LR, max(KW - 1, 0));
-            w[s2] = window_of(sh, wave + NW * k, oxw, oy, W, H);
+            w[s2] = window_of(sh, qe[s2], oxw, oy, W, H);
             nk[s2] = 0;
 #pragma unroll
             for (int u = 0; u < kCopyAhead; ++u) nk[s2] += jb[s2] + u < je[s2] && w[s2].holds(q[s2][u]);
