@@ -163,7 +163,8 @@ typedef struct {
     int32_t coarse_log2;        /* histogram cells of 2^m x 2^m bins, m in [0, 3]; -1: single
                                    bins; 0: chosen from n_det_hint */
     int32_t refine_cap;         /* capacity of the list of flagged cells (0: chosen by the plan) */
-    int32_t reserved;
+    int32_t packed;             /* 0: packed 16-bit votes wherever the tile allows them (a
+                                   histogram row and column span at most 2^16 Q8 px); -1: never */
 } sas_tuning;
 
 /* ------------------------------------------------------------------------
@@ -215,7 +216,7 @@ typedef struct {
     int32_t hist_x, hist_y; /* histogram cells per tile, guard cells included */
     int32_t stage_cap;
     int32_t lds_bytes;     /* LDS per vote workgroup */
-    int32_t reserved;
+    int32_t packed;        /* 1: votes use packed 16-bit arithmetic */
 } sas_plan_info;
 sas_status sas_plan_get_info(const sas_plan *plan, sas_plan_info *info);
 

@@ -112,6 +112,7 @@ struct sas_plan {
     int dense_mode = 0;
     int32_t tile_x = 16, tile_y = 16, vbx = 8, vby = 8, groups = 1, cell_log2 = 11;
     int32_t coarse_log2 = 0, hx = 0, hy = 0, stage_cap = 0, rows = 0, rows_log2 = 0;
+    int32_t packed = 0;  // packed 16-bit votes
     int32_t ncx = 1, ncy = 1;
     int64_t n_cells = 0, n_items = 0, n_segments = 0, n_tiles = 0, refine_cap = 0;
     size_t lds_bytes = 0;
@@ -220,6 +221,7 @@ DenseArgs dense_args(const sas_plan *p, const WsLayout &L, char *w, const PrepBu
     a.stage_cap = p->stage_cap;
     a.rows = p->rows;
     a.rows_log2 = p->rows_log2;
+    a.packed = p->packed;
     a.n_min = p->n_min;
     a.count_sat = p->count_sat;
     a.mode_epochs = p->mode == SAS_MODE_EPOCHS ? 1 : 0;
@@ -471,14 +473,21 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     // tile shape: the largest interior under the histogram budget with the
     // best ratio of interior to window area (exact windows: the window adds
     // the average spread of a block to each side length)
+    // packed 16-bit votes: a histogram row and column span at most 2^16 Q8 px
+    // and a row's words fit a 16-bit weight
+    auto packs = [&](int64_t tx, int64_t ty) {
+        return tu.packed >= 0 && ((tx + guard_x) << kc) <= 65536 &&
+               ((ty + guard_y) << kc) <= 65536 && (tx + guard_x) * NV * 4 <= 65535;
+    };
     int32_t TX = tu.tile_x, TY = tu.tile_y;
     if (!TX || !TY) {
-        const size_t hist_budget = lds_target * 3 / 4;
         double best = -1.0;
         for (int ty = 1; ty <= 128; ++ty)
             for (int tx = 1; tx <= 128; ++tx) {
                 if (tu.tile_x && tx != tu.tile_x) continue;
                 if (tu.tile_y && ty != tu.tile_y) continue;
+                // the stage of a packed tile takes half the bytes
+                const size_t hist_budget = lds_target * (packs(tx, ty) ? 17 : 15) / 20;
                 const size_t hb = (size_t)(tx + guard_x) * (ty + guard_y) * NV * 4;
                 if (hb > hist_budget) continue;
                 const double wx = tx + 0.5 * spread_x_avg / cellw + 0.5;
@@ -498,6 +507,8 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     if (TX < 1 || TY < 1 || TX > 4096 || TY > 4096)
         return fail(SAS_E_INVALID, "sas_plan_create: tile_x and tile_y must be in [1, 4096]");
     const int64_t HX = TX + guard_x, HY = TY + guard_y;
+    const int packed = packs(TX, TY) ? 1 : 0;
+    const size_t entry_bytes = packed ? sizeof(uint32_t) : sizeof(int2);
     if (!cl) cl = kc + 1;  // window-index cells of 2 x 2 histogram cells
     while (ncells_of(cl, ex[0], ex[1]) > 32767 || ncells_of(cl, ex[2], ex[3]) > 32767 ||
            ((((int64_t)d->n_epochs + 7) / 8) << log2_ceil(rows_bound(cl, TY))) > kMaxWavePairs)
@@ -511,8 +522,8 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     const size_t hist_bytes = (size_t)HX * HY * NV * 4;
     int64_t stage_cap = tu.stage_cap;
     if (!stage_cap) {
-        const size_t fixed = dense_lds_bytes(G, (int)HX, (int)HY, 0);
-        const size_t room = lds_target > fixed ? (lds_target - fixed) / sizeof(int2) : 0;
+        const size_t fixed = dense_lds_bytes(G, (int)HX, (int)HY, 0, packed);
+        const size_t room = lds_target > fixed ? (lds_target - fixed) / entry_bytes : 0;
         int64_t want = (int64_t)room;
         if (tu.n_det_hint > 0) {
             const double win = ((double)TX * cellw + 0.5 * spread_x_avg) *
@@ -524,7 +535,7 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     // one part per wave of the workgroup, at least two detections each
     stage_cap = std::max<int64_t>((stage_cap + kVoteWaves - 1) / kVoteWaves * kVoteWaves,
                                   2 * kVoteWaves);
-    const size_t lds = dense_lds_bytes(G, (int)HX, (int)HY, (int)stage_cap);
+    const size_t lds = dense_lds_bytes(G, (int)HX, (int)HY, (int)stage_cap, packed);
     if (HX > 65535 || HY > 65535 || hist_bytes > lds_cap || lds > lds_cap)
         return fail(SAS_E_INVALID, "sas_plan_create: tile + guard cells + stage exceed the LDS of "
                                    "a workgroup; lower tile_x, tile_y, stage_cap or vblock");
@@ -578,6 +589,7 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     p->stage_cap = (int32_t)stage_cap;
     p->rows = (int32_t)rows_bound(cl, TY);
     p->rows_log2 = rows_log2;
+    p->packed = packed;
     p->lds_bytes = lds + lds_static;
     p->cell_log2 = cl;
     p->ncx = (int32_t)ncx;
@@ -768,7 +780,7 @@ sas_status sas_plan_get_info(const sas_plan *p, sas_plan_info *info) {
     info->hist_y = p->hy;
     info->stage_cap = p->stage_cap;
     info->lds_bytes = (int32_t)p->lds_bytes;
-    info->reserved = 0;
+    info->packed = p->packed;
     return SAS_OK;
 }
 
@@ -923,7 +935,7 @@ struct sas_batch {
         DenseArgs args{};
     };
     struct Class {
-        int mode = 0, groups = 1;
+        int mode = 0, groups = 1, packed = 0;
         int32_t *d_items5 = nullptr;
         int64_t n_items = 0;
         int32_t hist_words_max = 0;
@@ -939,7 +951,11 @@ struct sas_batch {
 
 namespace {
 
-constexpr int kMaxBatchClasses = 9;  // 3 cell variants x 3 lane-group counts
+constexpr int kMaxBatchClasses = 18;  // 3 cell variants x 3 lane-group counts x 2 vote forms
+
+int batch_class(const sas_plan *p) {
+    return (p->dense_mode * 3 + (p->groups == 1 ? 0 : p->groups == 2 ? 1 : 2)) * 2 + p->packed;
+}
 
 sas_status batch_layout(const sas_batch_chip *chips, int32_t n_chips, std::vector<size_t> *offs,
                         size_t *total) {
@@ -1026,7 +1042,7 @@ sas_status sas_batch_create(const sas_batch_chip *chips, int32_t n_chips, void *
     for (int32_t c : chip_order) {
         const sas_plan *p = chips[c].plan;
         if (chips[c].n == 0 || p->n_items == 0) continue;
-        const int k = p->dense_mode * 3 + (p->groups == 1 ? 0 : p->groups == 2 ? 1 : 2);
+        const int k = batch_class(p);
         for (int64_t q = 0; q < p->n_items; ++q) {
             It it;
             const int32_t *src = &p->h_items[4 * q];
@@ -1042,16 +1058,18 @@ sas_status sas_batch_create(const sas_batch_chip *chips, int32_t n_chips, void *
         if (per_class[k].empty()) continue;
         const std::vector<It> &v = per_class[k];
         sas_batch::Class cl;
-        cl.mode = k / 3;
-        cl.groups = (k % 3 == 0) ? 1 : (k % 3 == 1) ? 2 : 4;
+        cl.mode = k / 6;
+        cl.groups = (k / 2 % 3 == 0) ? 1 : (k / 2 % 3 == 1) ? 2 : 4;
+        cl.packed = k % 2;
         std::vector<int32_t> flat;
         flat.reserve(v.size() * 5);
         for (const It &it : v) flat.insert(flat.end(), it.v, it.v + 5);
         for (int32_t c = 0; c < n_chips; ++c) {
             const sas_plan *p = chips[c].plan;
-            if (p->dense_mode * 3 + (p->groups == 1 ? 0 : p->groups == 2 ? 1 : 2) != k) continue;
+            if (batch_class(p) != k) continue;
             cl.hist_words_max = std::max(cl.hist_words_max, p->hx * p->hy * (64 / p->groups));
-            cl.lds = std::max(cl.lds, dense_lds_bytes(p->groups, p->hx, p->hy, p->stage_cap));
+            cl.lds = std::max(cl.lds, dense_lds_bytes(p->groups, p->hx, p->hy, p->stage_cap,
+                                                      p->packed));
         }
         cl.n_items = (int64_t)v.size();
         void *d = nullptr;
@@ -1124,8 +1142,8 @@ sas_status sas_vote_batch(const sas_batch *b, void *stream) {
         // persistent: as many workgroups as fit on the device at once
         const int per_cu = std::max<int>(1, (int)(kLdsPerCU / (cl.lds + dense_static_lds_bytes())));
         const int grid = (int)std::min<int64_t>(cl.n_items, (int64_t)n_cu * per_cu);
-        e = launch_vote_dense_batch(cl.mode, cl.groups, b->d_args, cl.d_items5, cl.n_items,
-                                    cl.hist_words_max, cl.lds, grid, s);
+        e = launch_vote_dense_batch(cl.mode, cl.groups, cl.packed, b->d_args, cl.d_items5,
+                                    cl.n_items, cl.hist_words_max, cl.lds, grid, s);
         if (e != hipSuccess) return hip_fail(e, "sas_vote_batch: vote launch");
     }
     if (b->probe[1] && (e = hipEventRecord(b->probe[1], s)) != hipSuccess)

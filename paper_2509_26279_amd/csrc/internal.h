@@ -46,6 +46,7 @@ struct DenseArgs {
     int32_t stage_cap;        // detections staged in LDS at a time
     int32_t rows;             // index rows a tile window can touch (planner bound)
     int32_t rows_log2;        // run rows per epoch: 2^rows_log2 >= rows
+    int32_t packed;           // 1: packed 16-bit votes (stage entries of 4 bytes)
     int32_t n_min, count_sat;
     int32_t mode_epochs;      // 1: count distinct epochs, 0: count detections
     const int32_t *vel;       // [n_v][2] velocities, Q8 px/h
@@ -191,12 +192,12 @@ hipError_t launch_vote_dense(int mode, int groups, const DenseArgs &a, hipStream
                              hipEvent_t ev0, hipEvent_t ev1);
 // One persistent launch over the merged items (chip, segment, ty0, txf,
 // ntiles) of many chips of one kernel class.
-hipError_t launch_vote_dense_batch(int mode, int groups, const DenseArgs *chips_dev,
+hipError_t launch_vote_dense_batch(int mode, int groups, int packed, const DenseArgs *chips_dev,
                                    const int32_t *items5_dev, int64_t n_items,
                                    int32_t hist_words_max, size_t lds, int grid,
                                    hipStream_t stream);
 hipError_t launch_refine(const DenseArgs &a, hipStream_t stream);
-size_t dense_lds_bytes(int groups, int hx, int hy, int stage_cap);
+size_t dense_lds_bytes(int groups, int hx, int hy, int stage_cap, int packed);
 size_t dense_static_lds_bytes();
 
 }  // namespace sas

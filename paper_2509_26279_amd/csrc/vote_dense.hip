@@ -32,6 +32,8 @@
 //               N_min distinct epochs (or detections) only if its cell holds
 //               N_min detections.  Used for EPOCHS with E > 32 and for coarse
 //               cells; k_refine resolves queued cells into exact bins.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace sas {
@@ -50,8 +52,10 @@ struct Shared {
     int32_t bad;
 };
 
-// Epochs per wave whose lane shifts stay in registers over a work item.
+// Epochs per wave whose lane shifts stay in registers over a work item (two
+// registers each, or one packed).
 constexpr int kEpochRegs = 10;
+constexpr int kEpochRegsPacked = 12;  // packed: one register per epoch
 
 // ceil(v * d / 65536) for d >= 0: the shift v (t_e - t0) in Q8 pixels,
 // rounded so that the floor of the shifted position is exact.
@@ -126,23 +130,54 @@ __device__ inline void lds_vote(uint32_t addr, uint32_t val) {
         __hip_atomic_fetch_add(p, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+typedef unsigned short us2 __attribute__((ext_vector_type(2)));
+
+__device__ inline uint32_t pack16(int32_t x, int32_t y) {
+    return ((uint32_t)x & 0xffffu) | ((uint32_t)y << 16);
+}
+
+// Word address of a vote: lane shift (sx, sy) = S(v_j, d) plus the Q8 origin
+// of the lane's histogram; bin (ix, iy) = ((x - sx) >> kc, (y - sy) >> kc).
+// 32-bit form: two subtracts, two shifts, a shift-add and a 24-bit
+// multiply-add.
+struct VoteAddr32 {
+    typedef int2 Entry;
+    uint32_t sx, sy, row_bytes, lane_addr;
+    int kc, lb;
+    __device__ uint32_t operator()(int2 q) const {
+        const uint32_t ix = ((uint32_t)q.x - sx) >> kc;
+        const uint32_t iy = ((uint32_t)q.y - sy) >> kc;
+        return hist_addr(ix, iy, row_bytes, lb, lane_addr);
+    }
+};
+
+// Packed form, for tiles whose histogram spans at most 2^16 Q8 px in x and
+// y: entries and shifts keep the low 16 bits of x (low half) and y (high
+// half).  Every staged detection satisfies 0 <= x - sx < 2^16 (guard cells),
+// so the halves' differences modulo 2^16 are exact: one packed subtract, one
+// packed shift and one dot product (ix * NV * 4 + iy * row_bytes + lane).
+struct VoteAddr16 {
+    typedef uint32_t Entry;
+    us2 s, kcv, wts;
+    uint32_t lane_addr;
+    __device__ uint32_t operator()(uint32_t q) const {
+        const us2 d = __builtin_bit_cast(us2, q) - s;
+        return __builtin_amdgcn_udot2(d >> kcv, wts, lane_addr, false);
+    }
+};
+
 // U consecutive votes of lane group g: detections st[g], st[g + G], ...,
-// st[g + (U - 1) G]; (sx, sy) is the lane's shift plus its histogram origin.
-template <int MODE, int G, int U>
-__device__ __attribute__((always_inline)) inline void vote_block(
-    const int2 *st, int g, uint32_t sx, uint32_t sy, int kc, uint32_t row_bytes,
-    uint32_t lane_addr, uint32_t val) {
-    constexpr int LNV = G == 1 ? 6 : G == 2 ? 5 : 4;
-    int2 q[U];
+// st[g + (U - 1) G].
+template <int MODE, int G, int U, class V>
+__device__ __attribute__((always_inline)) inline void vote_block(const typename V::Entry *st,
+                                                                int g, const V &va,
+                                                                uint32_t val) {
+    typename V::Entry q[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) q[u] = st[u * G + g];
     uint32_t addr[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const uint32_t ix = ((uint32_t)q[u].x - sx) >> kc;
-        const uint32_t iy = ((uint32_t)q[u].y - sy) >> kc;
-        addr[u] = hist_addr(ix, iy, row_bytes, LNV + 2, lane_addr);
-    }
+    for (int u = 0; u < U; ++u) addr[u] = va(q[u]);
 #pragma unroll
     for (int u = 0; u < U; ++u) lds_vote<MODE>(addr[u], val);
 }
@@ -151,22 +186,20 @@ __device__ __attribute__((always_inline)) inline void vote_block(
 // detections g, g + G, ...  Blocks of 4 G, then 2 G and G detections while
 // they last (block-uniform branches, no wasted votes); with G > 1 the last
 // partial round is voted by the groups g < n mod G only.
-template <int MODE, int G>
-__device__ inline void vote_run(const int2 *st, int32_t n, uint32_t sx, uint32_t sy, int kc,
-                                uint32_t row_bytes, uint32_t lane_addr, uint32_t val, int g) {
+template <int MODE, int G, class V>
+__device__ inline void vote_run(const typename V::Entry *st, int32_t n, const V &va,
+                                uint32_t val, int g) {
     int32_t i = 0;
-    for (; i + 4 * G <= n; i += 4 * G)
-        vote_block<MODE, G, 4>(st + i, g, sx, sy, kc, row_bytes, lane_addr, val);
+    for (; i + 4 * G <= n; i += 4 * G) vote_block<MODE, G, 4>(st + i, g, va, val);
     if (i + 2 * G <= n) {
-        vote_block<MODE, G, 2>(st + i, g, sx, sy, kc, row_bytes, lane_addr, val);
+        vote_block<MODE, G, 2>(st + i, g, va, val);
         i += 2 * G;
     }
     if (i + G <= n) {
-        vote_block<MODE, G, 1>(st + i, g, sx, sy, kc, row_bytes, lane_addr, val);
+        vote_block<MODE, G, 1>(st + i, g, va, val);
         i += G;
     }
-    if (G > 1 && i + g < n)
-        vote_block<MODE, G, 1>(st + i, g, sx, sy, kc, row_bytes, lane_addr, val);
+    if (G > 1 && i + g < n) vote_block<MODE, G, 1>(st + i, g, va, val);
 }
 
 constexpr int kCopyAhead = 4;  // detections of a run loaded at once
@@ -235,9 +268,12 @@ __device__ __attribute__((always_inline)) inline Window window_of(const Shared &
 // One lane's part [jb, je) of a window-index run (source src): the
 // detections inside the window w, counted (write = false) or appended at
 // dst (write = true).  kCopyAhead loads at a time.
-template <bool WRITE>
+__device__ inline void put_entry(int2 *dst, int2 q) { *dst = q; }
+__device__ inline void put_entry(uint32_t *dst, int2 q) { *dst = pack16(q.x, q.y); }
+
+template <bool WRITE, class Entry>
 __device__ __attribute__((always_inline)) inline int32_t run_part(
-    const PreparedCatalog &c, int32_t src, int32_t jb, int32_t je, Window w, int2 *dst) {
+    const PreparedCatalog &c, int32_t src, int32_t jb, int32_t je, Window w, Entry *dst) {
     int32_t n = 0;
     for (int32_t jj = jb; jj < je; jj += kCopyAhead) {
         int2 q[kCopyAhead];
@@ -247,7 +283,7 @@ __device__ __attribute__((always_inline)) inline int32_t run_part(
 #pragma unroll
         for (int u = 0; u < kCopyAhead; ++u) {
             if (jj + u < je && w.holds(q[u])) {
-                if (WRITE) dst[n] = q[u];
+                if (WRITE) put_entry(dst + n, q[u]);
                 ++n;
             }
         }
@@ -260,14 +296,17 @@ __device__ __attribute__((always_inline)) inline int32_t run_part(
 // One work item: a segment and a row of ntiles tiles starting at tile column
 // txf (cells), tile row ty0.  The histogram is all zero on entry and on exit;
 // sh.dt holds the catalog's d_e.
-template <int MODE, int G>
+template <int MODE, int G, bool PK>
 __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t sg, int32_t ty0,
                           int32_t txf, int32_t ntiles, int32_t &tseq) {
     constexpr int NV = 64 / G;
     constexpr int LNV = G == 1 ? 6 : G == 2 ? 5 : 4;
+    typedef typename std::conditional<PK, VoteAddr16, VoteAddr32>::type VA;
+    typedef typename VA::Entry Entry;
+    constexpr int ER = PK ? kEpochRegsPacked : kEpochRegs;
     uint32_t *hist = (uint32_t *)smem4;
     const int hist_words = a.hx * a.hy * NV;
-    int2 *stage = (int2 *)(hist + hist_words);
+    Entry *stage = (Entry *)(hist + hist_words);
 
     const PreparedCatalog &c = a.cat;
     const int E = c.n_epochs;
@@ -305,40 +344,44 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
     const uint32_t oy_lane = (uint32_t)(ty0 - my_gy) * (uint32_t)cellw;
     const uint32_t lane_addr = (uint32_t)(uintptr_t)(lds_u32 *)hist + (uint32_t)(j * 4);
 
-    // Lane shifts of this wave's epochs e = wave + k NW (k < kEpochRegs),
-    // kept in registers for the whole item.  The window of any tile then
-    // lands inside every lane's histogram (tile independent; checked here).
-    int32_t Sx[kEpochRegs], Sy[kEpochRegs];
+    // Lane shifts of this wave's epochs e = wave + k NW (k < ER), kept in
+    // registers for the whole item with the Q8 origin of the lane's
+    // histogram added (row 0 at ty0 - gy cells, column 0 at tx0 - gx cells of
+    // the current tile; packed: low 16 bits of x and y in one register).  The
+    // window of any tile lands inside every lane's histogram (tile
+    // independent; checked here).
+    const uint32_t ox_lane0 = (uint32_t)(txf - my_gx) * (uint32_t)cellw;
+    int32_t Sx[ER], Sy[PK ? 1 : ER];
     bool bad = false;
-#pragma unroll
-    for (int k = 0; k < kEpochRegs; ++k) {
-        const int e = wave + k * NW;
-        Sx[k] = 0;
-        Sy[k] = 0;
-        if (e < E) {
-            const int32_t d = sh.dt[e];
-            if (d >= 0) {
-                Sx[k] = shift_q8(my_vx, d);
-                Sy[k] = shift_q8(my_vy, d);
-                const int64_t gxq = (int64_t)my_gx << kc, gyq = (int64_t)my_gy << kc;
-                const int64_t lx = (int64_t)sh.es[0][e] - Sx[k] - 1 + gxq;
-                const int64_t hx = (int64_t)sh.es[1][e] - Sx[k] + W - 1 + gxq;
-                const int64_t ly = (int64_t)sh.es[2][e] - Sy[k] - 1 + gyq;
-                const int64_t hy = (int64_t)sh.es[3][e] - Sy[k] + H - 1 + gyq;
-                bad |= lx < 0 || ly < 0 || hx >= ((int64_t)a.hx << kc) ||
-                       hy >= ((int64_t)a.hy << kc);
-            }
-        }
-    }
-    for (int e = wave + kEpochRegs * NW; e < E; e += NW) {  // epochs past the registers
-        const int32_t d = sh.dt[e];
-        if (d < 0) continue;
-        const int64_t sxe = shift_q8(my_vx, d), sye = shift_q8(my_vy, d);
+    const auto guard_fails = [&](int e, int64_t sxe, int64_t sye) __attribute__((always_inline)) {
         const int64_t gxq = (int64_t)my_gx << kc, gyq = (int64_t)my_gy << kc;
-        bad |= (int64_t)sh.es[0][e] - sxe - 1 + gxq < 0 ||
+        return (int64_t)sh.es[0][e] - sxe - 1 + gxq < 0 ||
                (int64_t)sh.es[2][e] - sye - 1 + gyq < 0 ||
                (int64_t)sh.es[1][e] - sxe + W - 1 + gxq >= ((int64_t)a.hx << kc) ||
                (int64_t)sh.es[3][e] - sye + H - 1 + gyq >= ((int64_t)a.hy << kc);
+    };
+#pragma unroll
+    for (int k = 0; k < ER; ++k) {
+        const int e = wave + k * NW;
+        int32_t sxe = 0, sye = 0;
+        if (e < E) {
+            const int32_t d = sh.dt[e];
+            if (d >= 0) {
+                sxe = shift_q8(my_vx, d);
+                sye = shift_q8(my_vy, d);
+                bad |= guard_fails(e, sxe, sye);
+            }
+        }
+        if (PK) {
+            Sx[k] = (int32_t)pack16(sxe + (int32_t)ox_lane0, sye + (int32_t)oy_lane);
+        } else {
+            Sx[k] = sxe + (int32_t)ox_lane0;
+            Sy[PK ? 0 : k] = sye + (int32_t)oy_lane;
+        }
+    }
+    for (int e = wave + ER * NW; e < E; e += NW) {  // epochs past the registers
+        const int32_t d = sh.dt[e];
+        if (d >= 0) bad |= guard_fails(e, shift_q8(my_vx, d), shift_q8(my_vy, d));
     }
     if (bad) sh.bad = 1;
     __syncthreads();
@@ -346,14 +389,16 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         if (tid == 0) atomicOr(&a.res->status, SAS_DATA_INTERNAL);
         return;
     }
-    // from here on Sx, Sy hold the shift plus the Q8 origin of the lane's
-    // histogram for the current tile: row 0 at ty0 - gy cells, column 0 at
-    // tx0 - gx cells
-#pragma unroll
-    for (int k = 0; k < kEpochRegs; ++k) {
-        Sx[k] += (int32_t)((uint32_t)(txf - my_gx) * (uint32_t)cellw);
-        Sy[k] += (int32_t)oy_lane;
-    }
+    const us2 kcv = {(unsigned short)kc, (unsigned short)kc};
+    const us2 wts = {(unsigned short)(NV * 4), (unsigned short)row_bytes};
+    // vote address of lane shift (sx, sy) (full Q8 values; packed: low bits)
+    const auto vote_addr = [&](int32_t sx, int32_t sy) __attribute__((always_inline)) {
+        if constexpr (PK) {
+            return VoteAddr16{__builtin_bit_cast(us2, (uint32_t)sx), kcv, wts, lane_addr};
+        } else {
+            return VoteAddr32{(uint32_t)sx, (uint32_t)sy, row_bytes, lane_addr, kc, LNV + 2};
+        }
+    };
 
     // Each wave stages and votes its own epochs e = wave + NW k (k < KW)
     // without waiting for the others: its (epoch, index row) pairs
@@ -363,7 +408,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
     const int KW = E > wave ? (E - wave + NW - 1) / NW : 0;
     const int nq = KW << LR;  // <= 128 (planner)
     const int32_t wcap = a.stage_cap / NW;
-    int2 *wst = stage + wave * wcap;
+    Entry *wst = stage + wave * wcap;
     int32_t rsrc[2], rlen[2], rpre[2];
     int32_t Mw = 0;              // this wave's window-index entries of the tile (wave uniform)
     int32_t my_b = 0, my_n = 0;  // lane k < KW: stage start and count of epoch k
@@ -407,8 +452,10 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
             w[s2] = window_of(sh, qe[s2], oxw, oy, W, H);
             nk[s2] = 0;
 #pragma unroll
-            for (int u = 0; u < kCopyAhead; ++u) nk[s2] += jb[s2] + u < je[s2] && w[s2].holds(q[s2][u]);
-            nk[s2] += run_part<false>(c, rsrc[s2], jb[s2] + kCopyAhead, je[s2], w[s2], nullptr);
+            for (int u = 0; u < kCopyAhead; ++u)
+                nk[s2] += jb[s2] + u < je[s2] && w[s2].holds(q[s2][u]);
+            nk[s2] += run_part<false>(c, rsrc[s2], jb[s2] + kCopyAhead, je[s2], w[s2],
+                                      (Entry *)nullptr);
         }
         int32_t t0, t1;
         int32_t start[2];  // packed position of the lane's first kept detection, per slot
@@ -419,7 +466,8 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
             int32_t at = start[s2];
 #pragma unroll
             for (int u = 0; u < kCopyAhead; ++u)
-                if (jb[s2] + u < je[s2] && w[s2].holds(q[s2][u])) wst[at++] = q[s2][u];
+                if (jb[s2] + u < je[s2] && w[s2].holds(q[s2][u]))
+                    put_entry(wst + at++, q[s2][u]);
             run_part<true>(c, rsrc[s2], jb[s2] + kCopyAhead, je[s2], w[s2], wst + at);
         }
         // lane k < KW: the packed start of epoch k is the kept prefix at pair k << LR
@@ -451,24 +499,25 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         for (int32_t c0 = 0; c0 < Mw; c0 += wcap) {
             if (c0 > 0) stage_chunk(ox, c0);
 #pragma unroll
-            for (int k = 0; k < kEpochRegs; ++k) {
+            for (int k = 0; k < ER; ++k) {
                 const int e = wave + k * NW;
                 if (e >= E) break;
                 const int32_t n = __builtin_amdgcn_readlane(my_n, k);
                 if (n == 0) continue;
                 const int32_t b = __builtin_amdgcn_readlane(my_b, k);
-                vote_run<MODE, G>(wst + b, n, (uint32_t)Sx[k], (uint32_t)Sy[k], kc, row_bytes,
-                                  lane_addr, MODE == kMask32 ? (1u << e) : 1u, g);
+                vote_run<MODE, G>(wst + b, n, vote_addr(Sx[k], Sy[PK ? 0 : k]),
+                                  MODE == kMask32 ? (1u << e) : 1u, g);
             }
-            for (int k = kEpochRegs; wave + k * NW < E; ++k) {
+            for (int k = ER; wave + k * NW < E; ++k) {
                 const int e = wave + k * NW;
                 const int32_t n = __builtin_amdgcn_readlane(my_n, k);
                 if (n == 0) continue;
                 const int32_t b = __builtin_amdgcn_readlane(my_b, k);
                 const int32_t d = sh.dt[e];
-                vote_run<MODE, G>(wst + b, n, (uint32_t)shift_q8(my_vx, d) + ox_lane,
-                                  (uint32_t)shift_q8(my_vy, d) + oy_lane, kc, row_bytes,
-                                  lane_addr, MODE == kMask32 ? (1u << e) : 1u, g);
+                const int32_t sx = shift_q8(my_vx, d) + (int32_t)ox_lane;
+                const int32_t sy = shift_q8(my_vy, d) + (int32_t)oy_lane;
+                vote_run<MODE, G>(wst + b, n, vote_addr(PK ? (int32_t)pack16(sx, sy) : sx, sy),
+                                  MODE == kMask32 ? (1u << e) : 1u, g);
             }
             __builtin_amdgcn_wave_barrier();  // the stage is read before it is refilled
         }
@@ -532,13 +581,20 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         }
         __syncthreads();  // the histogram is clear before the next tile's votes
 #pragma unroll
-        for (int k = 0; k < kEpochRegs; ++k) Sx[k] += a.tile_x * cellw;
+        for (int k = 0; k < ER; ++k) {
+            if constexpr (PK) {  // low half only, modulo 2^16
+                const us2 step = {(unsigned short)(a.tile_x << kc), 0};
+                Sx[k] = (int32_t)__builtin_bit_cast(uint32_t, __builtin_bit_cast(us2, Sx[k]) + step);
+            } else {
+                Sx[k] += a.tile_x * cellw;
+            }
+        }
     }
 }
 
-// Dynamic LDS: histogram [HY][HX][NV] words, then the stage (int2), one
-// part of stage_cap / NW detections per wave.
-template <int MODE, int G>
+// Dynamic LDS: histogram [HY][HX][NV] words, then the stage (int2, or one
+// packed word per detection), one part of stage_cap / NW detections per wave.
+template <int MODE, int G, bool PK>
 __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_vote_dense(DenseArgs a) {
     extern __shared__ uint4 smem4[];
     __shared__ Shared sh;
@@ -555,7 +611,7 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
     const int64_t logical = (int64_t)(blockIdx.x % kXcds) * (grid / kXcds) + blockIdx.x / kXcds;
     for (int64_t item = logical; item < a.n_items; item += grid) {
         const int32_t *it = a.items + 4 * item;
-        vote_item<MODE, G>(a, sh, smem4, it[0], it[1], it[2], it[3], tseq);
+        vote_item<MODE, G, PK>(a, sh, smem4, it[0], it[1], it[2], it[3], tseq);
     }
 }
 
@@ -564,8 +620,9 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
 // chip in its own L2-friendly order) are walked like the single-catalog
 // kernel walks its items, and each item reads its chip's parameters from
 // chips[].  Every chip of the launch uses this kernel's cell variant and lane
-// groups; hist_words_max covers the largest histogram among them.
-template <int MODE, int G>
+// groups (and vote form); hist_words_max covers the largest histogram among
+// them.
+template <int MODE, int G, bool PK>
 __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_vote_dense_batch(const DenseArgs *__restrict__ chips,
                                                          const int32_t *__restrict__ items5,
                                                          int64_t n_items, int32_t hist_words_max) {
@@ -589,7 +646,7 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
             for (int i = tid; i < hw / 4; i += T) smem4[i] = make_uint4(0, 0, 0, 0);
             chip_now = chip;
         }
-        vote_item<MODE, G>(a, sh, smem4, it[1], it[2], it[3], it[4], tseq);
+        vote_item<MODE, G, PK>(a, sh, smem4, it[1], it[2], it[3], it[4], tseq);
     }
 }
 
@@ -663,7 +720,6 @@ __global__ void __launch_bounds__(T) k_refine(DenseArgs a) {
     }
 }
 
-template <int MODE, int G>
 hipError_t set_lds_limit(const void *fn, size_t lds, size_t *lds_set) {
     if (lds > 65536 && lds > *lds_set) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -673,80 +729,96 @@ hipError_t set_lds_limit(const void *fn, size_t lds, size_t *lds_set) {
     return hipSuccess;
 }
 
-template <int MODE, int G>
+template <int MODE, int G, bool PK>
 hipError_t launch_mg(const DenseArgs &a, size_t lds, hipStream_t stream, hipEvent_t ev0,
                      hipEvent_t ev1) {
     static size_t lds_set = 0;  // dynamic LDS limit raised so far for this kernel
-    hipError_t e = set_lds_limit<MODE, G>((const void *)k_vote_dense<MODE, G>, lds, &lds_set);
+    hipError_t e = set_lds_limit((const void *)k_vote_dense<MODE, G, PK>, lds, &lds_set);
     if (e != hipSuccess) return e;
     const int64_t want = a.n_items < kMaxVoteGrid ? a.n_items : kMaxVoteGrid;
     const dim3 grid((unsigned)((want + kXcds - 1) / kXcds * kXcds)), block(T);
     if (ev0 && (e = hipEventRecord(ev0, stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_vote_dense<MODE, G>), grid, block, lds, stream, a);
+    hipLaunchKernelGGL((k_vote_dense<MODE, G, PK>), grid, block, lds, stream, a);
     if (ev1 && (e = hipEventRecord(ev1, stream)) != hipSuccess) return e;
     if (MODE == kCountRef)
         hipLaunchKernelGGL(k_refine, dim3(kRefineGrid), block, 0, stream, a);
     return hipGetLastError();
 }
 
-template <int MODE>
+template <int MODE, bool PK>
 hipError_t launch_m(int groups, const DenseArgs &a, size_t lds, hipStream_t s, hipEvent_t e0,
                     hipEvent_t e1) {
     switch (groups) {
-    case 1: return launch_mg<MODE, 1>(a, lds, s, e0, e1);
-    case 2: return launch_mg<MODE, 2>(a, lds, s, e0, e1);
-    default: return launch_mg<MODE, 4>(a, lds, s, e0, e1);
+    case 1: return launch_mg<MODE, 1, PK>(a, lds, s, e0, e1);
+    case 2: return launch_mg<MODE, 2, PK>(a, lds, s, e0, e1);
+    default: return launch_mg<MODE, 4, PK>(a, lds, s, e0, e1);
     }
 }
 
-template <int MODE, int G>
+template <int MODE, int G, bool PK>
 hipError_t launch_batch_mg(const DenseArgs *chips, const int32_t *items5, int64_t n_items,
                            int32_t hist_words_max, size_t lds, int grid, hipStream_t stream) {
     static size_t lds_set = 0;
-    hipError_t e = set_lds_limit<MODE, G>((const void *)k_vote_dense_batch<MODE, G>, lds, &lds_set);
+    hipError_t e = set_lds_limit((const void *)k_vote_dense_batch<MODE, G, PK>, lds, &lds_set);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_vote_dense_batch<MODE, G>), dim3(grid), dim3(T), lds, stream, chips,
-                       items5, n_items, hist_words_max);
+    hipLaunchKernelGGL((k_vote_dense_batch<MODE, G, PK>), dim3(grid), dim3(T), lds, stream,
+                       chips, items5, n_items, hist_words_max);
     return hipGetLastError();
 }
 
-template <int MODE>
+template <int MODE, bool PK>
 hipError_t launch_batch_m(int groups, const DenseArgs *chips, const int32_t *items5,
                           int64_t n_items, int32_t hwm, size_t lds, int grid, hipStream_t s) {
     switch (groups) {
-    case 1: return launch_batch_mg<MODE, 1>(chips, items5, n_items, hwm, lds, grid, s);
-    case 2: return launch_batch_mg<MODE, 2>(chips, items5, n_items, hwm, lds, grid, s);
-    default: return launch_batch_mg<MODE, 4>(chips, items5, n_items, hwm, lds, grid, s);
+    case 1: return launch_batch_mg<MODE, 1, PK>(chips, items5, n_items, hwm, lds, grid, s);
+    case 2: return launch_batch_mg<MODE, 2, PK>(chips, items5, n_items, hwm, lds, grid, s);
+    default: return launch_batch_mg<MODE, 4, PK>(chips, items5, n_items, hwm, lds, grid, s);
+    }
+}
+
+template <bool PK>
+hipError_t launch_batch_p(int mode, int groups, const DenseArgs *chips, const int32_t *items5,
+                          int64_t n_items, int32_t hwm, size_t lds, int grid, hipStream_t s) {
+    switch (mode) {
+    case kMask32:
+        return launch_batch_m<kMask32, PK>(groups, chips, items5, n_items, hwm, lds, grid, s);
+    case kCountDet:
+        return launch_batch_m<kCountDet, PK>(groups, chips, items5, n_items, hwm, lds, grid, s);
+    default:
+        return launch_batch_m<kCountRef, PK>(groups, chips, items5, n_items, hwm, lds, grid, s);
+    }
+}
+
+template <bool PK>
+hipError_t launch_p(int mode, int groups, const DenseArgs &a, size_t lds, hipStream_t s,
+                    hipEvent_t e0, hipEvent_t e1) {
+    switch (mode) {
+    case kMask32: return launch_m<kMask32, PK>(groups, a, lds, s, e0, e1);
+    case kCountDet: return launch_m<kCountDet, PK>(groups, a, lds, s, e0, e1);
+    default: return launch_m<kCountRef, PK>(groups, a, lds, s, e0, e1);
     }
 }
 
 }  // namespace
 
-size_t dense_lds_bytes(int groups, int hx, int hy, int stage_cap) {
-    size_t b = (size_t)hx * hy * (64 / groups) * sizeof(uint32_t);  // histogram
-    b += (size_t)stage_cap * sizeof(int2);                            // stage (NW parts)
+size_t dense_lds_bytes(int groups, int hx, int hy, int stage_cap, int packed) {
+    size_t b = (size_t)hx * hy * (64 / groups) * sizeof(uint32_t);   // histogram
+    b += (size_t)stage_cap * (packed ? sizeof(uint32_t) : sizeof(int2));  // stage (NW parts)
     return (b + 15) & ~(size_t)15;
 }
 
 size_t dense_static_lds_bytes() { return sizeof(Shared); }
 
-hipError_t launch_vote_dense_batch(int mode, int groups, const DenseArgs *chips_dev,
+hipError_t launch_vote_dense_batch(int mode, int groups, int packed, const DenseArgs *chips_dev,
                                    const int32_t *items5_dev, int64_t n_items,
                                    int32_t hist_words_max, size_t lds, int grid,
                                    hipStream_t stream) {
     if (n_items <= 0) return hipSuccess;
     grid = (grid + kXcds - 1) / kXcds * kXcds;
-    switch (mode) {
-    case kMask32:
-        return launch_batch_m<kMask32>(groups, chips_dev, items5_dev, n_items, hist_words_max,
-                                       lds, grid, stream);
-    case kCountDet:
-        return launch_batch_m<kCountDet>(groups, chips_dev, items5_dev, n_items, hist_words_max,
-                                         lds, grid, stream);
-    default:
-        return launch_batch_m<kCountRef>(groups, chips_dev, items5_dev, n_items, hist_words_max,
-                                         lds, grid, stream);
-    }
+    return packed ? launch_batch_p<true>(mode, groups, chips_dev, items5_dev, n_items,
+                                         hist_words_max, lds, grid, stream)
+                  : launch_batch_p<false>(mode, groups, chips_dev, items5_dev, n_items,
+                                          hist_words_max, lds, grid, stream);
 }
 
 hipError_t launch_refine(const DenseArgs &a, hipStream_t stream) {
@@ -757,12 +829,9 @@ hipError_t launch_refine(const DenseArgs &a, hipStream_t stream) {
 hipError_t launch_vote_dense(int mode, int groups, const DenseArgs &a, hipStream_t stream,
                              hipEvent_t ev0, hipEvent_t ev1) {
     if (a.n_items <= 0) return hipSuccess;
-    const size_t lds = dense_lds_bytes(groups, a.hx, a.hy, a.stage_cap);
-    switch (mode) {
-    case kMask32: return launch_m<kMask32>(groups, a, lds, stream, ev0, ev1);
-    case kCountDet: return launch_m<kCountDet>(groups, a, lds, stream, ev0, ev1);
-    default: return launch_m<kCountRef>(groups, a, lds, stream, ev0, ev1);
-    }
+    const size_t lds = dense_lds_bytes(groups, a.hx, a.hy, a.stage_cap, a.packed);
+    return a.packed ? launch_p<true>(mode, groups, a, lds, stream, ev0, ev1)
+                    : launch_p<false>(mode, groups, a, lds, stream, ev0, ev1);
 }
 
 }  // namespace sas

@@ -52,7 +52,7 @@ class Tuning(ctypes.Structure):
                 ("groups", ctypes.c_int32), ("stage_cap", ctypes.c_int32),
                 ("cell_log2", ctypes.c_int32), ("sort_vblock", ctypes.c_int32),
                 ("n_det_hint", ctypes.c_int32), ("coarse_log2", ctypes.c_int32),
-                ("refine_cap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("refine_cap", ctypes.c_int32), ("packed", ctypes.c_int32)]
 
 
 class BatchChip(ctypes.Structure):
@@ -79,7 +79,7 @@ class PlanInfo(ctypes.Structure):
                 ("mode_variant", ctypes.c_int32), ("n_v", ctypes.c_int64),
                 ("groups", ctypes.c_int32), ("hist_x", ctypes.c_int32),
                 ("hist_y", ctypes.c_int32), ("stage_cap", ctypes.c_int32),
-                ("lds_bytes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("lds_bytes", ctypes.c_int32), ("packed", ctypes.c_int32)]
 
 
 _lib = None
@@ -218,7 +218,7 @@ class Plan:
             self._tuning = Tuning(*[int(tuning.get(k, 0)) for k in
                                     ("tile_x", "tile_y", "vblock_x", "vblock_y", "groups",
                                      "stage_cap", "cell_log2", "sort_vblock", "n_det_hint",
-                                     "coarse_log2", "refine_cap")])
+                                     "coarse_log2", "refine_cap", "packed")])
         desc = PlanDesc(self._v.ctypes.data, self._v.shape[0], self._t.shape[0],
                         self._t.ctypes.data, int(binw_q8), int(n_min), MODES[mode],
                         int(count_sat), PATHS[path], (ctypes.c_int32 * 4)(*map(int, extent_q8)),

@@ -80,7 +80,9 @@ def test_random_adversarial(gpu, seed, mode):
                     dict(coarse_log2=2, groups=1), dict(coarse_log2=3, tile_x=4, tile_y=4, groups=4),
                     dict(coarse_log2=1, vblock_x=2, vblock_y=16, groups=2),
                     dict(tile_x=5, tile_y=3, stage_cap=40, groups=4),
-                    dict(tile_x=7, tile_y=9, stage_cap=16, groups=1, vblock_x=5, vblock_y=7)):
+                    dict(tile_x=7, tile_y=9, stage_cap=16, groups=1, vblock_x=5, vblock_y=7),
+                    dict(packed=-1), dict(tile_x=5, tile_y=3, stage_cap=40, groups=2, packed=-1),
+                    dict(coarse_log2=2, groups=1, packed=-1)):
             g = gpu_vote(d["x_q8"], d["y_q8"], d["epoch"], d["t_q16"], d["v_q8"], d["binw_q8"],
                          n_min, mode, tuning=tun)
             assert_same(g, o)
@@ -165,7 +167,8 @@ def test_fast_full_grid_every_tuning(gpu):
                 dict(tile_x=24, tile_y=8, vblock_x=8, vblock_y=2, groups=4),
                 dict(tile_x=12, tile_y=6, vblock_x=7, vblock_y=3, cell_log2=14, groups=2),
                 dict(tile_x=8, tile_y=8, groups=1, stage_cap=512),
-                dict(coarse_log2=-1)):
+                dict(coarse_log2=-1), dict(tile_x=12, tile_y=12, groups=4),
+                dict(tile_x=12, tile_y=12, groups=4, packed=-1)):
         tun["n_det_hint"] = wl.n
         _say(f"fast full grid {tun}")
         g = gpu_vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v, wl.binw_q8, wl.n_min, "epochs",
