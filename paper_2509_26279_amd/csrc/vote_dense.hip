@@ -437,25 +437,29 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
     const auto stage_chunk = [&](int32_t oxw, int32_t c0) __attribute__((always_inline)) {
         const int32_t c1 = c0 + wcap;
         int32_t jb[2], je[2], nk[2];
+        uint32_t km[2];  // which of the first kCopyAhead detections are kept
         Window w[2];
         int2 q[2][kCopyAhead];
 #pragma unroll
         for (int s2 = 0; s2 < 2; ++s2) {
             jb[s2] = max(0, c0 - rpre[s2]);
             je[s2] = max(jb[s2], min(rlen[s2], c1 - rpre[s2]));
+            // unconditional loads: at most kCopyAhead - 1 detections past the run,
+            // inside the slack that follows the detections in the workspace
+            const int2 *src = c.sxy + (rsrc[s2] + jb[s2]);
 #pragma unroll
-            for (int u = 0; u < kCopyAhead; ++u)
-                if (jb[s2] + u < je[s2]) q[s2][u] = c.sxy[rsrc[s2] + jb[s2] + u];
+            for (int u = 0; u < kCopyAhead; ++u) q[s2][u] = src[u];
         }
 #pragma unroll
         for (int s2 = 0; s2 < 2; ++s2) {
             w[s2] = window_of(sh, qe[s2], oxw, oy, W, H);
-            nk[s2] = 0;
+            km[s2] = 0;
 #pragma unroll
             for (int u = 0; u < kCopyAhead; ++u)
-                nk[s2] += jb[s2] + u < je[s2] && w[s2].holds(q[s2][u]);
-            nk[s2] += run_part<false>(c, rsrc[s2], jb[s2] + kCopyAhead, je[s2], w[s2],
-                                      (Entry *)nullptr);
+                km[s2] |= (uint32_t)(jb[s2] + u < je[s2] && w[s2].holds(q[s2][u])) << u;
+            nk[s2] = __popc(km[s2]) +
+                     run_part<false>(c, rsrc[s2], jb[s2] + kCopyAhead, je[s2], w[s2],
+                                     (Entry *)nullptr);
         }
         int32_t t0, t1;
         int32_t start[2];  // packed position of the lane's first kept detection, per slot
@@ -466,8 +470,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
             int32_t at = start[s2];
 #pragma unroll
             for (int u = 0; u < kCopyAhead; ++u)
-                if (jb[s2] + u < je[s2] && w[s2].holds(q[s2][u]))
-                    put_entry(wst + at++, q[s2][u]);
+                if ((km[s2] >> u) & 1u) put_entry(wst + at++, q[s2][u]);
             run_part<true>(c, rsrc[s2], jb[s2] + kCopyAhead, je[s2], w[s2], wst + at);
         }
         // lane k < KW: the packed start of epoch k is the kept prefix at pair k << LR
