@@ -14,6 +14,8 @@ Contents
   * ``grid.py``      - the velocity lattice of Sec. 2 (spacing Delta x / Delta t);
   * ``params.py``    - the threshold rule of Sec. 2.2 (N_min from a target
     number of false candidates);
+  * ``features.py``  - candidate features and labels for learned vetting;
+  * ``extract.py``   - the greedy cluster extraction of Step 3 (Sec. 2.1);
   * ``mlp_ref.py``   - FP64 reference of the candidate-vetting MLP.
 """
 from __future__ import annotations
