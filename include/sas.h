@@ -297,6 +297,53 @@ sas_status sas_vote_batch(const sas_batch *batch, void *stream);
 sas_status sas_batch_set_probe(sas_batch *batch, void *ev_before, void *ev_after);
 
 /* ------------------------------------------------------------------------
+ * Greedy cluster extraction (Step 3 of Sec. 2.1).
+ * ---------------------------------------------------------------------- */
+#define SAS_EXTRACT_MEMBERS_FULL 1  /* the contributor lists exceed member_cap */
+#define SAS_EXTRACT_CLUSTERS_FULL 2 /* more clusters than cluster_cap (n_clusters is true) */
+
+typedef struct {
+    int64_t n_clusters; /* clusters extracted (may exceed cluster_cap) */
+    int64_t n_members;  /* contributors of all reported cells (the lists' total size) */
+    int32_t status;     /* SAS_EXTRACT_* bits */
+    int32_t reserved;
+} sas_extract_result;
+
+/*
+ * sas_extract_clusters: Step 3 of Sec. 2.1 over the cells a vote reported.
+ * The loop takes the cell with the largest count (ties: smaller v_idx, then
+ * by, then bx), reports it as a cluster, removes its contributing
+ * detections (those whose exact bin at its velocity is the cell) from every
+ * cell, recounts, and stops when no cell reaches the plan's N_min.  Counts
+ * follow the plan's mode (distinct epochs or detections).  Counts only fall,
+ * so cells below N_min at the start are never needed.
+ *   workspace:   the workspace of the last sas_vote of this dense-path plan
+ *                on this catalog (n detections): its window index is read.
+ *   cand_dev:    device [n_cand] cells reported by that vote (any order).
+ *   member_cap:  capacity of the contributor lists (sum over the cells of
+ *                their contributors); see res->n_members when exceeded.
+ *   scratch:     device, >= sas_extract_scratch_size(n, n_cand, member_cap).
+ *   clusters_dev: device [cluster_cap] clusters in extraction order, count =
+ *                the count at extraction (saturated like the vote's).
+ *   cluster_of_dev: device int32 [n] by catalog index: the cluster that took
+ *                the detection, or -1.
+ *   res_dev:     device sas_extract_result.
+ * Asynchronous (one workgroup runs the loop), no allocation.  Errors:
+ * SAS_E_INVALID (arguments, member_cap >= 2^31, not a dense-path plan),
+ * SAS_E_WORKSPACE.
+ */
+sas_status sas_extract_clusters(const sas_plan *plan, const void *workspace, size_t ws_bytes,
+                                int64_t n, const sas_candidate *cand_dev, int64_t n_cand,
+                                int64_t member_cap, void *scratch, size_t scratch_bytes,
+                                sas_candidate *clusters_dev, int64_t cluster_cap,
+                                int32_t *cluster_of_dev, sas_extract_result *res_dev,
+                                void *stream);
+
+/* Bytes of scratch sas_extract_clusters needs. */
+sas_status sas_extract_scratch_size(int64_t n, int64_t n_cand, int64_t member_cap,
+                                    size_t *bytes);
+
+/* ------------------------------------------------------------------------
  * Learned vetting: candidate features.
  * ---------------------------------------------------------------------- */
 #define SAS_N_FEATURES 32

@@ -1229,3 +1229,83 @@ extern "C" sas_status sas_features(const sas_plan *p, const void *workspace, siz
     if (e != hipSuccess) return hip_fail(e, "sas_features: launch");
     return SAS_OK;
 }
+
+namespace {
+
+struct ExtractScratch {
+    size_t first, blocksum, member, member_epoch, live, open, total;
+};
+
+ExtractScratch extract_layout(int64_t n, int64_t n_cand, int64_t member_cap) {
+    ExtractScratch L{};
+    size_t o = 0;
+    L.first = o; o = align_up(o + sizeof(int32_t) * (n_cand + 1));
+    L.blocksum = o; o = align_up(o + sizeof(int32_t) * ((n_cand + 1 + kScanTile - 1) / kScanTile));
+    L.member = o; o = align_up(o + sizeof(int32_t) * member_cap);
+    L.member_epoch = o; o = align_up(o + member_cap);
+    L.live = o; o = align_up(o + n);
+    L.open = o; o = align_up(o + n_cand);
+    L.total = o;
+    return L;
+}
+
+constexpr int64_t kMaxMembers = ((int64_t)1 << 31) - 1;
+
+}  // namespace
+
+extern "C" sas_status sas_extract_scratch_size(int64_t n, int64_t n_cand, int64_t member_cap,
+                                               size_t *bytes) {
+    if (!bytes || n < 0 || n_cand < 0 || n_cand >= kMaxFeatureCands || member_cap < 0 ||
+        member_cap > kMaxMembers)
+        return fail(SAS_E_INVALID, "sas_extract_scratch_size: bad argument");
+    *bytes = extract_layout(n, n_cand, member_cap).total;
+    return SAS_OK;
+}
+
+extern "C" sas_status sas_extract_clusters(const sas_plan *p, const void *workspace,
+                                           size_t ws_bytes, int64_t n,
+                                           const sas_candidate *cand_dev, int64_t n_cand,
+                                           int64_t member_cap, void *scratch,
+                                           size_t scratch_bytes, sas_candidate *clusters_dev,
+                                           int64_t cluster_cap, int32_t *cluster_of_dev,
+                                           sas_extract_result *res_dev, void *stream) {
+    if (!p || n < 0 || n_cand < 0 || n_cand >= kMaxFeatureCands || member_cap < 0 ||
+        member_cap > kMaxMembers || cluster_cap < 0 || !res_dev ||
+        (n_cand > 0 && !cand_dev) || (cluster_cap > 0 && !clusters_dev) ||
+        (n > 0 && !cluster_of_dev))
+        return fail(SAS_E_INVALID, "sas_extract_clusters: bad argument");
+    if (p->path != SAS_PATH_DENSE)
+        return fail(SAS_E_INVALID, "sas_extract_clusters: needs the window index of a dense-path plan");
+    const WsLayout L = ws_layout(p, n);
+    if (!workspace || ws_bytes < L.total)
+        return fail(SAS_E_WORKSPACE, "sas_extract_clusters: workspace smaller than sas_vote_workspace_size()");
+    const ExtractScratch S = extract_layout(n, n_cand, member_cap);
+    if (!scratch || scratch_bytes < S.total)
+        return fail(SAS_E_WORKSPACE, "sas_extract_clusters: scratch smaller than sas_extract_scratch_size()");
+    char *w = (char *)workspace, *s = (char *)scratch;
+    const PrepBuffers pb = prep_buffers(L, w);
+    ExtractArgs a{};
+    a.cat = dense_args(p, L, w, pb, nullptr, 0, nullptr).cat;
+    a.log2b = p->log2b;
+    a.n_min = p->n_min;
+    a.mode_epochs = p->mode == SAS_MODE_EPOCHS ? 1 : 0;
+    a.count_sat = p->count_sat;
+    a.vel = p->d_vel;
+    a.cand = cand_dev;
+    a.n_cand = n_cand;
+    a.n = n;
+    a.first = (int32_t *)(s + S.first);
+    a.scan_blocksum = (int32_t *)(s + S.blocksum);
+    a.member = (int32_t *)(s + S.member);
+    a.member_epoch = (uint8_t *)(s + S.member_epoch);
+    a.member_cap = member_cap;
+    a.live = (uint8_t *)(s + S.live);
+    a.open = (uint8_t *)(s + S.open);
+    a.clusters = clusters_dev;
+    a.cluster_cap = cluster_cap;
+    a.cluster_of = cluster_of_dev;
+    a.res = res_dev;
+    hipError_t e = launch_extract(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "sas_extract_clusters: launch");
+    return SAS_OK;
+}

@@ -1,0 +1,253 @@
+// Greedy cluster extraction (Step 3 of Sec. 2.1) on the GPU.
+//
+// The vote reports every (velocity, bin) at or above N_min.  Step 3 takes
+// the maximum cell, calls the points that contributed to it a cluster,
+// removes them from every cell they counted in, and repeats while the
+// maximum still reaches N_min.  Counts only fall, so the loop runs over the
+// reported cells; ties of the maximum go to the smaller (v_idx, by, bx).
+//
+//   1. k_contrib: one wave per reported cell gathers its contributors (the
+//      detections whose exact Step-2 bin at the cell's velocity is the
+//      cell) through the window index, as the vote does: lanes take epochs,
+//      a wave scan places each lane's contributors.  A first pass counts,
+//      a scan lays the cells' lists out, a second pass writes the sorted
+//      positions of the contributors and their epochs.
+//   2. k_greedy: one workgroup runs the loop.  Each round every open cell
+//      recounts its live contributors (distinct epochs through a 256-bit
+//      mask in LDS, or their number), cells below N_min close, a block
+//      reduction finds the maximum under the tie rule, and its live
+//      contributors are marked taken (with the cluster's index).
+#include <algorithm>
+
+#include "internal.h"
+
+namespace sas {
+namespace {
+
+constexpr int CT = 256;    // threads per gather block (4 cells at a time)
+constexpr int GT = 1024;   // threads of the greedy workgroup
+constexpr int GW = GT / 64;
+
+__device__ inline int32_t shift_q8(int32_t v, int32_t d) {
+    return (int32_t)(((int64_t)v * (int64_t)d + 65535) >> 16);
+}
+
+__device__ inline bool cell_span(int64_t lo, int64_t hi, int32_t f0, int32_t f1, int cl, int *c0,
+                                 int *c1) {
+    if (hi <= f0 || lo >= f1) return false;
+    *c0 = (int)((max(lo, (int64_t)f0) - f0) >> cl);
+    *c1 = (int)((min(hi, (int64_t)f1) - 1 - f0) >> cl);
+    return true;
+}
+
+__device__ inline int32_t wave_excl(int32_t v, int32_t *total) {
+    const int lane = __lane_id();
+    int32_t incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    *total = __shfl(incl, 63, 64);
+    return incl - v;
+}
+
+// Contributors of cell k in the lane's epochs e = lane, lane + 64, ...:
+// counted (WRITE = false) or written from position at (WRITE = true).
+template <bool WRITE>
+__device__ int32_t lane_contributors(const ExtractArgs &a, const sas_candidate &cd,
+                                     int32_t at) {
+    const PreparedCatalog &c = a.cat;
+    const int lane = __lane_id();
+    const int lb = a.log2b;
+    const int32_t vx = a.vel[2 * (int64_t)cd.v_idx], vy = a.vel[2 * (int64_t)cd.v_idx + 1];
+    int32_t n = 0;
+    for (int e = lane; e < c.n_epochs; e += 64) {
+        const int32_t d = c.dt[e];
+        if (d < 0) continue;
+        const int64_t xlo = ((int64_t)cd.bx << lb) + shift_q8(vx, d);
+        const int64_t ylo = ((int64_t)cd.by << lb) + shift_q8(vy, d);
+        const int64_t xhi = xlo + ((int64_t)1 << lb), yhi = ylo + ((int64_t)1 << lb);
+        int cx0, cx1, cy0, cy1;
+        if (!cell_span(xlo, xhi, c.x0, c.x1, c.cell_log2, &cx0, &cx1) ||
+            !cell_span(ylo, yhi, c.y0, c.y1, c.cell_log2, &cy0, &cy1))
+            continue;
+        for (int cy = cy0; cy <= cy1; ++cy) {
+            const int64_t base = ((int64_t)e * c.ncy + cy) * c.ncx;
+            const int32_t j1 = c.off[base + cx1 + 1];
+            for (int32_t j = c.off[base + cx0]; j < j1; ++j) {
+                const int2 p = c.sxy[j];
+                if (p.x < xlo || p.x >= xhi || p.y < ylo || p.y >= yhi) continue;
+                if (WRITE) {
+                    a.member[at + n] = j;
+                    a.member_epoch[at + n] = (uint8_t)e;
+                }
+                ++n;
+            }
+        }
+    }
+    return n;
+}
+
+__global__ void __launch_bounds__(CT) k_contrib(ExtractArgs a, int write) {
+    const int lane = __lane_id();
+    const int64_t wave_id = ((int64_t)blockIdx.x * CT + threadIdx.x) >> 6;
+    const int64_t n_waves = ((int64_t)gridDim.x * CT) >> 6;
+    for (int64_t k = wave_id; k < a.n_cand; k += n_waves) {
+        const sas_candidate cd = a.cand[k];
+        if (!write) {
+            int32_t total;
+            wave_excl(lane_contributors<false>(a, cd, 0), &total);
+            if (lane == 0) a.first[k] = total;  // scanned into offsets afterwards
+        } else {
+            const int32_t mine = lane_contributors<false>(a, cd, 0);
+            int32_t total;
+            const int32_t pre = wave_excl(mine, &total);
+            const int64_t at = a.first[k] + pre;
+            if (a.first[a.n_cand] <= a.member_cap)  // all lists fit
+                lane_contributors<true>(a, cd, (int32_t)at);
+        }
+    }
+}
+
+// (count, v_idx, by, bx) order of the maximum: larger count, then smaller
+// v_idx, by, bx.
+struct Best {
+    int32_t count, k;
+    uint32_t v;
+    int32_t by, bx;
+};
+
+__device__ inline bool better(const Best &p, const Best &q) {
+    if (p.k < 0) return false;
+    if (q.k < 0) return true;
+    if (p.count != q.count) return p.count > q.count;
+    if (p.v != q.v) return p.v < q.v;
+    if (p.by != q.by) return p.by < q.by;
+    return p.bx < q.bx;
+}
+
+__device__ inline Best shfl_best(const Best &b, int src) {
+    Best o;
+    o.count = __shfl(b.count, src, 64);
+    o.k = __shfl(b.k, src, 64);
+    o.v = (uint32_t)__shfl((int32_t)b.v, src, 64);
+    o.by = __shfl(b.by, src, 64);
+    o.bx = __shfl(b.bx, src, 64);
+    return o;
+}
+
+__global__ void __launch_bounds__(GT) k_greedy(ExtractArgs a) {
+    __shared__ uint32_t masks[GT][kSlotWords];
+    __shared__ Best wbest[GW];
+    __shared__ Best best_all;
+    const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
+    uint32_t *mk = masks[tid];
+    const int64_t n_members = a.first[a.n_cand];
+    if (n_members > a.member_cap) {  // the lists did not fit: report, extract nothing
+        if (tid == 0) {
+            a.res->n_clusters = 0;
+            a.res->n_members = n_members;
+            a.res->status = SAS_EXTRACT_MEMBERS_FULL;
+        }
+        return;
+    }
+    for (int64_t j = tid; j < a.n; j += GT) a.live[j] = 1;
+    for (int64_t k = tid; k < a.n_cand; k += GT) a.open[k] = 1;
+    for (int64_t i = tid; i < a.n; i += GT) a.cluster_of[i] = -1;
+    __syncthreads();
+    int64_t n_out = 0;
+    const uint32_t sat = (uint32_t)a.count_sat;
+    for (;;) {
+        Best mine{0, -1, 0, 0, 0};
+        for (int64_t k = tid; k < a.n_cand; k += GT) {
+            if (!a.open[k]) continue;
+            const int32_t f = a.first[k], l = a.first[k + 1];
+            int32_t cnt = 0;
+            if (a.mode_epochs) {
+#pragma unroll
+                for (int w = 0; w < kSlotWords; ++w) mk[w] = 0;
+                for (int32_t m = f; m < l; ++m) {
+                    if (!a.live[a.member[m]]) continue;
+                    const uint32_t e = a.member_epoch[m];
+                    mk[e >> 5] |= 1u << (e & 31);
+                }
+#pragma unroll
+                for (int w = 0; w < kSlotWords; ++w) cnt += __popc(mk[w]);
+            } else {
+                for (int32_t m = f; m < l; ++m) cnt += a.live[a.member[m]];
+            }
+            if (cnt < a.n_min) {
+                a.open[k] = 0;
+                continue;
+            }
+            const sas_candidate cd = a.cand[k];
+            const Best b{cnt, (int32_t)k, cd.v_idx, cd.by, cd.bx};
+            if (better(b, mine)) mine = b;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const Best other = shfl_best(mine, lane ^ o);
+            if (better(other, mine)) mine = other;
+        }
+        if (lane == 0) wbest[wave] = mine;
+        __syncthreads();
+        if (tid == 0) {
+            Best b = wbest[0];
+            for (int w = 1; w < GW; ++w)
+                if (better(wbest[w], b)) b = wbest[w];
+            best_all = b;
+        }
+        __syncthreads();
+        const Best b = best_all;
+        if (b.k < 0) break;  // block uniform
+        if (tid == 0) {
+            if (n_out < a.cluster_cap) {
+                const uint32_t cnt = (uint32_t)b.count;
+                uint4 rec;
+                rec.x = b.v;
+                rec.y = (uint32_t)b.bx;
+                rec.z = (uint32_t)b.by;
+                rec.w = (cnt > sat ? sat : cnt) | ((cnt > sat ? 1u : 0u) << 16);
+                *(uint4 *)(a.clusters + n_out) = rec;
+            }
+            a.open[b.k] = 0;
+        }
+        const int32_t f = a.first[b.k], l = a.first[b.k + 1];
+        for (int32_t m = f + tid; m < l; m += GT) {
+            const int32_t j = a.member[m];
+            if (a.live[j]) a.cluster_of[a.cat.sidx[j]] = (int32_t)n_out;
+        }
+        __syncthreads();  // cluster_of is written before live drops
+        for (int32_t m = f + tid; m < l; m += GT) a.live[a.member[m]] = 0;
+        ++n_out;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        a.res->n_clusters = n_out;
+        a.res->n_members = n_members;
+        a.res->status = n_out > a.cluster_cap ? SAS_EXTRACT_CLUSTERS_FULL : 0;
+    }
+}
+
+__global__ void k_contrib_tail(int32_t *first, int64_t n_cand) { first[n_cand] = 0; }
+
+}  // namespace
+
+hipError_t launch_extract(const ExtractArgs &a, hipStream_t stream) {
+    if (a.n_cand > 0) {
+        const int64_t blocks = std::min<int64_t>((a.n_cand + CT / 64 - 1) / (CT / 64), 65536);
+        hipLaunchKernelGGL(k_contrib, dim3((unsigned)blocks), dim3(CT), 0, stream, a, 0);
+        // first[n_cand] must read 0 before the scan turns counts into offsets
+        hipLaunchKernelGGL(k_contrib_tail, dim3(1), dim3(1), 0, stream, a.first, a.n_cand);
+        hipError_t e = launch_scan_exclusive(a.first, a.n_cand + 1, a.scan_blocksum, stream);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_contrib, dim3((unsigned)blocks), dim3(CT), 0, stream, a, 1);
+    } else {
+        hipLaunchKernelGGL(k_contrib_tail, dim3(1), dim3(1), 0, stream, a.first, a.n_cand);
+    }
+    hipLaunchKernelGGL(k_greedy, dim3(1), dim3(GT), 0, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace sas

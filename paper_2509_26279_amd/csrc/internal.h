@@ -146,6 +146,29 @@ struct FeatureArgs {
 // Neighbour keys of the candidates, their sort, then the features.
 hipError_t launch_features(const FeatureArgs &a, hipStream_t stream);
 
+// ---- greedy cluster extraction (Step 3)
+struct ExtractArgs {
+    PreparedCatalog cat;
+    int32_t log2b;
+    int32_t n_min, mode_epochs, count_sat;
+    const int32_t *vel;        // [n_v][2]
+    const sas_candidate *cand;  // the cells the vote reported
+    int64_t n_cand;
+    int64_t n;                 // detections
+    int32_t *first;            // [n_cand + 1] contributor counts, then offsets
+    int32_t *scan_blocksum;
+    int32_t *member;           // [member_cap] sorted positions of the contributors
+    uint8_t *member_epoch;     // [member_cap] their epochs
+    int64_t member_cap;
+    uint8_t *live;             // [n] by sorted position: not yet in a cluster
+    uint8_t *open;             // [n_cand] cell may still reach N_min
+    sas_candidate *clusters;   // [cluster_cap] in extraction order
+    int64_t cluster_cap;
+    int32_t *cluster_of;       // [n] by catalog index: cluster or -1
+    sas_extract_result *res;
+};
+hipError_t launch_extract(const ExtractArgs &a, hipStream_t stream);
+
 // Vetting MLP 32 -> 128 -> 128 -> 1; parameters packed W1 (32 x 128),
 // b1, W2 (128 x 128), b2, W3 (128), b3.
 constexpr int kMlpIn = 32, kMlpHidden = 128;

@@ -89,7 +89,7 @@ EXPORTS = ["sas_status_string", "sas_last_error", "sas_version", "sas_grid_spaci
            "sas_plan_set_probe", "sas_vote_workspace_size", "sas_vote", "sas_peaks",
            "sas_threshold_n_min", "sas_batch_workspace_size", "sas_batch_create",
            "sas_batch_destroy", "sas_vote_batch", "sas_batch_set_probe", "sas_features",
-           "sas_features_scratch_size",
+           "sas_features_scratch_size", "sas_extract_scratch_size", "sas_extract_clusters",
            "sas_mlp_create", "sas_mlp_destroy", "sas_mlp_set_norm", "sas_mlp_get_params",
            "sas_mlp_set_params", "sas_mlp_forward", "sas_mlp_grad", "sas_mlp_train_step"]
 
@@ -131,6 +131,8 @@ def load():
         "sas_batch_set_probe": (I32, [P, P, P]),
         "sas_features": (I32, [P, P, SZ, I64, P, P, I64, I32, P, SZ, P, P]),
         "sas_features_scratch_size": (I32, [I64, ctypes.POINTER(ctypes.c_size_t)]),
+        "sas_extract_scratch_size": (I32, [I64, I64, I64, ctypes.POINTER(ctypes.c_size_t)]),
+        "sas_extract_clusters": (I32, [P, P, SZ, I64, P, I64, I64, P, SZ, P, I64, P, P, P]),
         "sas_mlp_create": (I32, [I64, ctypes.c_uint64, P]),
         "sas_mlp_destroy": (I32, [P]),
         "sas_mlp_set_norm": (I32, [P, P, P]),
@@ -329,6 +331,45 @@ class Search:
         r = self.res.cpu().numpy().view(np.int32)
         n_cand = int(r[0].astype(np.int64) | (r[1].astype(np.int64) << 32))
         return {"n_cand": n_cand, "status": int(r[2]), "n_spilled": int(r[3])}
+
+    def extract(self, n: int, member_cap: int = 0, cluster_cap: int = 0, stream=None):
+        """Step 3 (greedy cluster extraction) over the candidates left in the
+        device buffer by the last vote of an n-detection catalog.  Returns
+        (clusters as CAND_DTYPE in extraction order, int32 [n] cluster of each
+        detection or -1).  Synchronises; grows member_cap once if the
+        contributor lists did not fit."""
+        import torch
+        r = self.result()
+        k = min(r["n_cand"], self.cand.shape[0])
+        dev = self.cand.device
+        member_cap = int(member_cap or 64 * k + int(n))
+        cluster_cap = int(cluster_cap or max(k, 1))
+        for _ in range(2):
+            nb = ctypes.c_size_t(0)
+            _check(load().sas_extract_scratch_size(int(n), k, member_cap, ctypes.byref(nb)))
+            scratch = torch.empty(max(nb.value, 1), dtype=torch.uint8, device=dev)
+            clusters = torch.empty((max(cluster_cap, 1), 16), dtype=torch.uint8, device=dev)
+            owner = torch.empty(max(int(n), 1), dtype=torch.int32, device=dev)
+            res = torch.zeros(24, dtype=torch.uint8, device=dev)
+            _check(load().sas_extract_clusters(self.plan.handle, self.ws.data_ptr(),
+                                               self.ws.numel() * self.ws.element_size(), int(n),
+                                               self.cand.data_ptr(), k, member_cap,
+                                               scratch.data_ptr(), nb.value, clusters.data_ptr(),
+                                               cluster_cap, owner.data_ptr(), res.data_ptr(),
+                                               _stream_handle(stream)))
+            rr = res.cpu().numpy()
+            n_clusters = int(rr[0:8].view(np.int64)[0])
+            n_members = int(rr[8:16].view(np.int64)[0])
+            status = int(rr[16:20].view(np.int32)[0])
+            if status & 1:  # the contributor lists did not fit: once more, sized
+                member_cap = n_members
+                continue
+            if status & 2:
+                raise SasError(-3, "sas_extract_clusters: %d clusters, cluster_cap %d"
+                               % (n_clusters, cluster_cap))
+            recs = clusters[:n_clusters].cpu().numpy().view(CAND_DTYPE).reshape(-1).copy()
+            return recs, owner[:int(n)].cpu().numpy()
+        raise SasError(-3, "sas_extract_clusters: contributor lists exceed %d" % member_cap)
 
     def features(self, n: int, snr=None, spacing_q8: int = 0, stream=None):
         """Features of the candidates left in the device buffer by the last
