@@ -12,7 +12,7 @@ fast style, 5e4-5e5 detections, 40-120 epochs, each with its own grid and
 threshold) voted by one batched launch per kernel class, with launch shapes
 chosen by the autotuner per chip style.
 
-Prints one JSON line (rank 0).  --gpus above 1 is refused: this build
+Prints one JSON line (rank 0).  --gpus above 1 is refused: the benchmark
 measures one GPU.
 """
 from __future__ import annotations
@@ -212,9 +212,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--chips", type=int, default=64, help="night workload: number of chips")
     ap.add_argument("--no-tune", action="store_true", help="night workload: planner defaults")
+    ap.add_argument("--extract", action="store_true",
+                    help="also time the greedy cluster extraction over the step's candidates")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU; --gpus %d is not supported by this build" % args.gpus,
+        print("bench.py measures one GPU; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
@@ -296,6 +298,20 @@ def main():
                      "ops": "int16x2 packed" if info.get("packed") else "int32",
                      "lds_atomic_frac": votes / (kernel_ms * 1e-3) / LDS_ATOMIC_PEAK},
     }
+    if args.extract:
+        # Step 3's greedy extraction over the candidates of the last vote
+        # (not part of the step above): wall time of the whole call
+        ext = []
+        for k in range(args.warmup + args.steps):
+            s.vote(x, y, e)
+            s.peaks()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            clusters, _ = s.extract(wl.n)
+            if k >= args.warmup:
+                ext.append((time.perf_counter() - t1) * 1000.0)
+        rec["extract"] = {"ms": float(np.mean(ext)), "n_clusters": int(len(clusters)),
+                          "n_cells": n_cand}
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(wl, v, args.cpu_seconds)
     plan.close()

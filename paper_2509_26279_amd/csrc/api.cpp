@@ -1233,7 +1233,8 @@ extern "C" sas_status sas_features(const sas_plan *p, const void *workspace, siz
 namespace {
 
 struct ExtractScratch {
-    size_t first, blocksum, member, member_epoch, live, open, total;
+    size_t first, blocksum, member, member_epoch, member_cell, inv_first, inv_blocksum,
+        inv_cursor, inv, count, dirty, live, open, total;
 };
 
 ExtractScratch extract_layout(int64_t n, int64_t n_cand, int64_t member_cap) {
@@ -1243,6 +1244,13 @@ ExtractScratch extract_layout(int64_t n, int64_t n_cand, int64_t member_cap) {
     L.blocksum = o; o = align_up(o + sizeof(int32_t) * ((n_cand + 1 + kScanTile - 1) / kScanTile));
     L.member = o; o = align_up(o + sizeof(int32_t) * member_cap);
     L.member_epoch = o; o = align_up(o + member_cap);
+    L.member_cell = o; o = align_up(o + sizeof(int32_t) * member_cap);
+    L.inv_first = o; o = align_up(o + sizeof(int32_t) * (n + 1));
+    L.inv_blocksum = o; o = align_up(o + sizeof(int32_t) * ((n + 1 + kScanTile - 1) / kScanTile));
+    L.inv_cursor = o; o = align_up(o + sizeof(int32_t) * n);
+    L.inv = o; o = align_up(o + sizeof(int32_t) * member_cap);
+    L.count = o; o = align_up(o + sizeof(int32_t) * n_cand);
+    L.dirty = o; o = align_up(o + sizeof(uint32_t) * n_cand);
     L.live = o; o = align_up(o + n);
     L.open = o; o = align_up(o + n_cand);
     L.total = o;
@@ -1298,7 +1306,14 @@ extern "C" sas_status sas_extract_clusters(const sas_plan *p, const void *worksp
     a.scan_blocksum = (int32_t *)(s + S.blocksum);
     a.member = (int32_t *)(s + S.member);
     a.member_epoch = (uint8_t *)(s + S.member_epoch);
+    a.member_cell = (int32_t *)(s + S.member_cell);
     a.member_cap = member_cap;
+    a.inv_first = (int32_t *)(s + S.inv_first);
+    a.inv_blocksum = (int32_t *)(s + S.inv_blocksum);
+    a.inv_cursor = (int32_t *)(s + S.inv_cursor);
+    a.inv = (int32_t *)(s + S.inv);
+    a.count = (int32_t *)(s + S.count);
+    a.dirty = (uint32_t *)(s + S.dirty);
     a.live = (uint8_t *)(s + S.live);
     a.open = (uint8_t *)(s + S.open);
     a.clusters = clusters_dev;

@@ -12,11 +12,15 @@
 //      a wave scan places each lane's contributors.  A first pass counts,
 //      a scan lays the cells' lists out, a second pass writes the sorted
 //      positions of the contributors and their epochs.
-//   2. k_greedy: one workgroup runs the loop.  Each round every open cell
-//      recounts its live contributors (distinct epochs through a 256-bit
-//      mask in LDS, or their number), cells below N_min close, a block
-//      reduction finds the maximum under the tie rule, and its live
-//      contributors are marked taken (with the cluster's index).
+//   2. an inverse index (detection -> cells that hold it) by counting sort,
+//      and every cell's count (one wave per cell: distinct epochs through a
+//      256-bit mask in LDS, or the number of live contributors);
+//   3. k_greedy: one workgroup runs the loop.  Each round a block reduction
+//      finds the maximum of the stored counts under the tie rule (cells
+//      below N_min close), the maximum's live contributors are taken (with
+//      the cluster's index) and every open cell that held one of them is
+//      queued; only the queued cells are recounted (one wave each), since the
+//      counts of the others have not changed.
 #include <algorithm>
 
 #include "internal.h"
@@ -56,7 +60,7 @@ __device__ inline int32_t wave_excl(int32_t v, int32_t *total) {
 // counted (WRITE = false) or written from position at (WRITE = true).
 template <bool WRITE>
 __device__ int32_t lane_contributors(const ExtractArgs &a, const sas_candidate &cd,
-                                     int32_t at) {
+                                     int32_t cell, int32_t at) {
     const PreparedCatalog &c = a.cat;
     const int lane = __lane_id();
     const int lb = a.log2b;
@@ -81,6 +85,7 @@ __device__ int32_t lane_contributors(const ExtractArgs &a, const sas_candidate &
                 if (WRITE) {
                     a.member[at + n] = j;
                     a.member_epoch[at + n] = (uint8_t)e;
+                    a.member_cell[at + n] = cell;
                 }
                 ++n;
             }
@@ -97,15 +102,15 @@ __global__ void __launch_bounds__(CT) k_contrib(ExtractArgs a, int write) {
         const sas_candidate cd = a.cand[k];
         if (!write) {
             int32_t total;
-            wave_excl(lane_contributors<false>(a, cd, 0), &total);
+            wave_excl(lane_contributors<false>(a, cd, (int32_t)k, 0), &total);
             if (lane == 0) a.first[k] = total;  // scanned into offsets afterwards
         } else {
-            const int32_t mine = lane_contributors<false>(a, cd, 0);
+            const int32_t mine = lane_contributors<false>(a, cd, (int32_t)k, 0);
             int32_t total;
             const int32_t pre = wave_excl(mine, &total);
             const int64_t at = a.first[k] + pre;
             if (a.first[a.n_cand] <= a.member_cap)  // all lists fit
-                lane_contributors<true>(a, cd, (int32_t)at);
+                lane_contributors<true>(a, cd, (int32_t)k, (int32_t)at);
         }
     }
 }
@@ -137,12 +142,94 @@ __device__ inline Best shfl_best(const Best &b, int src) {
     return o;
 }
 
+// Whether the contributor lists fit (all kernels after the lists read it).
+__device__ inline bool lists_fit(const ExtractArgs &a) {
+    return a.first[a.n_cand] <= a.member_cap;
+}
+
+// Per-detection state and the inverse index counts, cleared.
+__global__ void k_inv_init(ExtractArgs a) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t j = t0; j <= a.n; j += stride) a.inv_first[j] = 0;
+    for (int64_t j = t0; j < a.n; j += stride) {
+        a.inv_cursor[j] = 0;
+        a.live[j] = 1;
+        a.cluster_of[j] = -1;
+    }
+    for (int64_t k = t0; k < a.n_cand; k += stride) {
+        a.open[k] = 1;
+        a.dirty[k] = 0;
+    }
+}
+
+__global__ void k_inv_count(ExtractArgs a) {
+    if (!lists_fit(a)) return;
+    const int64_t n_members = a.first[a.n_cand];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < n_members; m += stride)
+        atomicAdd(&a.inv_first[a.member[m]], 1);
+}
+
+__global__ void k_inv_fill(ExtractArgs a) {
+    if (!lists_fit(a)) return;
+    const int64_t n_members = a.first[a.n_cand];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < n_members; m += stride) {
+        const int32_t j = a.member[m];
+        a.inv[a.inv_first[j] + atomicAdd(&a.inv_cursor[j], 1)] = a.member_cell[m];
+    }
+}
+
+// Count of cell k over its live contributors, by one wave (wave uniform);
+// wmask: 8 words of LDS for this wave.
+__device__ int32_t recount(const ExtractArgs &a, int64_t k, uint32_t *wmask) {
+    const int lane = __lane_id();
+    if (lane < kSlotWords) wmask[lane] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int32_t f = a.first[k], l = a.first[k + 1];
+    int32_t n = 0;
+    for (int32_t m = f + lane; m < l; m += 64) {
+        if (!a.live[a.member[m]]) continue;
+        if (a.mode_epochs) {
+            const uint32_t e = a.member_epoch[m];
+            atomicOr(&wmask[e >> 5], 1u << (e & 31));
+        } else {
+            ++n;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (a.mode_epochs) n = lane < kSlotWords ? __popc(wmask[lane]) : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, 64);
+    return n;
+}
+
+__global__ void __launch_bounds__(CT) k_count_all(ExtractArgs a) {
+    __shared__ uint32_t wmask[CT / 64][kSlotWords];
+    if (!lists_fit(a)) return;
+    const int wave = threadIdx.x >> 6;
+    const int64_t wave_id = ((int64_t)blockIdx.x * CT + threadIdx.x) >> 6;
+    const int64_t n_waves = ((int64_t)gridDim.x * CT) >> 6;
+    for (int64_t k = wave_id; k < a.n_cand; k += n_waves) {
+        const int32_t n = recount(a, k, wmask[wave]);
+        if (__lane_id() == 0) a.count[k] = n;
+    }
+}
+
+constexpr int kQueueCap = 4096;  // cells recounted after one take
+
 __global__ void __launch_bounds__(GT) k_greedy(ExtractArgs a) {
-    __shared__ uint32_t masks[GT][kSlotWords];
+    __shared__ uint32_t wmask[GW][kSlotWords];
+    __shared__ int32_t queue[kQueueCap];
+    __shared__ int32_t queue_n;
     __shared__ Best wbest[GW];
     __shared__ Best best_all;
     const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
-    uint32_t *mk = masks[tid];
     const int64_t n_members = a.first[a.n_cand];
     if (n_members > a.member_cap) {  // the lists did not fit: report, extract nothing
         if (tid == 0) {
@@ -152,35 +239,19 @@ __global__ void __launch_bounds__(GT) k_greedy(ExtractArgs a) {
         }
         return;
     }
-    for (int64_t j = tid; j < a.n; j += GT) a.live[j] = 1;
-    for (int64_t k = tid; k < a.n_cand; k += GT) a.open[k] = 1;
-    for (int64_t i = tid; i < a.n; i += GT) a.cluster_of[i] = -1;
-    __syncthreads();
     int64_t n_out = 0;
     const uint32_t sat = (uint32_t)a.count_sat;
     for (;;) {
+        // the maximum of the stored counts; cells below N_min close
         Best mine{0, -1, 0, 0, 0};
         for (int64_t k = tid; k < a.n_cand; k += GT) {
             if (!a.open[k]) continue;
-            const int32_t f = a.first[k], l = a.first[k + 1];
-            int32_t cnt = 0;
-            if (a.mode_epochs) {
-#pragma unroll
-                for (int w = 0; w < kSlotWords; ++w) mk[w] = 0;
-                for (int32_t m = f; m < l; ++m) {
-                    if (!a.live[a.member[m]]) continue;
-                    const uint32_t e = a.member_epoch[m];
-                    mk[e >> 5] |= 1u << (e & 31);
-                }
-#pragma unroll
-                for (int w = 0; w < kSlotWords; ++w) cnt += __popc(mk[w]);
-            } else {
-                for (int32_t m = f; m < l; ++m) cnt += a.live[a.member[m]];
-            }
+            const int32_t cnt = a.count[k];
             if (cnt < a.n_min) {
                 a.open[k] = 0;
                 continue;
             }
+            if (cnt < mine.count) continue;
             const sas_candidate cd = a.cand[k];
             const Best b{cnt, (int32_t)k, cd.v_idx, cd.by, cd.bx};
             if (better(b, mine)) mine = b;
@@ -197,6 +268,7 @@ __global__ void __launch_bounds__(GT) k_greedy(ExtractArgs a) {
             for (int w = 1; w < GW; ++w)
                 if (better(wbest[w], b)) b = wbest[w];
             best_all = b;
+            queue_n = 0;
         }
         __syncthreads();
         const Best b = best_all;
@@ -213,13 +285,45 @@ __global__ void __launch_bounds__(GT) k_greedy(ExtractArgs a) {
             }
             a.open[b.k] = 0;
         }
+        // take its live contributors; queue the open cells that held them
         const int32_t f = a.first[b.k], l = a.first[b.k + 1];
         for (int32_t m = f + tid; m < l; m += GT) {
             const int32_t j = a.member[m];
-            if (a.live[j]) a.cluster_of[a.cat.sidx[j]] = (int32_t)n_out;
+            if (!a.live[j]) continue;
+            a.cluster_of[a.cat.sidx[j]] = (int32_t)n_out;
+            for (int32_t i = a.inv_first[j]; i < a.inv_first[j + 1]; ++i) {
+                const int32_t c = a.inv[i];
+                if (c == b.k || !a.open[c]) continue;
+                if (atomicExch(&a.dirty[c], 1u) == 0u) {
+                    const int32_t q = atomicAdd(&queue_n, 1);
+                    if (q < kQueueCap) queue[q] = c;
+                }
+            }
         }
-        __syncthreads();  // cluster_of is written before live drops
+        __syncthreads();  // every mark reads live before it drops
         for (int32_t m = f + tid; m < l; m += GT) a.live[a.member[m]] = 0;
+        __syncthreads();
+        // recount the queued cells (all open cells if the queue overflowed)
+        const int32_t nq = queue_n;
+        if (nq <= kQueueCap) {
+            for (int32_t q = wave; q < nq; q += GW) {
+                const int32_t c = queue[q];
+                const int32_t n = recount(a, c, wmask[wave]);
+                if (lane == 0) {
+                    a.count[c] = n;
+                    a.dirty[c] = 0;
+                }
+            }
+        } else {
+            for (int64_t c = wave; c < a.n_cand; c += GW) {
+                if (!a.open[c]) continue;  // wave uniform
+                const int32_t n = recount(a, c, wmask[wave]);
+                if (lane == 0) {
+                    a.count[c] = n;
+                    a.dirty[c] = 0;
+                }
+            }
+        }
         ++n_out;
         __syncthreads();
     }
@@ -235,16 +339,25 @@ __global__ void k_contrib_tail(int32_t *first, int64_t n_cand) { first[n_cand] =
 }  // namespace
 
 hipError_t launch_extract(const ExtractArgs &a, hipStream_t stream) {
+    const unsigned init_blocks = (unsigned)std::min<int64_t>(
+        (std::max(a.n + 1, a.n_cand) + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_inv_init, dim3(init_blocks), dim3(256), 0, stream, a);
+    const unsigned cell_blocks =
+        (unsigned)std::max<int64_t>(1, std::min<int64_t>((a.n_cand + CT / 64 - 1) / (CT / 64),
+                                                         65536));
+    if (a.n_cand > 0)
+        hipLaunchKernelGGL(k_contrib, dim3(cell_blocks), dim3(CT), 0, stream, a, 0);
+    // first[n_cand] must read 0 before the scan turns counts into offsets
+    hipLaunchKernelGGL(k_contrib_tail, dim3(1), dim3(1), 0, stream, a.first, a.n_cand);
+    hipError_t e = launch_scan_exclusive(a.first, a.n_cand + 1, a.scan_blocksum, stream);
+    if (e != hipSuccess) return e;
     if (a.n_cand > 0) {
-        const int64_t blocks = std::min<int64_t>((a.n_cand + CT / 64 - 1) / (CT / 64), 65536);
-        hipLaunchKernelGGL(k_contrib, dim3((unsigned)blocks), dim3(CT), 0, stream, a, 0);
-        // first[n_cand] must read 0 before the scan turns counts into offsets
-        hipLaunchKernelGGL(k_contrib_tail, dim3(1), dim3(1), 0, stream, a.first, a.n_cand);
-        hipError_t e = launch_scan_exclusive(a.first, a.n_cand + 1, a.scan_blocksum, stream);
+        hipLaunchKernelGGL(k_contrib, dim3(cell_blocks), dim3(CT), 0, stream, a, 1);
+        hipLaunchKernelGGL(k_inv_count, dim3(2048), dim3(256), 0, stream, a);
+        e = launch_scan_exclusive(a.inv_first, a.n + 1, a.inv_blocksum, stream);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_contrib, dim3((unsigned)blocks), dim3(CT), 0, stream, a, 1);
-    } else {
-        hipLaunchKernelGGL(k_contrib_tail, dim3(1), dim3(1), 0, stream, a.first, a.n_cand);
+        hipLaunchKernelGGL(k_inv_fill, dim3(2048), dim3(256), 0, stream, a);
+        hipLaunchKernelGGL(k_count_all, dim3(cell_blocks), dim3(CT), 0, stream, a);
     }
     hipLaunchKernelGGL(k_greedy, dim3(1), dim3(GT), 0, stream, a);
     return hipGetLastError();

@@ -159,7 +159,14 @@ struct ExtractArgs {
     int32_t *scan_blocksum;
     int32_t *member;           // [member_cap] sorted positions of the contributors
     uint8_t *member_epoch;     // [member_cap] their epochs
+    int32_t *member_cell;      // [member_cap] the cell of each entry
     int64_t member_cap;
+    int32_t *inv_first;        // [n + 1] cells holding a detection: counts, then offsets
+    int32_t *inv_blocksum;
+    int32_t *inv_cursor;       // [n]
+    int32_t *inv;              // [member_cap] the cells, grouped by detection
+    int32_t *count;            // [n_cand] current count of each cell
+    uint32_t *dirty;           // [n_cand] queued for a recount
     uint8_t *live;             // [n] by sorted position: not yet in a cluster
     uint8_t *open;             // [n_cand] cell may still reach N_min
     sas_candidate *clusters;   // [cluster_cap] in extraction order
