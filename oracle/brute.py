@@ -15,7 +15,11 @@ detections at most:
     [k Delta x, (k+1) Delta x));
   * the count of a bin is the number of distinct epochs (or of detections)
     that fall in it, and bins with count >= N_min are reported (the stopping
-    rule of Step 3 read as a threshold).
+    rule of Step 3 read as a threshold);
+  * weighted counts (a per-detection likelihood accumulated instead of an
+    indicator, Conclusions): per epoch the largest weight among the bin's
+    detections of that epoch, summed over epochs ("weighted_epochs"), or the
+    sum of all their weights ("weighted_detections").
 
 Units: positions in px, velocities in px/h, times in h, all as exact
 rationals built from the integer catalog (Q8 px, Q8 px/h, Q16 h).
@@ -33,8 +37,22 @@ def project(x_q8, t_q16, t0_q16, u_q8):
     return x - Fraction(int(u_q8), 256) * dt
 
 
+def _score(members, mode):
+    """Count of a bin from its (epoch, weight) members."""
+    if mode == "epochs":
+        return len({e for e, _ in members})
+    if mode == "detections":
+        return len(members)
+    if mode == "weighted_detections":
+        return sum(w for _, w in members)
+    best = {}
+    for e, w in members:
+        best[e] = max(best.get(e, 0), w)
+    return sum(best.values())
+
+
 def brute_vote(x_q8, y_q8, epoch, t_q16, v_q8, binw_q8, n_min, mode="epochs",
-               count_sat=65535):
+               count_sat=65535, weight=None):
     """List of (v_idx, bx, by, count, flags) ordered by (v_idx, by, bx)."""
     n = len(x_q8)
     if n == 0:
@@ -49,10 +67,9 @@ def brute_vote(x_q8, y_q8, epoch, t_q16, v_q8, binw_q8, n_min, mode="epochs",
             xp = project(x_q8[i], t_q16[e], t0, u)
             yp = project(y_q8[i], t_q16[e], t0, w)
             key = (math.floor(yp / width), math.floor(xp / width))
-            bins.setdefault(key, []).append(e)
+            bins.setdefault(key, []).append((e, int(weight[i]) if weight is not None else 1))
         for (by, bx) in sorted(bins):
-            eps = bins[(by, bx)]
-            c = len(set(eps)) if mode == "epochs" else len(eps)
+            c = _score(bins[(by, bx)], mode)
             if c >= n_min:
                 sat = c > count_sat
                 out.append((j, bx, by, min(c, count_sat), 1 if sat else 0))

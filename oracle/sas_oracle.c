@@ -21,6 +21,15 @@
  *   DETECTIONS:  c_j(bx,by) = |{ i   : (bx_ij,by_ij) = (bx,by) }|
  *   output: every (j, bx, by, c) with c >= N_min, ordered by (j, by, bx).
  *
+ * Weighted counts (the accumulation of a per-detection likelihood instead
+ * of an indicator, suggested in the Conclusions): every detection carries
+ * an integer weight w_i in [0, 255], and
+ *   WEIGHTED_EPOCHS:     c_j(bx,by) = sum over epochs e of the largest w_i
+ *                        among the detections of epoch e in the bin,
+ *   WEIGHTED_DETECTIONS: c_j(bx,by) = sum of w_i over the bin's detections,
+ * with N_min the threshold on that score.  All weights 1 give EPOCHS and
+ * DETECTIONS back.
+ *
  * Products are formed in 128-bit integers and divided with an explicit floor
  * division (not shifts), so no range assumption is needed here.  Each
  * velocity is handled by sorting its (by, bx, e) triples and walking the runs:
@@ -45,6 +54,7 @@ typedef struct {
 typedef struct {
     int64_t by, bx;
     int32_t e;
+    int32_t w;
 } triple;
 
 static __int128 floor_div128(__int128 a, __int128 b) /* b > 0 */
@@ -75,10 +85,44 @@ static int reference_time(int64_t n, const uint8_t *epoch, const int64_t *t, int
     return 1;
 }
 
+#define MODE_EPOCHS 0
+#define MODE_DETECTIONS 1
+#define MODE_WEIGHTED_EPOCHS 2
+#define MODE_WEIGHTED_DETECTIONS 3
+
+/* Count of the bin held by the sorted run r[0, len) (one epoch after
+ * another, by the sort order) in the given mode. */
+static int64_t run_count(const triple *r, int64_t len, int32_t mode)
+{
+    int64_t count = 0, best = 0;
+    for (int64_t k = 0; k < len; ++k) {
+        const int new_epoch = k == 0 || r[k].e != r[k - 1].e;
+        switch (mode) {
+        case MODE_EPOCHS:
+            if (new_epoch) count += 1;                   /* a new epoch in this bin */
+            break;
+        case MODE_DETECTIONS:
+            count += 1;                                  /* every detection */
+            break;
+        case MODE_WEIGHTED_EPOCHS:
+            if (new_epoch) {                             /* close the previous epoch */
+                count += best;
+                best = 0;
+            }
+            if (r[k].w > best) best = r[k].w;            /* largest weight of this epoch */
+            break;
+        default:
+            count += r[k].w;                             /* every detection's weight */
+        }
+    }
+    return count + best;
+}
+
 /* One velocity: fills `out` (capacity n) with this velocity's candidates in
  * (by, bx) order and returns how many there are. */
 static int64_t one_velocity(int64_t n, const int32_t *x, const int32_t *y, const uint8_t *epoch,
-                            const int64_t *dt, int64_t u, int64_t w, int64_t binw,
+                            const uint8_t *weight, const int64_t *dt, int64_t u, int64_t w,
+                            int64_t binw,
                             int32_t n_min, int32_t mode, int32_t count_sat, uint32_t j,
                             triple *scratch, oracle_cand *out)
 {
@@ -90,6 +134,7 @@ static int64_t one_velocity(int64_t n, const int32_t *x, const int32_t *y, const
         scratch[i].bx = (int64_t)floor_div128(X, denom);
         scratch[i].by = (int64_t)floor_div128(Y, denom);
         scratch[i].e = epoch[i];
+        scratch[i].w = weight ? weight[i] : 1;
     }
     qsort(scratch, (size_t)n, sizeof(triple), cmp_triple);
 
@@ -97,15 +142,8 @@ static int64_t one_velocity(int64_t n, const int32_t *x, const int32_t *y, const
     int64_t i = 0;
     while (i < n) {
         int64_t k = i;
-        int64_t count = 0;
-        while (k < n && scratch[k].by == scratch[i].by && scratch[k].bx == scratch[i].bx) {
-            if (mode == 1) {
-                count += 1;                              /* every detection */
-            } else if (k == i || scratch[k].e != scratch[k - 1].e) {
-                count += 1;                              /* a new epoch in this bin */
-            }
-            ++k;
-        }
+        while (k < n && scratch[k].by == scratch[i].by && scratch[k].bx == scratch[i].bx) ++k;
+        const int64_t count = run_count(scratch + i, k - i, mode);
         if (count >= n_min) {
             oracle_cand c;
             c.v_idx = j;
@@ -126,18 +164,21 @@ static int64_t one_velocity(int64_t n, const int32_t *x, const int32_t *y, const
  *   t_q16     [n_epochs] int64 Q16 h (any origin)
  *   v         [n_v][2] int32 Q8 px/h
  *   binw      bin width, Q8 px (> 0)
- *   mode      0 = distinct epochs, 1 = detections
+ *   weight    [n] in [0, 255] for the weighted modes, NULL otherwise
+ *   mode      0 = distinct epochs, 1 = detections, 2 = weighted epochs,
+ *             3 = weighted detections
  *   count_sat largest reportable count (255 or 65535)
  *   out/cap   caller buffer; the return value is the total number of
  *             candidates (out holds the first min(total, cap) of them).
  * Returns -1 on invalid arguments or allocation failure.
  */
 int64_t oracle_vote(int64_t n, const int32_t *x, const int32_t *y, const uint8_t *epoch,
-                    int32_t n_epochs, const int64_t *t_q16, int64_t n_v, const int32_t *v,
-                    int64_t binw, int32_t n_min, int32_t mode, int32_t count_sat,
-                    int32_t n_threads, oracle_cand *out, int64_t cap)
+                    const uint8_t *weight, int32_t n_epochs, const int64_t *t_q16, int64_t n_v,
+                    const int32_t *v, int64_t binw, int32_t n_min, int32_t mode,
+                    int32_t count_sat, int32_t n_threads, oracle_cand *out, int64_t cap)
 {
-    if (n < 0 || n_v < 0 || binw <= 0 || n_min < 1 || n_epochs < 1 || (mode != 0 && mode != 1))
+    if (n < 0 || n_v < 0 || binw <= 0 || n_min < 1 || n_epochs < 1 || mode < 0 || mode > 3 ||
+        (mode >= MODE_WEIGHTED_EPOCHS) != (weight != NULL))
         return -1;
     for (int64_t i = 0; i < n; ++i)
         if (epoch[i] >= n_epochs) return -1;
@@ -167,8 +208,8 @@ int64_t oracle_vote(int64_t n, const int32_t *x, const int32_t *y, const uint8_t
 #pragma omp for schedule(dynamic, 1)
         for (int64_t j = 0; j < n_v; ++j) {
             if (!scratch || !tmp) continue;
-            int64_t k = one_velocity(n, x, y, epoch, dt, v[2 * j], v[2 * j + 1], binw, n_min,
-                                     mode, count_sat, (uint32_t)j, scratch, tmp);
+            int64_t k = one_velocity(n, x, y, epoch, weight, dt, v[2 * j], v[2 * j + 1], binw,
+                                     n_min, mode, count_sat, (uint32_t)j, scratch, tmp);
             per_v[j] = k;
             if (k > 0) {
                 res[j] = (oracle_cand *)malloc(sizeof(oracle_cand) * (size_t)k);
@@ -205,22 +246,29 @@ int64_t oracle_vote(int64_t n, const int32_t *x, const int32_t *y, const uint8_t
  * Detections outside the window are counted into *outside.
  */
 int oracle_histogram(int64_t n, const int32_t *x, const int32_t *y, const uint8_t *epoch,
-                     int32_t n_epochs, const int64_t *t_q16, int32_t u, int32_t w, int64_t binw,
-                     int32_t mode, int64_t bx0, int64_t by0, int64_t nbx, int64_t nby,
-                     int64_t *hist, int64_t *outside)
+                     const uint8_t *weight, int32_t n_epochs, const int64_t *t_q16, int32_t u,
+                     int32_t w, int64_t binw, int32_t mode, int64_t bx0, int64_t by0,
+                     int64_t nbx, int64_t nby, int64_t *hist, int64_t *outside)
 {
-    if (n < 0 || binw <= 0 || n_epochs < 1 || nbx < 0 || nby < 0) return -1;
+    if (n < 0 || binw <= 0 || n_epochs < 1 || nbx < 0 || nby < 0 || mode < 0 || mode > 3 ||
+        (mode >= MODE_WEIGHTED_EPOCHS) != (weight != NULL))
+        return -1;
     for (int64_t i = 0; i < n; ++i)
         if (epoch[i] >= n_epochs) return -1;
     memset(hist, 0, sizeof(int64_t) * (size_t)(nbx * nby));
     *outside = 0;
     int64_t t0 = 0;
     if (!reference_time(n, epoch, t_q16, &t0)) return 0;
-    /* per bin, a record of which epochs were seen (n_epochs <= 256) */
+    /* per bin, a record of which epochs were seen (n_epochs <= 256); in
+     * WEIGHTED_EPOCHS, the largest weight (+1) seen per (bin, epoch) */
     uint8_t *seen = NULL;
-    if (mode == 0) {
+    int32_t *best = NULL;
+    if (mode == MODE_EPOCHS) {
         seen = (uint8_t *)calloc((size_t)(nbx * nby) * 256, 1);
         if (!seen) return -1;
+    } else if (mode == MODE_WEIGHTED_EPOCHS) {
+        best = (int32_t *)calloc((size_t)(nbx * nby) * 256, sizeof(int32_t));
+        if (!best) return -1;
     }
     const __int128 denom = (__int128)binw * 65536;
     for (int64_t i = 0; i < n; ++i) {
@@ -231,13 +279,23 @@ int oracle_histogram(int64_t n, const int32_t *x, const int32_t *y, const uint8_
         const int64_t by = (int64_t)floor_div128(Y, denom) - by0;
         if (bx < 0 || bx >= nbx || by < 0 || by >= nby) { *outside += 1; continue; }
         const int64_t cell = by * nbx + bx;
-        if (mode == 1) {
+        if (mode == MODE_DETECTIONS) {
             hist[cell] += 1;
+        } else if (mode == MODE_WEIGHTED_DETECTIONS) {
+            hist[cell] += weight[i];
+        } else if (mode == MODE_WEIGHTED_EPOCHS) {
+            /* replace this epoch's contribution when a heavier detection comes */
+            int32_t *b = &best[cell * 256 + epoch[i]];
+            if (weight[i] > *b) {
+                hist[cell] += weight[i] - *b;
+                *b = weight[i];
+            }
         } else if (!seen[cell * 256 + epoch[i]]) {
             seen[cell * 256 + epoch[i]] = 1;
             hist[cell] += 1;
         }
     }
     free(seen);
+    free(best);
     return 0;
 }
