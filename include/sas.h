@@ -24,6 +24,12 @@
  * the same for y.  Bins are anchored at 0 and half open: [k b, (k+1) b).
  * Count of a bin: the number of distinct epochs among its detections
  * (SAS_MODE_EPOCHS) or the number of its detections (SAS_MODE_DETECTIONS).
+ * Weighted counts accumulate a per-detection weight w_i in [0, 255] (for
+ * example a quantised detection likelihood) in place of the indicator, as
+ * the Conclusions suggest: per epoch the largest weight among the bin's
+ * detections of that epoch, summed over epochs (SAS_MODE_WEIGHTED_EPOCHS),
+ * or the sum of all their weights (SAS_MODE_WEIGHTED_DETECTIONS).  N_min is
+ * then the threshold on that score.  Weights of 1 give the indicator modes.
  *
  * Memory: "host" pointers are ordinary CPU memory, "device" pointers are
  * HIP device memory (hipMalloc or a framework's allocator) of the GPU that
@@ -129,7 +135,7 @@ sas_status sas_threshold_n_min(int32_t n_epochs, double mu, double n_stacks, dou
 typedef struct {
     uint32_t v_idx;  /* index of the trial velocity in the plan's velocity set */
     int32_t bx, by;  /* bin of the projected positions, anchored at 0 */
-    uint16_t count;  /* distinct epochs (or detections), capped at count_sat */
+    uint16_t count;  /* the bin's count or weighted score, capped at count_sat */
     uint16_t flags;  /* bit 0: the true count exceeded count_sat */
 } sas_candidate;     /* 16 bytes */
 
@@ -142,6 +148,8 @@ typedef struct {
 
 #define SAS_MODE_EPOCHS 0
 #define SAS_MODE_DETECTIONS 1
+#define SAS_MODE_WEIGHTED_EPOCHS 2     /* dense path; voted with sas_vote_weighted */
+#define SAS_MODE_WEIGHTED_DETECTIONS 3 /* dense path; voted with sas_vote_weighted */
 
 #define SAS_PATH_AUTO 0
 #define SAS_PATH_DENSE 1   /* LDS-resident count tiles (velocity block x spatial tile) */
@@ -196,7 +204,10 @@ typedef struct sas_plan sas_plan;
  * velocity array is copied; the caller may free it on return.
  * Errors: SAS_E_INVALID (arguments; message in sas_last_error),
  * SAS_E_UNSUPPORTED (bin width not a power of two, |v| * Delta t too large
- * for 32-bit bins), SAS_E_NOMEM, SAS_E_DEVICE.
+ * for 32-bit bins, a weighted mode on the sort path, a weighted tile row of
+ * 2^24 Q8 px or more), SAS_E_NOMEM, SAS_E_DEVICE.
+ * Weighted plans use single-bin histograms unless tuning.coarse_log2 > 0
+ * asks for coarse cells, and never the packed 16-bit votes.
  */
 sas_status sas_plan_create(const sas_plan_desc *desc, sas_plan **plan_out);
 sas_status sas_plan_destroy(sas_plan *plan);
@@ -210,7 +221,8 @@ typedef struct {
     int32_t vblock_x, vblock_y;
     int32_t cell_log2;
     int32_t coarse_log2;   /* histogram cells of 2^m x 2^m bins */
-    int32_t mode_variant;  /* 0 epoch masks, 1 detection counts, 2 counts + refinement */
+    int32_t mode_variant;  /* 0 epoch masks, 1 detection counts, 2 counts + refinement,
+                              3 weight sums, 4 weight sums + refinement */
     int64_t n_v;
     int32_t groups;        /* lane groups G */
     int32_t hist_x, hist_y; /* histogram cells per tile, guard cells included */
@@ -243,11 +255,29 @@ sas_status sas_vote_workspace_size(const sas_plan *plan, int64_t n, size_t *byte
  * Asynchronous: returns once the work is enqueued.  No allocation, no
  * synchronisation, no memset nodes: safe to capture in a HIP graph.  Calls
  * that share a workspace or a result must be ordered by the caller.
- * Errors (host side, nothing enqueued): SAS_E_INVALID, SAS_E_WORKSPACE.
+ * Errors (host side, nothing enqueued): SAS_E_INVALID (also for a plan in
+ * a weighted mode), SAS_E_WORKSPACE.
  */
 sas_status sas_vote(const sas_plan *plan, const int32_t *x_q8, const int32_t *y_q8,
                     const uint8_t *epoch, int64_t n, sas_candidate *cand_dev, int64_t cand_cap,
                     sas_vote_result *res_dev, void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * sas_vote_weighted: sas_vote for a plan in SAS_MODE_WEIGHTED_EPOCHS or
+ * SAS_MODE_WEIGHTED_DETECTIONS (the weighted accumulation the Conclusions
+ * propose in place of the detection indicator).
+ *   weight: device [n] uint8, the weight of each detection (0..255).
+ * Every other argument, the outputs and the asynchronous, allocation-free
+ * behaviour are those of sas_vote; a candidate's count is its score capped
+ * at count_sat.  Weighted plans are not accepted by sas_batch_create or
+ * sas_extract_clusters.
+ * Errors (host side, nothing enqueued): SAS_E_INVALID (also for a plan in
+ * an indicator mode, or a null weight array with n > 0), SAS_E_WORKSPACE.
+ */
+sas_status sas_vote_weighted(const sas_plan *plan, const int32_t *x_q8, const int32_t *y_q8,
+                             const uint8_t *epoch, const uint8_t *weight, int64_t n,
+                             sas_candidate *cand_dev, int64_t cand_cap, sas_vote_result *res_dev,
+                             void *workspace, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
  * Batches: many catalogs (e.g. the chips of one night, each with its own

@@ -148,8 +148,15 @@ sas_status upload(sas_plan *p, T **dst, const std::vector<T> &src) {
     return SAS_OK;
 }
 
+bool is_weighted(int32_t mode) {
+    return mode == SAS_MODE_WEIGHTED_EPOCHS || mode == SAS_MODE_WEIGHTED_DETECTIONS;
+}
+
+bool refines(int dense_mode) { return dense_mode == kCountRef || dense_mode == kWeightRef; }
+
 struct WsLayout {
-    size_t count, blocksum, cellid, rank, sxy, sidx, present, dt, refine_count, refine;
+    size_t count, blocksum, cellid, rank, sxy, sw, sidx, present, dt, refine_count, refine;
+    bool has_sw;
     size_t keys, keys_alt, hist, hist_blocksum;  // sort path
     size_t total;
 };
@@ -166,12 +173,14 @@ WsLayout ws_layout(const sas_plan *p, int64_t n) {
     L.rank = o; o = align_up(o + sizeof(int32_t) * nn);
     // the vote kernel may read up to 3 detections past a run: 32 bytes of slack
     L.sxy = o; o = align_up(o + 2 * sizeof(int32_t) * nn + 32);
+    L.has_sw = is_weighted(p->mode);  // weights in sorted order, with the same slack
+    L.sw = o; o = align_up(o + (L.has_sw ? nn + 32 : 0));
     L.sidx = o; o = align_up(o + sizeof(int32_t) * nn);
     L.present = o; o = align_up(o + sizeof(int32_t) * kMaxEpochs);
     L.dt = o; o = align_up(o + sizeof(int32_t) * kMaxEpochs);
     L.refine_count = o; o = align_up(o + sizeof(unsigned long long));
     L.refine = o;
-    o = align_up(o + sizeof(int4) * (p->path == SAS_PATH_DENSE && p->dense_mode == kCountRef
+    o = align_up(o + sizeof(int4) * (p->path == SAS_PATH_DENSE && refines(p->dense_mode)
                                          ? p->refine_cap : 1));
     const int64_t keys = p->path == SAS_PATH_SORT ? p->sort_max_nv * std::max<int64_t>(n, 1) : 1;
     const int64_t tiles = (keys + kSortKeysPerTile - 1) / kSortKeysPerTile;
@@ -191,6 +200,7 @@ PrepBuffers prep_buffers(const WsLayout &L, char *w) {
     pb.cellid = (int32_t *)(w + L.cellid);
     pb.rank = (int32_t *)(w + L.rank);
     pb.sxy = (int2 *)(w + L.sxy);
+    pb.sw = L.has_sw ? (uint8_t *)(w + L.sw) : nullptr;
     pb.sidx = (int32_t *)(w + L.sidx);
     pb.present = (int32_t *)(w + L.present);
     pb.dt = (int32_t *)(w + L.dt);
@@ -202,6 +212,7 @@ DenseArgs dense_args(const sas_plan *p, const WsLayout &L, char *w, const PrepBu
                      sas_candidate *cand, int64_t cand_cap, sas_vote_result *res) {
     DenseArgs a{};
     a.cat.sxy = pb.sxy;
+    a.cat.sw = pb.sw;
     a.cat.sidx = pb.sidx;
     a.cat.off = pb.count;
     a.cat.dt = pb.dt;
@@ -226,6 +237,7 @@ DenseArgs dense_args(const sas_plan *p, const WsLayout &L, char *w, const PrepBu
     a.n_min = p->n_min;
     a.count_sat = p->count_sat;
     a.mode_epochs = p->mode == SAS_MODE_EPOCHS ? 1 : 0;
+    a.weighted = is_weighted(p->mode) ? p->mode : 0;
     a.vel = p->d_vel;
     a.seg = p->d_seg;
     a.seg_v = p->d_seg_v;
@@ -235,7 +247,7 @@ DenseArgs dense_args(const sas_plan *p, const WsLayout &L, char *w, const PrepBu
     a.n_items = p->n_items;
     a.refine = (int4 *)(w + L.refine);
     a.refine_count = pb.refine_count;
-    a.refine_cap = p->dense_mode == kCountRef ? p->refine_cap : 0;
+    a.refine_cap = refines(p->dense_mode) ? p->refine_cap : 0;
     a.cand = cand;
     a.cand_cap = cand_cap;
     a.res = res;
@@ -274,8 +286,11 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     if (!d->t_q16) return fail(SAS_E_INVALID, "sas_plan_create: t_q16 is null");
     if (d->binw_q8 <= 0) return fail(SAS_E_INVALID, "sas_plan_create: binw_q8 must be > 0");
     if (d->n_min < 1) return fail(SAS_E_INVALID, "sas_plan_create: n_min must be >= 1");
-    if (d->mode != SAS_MODE_EPOCHS && d->mode != SAS_MODE_DETECTIONS)
+    if (d->mode < SAS_MODE_EPOCHS || d->mode > SAS_MODE_WEIGHTED_DETECTIONS)
         return fail(SAS_E_INVALID, "sas_plan_create: unknown mode");
+    const bool weighted = is_weighted(d->mode);
+    if (weighted && d->path == SAS_PATH_SORT)
+        return fail(SAS_E_UNSUPPORTED, "sas_plan_create: weighted counts run on the dense path only");
     if (d->count_sat != 255 && d->count_sat != 65535)
         return fail(SAS_E_INVALID, "sas_plan_create: count_sat must be 255 or 65535");
     if (d->path < SAS_PATH_AUTO || d->path > SAS_PATH_SORT)
@@ -324,7 +339,9 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     int m = 0;
     if (tu.coarse_log2 > 0) {
         m = tu.coarse_log2;
-    } else if (tu.coarse_log2 == 0 && tu.n_det_hint > 0 && n_v > 0) {
+    } else if (tu.coarse_log2 == 0 && tu.n_det_hint > 0 && n_v > 0 && !weighted) {
+        // (a weighted threshold is not a detection count: weighted plans use
+        // coarse cells only when the tuning asks for them)
         const double lam1 = (double)tu.n_det_hint * (double)d->binw_q8 * d->binw_q8 / area;
         for (int mm = 3; mm >= 1; --mm) {
             const double lam = lam1 * (double)(1 << (2 * mm));
@@ -477,7 +494,7 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     // packed 16-bit votes: a histogram row and column span at most 2^16 Q8 px
     // and a row's words fit a 16-bit weight
     auto packs = [&](int64_t tx, int64_t ty) {
-        return tu.packed >= 0 && ((tx + guard_x) << kc) <= 65536 &&
+        return !weighted && tu.packed >= 0 && ((tx + guard_x) << kc) <= 65536 &&
                ((ty + guard_y) << kc) <= 65536 && (tx + guard_x) * NV * 4 <= 65535;
     };
     int32_t TX = tu.tile_x, TY = tu.tile_y;
@@ -540,6 +557,9 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     if (HX > 65535 || HY > 65535 || hist_bytes > lds_cap || lds > lds_cap)
         return fail(SAS_E_INVALID, "sas_plan_create: tile + guard cells + stage exceed the LDS of "
                                    "a workgroup; lower tile_x, tile_y, stage_cap or vblock");
+    if (weighted && (HX << kc) >= ((int64_t)1 << 24))  // x - S < 2^24 with the weight below it
+        return fail(SAS_E_UNSUPPORTED, "sas_plan_create: a weighted tile row spans 2^24 Q8 px or "
+                                       "more; lower tile_x or vblock_x");
     {   // window and projected positions are held in 32 bits by the kernels
         int64_t vmax_abs = 0;
         for (int64_t j = 0; j < 2 * n_v; ++j)
@@ -572,7 +592,9 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     std::memcpy(p->ext, ex, sizeof(p->ext));
     p->n_v = n_v;
     p->coarse_log2 = m;
-    if (m > 0 || (d->mode == SAS_MODE_EPOCHS && d->n_epochs > 32))
+    if (weighted)
+        p->dense_mode = d->mode == SAS_MODE_WEIGHTED_DETECTIONS && m == 0 ? kWeightDet : kWeightRef;
+    else if (m > 0 || (d->mode == SAS_MODE_EPOCHS && d->n_epochs > 32))
         p->dense_mode = kCountRef;
     else
         p->dense_mode = d->mode == SAS_MODE_DETECTIONS ? kCountDet : kMask32;
@@ -800,10 +822,14 @@ sas_status sas_vote_workspace_size(const sas_plan *p, int64_t n, size_t *bytes) 
     return SAS_OK;
 }
 
-sas_status sas_vote(const sas_plan *p, const int32_t *x_q8, const int32_t *y_q8,
-                    const uint8_t *epoch, int64_t n, sas_candidate *cand_dev, int64_t cand_cap,
-                    sas_vote_result *res_dev, void *workspace, size_t ws_bytes, void *stream) {
-    if (!p) return fail(SAS_E_INVALID, "sas_vote: null plan");
+}  // extern "C"
+
+namespace {
+
+sas_status vote_impl(const sas_plan *p, const int32_t *x_q8, const int32_t *y_q8,
+                     const uint8_t *epoch, const uint8_t *weight, int64_t n,
+                     sas_candidate *cand_dev, int64_t cand_cap, sas_vote_result *res_dev,
+                     void *workspace, size_t ws_bytes, void *stream) {
     if (n < 0 || n >= ((int64_t)1 << 31)) return fail(SAS_E_INVALID, "sas_vote: n must be in [0, 2^31)");
     if (n > 0 && (!x_q8 || !y_q8 || !epoch)) return fail(SAS_E_INVALID, "sas_vote: null catalog array");
     if (!res_dev) return fail(SAS_E_INVALID, "sas_vote: null result pointer");
@@ -817,7 +843,7 @@ sas_status sas_vote(const sas_plan *p, const int32_t *x_q8, const int32_t *y_q8,
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)workspace;
     const PrepBuffers pb = prep_buffers(L, w);
-    hipError_t e = launch_prep(x_q8, y_q8, epoch, n, p->d_t, p->n_epochs, p->ncx, p->ncy,
+    hipError_t e = launch_prep(x_q8, y_q8, epoch, weight, n, p->d_t, p->n_epochs, p->ncx, p->ncy,
                                p->cell_log2, p->ext, p->n_cells, pb, res_dev, s);
     if (e != hipSuccess) return hip_fail(e, "sas_vote: preparation launch");
     if (n == 0 || p->n_v == 0) return SAS_OK;
@@ -865,6 +891,33 @@ sas_status sas_vote(const sas_plan *p, const int32_t *x_q8, const int32_t *y_q8,
     e = launch_vote_dense(p->dense_mode, p->groups, a, s, p->probe[0], p->probe[1]);
     if (e != hipSuccess) return hip_fail(e, "sas_vote: vote launch");
     return SAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sas_status sas_vote(const sas_plan *p, const int32_t *x_q8, const int32_t *y_q8,
+                    const uint8_t *epoch, int64_t n, sas_candidate *cand_dev, int64_t cand_cap,
+                    sas_vote_result *res_dev, void *workspace, size_t ws_bytes, void *stream) {
+    if (!p) return fail(SAS_E_INVALID, "sas_vote: null plan");
+    if (is_weighted(p->mode))
+        return fail(SAS_E_INVALID, "sas_vote: the plan counts weights; use sas_vote_weighted");
+    return vote_impl(p, x_q8, y_q8, epoch, nullptr, n, cand_dev, cand_cap, res_dev, workspace,
+                     ws_bytes, stream);
+}
+
+sas_status sas_vote_weighted(const sas_plan *p, const int32_t *x_q8, const int32_t *y_q8,
+                             const uint8_t *epoch, const uint8_t *weight, int64_t n,
+                             sas_candidate *cand_dev, int64_t cand_cap, sas_vote_result *res_dev,
+                             void *workspace, size_t ws_bytes, void *stream) {
+    if (!p) return fail(SAS_E_INVALID, "sas_vote_weighted: null plan");
+    if (!is_weighted(p->mode))
+        return fail(SAS_E_INVALID, "sas_vote_weighted: the plan does not count weights; use "
+                                   "sas_vote");
+    if (n > 0 && !weight) return fail(SAS_E_INVALID, "sas_vote_weighted: null weight array");
+    return vote_impl(p, x_q8, y_q8, epoch, weight, n, cand_dev, cand_cap, res_dev, workspace,
+                     ws_bytes, stream);
 }
 
 sas_status sas_peaks(const sas_candidate *cand_dev, const sas_vote_result *res_dev,
@@ -968,6 +1021,8 @@ sas_status batch_layout(const sas_batch_chip *chips, int32_t n_chips, std::vecto
         if (!p) return fail(SAS_E_INVALID, "batch: null plan");
         if (p->path != SAS_PATH_DENSE)
             return fail(SAS_E_INVALID, "batch: every chip needs a dense-path plan");
+        if (is_weighted(p->mode))
+            return fail(SAS_E_UNSUPPORTED, "batch: weighted plans are voted with sas_vote_weighted");
         if (chips[c].n < 0 || chips[c].n >= ((int64_t)1 << 31))
             return fail(SAS_E_INVALID, "batch: chip n must be in [0, 2^31)");
         offs->push_back(o);
@@ -1128,7 +1183,7 @@ sas_status sas_vote_batch(const sas_batch *b, void *stream) {
     for (const sas_batch::Chip &ch : b->chips) {
         const sas_plan *p = ch.b.plan;
         char *w = b->ws + ch.ws_off;
-        e = launch_prep(ch.b.x_q8, ch.b.y_q8, ch.b.epoch, ch.b.n, p->d_t, p->n_epochs, p->ncx,
+        e = launch_prep(ch.b.x_q8, ch.b.y_q8, ch.b.epoch, nullptr, ch.b.n, p->d_t, p->n_epochs, p->ncx,
                         p->ncy, p->cell_log2, p->ext, p->n_cells, prep_buffers(ch.L, w),
                         ch.b.res_dev, s);
         if (e != hipSuccess) return hip_fail(e, "sas_vote_batch: preparation launch");
@@ -1150,7 +1205,7 @@ sas_status sas_vote_batch(const sas_batch *b, void *stream) {
     if (b->probe[1] && (e = hipEventRecord(b->probe[1], s)) != hipSuccess)
         return hip_fail(e, "sas_vote_batch: probe");
     for (const sas_batch::Chip &ch : b->chips) {
-        if (ch.b.plan->dense_mode != kCountRef || ch.b.n == 0) continue;
+        if (!refines(ch.b.plan->dense_mode) || ch.b.n == 0) continue;
         e = launch_refine(ch.args, s);
         if (e != hipSuccess) return hip_fail(e, "sas_vote_batch: refinement launch");
     }
@@ -1284,6 +1339,9 @@ extern "C" sas_status sas_extract_clusters(const sas_plan *p, const void *worksp
         return fail(SAS_E_INVALID, "sas_extract_clusters: bad argument");
     if (p->path != SAS_PATH_DENSE)
         return fail(SAS_E_INVALID, "sas_extract_clusters: needs the window index of a dense-path plan");
+    if (is_weighted(p->mode))
+        return fail(SAS_E_UNSUPPORTED, "sas_extract_clusters: indicator counts only (EPOCHS or "
+                                       "DETECTIONS plans)");
     const WsLayout L = ws_layout(p, n);
     if (!workspace || ws_bytes < L.total)
         return fail(SAS_E_WORKSPACE, "sas_extract_clusters: workspace smaller than sas_vote_workspace_size()");

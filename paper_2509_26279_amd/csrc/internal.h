@@ -24,11 +24,14 @@ enum DenseMode : int {
     kMask32 = 0,    // EPOCHS, E <= 32, single bins: epoch bitmask per cell, emitted directly
     kCountDet = 1,  // DETECTIONS, single bins: counter per cell, emitted directly
     kCountRef = 2,  // counter of detections as a filter; lifted cells are refined
+    kWeightDet = 3, // WEIGHTED_DETECTIONS, single bins: sum of weights, emitted directly
+    kWeightRef = 4, // sum of weights as a filter (weighted modes); lifted cells are refined
 };
 
 // Catalog after preparation: detections grouped by (epoch, cell row, cell column).
 struct PreparedCatalog {
     const int2 *sxy;      // [n_valid] (x, y), Q8
+    const uint8_t *sw;    // [n_valid] weight of each detection (weighted plans), else null
     const int32_t *sidx;  // [n_valid] catalog index of each detection
     const int32_t *off;   // [n_cells + 1] CSR offsets; cell = (e * ncy + cy) * ncx + cx
     const int32_t *dt;    // [E] t[e] - t0, Q16 h; -1 for epochs without detections
@@ -49,6 +52,7 @@ struct DenseArgs {
     int32_t packed;           // 1: packed 16-bit votes (stage entries of 4 bytes)
     int32_t n_min, count_sat;
     int32_t mode_epochs;      // 1: count distinct epochs, 0: count detections
+    int32_t weighted;         // 0, or SAS_MODE_WEIGHTED_EPOCHS / _DETECTIONS
     const int32_t *vel;       // [n_v][2] velocities, Q8 px/h
     const int32_t *seg;       // [n_seg][4] vx_lo, vx_hi, vy_lo, vy_hi (Q8 px/h)
     const int32_t *seg_v;     // [n_seg][NV] v_idx of each lane (-1: unused)
@@ -71,6 +75,7 @@ struct PrepBuffers {
     int32_t *cellid;    // [n]
     int32_t *rank;      // [n]
     int2 *sxy;          // [n]
+    uint8_t *sw;        // [n] weights in sorted order (weighted plans), else null
     int32_t *sidx;      // [n] catalog index of each sorted detection
     int32_t *present;   // [E]
     int32_t *dt;        // [E]
@@ -81,7 +86,8 @@ constexpr int kScanThreads = 1024;
 constexpr int kScanPerThread = 8;
 constexpr int64_t kScanTile = (int64_t)kScanThreads * kScanPerThread;
 
-hipError_t launch_prep(const int32_t *x, const int32_t *y, const uint8_t *epoch, int64_t n,
+hipError_t launch_prep(const int32_t *x, const int32_t *y, const uint8_t *epoch,
+                       const uint8_t *weight, int64_t n,
                        const int64_t *t_dev, int32_t n_epochs, int32_t ncx, int32_t ncy,
                        int32_t cell_log2, const int32_t ext[4], int64_t n_cells,
                        const PrepBuffers &pb, sas_vote_result *res, hipStream_t stream);

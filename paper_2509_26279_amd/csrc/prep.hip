@@ -151,15 +151,18 @@ __global__ void k_prep_reftime(const int64_t *t, const int32_t *present, int32_t
 }
 
 __global__ void k_prep_scatter(const int32_t *__restrict__ x, const int32_t *__restrict__ y,
-                               int64_t n, const int32_t *__restrict__ cellid,
+                               const uint8_t *__restrict__ weight, int64_t n,
+                               const int32_t *__restrict__ cellid,
                                const int32_t *__restrict__ rank, const int32_t *__restrict__ off,
-                               int2 *__restrict__ sxy, int32_t *__restrict__ sidx) {
+                               int2 *__restrict__ sxy, uint8_t *__restrict__ sw,
+                               int32_t *__restrict__ sidx) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t c = cellid[i];
     if (c < 0) return;
     const int32_t pos = off[c] + rank[i];
     sxy[pos] = make_int2(x[i], y[i]);
+    if (weight) sw[pos] = weight[i];
     sidx[pos] = (int32_t)i;  // position in the caller's catalog (candidate features)
 }
 
@@ -180,7 +183,8 @@ hipError_t launch_scan_exclusive(int32_t *data, int64_t n, int32_t *blocksum, hi
     return hipGetLastError();
 }
 
-hipError_t launch_prep(const int32_t *x, const int32_t *y, const uint8_t *epoch, int64_t n,
+hipError_t launch_prep(const int32_t *x, const int32_t *y, const uint8_t *epoch,
+                       const uint8_t *weight, int64_t n,
                        const int64_t *t_dev, int32_t n_epochs, int32_t ncx, int32_t ncy,
                        int32_t cell_log2, const int32_t ext[4], int64_t n_cells,
                        const PrepBuffers &pb, sas_vote_result *res, hipStream_t stream) {
@@ -204,7 +208,7 @@ hipError_t launch_prep(const int32_t *x, const int32_t *y, const uint8_t *epoch,
                        n_epochs, pb.dt);
     if (n > 0) {
         hipLaunchKernelGGL(k_prep_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, stream, x, y,
-                           n, pb.cellid, pb.rank, pb.count, pb.sxy, pb.sidx);
+                           weight, n, pb.cellid, pb.rank, pb.count, pb.sxy, pb.sw, pb.sidx);
     }
     return hipGetLastError();
 }

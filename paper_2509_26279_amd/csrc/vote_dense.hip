@@ -32,6 +32,13 @@
 //               N_min distinct epochs (or detections) only if its cell holds
 //               N_min detections.  Used for EPOCHS with E > 32 and for coarse
 //               cells; k_refine resolves queued cells into exact bins.
+//   kWeightDet - weighted detections, single bins: the sum of the weights.
+//   kWeightRef - sum of the weights per cell as a filter (it bounds both
+//               weighted counts of every bin of the cell); k_refine resolves
+//               queued cells.
+// Weighted variants stage x as (x << 8) | w, so the weight rides along with
+// the position: the bin of (x << 8 | w) - (S << 8) shifted by log2(b) + 8 is
+// the bin of x - S, since w < 256 only adds a fraction of one Q8 step.
 #include <type_traits>
 
 #include "internal.h"
@@ -105,6 +112,11 @@ __device__ inline bool cell_span(int32_t lo, int32_t hi, int32_t f0, int32_t f1,
 }
 
 template <int MODE>
+constexpr bool weighted_mode() { return MODE == kWeightDet || MODE == kWeightRef; }
+template <int MODE>
+constexpr bool refined_mode() { return MODE == kCountRef || MODE == kWeightRef; }
+
+template <int MODE>
 __device__ inline uint32_t cell_count(uint32_t w) {
     return MODE == kMask32 ? (uint32_t)__popc(w) : w;
 }
@@ -149,6 +161,22 @@ struct VoteAddr32 {
         const uint32_t iy = ((uint32_t)q.y - sy) >> kc;
         return hist_addr(ix, iy, row_bytes, lb, lane_addr);
     }
+    __device__ uint32_t value(int2, uint32_t val) const { return val; }
+};
+
+// Weighted form: entries hold ((x << 8) | w, y) and sx is the lane shift
+// times 256 (modulo 2^32).  Every staged detection has 0 <= x - S < 2^24
+// (planner), so the modular difference is exact; the vote adds w.
+struct VoteAddr32W {
+    typedef int2 Entry;
+    uint32_t sx, sy, row_bytes, lane_addr;
+    int kc, lb;
+    __device__ uint32_t operator()(int2 q) const {
+        const uint32_t ix = ((uint32_t)q.x - sx) >> (kc + 8);
+        const uint32_t iy = ((uint32_t)q.y - sy) >> kc;
+        return hist_addr(ix, iy, row_bytes, lb, lane_addr);
+    }
+    __device__ uint32_t value(int2 q, uint32_t) const { return (uint32_t)q.x & 0xffu; }
 };
 
 // Packed form, for tiles whose histogram spans at most 2^16 Q8 px in x and
@@ -164,6 +192,7 @@ struct VoteAddr16 {
         const us2 d = __builtin_bit_cast(us2, q) - s;
         return __builtin_amdgcn_udot2(d >> kcv, wts, lane_addr, false);
     }
+    __device__ uint32_t value(uint32_t, uint32_t val) const { return val; }
 };
 
 // U consecutive votes of lane group g: detections st[g], st[g + G], ...,
@@ -179,7 +208,7 @@ __device__ __attribute__((always_inline)) inline void vote_block(const typename 
 #pragma unroll
     for (int u = 0; u < U; ++u) addr[u] = va(q[u]);
 #pragma unroll
-    for (int u = 0; u < U; ++u) lds_vote<MODE>(addr[u], val);
+    for (int u = 0; u < U; ++u) lds_vote<MODE>(addr[u], va.value(q[u], val));
 }
 
 // Votes of n staged detections st[0, n) of one epoch: lane (g, j) takes
@@ -268,22 +297,36 @@ __device__ __attribute__((always_inline)) inline Window window_of(const Shared &
 // One lane's part [jb, je) of a window-index run (source src): the
 // detections inside the window w, counted (write = false) or appended at
 // dst (write = true).  kCopyAhead loads at a time.
-__device__ inline void put_entry(int2 *dst, int2 q) { *dst = q; }
-__device__ inline void put_entry(uint32_t *dst, int2 q) { *dst = pack16(q.x, q.y); }
+// (The weight wt is used by the weighted form only.)
+template <bool WT>
+__device__ inline void put_entry(int2 *dst, int2 q, uint32_t wt) {
+    if (WT)
+        *dst = make_int2((int32_t)(((uint32_t)q.x << 8) | wt), q.y);
+    else
+        *dst = q;
+}
+template <bool WT>
+__device__ inline void put_entry(uint32_t *dst, int2 q, uint32_t) { *dst = pack16(q.x, q.y); }
 
-template <bool WRITE, class Entry>
+template <bool WRITE, bool WT, class Entry>
 __device__ __attribute__((always_inline)) inline int32_t run_part(
     const PreparedCatalog &c, int32_t src, int32_t jb, int32_t je, Window w, Entry *dst) {
     int32_t n = 0;
     for (int32_t jj = jb; jj < je; jj += kCopyAhead) {
         int2 q[kCopyAhead];
+        uint32_t wt[kCopyAhead];
 #pragma unroll
-        for (int u = 0; u < kCopyAhead; ++u)
-            if (jj + u < je) q[u] = c.sxy[src + jj + u];
+        for (int u = 0; u < kCopyAhead; ++u) {
+            wt[u] = 0;
+            if (jj + u < je) {
+                q[u] = c.sxy[src + jj + u];
+                if (WRITE && WT) wt[u] = c.sw[src + jj + u];
+            }
+        }
 #pragma unroll
         for (int u = 0; u < kCopyAhead; ++u) {
             if (jj + u < je && w.holds(q[u])) {
-                if (WRITE) put_entry(dst + n, q[u]);
+                if (WRITE) put_entry<WT>(dst + n, q[u], wt[u]);
                 ++n;
             }
         }
@@ -301,7 +344,10 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                           int32_t txf, int32_t ntiles, int32_t &tseq) {
     constexpr int NV = 64 / G;
     constexpr int LNV = G == 1 ? 6 : G == 2 ? 5 : 4;
-    typedef typename std::conditional<PK, VoteAddr16, VoteAddr32>::type VA;
+    constexpr bool WT = weighted_mode<MODE>();
+    static_assert(!(WT && PK), "weighted votes use the 32-bit form");
+    typedef typename std::conditional<
+        PK, VoteAddr16, typename std::conditional<WT, VoteAddr32W, VoteAddr32>::type>::type VA;
     typedef typename VA::Entry Entry;
     constexpr int ER = PK ? kEpochRegsPacked : kEpochRegs;
     uint32_t *hist = (uint32_t *)smem4;
@@ -375,7 +421,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         if (PK) {
             Sx[k] = (int32_t)pack16(sxe + (int32_t)ox_lane0, sye + (int32_t)oy_lane);
         } else {
-            Sx[k] = sxe + (int32_t)ox_lane0;
+            Sx[k] = (int32_t)((uint32_t)(sxe + (int32_t)ox_lane0) << (WT ? 8 : 0));
             Sy[PK ? 0 : k] = sye + (int32_t)oy_lane;
         }
     }
@@ -396,7 +442,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         if constexpr (PK) {
             return VoteAddr16{__builtin_bit_cast(us2, (uint32_t)sx), kcv, wts, lane_addr};
         } else {
-            return VoteAddr32{(uint32_t)sx, (uint32_t)sy, row_bytes, lane_addr, kc, LNV + 2};
+            return VA{(uint32_t)sx, (uint32_t)sy, row_bytes, lane_addr, kc, LNV + 2};
         }
     };
 
@@ -440,15 +486,23 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         uint32_t km[2];  // which of the first kCopyAhead detections are kept
         Window w[2];
         int2 q[2][kCopyAhead];
+        uint32_t wq[2];  // their weights, one byte each (weighted form)
 #pragma unroll
         for (int s2 = 0; s2 < 2; ++s2) {
-            jb[s2] = max(0, c0 - rpre[s2]);
+            // clamped to the run: a run staged by earlier chunks gives jb = je =
+            // rlen, so the loads below stay within kCopyAhead - 1 of its end
+            jb[s2] = min(rlen[s2], max(0, c0 - rpre[s2]));
             je[s2] = max(jb[s2], min(rlen[s2], c1 - rpre[s2]));
             // unconditional loads: at most kCopyAhead - 1 detections past the run,
-            // inside the slack that follows the detections in the workspace
+            // inside the slack that follows the detections (and the weights) in
+            // the workspace
             const int2 *src = c.sxy + (rsrc[s2] + jb[s2]);
 #pragma unroll
             for (int u = 0; u < kCopyAhead; ++u) q[s2][u] = src[u];
+            wq[s2] = 0;
+#pragma unroll
+            for (int u = 0; u < kCopyAhead; ++u)
+                if (WT) wq[s2] |= (uint32_t)c.sw[rsrc[s2] + jb[s2] + u] << (8 * u);
         }
 #pragma unroll
         for (int s2 = 0; s2 < 2; ++s2) {
@@ -458,8 +512,8 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
             for (int u = 0; u < kCopyAhead; ++u)
                 km[s2] |= (uint32_t)(jb[s2] + u < je[s2] && w[s2].holds(q[s2][u])) << u;
             nk[s2] = __popc(km[s2]) +
-                     run_part<false>(c, rsrc[s2], jb[s2] + kCopyAhead, je[s2], w[s2],
-                                     (Entry *)nullptr);
+                     run_part<false, WT>(c, rsrc[s2], jb[s2] + kCopyAhead, je[s2], w[s2],
+                                         (Entry *)nullptr);
         }
         int32_t t0, t1;
         int32_t start[2];  // packed position of the lane's first kept detection, per slot
@@ -470,8 +524,9 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
             int32_t at = start[s2];
 #pragma unroll
             for (int u = 0; u < kCopyAhead; ++u)
-                if ((km[s2] >> u) & 1u) put_entry(wst + at++, q[s2][u]);
-            run_part<true>(c, rsrc[s2], jb[s2] + kCopyAhead, je[s2], w[s2], wst + at);
+                if ((km[s2] >> u) & 1u)
+                    put_entry<WT>(wst + at++, q[s2][u], (wq[s2] >> (8 * u)) & 0xffu);
+            run_part<true, WT>(c, rsrc[s2], jb[s2] + kCopyAhead, je[s2], w[s2], wst + at);
         }
         // lane k < KW: the packed start of epoch k is the kept prefix at pair k << LR
         const int qk = min(lane, 31) << LR;
@@ -519,7 +574,10 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                 const int32_t d = sh.dt[e];
                 const int32_t sx = shift_q8(my_vx, d) + (int32_t)ox_lane;
                 const int32_t sy = shift_q8(my_vy, d) + (int32_t)oy_lane;
-                vote_run<MODE, G>(wst + b, n, vote_addr(PK ? (int32_t)pack16(sx, sy) : sx, sy),
+                const int32_t sxv = PK   ? (int32_t)pack16(sx, sy)
+                                    : WT ? (int32_t)((uint32_t)sx << 8)
+                                         : sx;
+                vote_run<MODE, G>(wst + b, n, vote_addr(sxv, sy),
                                   MODE == kMask32 ? (1u << e) : 1u, g);
             }
             __builtin_amdgcn_wave_barrier();  // the stage is read before it is refilled
@@ -569,7 +627,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                         bx = tx0 + cx;
                         by = ty0 + cy;
                     }
-                    if (MODE == kCountRef) {
+                    if (refined_mode<MODE>()) {
                         const int64_t idx = wave_append(ok, a.refine_count);
                         if (ok && idx < a.refine_cap)
                             a.refine[idx] = make_int4((int32_t)v, bx, by, 0);
@@ -589,7 +647,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                 const us2 step = {(unsigned short)(a.tile_x << kc), 0};
                 Sx[k] = (int32_t)__builtin_bit_cast(uint32_t, __builtin_bit_cast(us2, Sx[k]) + step);
             } else {
-                Sx[k] += a.tile_x * cellw;
+                Sx[k] = (int32_t)((uint32_t)Sx[k] + ((uint32_t)(a.tile_x * cellw) << (WT ? 8 : 0)));
             }
         }
     }
@@ -657,10 +715,17 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
 // bins, gather the detections that project into it (window index, one
 // epoch per lane), count distinct epochs (or detections) per bin, emit the
 // bins at or above N_min.  One wave per queued cell.
+// WM: kRefineCount (the indicator counts of mode_epochs), kRefineWeightDet
+// (sum of the weights) or kRefineWeightEpochs (per epoch the largest
+// weight, summed: each lane keeps its epoch's maxima in a private column of
+// LDS and adds them to the bins when the epoch is done).
 constexpr int kRefineBins = 64;  // up to 8 x 8 bins per cell
+enum RefineMode : int { kRefineCount = 0, kRefineWeightDet = 1, kRefineWeightEpochs = 2 };
 
+template <int WM>
 __global__ void __launch_bounds__(T) k_refine(DenseArgs a) {
     __shared__ uint32_t masks[NW][kRefineBins * kSlotWords];
+    __shared__ uint8_t best[WM == kRefineWeightEpochs ? NW : 1][kRefineBins][64];
     const int wave = threadIdx.x >> 6, lane = __lane_id();
     uint32_t *mk = masks[wave];
     const PreparedCatalog &c = a.cat;
@@ -677,6 +742,8 @@ __global__ void __launch_bounds__(T) k_refine(DenseArgs a) {
         const int32_t vx = a.vel[2 * (int64_t)v], vy = a.vel[2 * (int64_t)v + 1];
         const int32_t fbx0 = q.y * cw, fby0 = q.z * cw;  // first bin of the cell
         for (int i = lane; i < kRefineBins * kSlotWords; i += 64) mk[i] = 0;
+        if (WM == kRefineWeightEpochs)
+            for (int i = 0; i < kRefineBins; ++i) best[wave][i][lane] = 0;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         for (int e = lane; e < E; e += 64) {
@@ -688,6 +755,7 @@ __global__ void __launch_bounds__(T) k_refine(DenseArgs a) {
             if (!cell_span(xlo, xlo + ((int64_t)cw << k), c.x0, c.x1, c.cell_log2, &cx0, &cx1) ||
                 !cell_span(ylo, ylo + ((int64_t)cw << k), c.y0, c.y1, c.cell_log2, &cy0, &cy1))
                 continue;
+            uint64_t touched = 0;  // kRefineWeightEpochs: bins this lane's epoch reached
             for (int cy = cy0; cy <= cy1; ++cy) {
                 const int64_t base = ((int64_t)e * c.ncy + cy) * c.ncx;
                 const int32_t j1 = c.off[base + cx1 + 1];
@@ -696,19 +764,33 @@ __global__ void __launch_bounds__(T) k_refine(DenseArgs a) {
                     const int32_t bx = ((p.x - sx) >> k) - fbx0, by = ((p.y - sy) >> k) - fby0;
                     if ((uint32_t)bx < (uint32_t)cw && (uint32_t)by < (uint32_t)cw) {
                         const int bin = by * cw + bx;
-                        if (a.mode_epochs)
+                        if (WM == kRefineWeightDet) {
+                            atomicAdd(&mk[bin * kSlotWords], (uint32_t)c.sw[jj]);
+                        } else if (WM == kRefineWeightEpochs) {
+                            const uint8_t wt = c.sw[jj];
+                            if (wt > best[wave][bin][lane]) best[wave][bin][lane] = wt;
+                            touched |= (uint64_t)1 << bin;
+                        } else if (a.mode_epochs) {
                             atomicOr(&mk[bin * kSlotWords + (e >> 5)], 1u << (e & 31));
-                        else
+                        } else {
                             atomicAdd(&mk[bin * kSlotWords], 1u);
+                        }
                     }
                 }
+            }
+            // kRefineWeightEpochs: the epoch is done; add its largest weights
+            while (WM == kRefineWeightEpochs && touched) {
+                const int bin = __builtin_ctzll(touched);
+                touched &= touched - 1;
+                atomicAdd(&mk[bin * kSlotWords], (uint32_t)best[wave][bin][lane]);
+                best[wave][bin][lane] = 0;
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         __builtin_amdgcn_wave_barrier();
         uint32_t cnt = 0;
         if (lane < nb) {
-            if (a.mode_epochs) {
+            if (WM == kRefineCount && a.mode_epochs) {
                 for (int w = 0; w < kSlotWords; ++w) cnt += __popc(mk[lane * kSlotWords + w]);
             } else {
                 cnt = mk[lane * kSlotWords];
@@ -743,8 +825,7 @@ hipError_t launch_mg(const DenseArgs &a, size_t lds, hipStream_t stream, hipEven
     if (ev0 && (e = hipEventRecord(ev0, stream)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_vote_dense<MODE, G, PK>), grid, block, lds, stream, a);
     if (ev1 && (e = hipEventRecord(ev1, stream)) != hipSuccess) return e;
-    if (MODE == kCountRef)
-        hipLaunchKernelGGL(k_refine, dim3(kRefineGrid), block, 0, stream, a);
+    if (refined_mode<MODE>()) return launch_refine(a, stream);
     return hipGetLastError();
 }
 
@@ -802,6 +883,13 @@ hipError_t launch_p(int mode, int groups, const DenseArgs &a, size_t lds, hipStr
     }
 }
 
+// Weighted variants: 32-bit votes only.
+hipError_t launch_w(int mode, int groups, const DenseArgs &a, size_t lds, hipStream_t s,
+                    hipEvent_t e0, hipEvent_t e1) {
+    if (mode == kWeightDet) return launch_m<kWeightDet, false>(groups, a, lds, s, e0, e1);
+    return launch_m<kWeightRef, false>(groups, a, lds, s, e0, e1);
+}
+
 }  // namespace
 
 size_t dense_lds_bytes(int groups, int hx, int hy, int stage_cap, int packed) {
@@ -825,7 +913,13 @@ hipError_t launch_vote_dense_batch(int mode, int groups, int packed, const Dense
 }
 
 hipError_t launch_refine(const DenseArgs &a, hipStream_t stream) {
-    hipLaunchKernelGGL(k_refine, dim3(kRefineGrid), dim3(T), 0, stream, a);
+    if (a.weighted == SAS_MODE_WEIGHTED_EPOCHS)
+        hipLaunchKernelGGL(k_refine<kRefineWeightEpochs>, dim3(kRefineGrid), dim3(T), 0, stream,
+                           a);
+    else if (a.weighted == SAS_MODE_WEIGHTED_DETECTIONS)
+        hipLaunchKernelGGL(k_refine<kRefineWeightDet>, dim3(kRefineGrid), dim3(T), 0, stream, a);
+    else
+        hipLaunchKernelGGL(k_refine<kRefineCount>, dim3(kRefineGrid), dim3(T), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -833,6 +927,10 @@ hipError_t launch_vote_dense(int mode, int groups, const DenseArgs &a, hipStream
                              hipEvent_t ev0, hipEvent_t ev1) {
     if (a.n_items <= 0) return hipSuccess;
     const size_t lds = dense_lds_bytes(groups, a.hx, a.hy, a.stage_cap, a.packed);
+    if (mode == kWeightDet || mode == kWeightRef) {
+        if (a.packed) return hipErrorInvalidValue;  // excluded by the planner
+        return launch_w(mode, groups, a, lds, stream, ev0, ev1);
+    }
     return a.packed ? launch_p<true>(mode, groups, a, lds, stream, ev0, ev1)
                     : launch_p<false>(mode, groups, a, lds, stream, ev0, ev1);
 }

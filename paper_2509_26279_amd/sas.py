@@ -23,7 +23,7 @@ SAS_E_UNSUPPORTED = -5
 SAS_E_WORKSPACE = -6
 
 GRID_SHAPES = {"box": 0, "disk": 1, "annulus": 2, "sector": 3}
-MODES = {"epochs": 0, "detections": 1}
+MODES = {"epochs": 0, "detections": 1, "weighted_epochs": 2, "weighted_detections": 3}
 PATHS = {"auto": 0, "dense": 1, "sort": 2}
 ORDERS = {"canonical": 0, "by_count": 1}
 
@@ -86,7 +86,8 @@ _lib = None
 
 EXPORTS = ["sas_status_string", "sas_last_error", "sas_version", "sas_grid_spacing",
            "sas_build_grid", "sas_plan_create", "sas_plan_destroy", "sas_plan_get_info",
-           "sas_plan_set_probe", "sas_vote_workspace_size", "sas_vote", "sas_peaks",
+           "sas_plan_set_probe", "sas_vote_workspace_size", "sas_vote", "sas_vote_weighted",
+           "sas_peaks",
            "sas_threshold_n_min", "sas_batch_workspace_size", "sas_batch_create",
            "sas_batch_destroy", "sas_vote_batch", "sas_batch_set_probe", "sas_features",
            "sas_features_scratch_size", "sas_extract_scratch_size", "sas_extract_clusters",
@@ -121,6 +122,7 @@ def load():
         "sas_plan_set_probe": (I32, [P, P, P]),
         "sas_vote_workspace_size": (I32, [P, I64, P]),
         "sas_vote": (I32, [P, P, P, P, I64, P, I64, P, P, SZ, P]),
+        "sas_vote_weighted": (I32, [P, P, P, P, P, I64, P, I64, P, P, SZ, P]),
         "sas_peaks": (I32, [P, P, I64, I32, I64, P, I64, P, P]),
         "sas_threshold_n_min": (I32, [I32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                       I32, P]),
@@ -227,6 +229,8 @@ class Plan:
                         ctypes.addressof(self._tuning) if self._tuning is not None else None)
         self._p = ctypes.c_void_p()
         _check(lib.sas_plan_create(ctypes.byref(desc), ctypes.byref(self._p)))
+        self.mode = mode
+        self.weighted = MODES[mode] >= 2
         self.n_v = self._v.shape[0]
         self.n_epochs = self._t.shape[0]
 
@@ -269,15 +273,25 @@ def _stream_handle(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def vote(plan: Plan, x, y, epoch, cand, res, workspace, stream=None):
-    """Enqueue sas_vote.  x, y: int32, epoch: uint8 device tensors;
-    cand: device tensor of >= 16*cap bytes; res: 16-byte device tensor;
-    workspace: device uint8 tensor."""
+def vote(plan: Plan, x, y, epoch, cand, res, workspace, stream=None, weight=None):
+    """Enqueue sas_vote (sas_vote_weighted when `weight` is given).  x, y:
+    int32, epoch and weight: uint8 device tensors; cand: device tensor of
+    >= 16*cap bytes; res: 16-byte device tensor; workspace: device uint8
+    tensor."""
     n = int(x.numel())
     cap = cand.numel() * cand.element_size() // 16
-    _check(load().sas_vote(plan.handle, x.data_ptr(), y.data_ptr(), epoch.data_ptr(), n,
-                           cand.data_ptr(), cap, res.data_ptr(), workspace.data_ptr(),
-                           workspace.numel() * workspace.element_size(), _stream_handle(stream)))
+    ws = workspace.numel() * workspace.element_size()
+    if weight is None:
+        _check(load().sas_vote(plan.handle, x.data_ptr(), y.data_ptr(), epoch.data_ptr(), n,
+                               cand.data_ptr(), cap, res.data_ptr(), workspace.data_ptr(), ws,
+                               _stream_handle(stream)))
+    else:
+        if weight.numel() != n:
+            raise ValueError("one weight per detection")
+        _check(load().sas_vote_weighted(plan.handle, x.data_ptr(), y.data_ptr(),
+                                        epoch.data_ptr(), weight.data_ptr(), n,
+                                        cand.data_ptr(), cap, res.data_ptr(),
+                                        workspace.data_ptr(), ws, _stream_handle(stream)))
 
 
 def peaks(cand, res, order="canonical", top_k=0, stream=None):
@@ -311,17 +325,26 @@ class Search:
         self.cand = torch.empty((max(int(cand_cap), 1), 4), dtype=torch.int32, device=device)
         self.res = torch.zeros(4, dtype=torch.int32, device=device)
 
-    def upload(self, x_q8, y_q8, epoch):
+    def upload(self, x_q8, y_q8, epoch, weight=None):
+        """Device copies of a catalog (and of its weights, when given)."""
         import torch
         x = torch.as_tensor(np.ascontiguousarray(x_q8, dtype=np.int32)).to(self.device)
         y = torch.as_tensor(np.ascontiguousarray(y_q8, dtype=np.int32)).to(self.device)
         e = torch.as_tensor(np.ascontiguousarray(epoch, dtype=np.uint8)).to(self.device)
-        return x, y, e
+        if weight is None:
+            return x, y, e
+        w = np.asarray(weight)
+        if w.size and (w.min() < 0 or w.max() > 255):
+            raise ValueError("weights must lie in [0, 255]")
+        return x, y, e, torch.as_tensor(np.ascontiguousarray(w, dtype=np.uint8)).to(self.device)
 
-    def vote(self, x, y, e, stream=None):
+    def vote(self, x, y, e, w=None, stream=None):
+        """Vote a device catalog; a weighted plan takes the weights w."""
         if x.numel() > self.n_max:
             raise ValueError("catalog larger than this Search was sized for")
-        vote(self.plan, x, y, e, self.cand, self.res, self.ws, stream)
+        if self.plan.weighted != (w is not None):
+            raise ValueError("weights are given exactly when the plan counts weights")
+        vote(self.plan, x, y, e, self.cand, self.res, self.ws, stream, weight=w)
 
     def peaks(self, order="canonical", top_k=0, stream=None):
         return peaks(self.cand, self.res, order, top_k, stream)
@@ -392,9 +415,10 @@ class Search:
         recs = self.cand[:k].cpu().numpy().view(CAND_DTYPE).reshape(-1)
         return recs.copy(), feat[:k].cpu().numpy()
 
-    def run(self, x_q8, y_q8, epoch, order="canonical", top_k=0):
-        x, y, e = self.upload(x_q8, y_q8, epoch)
-        self.vote(x, y, e)
+    def run(self, x_q8, y_q8, epoch, order="canonical", top_k=0, weight=None):
+        """Upload, vote (with the weights of a weighted plan) and collect."""
+        dev = self.upload(x_q8, y_q8, epoch, weight)
+        self.vote(*dev)
         return self.peaks(order, top_k)
 
 

@@ -93,6 +93,8 @@ def _plan_error(**over):
     (dict(count_sat=1000), sas.SAS_E_INVALID),
     (dict(velocities=np.array([[1 << 29, 0]], np.int32), t_q16=np.array([0, 1 << 30])),
      sas.SAS_E_UNSUPPORTED),
+    (dict(mode="weighted_epochs", path="sort"), sas.SAS_E_UNSUPPORTED),
+    (dict(mode="weighted_detections", path="sort"), sas.SAS_E_UNSUPPORTED),
 ])
 def test_plan_argument_errors(over, status):
     assert _plan_error(**over) == status
