@@ -46,6 +46,8 @@ LDS_ATOMIC_PEAK = N_CU * LDS_BANKS * CLOCK_GHZ * 1e9  # lane atomics per second
 # (bin row * row pitch + bin column * lanes + lane: one multiply-add and one
 # shift-add).  The count increment itself is the LDS atomic.
 OPS_PER_VOTE = 6
+# A weighted vote also takes its weight out of the staged entry (one and).
+OPS_PER_WEIGHTED_VOTE = 7
 VOTE_KERNEL = "k_vote_dense"
 
 
@@ -214,6 +216,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="night workload: planner defaults")
     ap.add_argument("--extract", action="store_true",
                     help="also time the greedy cluster extraction over the step's candidates")
+    ap.add_argument("--weighted", choices=["epochs", "detections"], default=None,
+                    help="also time the weighted vote of the same catalog (likelihood weights "
+                         "of the detections' SNR, threshold N_min x the mean weight)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; --gpus %d is not supported" % args.gpus,
@@ -312,10 +317,59 @@ def main():
                 ext.append((time.perf_counter() - t1) * 1000.0)
         rec["extract"] = {"ms": float(np.mean(ext)), "n_clusters": int(len(clusters)),
                           "n_cells": n_cand}
+    if args.weighted:
+        rec["weighted"] = time_weighted(args, wl, v, count_sat)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(wl, v, args.cpu_seconds)
     plan.close()
     print(json.dumps(rec), flush=True)
+
+
+def time_weighted(args, wl, v, count_sat):
+    """The step of main() with a weighted plan (not the headline value)."""
+    import numpy as np
+    import torch
+
+    from paper_2509_26279_amd import sas, synth
+    w = synth.likelihood_weights(wl.snr)
+    n_min = int(round(wl.n_min * float(w.mean())))
+    mode = "weighted_" + args.weighted
+    plan = sas.Plan(v, wl.t_q16, wl.binw_q8, n_min, wl.extent_q8, mode=mode,
+                    count_sat=65535, tuning={"n_det_hint": wl.n,
+                                             "weight_hint": int(round(float(w.mean())))})
+    info = plan.info()
+    s = sas.Search(plan, wl.n, cand_cap=1 << 22)
+    x, y, e, wd = s.upload(wl.x_q8, wl.y_q8, wl.epoch, w)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        s.vote(x, y, e, wd)
+        s.peaks()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    for a, b in evs:
+        a.record(stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        plan.set_probe(evs[k][0], evs[k][1])
+        s.vote(x, y, e, wd)
+        out = s.peaks()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.set_probe(None, None)
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    ms_step = wall * 1000.0 / args.steps
+    votes = float(wl.n) * len(v)
+    achieved = OPS_PER_WEIGHTED_VOTE * votes / (kernel_ms * 1e-3) / 1e12
+    plan.close()
+    return {"mode": mode, "n_min": n_min, "weights": "round(2 snr^2), capped at 255",
+            "value": votes / (ms_step * 1e-3), "unit": "votes/s", "ms_per_step": ms_step,
+            "vote_kernel_ms": kernel_ms, "n_candidates": int(len(out)), "plan": info,
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": INT_PEAK_TOPS,
+                         "unit": "Tops/s", "frac": achieved / INT_PEAK_TOPS,
+                         "kernel": VOTE_KERNEL, "ops_per_vote": OPS_PER_WEIGHTED_VOTE,
+                         "ops": "int32"}}
 
 
 if __name__ == "__main__":

@@ -173,6 +173,9 @@ typedef struct {
     int32_t refine_cap;         /* capacity of the list of flagged cells (0: chosen by the plan) */
     int32_t packed;             /* 0: packed 16-bit votes wherever the tile allows them (a
                                    histogram row and column span at most 2^16 Q8 px); -1: never */
+    int32_t weight_hint;        /* weighted plans: typical weight of a detection (1..255); with
+                                   n_det_hint it lets coarse_log2 = 0 choose coarse cells.
+                                   0: weighted plans use single bins unless coarse_log2 > 0 */
 } sas_tuning;
 
 /* ------------------------------------------------------------------------
@@ -205,9 +208,10 @@ typedef struct sas_plan sas_plan;
  * Errors: SAS_E_INVALID (arguments; message in sas_last_error),
  * SAS_E_UNSUPPORTED (bin width not a power of two, |v| * Delta t too large
  * for 32-bit bins, a weighted mode on the sort path, a weighted tile row of
- * 2^24 Q8 px or more), SAS_E_NOMEM, SAS_E_DEVICE.
- * Weighted plans use single-bin histograms unless tuning.coarse_log2 > 0
- * asks for coarse cells, and never the packed 16-bit votes.
+ * 2^24 Q8 px or more, a weighted plan whose footprint plus largest shift
+ * reaches 2^23 Q8 px), SAS_E_NOMEM, SAS_E_DEVICE.
+ * Weighted plans choose coarse cells only with tuning.weight_hint (or an
+ * explicit coarse_log2 > 0), and never use the packed 16-bit votes.
  */
 sas_status sas_plan_create(const sas_plan_desc *desc, sas_plan **plan_out);
 sas_status sas_plan_destroy(sas_plan *plan);
@@ -269,8 +273,8 @@ sas_status sas_vote(const sas_plan *plan, const int32_t *x_q8, const int32_t *y_
  *   weight: device [n] uint8, the weight of each detection (0..255).
  * Every other argument, the outputs and the asynchronous, allocation-free
  * behaviour are those of sas_vote; a candidate's count is its score capped
- * at count_sat.  Weighted plans are not accepted by sas_batch_create or
- * sas_extract_clusters.
+ * at count_sat.  Weighted plans are not accepted by sas_batch_create,
+ * sas_features or sas_extract_clusters.
  * Errors (host side, nothing enqueued): SAS_E_INVALID (also for a plan in
  * an indicator mode, or a null weight array with n > 0), SAS_E_WORKSPACE.
  */

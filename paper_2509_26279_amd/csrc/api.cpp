@@ -155,8 +155,7 @@ bool is_weighted(int32_t mode) {
 bool refines(int dense_mode) { return dense_mode == kCountRef || dense_mode == kWeightRef; }
 
 struct WsLayout {
-    size_t count, blocksum, cellid, rank, sxy, sw, sidx, present, dt, refine_count, refine;
-    bool has_sw;
+    size_t count, blocksum, cellid, rank, sxy, sidx, present, dt, refine_count, refine;
     size_t keys, keys_alt, hist, hist_blocksum;  // sort path
     size_t total;
 };
@@ -173,8 +172,6 @@ WsLayout ws_layout(const sas_plan *p, int64_t n) {
     L.rank = o; o = align_up(o + sizeof(int32_t) * nn);
     // the vote kernel may read up to 3 detections past a run: 32 bytes of slack
     L.sxy = o; o = align_up(o + 2 * sizeof(int32_t) * nn + 32);
-    L.has_sw = is_weighted(p->mode);  // weights in sorted order, with the same slack
-    L.sw = o; o = align_up(o + (L.has_sw ? nn + 32 : 0));
     L.sidx = o; o = align_up(o + sizeof(int32_t) * nn);
     L.present = o; o = align_up(o + sizeof(int32_t) * kMaxEpochs);
     L.dt = o; o = align_up(o + sizeof(int32_t) * kMaxEpochs);
@@ -200,7 +197,6 @@ PrepBuffers prep_buffers(const WsLayout &L, char *w) {
     pb.cellid = (int32_t *)(w + L.cellid);
     pb.rank = (int32_t *)(w + L.rank);
     pb.sxy = (int2 *)(w + L.sxy);
-    pb.sw = L.has_sw ? (uint8_t *)(w + L.sw) : nullptr;
     pb.sidx = (int32_t *)(w + L.sidx);
     pb.present = (int32_t *)(w + L.present);
     pb.dt = (int32_t *)(w + L.dt);
@@ -212,7 +208,6 @@ DenseArgs dense_args(const sas_plan *p, const WsLayout &L, char *w, const PrepBu
                      sas_candidate *cand, int64_t cand_cap, sas_vote_result *res) {
     DenseArgs a{};
     a.cat.sxy = pb.sxy;
-    a.cat.sw = pb.sw;
     a.cat.sidx = pb.sidx;
     a.cat.off = pb.count;
     a.cat.dt = pb.dt;
@@ -326,6 +321,8 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     if (tu.coarse_log2 < -1 || tu.coarse_log2 > 3)
         return fail(SAS_E_INVALID, "sas_plan_create: coarse_log2 must be in [-1, 3]");
     if (tu.refine_cap < 0) return fail(SAS_E_INVALID, "sas_plan_create: refine_cap must be >= 0");
+    if (tu.weight_hint < 0 || tu.weight_hint > 255)
+        return fail(SAS_E_INVALID, "sas_plan_create: weight_hint must be in [0, 255]");
     if (tu.tile_x < 0 || tu.tile_y < 0 || tu.stage_cap < 0 || tu.vblock_x < 0 || tu.vblock_y < 0)
         return fail(SAS_E_INVALID, "sas_plan_create: negative tuning value");
 
@@ -339,22 +336,27 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     int m = 0;
     if (tu.coarse_log2 > 0) {
         m = tu.coarse_log2;
-    } else if (tu.coarse_log2 == 0 && tu.n_det_hint > 0 && n_v > 0 && !weighted) {
-        // (a weighted threshold is not a detection count: weighted plans use
-        // coarse cells only when the tuning asks for them)
+    } else if (tu.coarse_log2 == 0 && tu.n_det_hint > 0 && n_v > 0 &&
+               (!weighted || tu.weight_hint > 0)) {
+        // A weighted threshold is read as a detection count through the
+        // typical weight (the estimate only sizes the filter; a cell that
+        // does lift is refined exactly either way).
+        const int32_t n_eq = weighted ? std::max<int32_t>(1, (int32_t)std::floor(
+                                            (double)d->n_min / tu.weight_hint))
+                                      : d->n_min;
         const double lam1 = (double)tu.n_det_hint * (double)d->binw_q8 * d->binw_q8 / area;
         for (int mm = 3; mm >= 1; --mm) {
             const double lam = lam1 * (double)(1 << (2 * mm));
-            // P(Poisson(lam) >= n_min)
+            // P(Poisson(lam) >= n_eq)
             double term = std::exp(-lam), cdf = 0.0;
-            for (int k = 0; k < d->n_min; ++k) {
+            for (int k = 0; k < n_eq; ++k) {
                 cdf += term;
                 term *= lam / (k + 1);
             }
             const double tail = std::max(0.0, 1.0 - cdf);
             const double cells_per_v = area / ((double)d->binw_q8 * d->binw_q8 * (1 << (2 * mm)));
             const double flags = tail * cells_per_v * (double)n_v;
-            if (lam < 0.5 * d->n_min && flags < 2.0e5) {
+            if (lam < 0.5 * n_eq && flags < 2.0e5) {
                 m = mm;
                 expected_flags = flags;
                 break;
@@ -575,6 +577,9 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
         if (reach >= ((__int128)1 << 30))
             return fail(SAS_E_UNSUPPORTED, "sas_plan_create: footprint + largest shift + tile "
                                            "must stay below 2^30 Q8 px");
+        if (weighted && reach >= ((__int128)1 << 23))  // the index holds 256 x + w in 32 bits
+            return fail(SAS_E_UNSUPPORTED, "sas_plan_create: weighted plans need footprint + "
+                                           "largest shift + tile below 2^23 Q8 px (32768 px)");
     }
 
     std::unique_ptr<sas_plan> p(new sas_plan());
@@ -1253,6 +1258,8 @@ extern "C" sas_status sas_features(const sas_plan *p, const void *workspace, siz
         return fail(SAS_E_INVALID, "sas_features: bad argument");
     if (p->path != SAS_PATH_DENSE)
         return fail(SAS_E_INVALID, "sas_features: needs the window index of a dense-path plan");
+    if (is_weighted(p->mode))
+        return fail(SAS_E_UNSUPPORTED, "sas_features: indicator plans only (EPOCHS or DETECTIONS)");
     const WsLayout L = ws_layout(p, n);
     if (!workspace || ws_bytes < L.total)
         return fail(SAS_E_WORKSPACE, "sas_features: workspace smaller than sas_vote_workspace_size()");

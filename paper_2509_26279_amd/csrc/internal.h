@@ -30,8 +30,7 @@ enum DenseMode : int {
 
 // Catalog after preparation: detections grouped by (epoch, cell row, cell column).
 struct PreparedCatalog {
-    const int2 *sxy;      // [n_valid] (x, y), Q8
-    const uint8_t *sw;    // [n_valid] weight of each detection (weighted plans), else null
+    const int2 *sxy;      // [n_valid] (x, y), Q8; weighted plans: (256 x + w, y)
     const int32_t *sidx;  // [n_valid] catalog index of each detection
     const int32_t *off;   // [n_cells + 1] CSR offsets; cell = (e * ncy + cy) * ncx + cx
     const int32_t *dt;    // [E] t[e] - t0, Q16 h; -1 for epochs without detections
@@ -74,8 +73,7 @@ struct PrepBuffers {
     int32_t *blocksum;  // [scan blocks]
     int32_t *cellid;    // [n]
     int32_t *rank;      // [n]
-    int2 *sxy;          // [n]
-    uint8_t *sw;        // [n] weights in sorted order (weighted plans), else null
+    int2 *sxy;          // [n]; with weights: (256 x + w, y)
     int32_t *sidx;      // [n] catalog index of each sorted detection
     int32_t *present;   // [E]
     int32_t *dt;        // [E]

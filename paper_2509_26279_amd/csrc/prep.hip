@@ -154,15 +154,14 @@ __global__ void k_prep_scatter(const int32_t *__restrict__ x, const int32_t *__r
                                const uint8_t *__restrict__ weight, int64_t n,
                                const int32_t *__restrict__ cellid,
                                const int32_t *__restrict__ rank, const int32_t *__restrict__ off,
-                               int2 *__restrict__ sxy, uint8_t *__restrict__ sw,
-                               int32_t *__restrict__ sidx) {
+                               int2 *__restrict__ sxy, int32_t *__restrict__ sidx) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t c = cellid[i];
     if (c < 0) return;
     const int32_t pos = off[c] + rank[i];
-    sxy[pos] = make_int2(x[i], y[i]);
-    if (weight) sw[pos] = weight[i];
+    // with weights the index keeps 256 x + w (|x| < 2^23 for weighted plans)
+    sxy[pos] = make_int2(weight ? (int32_t)(((uint32_t)x[i] << 8) | weight[i]) : x[i], y[i]);
     sidx[pos] = (int32_t)i;  // position in the caller's catalog (candidate features)
 }
 
@@ -208,7 +207,7 @@ hipError_t launch_prep(const int32_t *x, const int32_t *y, const uint8_t *epoch,
                        n_epochs, pb.dt);
     if (n > 0) {
         hipLaunchKernelGGL(k_prep_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, stream, x, y,
-                           weight, n, pb.cellid, pb.rank, pb.count, pb.sxy, pb.sw, pb.sidx);
+                           weight, n, pb.cellid, pb.rank, pb.count, pb.sxy, pb.sidx);
     }
     return hipGetLastError();
 }

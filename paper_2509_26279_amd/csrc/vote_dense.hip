@@ -36,9 +36,10 @@
 //   kWeightRef - sum of the weights per cell as a filter (it bounds both
 //               weighted counts of every bin of the cell); k_refine resolves
 //               queued cells.
-// Weighted variants stage x as (x << 8) | w, so the weight rides along with
-// the position: the bin of (x << 8 | w) - (S << 8) shifted by log2(b) + 8 is
-// the bin of x - S, since w < 256 only adds a fraction of one Q8 step.
+// Weighted plans keep x as 256 x + w in the window index itself (w < 256 in
+// the low byte), so the weight rides along with the position through the
+// staging unchanged: the window's x bounds are scaled by 256 too, and the
+// bin of (256 x + w) - 256 S shifted by log2(b) + 8 is the bin of x - S.
 #include <type_traits>
 
 #include "internal.h"
@@ -164,7 +165,7 @@ struct VoteAddr32 {
     __device__ uint32_t value(int2, uint32_t val) const { return val; }
 };
 
-// Weighted form: entries hold ((x << 8) | w, y) and sx is the lane shift
+// Weighted form: entries hold (256 x + w, y) and sx is the lane shift
 // times 256 (modulo 2^32).  Every staged detection has 0 <= x - S < 2^24
 // (planner), so the modular difference is exact; the vote adds w.
 struct VoteAddr32W {
@@ -297,36 +298,22 @@ __device__ __attribute__((always_inline)) inline Window window_of(const Shared &
 // One lane's part [jb, je) of a window-index run (source src): the
 // detections inside the window w, counted (write = false) or appended at
 // dst (write = true).  kCopyAhead loads at a time.
-// (The weight wt is used by the weighted form only.)
-template <bool WT>
-__device__ inline void put_entry(int2 *dst, int2 q, uint32_t wt) {
-    if (WT)
-        *dst = make_int2((int32_t)(((uint32_t)q.x << 8) | wt), q.y);
-    else
-        *dst = q;
-}
-template <bool WT>
-__device__ inline void put_entry(uint32_t *dst, int2 q, uint32_t) { *dst = pack16(q.x, q.y); }
+__device__ inline void put_entry(int2 *dst, int2 q) { *dst = q; }
+__device__ inline void put_entry(uint32_t *dst, int2 q) { *dst = pack16(q.x, q.y); }
 
-template <bool WRITE, bool WT, class Entry>
+template <bool WRITE, class Entry>
 __device__ __attribute__((always_inline)) inline int32_t run_part(
     const PreparedCatalog &c, int32_t src, int32_t jb, int32_t je, Window w, Entry *dst) {
     int32_t n = 0;
     for (int32_t jj = jb; jj < je; jj += kCopyAhead) {
         int2 q[kCopyAhead];
-        uint32_t wt[kCopyAhead];
 #pragma unroll
-        for (int u = 0; u < kCopyAhead; ++u) {
-            wt[u] = 0;
-            if (jj + u < je) {
-                q[u] = c.sxy[src + jj + u];
-                if (WRITE && WT) wt[u] = c.sw[src + jj + u];
-            }
-        }
+        for (int u = 0; u < kCopyAhead; ++u)
+            if (jj + u < je) q[u] = c.sxy[src + jj + u];
 #pragma unroll
         for (int u = 0; u < kCopyAhead; ++u) {
             if (jj + u < je && w.holds(q[u])) {
-                if (WRITE) put_entry<WT>(dst + n, q[u], wt[u]);
+                if (WRITE) put_entry(dst + n, q[u]);
                 ++n;
             }
         }
@@ -486,7 +473,6 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         uint32_t km[2];  // which of the first kCopyAhead detections are kept
         Window w[2];
         int2 q[2][kCopyAhead];
-        uint32_t wq[2];  // their weights, one byte each (weighted form)
 #pragma unroll
         for (int s2 = 0; s2 < 2; ++s2) {
             // clamped to the run: a run staged by earlier chunks gives jb = je =
@@ -494,26 +480,25 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
             jb[s2] = min(rlen[s2], max(0, c0 - rpre[s2]));
             je[s2] = max(jb[s2], min(rlen[s2], c1 - rpre[s2]));
             // unconditional loads: at most kCopyAhead - 1 detections past the run,
-            // inside the slack that follows the detections (and the weights) in
-            // the workspace
+            // inside the slack that follows the detections in the workspace
             const int2 *src = c.sxy + (rsrc[s2] + jb[s2]);
 #pragma unroll
             for (int u = 0; u < kCopyAhead; ++u) q[s2][u] = src[u];
-            wq[s2] = 0;
-#pragma unroll
-            for (int u = 0; u < kCopyAhead; ++u)
-                if (WT) wq[s2] |= (uint32_t)c.sw[rsrc[s2] + jb[s2] + u] << (8 * u);
         }
 #pragma unroll
         for (int s2 = 0; s2 < 2; ++s2) {
             w[s2] = window_of(sh, qe[s2], oxw, oy, W, H);
+            if (WT) {  // the index holds 256 x + w
+                w[s2].x0 = (int32_t)((uint32_t)w[s2].x0 << 8);
+                w[s2].x1 = (int32_t)((uint32_t)w[s2].x1 << 8);
+            }
             km[s2] = 0;
 #pragma unroll
             for (int u = 0; u < kCopyAhead; ++u)
                 km[s2] |= (uint32_t)(jb[s2] + u < je[s2] && w[s2].holds(q[s2][u])) << u;
             nk[s2] = __popc(km[s2]) +
-                     run_part<false, WT>(c, rsrc[s2], jb[s2] + kCopyAhead, je[s2], w[s2],
-                                         (Entry *)nullptr);
+                     run_part<false>(c, rsrc[s2], jb[s2] + kCopyAhead, je[s2], w[s2],
+                                     (Entry *)nullptr);
         }
         int32_t t0, t1;
         int32_t start[2];  // packed position of the lane's first kept detection, per slot
@@ -524,9 +509,8 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
             int32_t at = start[s2];
 #pragma unroll
             for (int u = 0; u < kCopyAhead; ++u)
-                if ((km[s2] >> u) & 1u)
-                    put_entry<WT>(wst + at++, q[s2][u], (wq[s2] >> (8 * u)) & 0xffu);
-            run_part<true, WT>(c, rsrc[s2], jb[s2] + kCopyAhead, je[s2], w[s2], wst + at);
+                if ((km[s2] >> u) & 1u) put_entry(wst + at++, q[s2][u]);
+            run_part<true>(c, rsrc[s2], jb[s2] + kCopyAhead, je[s2], w[s2], wst + at);
         }
         // lane k < KW: the packed start of epoch k is the kept prefix at pair k << LR
         const int qk = min(lane, 31) << LR;
@@ -761,14 +745,16 @@ __global__ void __launch_bounds__(T) k_refine(DenseArgs a) {
                 const int32_t j1 = c.off[base + cx1 + 1];
                 for (int32_t jj = c.off[base + cx0]; jj < j1; ++jj) {
                     const int2 p = c.sxy[jj];
-                    const int32_t bx = ((p.x - sx) >> k) - fbx0, by = ((p.y - sy) >> k) - fby0;
+                    // weighted plans: the index holds 256 x + w
+                    const int32_t px = WM == kRefineCount ? p.x : p.x >> 8;
+                    const uint32_t wt = (uint32_t)p.x & 0xffu;
+                    const int32_t bx = ((px - sx) >> k) - fbx0, by = ((p.y - sy) >> k) - fby0;
                     if ((uint32_t)bx < (uint32_t)cw && (uint32_t)by < (uint32_t)cw) {
                         const int bin = by * cw + bx;
                         if (WM == kRefineWeightDet) {
-                            atomicAdd(&mk[bin * kSlotWords], (uint32_t)c.sw[jj]);
+                            atomicAdd(&mk[bin * kSlotWords], wt);
                         } else if (WM == kRefineWeightEpochs) {
-                            const uint8_t wt = c.sw[jj];
-                            if (wt > best[wave][bin][lane]) best[wave][bin][lane] = wt;
+                            if (wt > best[wave][bin][lane]) best[wave][bin][lane] = (uint8_t)wt;
                             touched |= (uint64_t)1 << bin;
                         } else if (a.mode_epochs) {
                             atomicOr(&mk[bin * kSlotWords + (e >> 5)], 1u << (e & 31));

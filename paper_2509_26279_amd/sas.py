@@ -52,7 +52,8 @@ class Tuning(ctypes.Structure):
                 ("groups", ctypes.c_int32), ("stage_cap", ctypes.c_int32),
                 ("cell_log2", ctypes.c_int32), ("sort_vblock", ctypes.c_int32),
                 ("n_det_hint", ctypes.c_int32), ("coarse_log2", ctypes.c_int32),
-                ("refine_cap", ctypes.c_int32), ("packed", ctypes.c_int32)]
+                ("refine_cap", ctypes.c_int32), ("packed", ctypes.c_int32),
+                ("weight_hint", ctypes.c_int32)]
 
 
 class BatchChip(ctypes.Structure):
@@ -222,7 +223,7 @@ class Plan:
             self._tuning = Tuning(*[int(tuning.get(k, 0)) for k in
                                     ("tile_x", "tile_y", "vblock_x", "vblock_y", "groups",
                                      "stage_cap", "cell_log2", "sort_vblock", "n_det_hint",
-                                     "coarse_log2", "refine_cap", "packed")])
+                                     "coarse_log2", "refine_cap", "packed", "weight_hint")])
         desc = PlanDesc(self._v.ctypes.data, self._v.shape[0], self._t.shape[0],
                         self._t.ctypes.data, int(binw_q8), int(n_min), MODES[mode],
                         int(count_sat), PATHS[path], (ctypes.c_int32 * 4)(*map(int, extent_q8)),

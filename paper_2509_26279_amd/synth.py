@@ -27,9 +27,16 @@ Workloads (all detections shuffled with the workload seed):
   * ``night`` - 64 chips with log-uniform detection counts 5e4..5e5 and
     epoch counts U{40..120}, each chip drawn as a ``wide``- or
     ``fast``-style search (seeded coin).
+  * ``faint`` - the fast chip's noise law with 400 faint movers whose
+    detections come from their flux: true SNR mu ~ U(1.5, 4), each epoch's
+    measured SNR ~ N(mu, 1), kept when it reaches 3; noise SNR follows the
+    standard normal tail above 3 (a detector's false peaks); speeds
+    U(20, 600) px/h, disk grid to 600 px/h, 16 px bins.
 
-Detection SNR follows 3 + |N(0,1)| for noise and movers alike, so that SNR
-alone cannot separate them.
+Detection SNR follows 3 + |N(0,1)| for noise and movers alike in every
+workload but ``faint``, so that SNR alone cannot separate them there.
+``likelihood_weights`` turns SNRs into the integer weights of a weighted
+vote (an input, like the catalog itself).
 """
 from __future__ import annotations
 
@@ -141,13 +148,14 @@ def _movers(rng, n_movers, speed_law, angle_law, presence_law, width, height,
         cat(ids, np.int64), truth
 
 
-def _assemble(rng, wl: Workload, noise_x, noise_y, noise_e, mov):
+def _assemble(rng, wl: Workload, noise_x, noise_y, noise_e, mov, snr=None):
     mx, my, me, mid, truth = mov
     x = np.concatenate([noise_x, mx])
     y = np.concatenate([noise_y, my])
     e = np.concatenate([noise_e, me])
     ids = np.concatenate([np.full(noise_x.shape[0], -1, np.int64), mid])
-    snr = 3.0 + np.abs(rng.normal(0.0, 1.0, x.shape[0]))
+    if snr is None:
+        snr = 3.0 + np.abs(rng.normal(0.0, 1.0, x.shape[0]))
     perm = rng.permutation(x.shape[0])
     wl.x_q8 = quantize_pos(x[perm])
     wl.y_q8 = quantize_pos(y[perm])
@@ -236,6 +244,47 @@ def make_fast(seed: int = 3, n_epochs: int = 60, noise_per_epoch=3000,
                   GridSpec("disk", 0.0, 5000.0))
     return _chip(rng, wl, noise_per_epoch, 500, _uniform(20.0, 5000.0),
                  _uniform(0.0, 2 * math.pi))
+
+
+def make_faint(seed: int = 500, n_epochs: int = 60, noise_per_epoch: int = 3000,
+               n_movers: int = 400, snr_lo: float = 1.5, snr_hi: float = 4.0) -> Workload:
+    """Faint movers whose detections follow from their flux (see the module
+    header).  truth["snr"] holds each mover's true SNR; n_min is left at 0
+    for the search to set."""
+    from scipy.stats import norm
+    rng = np.random.default_rng(seed)
+    wl = Workload("faint", seed, 2048, 4096, n_epochs, 2.0, 16.0, 0, "u16",
+                  GridSpec("disk", 0.0, 600.0))
+    t_h = _epoch_hours(wl.n_epochs, wl.span_h)
+    wl.t_q16 = quantize_time(T_ORIGIN_H + t_h)
+    tot = noise_per_epoch * n_epochs
+    nx = rng.uniform(0, wl.width_px, tot)
+    ny = rng.uniform(0, wl.height_px, tot)
+    ne = np.repeat(np.arange(n_epochs), noise_per_epoch)
+    # the standard normal tail above 3, by its inverse survival function
+    noise_snr = norm.isf(rng.uniform(0.0, 1.0, tot) * norm.sf(3.0))
+    drawn = []  # per mover: true SNR and the measured SNR of every epoch
+
+    def presence(r, n_ep):
+        mu = r.uniform(snr_lo, snr_hi)
+        s = mu + r.normal(0.0, 1.0, n_ep)
+        drawn.append((mu, s))
+        return s >= 3.0
+    mov = _movers(rng, n_movers, _uniform(20.0, 600.0), _uniform(0.0, 2 * math.pi), presence,
+                  wl.width_px, wl.height_px, t_h, 0.5)
+    mids, mes = mov[3], mov[2]
+    mover_snr = np.array([drawn[m][1][e] for m, e in zip(mids, mes)], dtype=np.float64)
+    wl = _assemble(rng, wl, nx, ny, ne, mov, snr=np.concatenate([noise_snr, mover_snr]))
+    wl.truth["snr"] = np.array([d[0] for d in drawn], dtype=np.float64)
+    return wl
+
+
+def likelihood_weights(snr, scale: float = 4.0) -> np.ndarray:
+    """Integer weights for a weighted vote: the log-likelihood ratio of a
+    detection of measured SNR s against noise, maximised over the source's
+    flux (s^2 / 2), times `scale`, rounded and capped at 255."""
+    s = np.asarray(snr, dtype=np.float64)
+    return np.minimum(np.rint(scale * s * s / 2.0), 255).astype(np.uint8)
 
 
 def night_chip_params(seed: int = 4, n_chips: int = 64):

@@ -98,20 +98,26 @@ def test_adversarial(gpu, seed, mode):
 
 @pytest.mark.parametrize("maker,k", [(synth.make_wide, 200), (synth.make_fast, 160)])
 @pytest.mark.parametrize("mode", MODES)
-def test_full_catalog_velocity_subset(gpu, maker, k, mode):
+@pytest.mark.parametrize("hint", [False, True])
+def test_full_catalog_velocity_subset(gpu, maker, k, mode, hint):
     """The workload's whole catalog, weights from its detections' SNR, against
-    a seeded subset of its grid, at two thresholds."""
+    a seeded subset of its grid, at two thresholds; single bins, or the
+    coarse cells the weight hint lets the planner choose."""
     wl = maker()
     v = _grid(wl)
     w = _snr_weights(wl.snr)
     idx = np.sort(np.random.default_rng(41).choice(len(v), size=min(k, len(v)), replace=False))
     mean_w = float(w.mean())
+    tun = dict(n_det_hint=wl.n)
+    if hint:
+        tun["weight_hint"] = int(round(mean_w))
     for n_min in (int(wl.n_min * mean_w), int(0.4 * wl.n_min * mean_w)):
-        _say(f"weighted {wl.name} |V|={len(idx)} mode={mode} n_min={n_min}")
+        _say(f"weighted {wl.name} |V|={len(idx)} mode={mode} n_min={n_min} tuning={tun}")
         o = oracle.vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v[idx], wl.binw_q8, n_min, mode,
                         weight=w)
-        g, _ = gpu_vote(wl.x_q8, wl.y_q8, wl.epoch, w, wl.t_q16, v[idx], wl.binw_q8, n_min,
-                        mode, extent=wl.extent_q8, tuning=dict(n_det_hint=wl.n), cap=1 << 22)
+        g, info = gpu_vote(wl.x_q8, wl.y_q8, wl.epoch, w, wl.t_q16, v[idx], wl.binw_q8, n_min,
+                           mode, extent=wl.extent_q8, tuning=tun, cap=1 << 22)
+        _say(f"  coarse_log2={info['coarse_log2']} mode_variant={info['mode_variant']}")
         assert len(o) > 0
         assert_same(g, o)
 
@@ -124,9 +130,11 @@ def test_wide_full_grid_sampled_outputs(gpu):
     w = _snr_weights(wl.snr)
     n_min = int(wl.n_min * float(w.mean()))
     _say(f"weighted wide full grid |V|={len(v)} n_min={n_min}")
-    g, _ = gpu_vote(wl.x_q8, wl.y_q8, wl.epoch, w, wl.t_q16, v, wl.binw_q8, n_min,
-                    "weighted_epochs", extent=wl.extent_q8, tuning=dict(n_det_hint=wl.n),
-                    cap=1 << 22)
+    g, info = gpu_vote(wl.x_q8, wl.y_q8, wl.epoch, w, wl.t_q16, v, wl.binw_q8, n_min,
+                       "weighted_epochs", extent=wl.extent_q8,
+                       tuning=dict(n_det_hint=wl.n, weight_hint=int(round(float(w.mean())))),
+                       cap=1 << 22)
+    assert info["coarse_log2"] > 0  # the sparse wide catalog takes coarse cells
     assert len(g) > 0 and np.all(g["count"] >= n_min)
     idx = np.sort(np.random.default_rng(23).choice(len(v), size=64, replace=False))
     idx = np.union1d(idx, np.unique(g["v_idx"])[:: max(1, len(np.unique(g["v_idx"])) // 32)])
@@ -188,6 +196,9 @@ def test_entry_points_check_the_mode(gpu):
         s.peaks()
         with pytest.raises(sas.SasError) as ei:  # so does the greedy extraction
             s.extract(50)
+        assert ei.value.status == sas.SAS_E_UNSUPPORTED
+        with pytest.raises(sas.SasError) as ei:  # and the vetting features
+            s.features(50)
         assert ei.value.status == sas.SAS_E_UNSUPPORTED
         torch.cuda.synchronize()
     finally:
