@@ -125,24 +125,39 @@ def compare(val_seeds=VAL_SEEDS, test_seeds=TEST_SEEDS, scale: float = 4.0, n_mo
             break
     if w_star is None:
         w_star = int(cand_w.max()) + 1
+    # the other reading: every unmatched candidate of the full catalogs a false positive
+    unm_plain = sum(_selection(chips[s]["ci"], chips[s]["mi"], chips[s]["n_min"], n_movers)[1]
+                    for s in val_seeds)
+    cand_u = np.unique(np.concatenate([chips[s]["cw"] for s in val_seeds]))
+    w_unm = int(cand_u.max()) + 1 if len(cand_u) else w_lo
+    for thr in cand_u:
+        if sum(_selection(chips[s]["cw"], chips[s]["mw"], thr, n_movers)[1]
+               for s in val_seeds) <= unm_plain:
+            w_unm = int(thr)
+            break
     res = {"val_noise_plain": noise_plain, "w_star": w_star, "scale": scale,
+           "val_unmatched_plain": unm_plain, "w_unmatched": w_unm,
            "w_lo": int(min(chips[s]["cw"].min() if len(chips[s]["cw"]) else 0 for s in chips))}
-    snr_all, f_i, f_w = [], [], []
-    fp_i = fp_w = nz_i = nz_w = 0
+    snr_all, f_i, f_w, f_u = [], [], [], []
+    fp_i = fp_w = fp_u = nz_i = nz_w = 0
     for s in test_seeds:
         c = chips[s]
         fi, pi = _selection(c["ci"], c["mi"], c["n_min"], n_movers)
         fw, pw = _selection(c["cw"], c["mw"], w_star, n_movers)
+        fu, pu = _selection(c["cw"], c["mw"], w_unm, n_movers)
         snr_all.append(c["wl"].truth["snr"])
         f_i.append(fi)
         f_w.append(fw)
+        f_u.append(fu)
         fp_i += pi
         fp_w += pw
+        fp_u += pu
         nz_i += int((c["ni"] >= c["n_min"]).sum())
         nz_w += int((c["nw"] >= w_star).sum())
-    snr_all, f_i, f_w = map(np.concatenate, (snr_all, f_i, f_w))
+    snr_all, f_i, f_w, f_u = map(np.concatenate, (snr_all, f_i, f_w, f_u))
     s50_i, frac_i = snr50(snr_all, f_i)
     s50_w, frac_w = snr50(snr_all, f_w)
+    s50_u, _ = snr50(snr_all, f_u)
     res.update({"test_movers": int(len(snr_all)),
                 "indicator": {"recall": float(f_i.mean()), "noise_candidates": nz_i,
                               "unmatched": fp_i, "snr50": s50_i,
@@ -150,6 +165,8 @@ def compare(val_seeds=VAL_SEEDS, test_seeds=TEST_SEEDS, scale: float = 4.0, n_mo
                 "weighted": {"recall": float(f_w.mean()), "noise_candidates": nz_w,
                              "unmatched": fp_w, "snr50": s50_w,
                              "recall_by_snr": frac_w.tolist()},
+                "weighted_matched_unmatched": {"recall": float(f_u.mean()), "unmatched": fp_u,
+                                               "snr50": s50_u},
                 "snr_bins": SNR_BINS.tolist(),
                 "n_min": {int(s): int(chips[s]["n_min"]) for s in chips}})
     return res
