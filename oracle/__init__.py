@@ -18,6 +18,8 @@ Contents
     number of false candidates);
   * ``features.py``  - candidate features and labels for learned vetting;
   * ``extract.py``   - the greedy cluster extraction of Step 3 (Sec. 2.1);
+  * ``refine.py``    - Refine (FAST-MCD robust regression), Gather and their
+    iteration, Steps 4-6 (Sec. 2.1, with the regression of Sec. 2);
   * ``mlp_ref.py``   - FP64 reference of the candidate-vetting MLP.
 """
 from __future__ import annotations

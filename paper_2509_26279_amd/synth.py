@@ -287,6 +287,13 @@ def likelihood_weights(snr, scale: float = 4.0) -> np.ndarray:
     return np.minimum(np.rint(scale * s * s / 2.0), 255).astype(np.uint8)
 
 
+def mcd_starts(seed: int = 7, n_starts: int = 500) -> np.ndarray:
+    """The random draws of FAST-MCD's starting subsets, as an input: 4
+    uint32 per start (a start takes the points value mod n)."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, 1 << 32, (n_starts, 4), dtype=np.uint64).astype(np.uint32)
+
+
 def night_chip_params(seed: int = 4, n_chips: int = 64):
     """Per-chip draws of the batched night: style, detection count, epochs."""
     out = []
