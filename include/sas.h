@@ -472,6 +472,74 @@ sas_status sas_peaks(const sas_candidate *cand_dev, const sas_vote_result *res_d
                      int64_t cand_cap, int32_t order, int64_t top_k, sas_candidate *out_host,
                      int64_t out_cap, int64_t *n_out, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Refine, Gather, iterate (Steps 4-6 of Sec. 2.1).
+ *
+ * Step 4 fits each cluster with the multivariate regression of Sec. 2
+ * (independent variable t, responses x and y): slope B (the velocity),
+ * intercept c (the position at the reference epoch t0) and error
+ * covariance Sigma_eps, all from the mean and covariance of the Minimum
+ * Covariance Determinant subset of the cluster's points (t, x, y) instead
+ * of the sample ones, which tolerates up to half outliers.  FAST-MCD
+ * (Rousseeuw and Van Driessen 1999) approximates that subset: h = (n + 4) / 2
+ * points; from n_starts random 4-point starts two C-steps each, the 10
+ * lowest determinants iterated until the subset stops changing (at most 30
+ * C-steps), the lowest determinant wins.  Step 5 gathers the catalog
+ * detections within the radius of the line c + B t (Euclidean, <=) at their
+ * epoch's time; Step 6 refits on the gathered set and repeats until it no
+ * longer changes (at most 10 rounds).
+ * ---------------------------------------------------------------------- */
+#define SAS_REFINE_MAX_POINTS 512   /* points of one set (cluster or gathered) */
+#define SAS_REFINE_MAX_STARTS 1024
+
+#define SAS_REFINE_CONVERGED 0   /* the gathered set equals the set fitted */
+#define SAS_REFINE_MAX_ROUNDS 1  /* still changing after 10 rounds */
+#define SAS_REFINE_TOO_SMALL 2   /* a set of fewer than 5 points */
+#define SAS_REFINE_NO_START 3    /* every start repeated a point or was degenerate */
+#define SAS_REFINE_TOO_LARGE 4   /* a set of more than SAS_REFINE_MAX_POINTS points */
+#define SAS_REFINE_BAD_INPUT 5   /* the cluster's CSR range or a member index is invalid */
+
+typedef struct {
+    double vx, vy;          /* B: px/h */
+    double x0, y0;          /* c: px at t0 (t0 = the earliest epoch holding a detection) */
+    double sxx, sxy, syy;   /* Sigma_eps, px^2 */
+    int32_t n_points;       /* h of the last fit */
+    int32_t n_gathered;     /* detections gathered by the last fit */
+    int32_t rounds;         /* fits made (0: none) */
+    int32_t status;         /* SAS_REFINE_* */
+} sas_refined;              /* 72 bytes */
+
+/*
+ * sas_refine_clusters: enqueue Steps 4-6 for n_clusters clusters of the
+ * catalog last voted with this dense-path plan and workspace (its window
+ * index serves the gather).
+ *   x_q8, y_q8, epoch: device [n], the catalog that was voted.
+ *   first_dev:   device [n_clusters + 1], CSR offsets into members_dev;
+ *   members_dev: device [n_members] catalog indices of each cluster's
+ *                detections (any order; for example from the owners that
+ *                sas_extract_clusters writes).
+ *   starts_dev:  device [n_starts][4] uint32, the random draws of the
+ *                FAST-MCD starts (a start takes the points value mod n);
+ *                1 <= n_starts <= SAS_REFINE_MAX_STARTS.
+ *   radius_q8:   gather radius in Q8 px (0: the plan's bin width Delta x).
+ *   out_dev:     device [n_clusters] results.
+ *   gathered_dev: device [n_clusters][gather_cap] or NULL: the final
+ *                gathered set, catalog indices ascending (the first
+ *                min(n_gathered, gather_cap) of them).
+ *   subset_dev:  device [n_clusters][SAS_REFINE_MAX_POINTS] or NULL: the
+ *                MCD subset of the last fit, ascending (n_points of them).
+ * Asynchronous, allocates nothing.  An invalid cluster gets status
+ * SAS_REFINE_BAD_INPUT; the call itself checks the arguments on the host.
+ * Errors: SAS_E_INVALID (arguments, a plan not on the dense path).
+ */
+sas_status sas_refine_clusters(const sas_plan *plan, const void *workspace, size_t ws_bytes,
+                               const int32_t *x_q8, const int32_t *y_q8, const uint8_t *epoch,
+                               int64_t n, const int32_t *first_dev, const int32_t *members_dev,
+                               int64_t n_members, int64_t n_clusters, const uint32_t *starts_dev,
+                               int32_t n_starts, int32_t radius_q8, sas_refined *out_dev,
+                               int32_t *gathered_dev, int32_t gather_cap, int32_t *subset_dev,
+                               void *stream);
+
 #ifdef __cplusplus
 }
 #endif

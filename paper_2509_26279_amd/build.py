@@ -26,6 +26,9 @@ DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang",
 PER_FILE = {
     # region tests of the grid builder are plain IEEE comparisons
     "grid.cpp": ["-ffp-contract=off"],
+    # FP64 regression and gather: each operation rounded as written, as the
+    # reference definition computes it
+    "refine.hip": ["-ffp-contract=off"],
 }
 
 

@@ -1389,3 +1389,49 @@ extern "C" sas_status sas_extract_clusters(const sas_plan *p, const void *worksp
     if (e != hipSuccess) return hip_fail(e, "sas_extract_clusters: launch");
     return SAS_OK;
 }
+
+extern "C" sas_status sas_refine_clusters(const sas_plan *p, const void *workspace,
+                                          size_t ws_bytes, const int32_t *x_q8,
+                                          const int32_t *y_q8, const uint8_t *epoch, int64_t n,
+                                          const int32_t *first_dev, const int32_t *members_dev,
+                                          int64_t n_members, int64_t n_clusters,
+                                          const uint32_t *starts_dev, int32_t n_starts,
+                                          int32_t radius_q8, sas_refined *out_dev,
+                                          int32_t *gathered_dev, int32_t gather_cap,
+                                          int32_t *subset_dev, void *stream) {
+    if (!p || n < 0 || n >= ((int64_t)1 << 31) || n_members < 0 || n_clusters < 0 ||
+        n_clusters >= ((int64_t)1 << 31) || n_starts < 1 || n_starts > SAS_REFINE_MAX_STARTS ||
+        radius_q8 < 0 || gather_cap < 0 || (n > 0 && (!x_q8 || !y_q8 || !epoch)) ||
+        (n_clusters > 0 && (!first_dev || !out_dev || !starts_dev)) ||
+        (n_members > 0 && !members_dev) || (gathered_dev && gather_cap == 0))
+        return fail(SAS_E_INVALID, "sas_refine_clusters: bad argument");
+    if (p->path != SAS_PATH_DENSE)
+        return fail(SAS_E_INVALID, "sas_refine_clusters: needs the window index of a dense-path plan");
+    const WsLayout L = ws_layout(p, n);
+    if (!workspace || ws_bytes < L.total)
+        return fail(SAS_E_WORKSPACE, "sas_refine_clusters: workspace smaller than sas_vote_workspace_size()");
+    char *w = (char *)workspace;
+    const PrepBuffers pb = prep_buffers(L, w);
+    RefineArgs a{};
+    a.cat = dense_args(p, L, w, pb, nullptr, 0, nullptr).cat;
+    a.weighted = is_weighted(p->mode) ? 1 : 0;
+    a.x = x_q8;
+    a.y = y_q8;
+    a.epoch = epoch;
+    a.n = n;
+    a.first = first_dev;
+    a.members = members_dev;
+    a.n_members = n_members;
+    a.n_clusters = n_clusters;
+    a.starts = starts_dev;
+    a.n_starts = n_starts;
+    a.radius_px = (double)(radius_q8 ? radius_q8 : p->binw) / 256.0;
+    a.out = out_dev;
+    a.gathered = gathered_dev;
+    a.gather_cap = gather_cap;
+    a.subset = subset_dev;
+    a.subset_clusters = subset_dev ? n_clusters : 0;
+    hipError_t e = launch_refine_clusters(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "sas_refine_clusters: launch");
+    return SAS_OK;
+}

@@ -234,4 +234,26 @@ hipError_t launch_refine(const DenseArgs &a, hipStream_t stream);
 size_t dense_lds_bytes(int groups, int hx, int hy, int stage_cap, int packed);
 size_t dense_static_lds_bytes();
 
+// Refine / Gather / iterate (Steps 4-6) per cluster.
+constexpr int kMaxRefineStarts = SAS_REFINE_MAX_STARTS;
+struct RefineArgs {
+    PreparedCatalog cat;       // window index of the voted catalog
+    int32_t weighted;          // the index holds 256 x + w
+    const int32_t *x, *y;      // [n] caller's catalog, Q8
+    const uint8_t *epoch;      // [n]
+    int64_t n;
+    const int32_t *first;      // [n_clusters + 1] CSR over members
+    const int32_t *members;    // [n_members] catalog indices
+    int64_t n_members, n_clusters;
+    const uint32_t *starts;    // [n_starts][4] random draws of the FAST-MCD starts
+    int32_t n_starts;
+    double radius_px;          // gather radius
+    sas_refined *out;          // [n_clusters]
+    int32_t *gathered;         // [n_clusters][gather_cap] or null
+    int32_t gather_cap;
+    int32_t *subset;           // [subset_clusters][SAS_REFINE_MAX_POINTS] or null
+    int64_t subset_clusters;
+};
+hipError_t launch_refine_clusters(const RefineArgs &a, hipStream_t stream);
+
 }  // namespace sas

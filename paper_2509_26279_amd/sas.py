@@ -28,6 +28,13 @@ PATHS = {"auto": 0, "dense": 1, "sort": 2}
 ORDERS = {"canonical": 0, "by_count": 1}
 
 N_FEATURES = 32
+REFINE_MAX_POINTS = 512
+REFINE_STATUS = {0: "converged", 1: "max_rounds", 2: "too_small", 3: "no_start", 4: "too_large",
+                 5: "bad_input"}
+REFINED_DTYPE = np.dtype([("vx", "<f8"), ("vy", "<f8"), ("x0", "<f8"), ("y0", "<f8"),
+                          ("sxx", "<f8"), ("sxy", "<f8"), ("syy", "<f8"),
+                          ("n_points", "<i4"), ("n_gathered", "<i4"), ("rounds", "<i4"),
+                          ("status", "<i4")])
 CAND_DTYPE = np.dtype([("v_idx", "<u4"), ("bx", "<i4"), ("by", "<i4"),
                        ("count", "<u2"), ("flags", "<u2")])
 
@@ -92,6 +99,7 @@ EXPORTS = ["sas_status_string", "sas_last_error", "sas_version", "sas_grid_spaci
            "sas_threshold_n_min", "sas_batch_workspace_size", "sas_batch_create",
            "sas_batch_destroy", "sas_vote_batch", "sas_batch_set_probe", "sas_features",
            "sas_features_scratch_size", "sas_extract_scratch_size", "sas_extract_clusters",
+           "sas_refine_clusters",
            "sas_mlp_create", "sas_mlp_destroy", "sas_mlp_set_norm", "sas_mlp_get_params",
            "sas_mlp_set_params", "sas_mlp_forward", "sas_mlp_grad", "sas_mlp_train_step"]
 
@@ -124,6 +132,8 @@ def load():
         "sas_vote_workspace_size": (I32, [P, I64, P]),
         "sas_vote": (I32, [P, P, P, P, I64, P, I64, P, P, SZ, P]),
         "sas_vote_weighted": (I32, [P, P, P, P, P, I64, P, I64, P, P, SZ, P]),
+        "sas_refine_clusters": (I32, [P, P, SZ, P, P, P, I64, P, P, I64, I64, P, I32, I32, P, P,
+                                      I32, P, P]),
         "sas_peaks": (I32, [P, P, I64, I32, I64, P, I64, P, P]),
         "sas_threshold_n_min": (I32, [I32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                       I32, P]),
@@ -415,6 +425,46 @@ class Search:
                                    _stream_handle(stream)))
         recs = self.cand[:k].cpu().numpy().view(CAND_DTYPE).reshape(-1)
         return recs.copy(), feat[:k].cpu().numpy()
+
+    def refine(self, x, y, e, clusters, starts, radius_q8: int = 0, gather_cap: int = 512,
+               subsets: bool = True, stream=None):
+        """Steps 4-6 for clusters of the catalog last voted (device tensors
+        x, y, e): clusters is a list of catalog-index arrays, starts the
+        uint32 [k, 4] draws of the FAST-MCD starts.  Returns (records as
+        REFINED_DTYPE, gathered sets, MCD subsets) with the sets as sorted
+        catalog-index arrays."""
+        import torch
+        lens = np.array([len(c) for c in clusters], dtype=np.int64)
+        first = np.zeros(len(clusters) + 1, dtype=np.int32)
+        first[1:] = np.cumsum(lens)
+        members = (np.concatenate([np.asarray(c, dtype=np.int32) for c in clusters])
+                   if len(clusters) and lens.sum() else np.zeros(1, np.int32))
+        st = np.ascontiguousarray(starts, dtype=np.uint32).reshape(-1, 4)
+        dev = self.cand.device
+        first_d = torch.as_tensor(first).to(dev)
+        mem_d = torch.as_tensor(members).to(dev)
+        st_d = torch.as_tensor(st.view(np.int32)).to(dev)
+        k = max(len(clusters), 1)
+        out = torch.zeros((k, REFINED_DTYPE.itemsize), dtype=torch.uint8, device=dev)
+        gath = torch.zeros((k, gather_cap), dtype=torch.int32, device=dev)
+        sub = (torch.zeros((k, REFINE_MAX_POINTS), dtype=torch.int32, device=dev)
+               if subsets else None)
+        _check(load().sas_refine_clusters(
+            self.plan.handle, self.ws.data_ptr(), self.ws.numel() * self.ws.element_size(),
+            x.data_ptr(), y.data_ptr(), e.data_ptr(), int(x.numel()), first_d.data_ptr(),
+            mem_d.data_ptr(), int(lens.sum()), len(clusters), st_d.data_ptr(), st.shape[0],
+            int(radius_q8), out.data_ptr(), gath.data_ptr(), int(gather_cap),
+            sub.data_ptr() if sub is not None else None, _stream_handle(stream)))
+        recs = out.cpu().numpy().view(REFINED_DTYPE).reshape(-1)[:len(clusters)].copy()
+        g = gath.cpu().numpy()
+        gathered = [g[i, :min(int(r["n_gathered"]), gather_cap)].copy() if r["rounds"] > 0
+                    else np.zeros(0, np.int32) for i, r in enumerate(recs)]
+        subs = None
+        if sub is not None:
+            sm = sub.cpu().numpy()
+            subs = [sm[i, :int(r["n_points"])].copy() if r["rounds"] > 0
+                    else np.zeros(0, np.int32) for i, r in enumerate(recs)]
+        return recs, gathered, subs
 
     def run(self, x_q8, y_q8, epoch, order="canonical", top_k=0, weight=None):
         """Upload, vote (with the weights of a weighted plan) and collect."""
