@@ -216,6 +216,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="night workload: planner defaults")
     ap.add_argument("--extract", action="store_true",
                     help="also time the greedy cluster extraction over the step's candidates")
+    ap.add_argument("--refine", action="store_true",
+                    help="also time Steps 4-6 (FAST-MCD refine, gather, iterate) over the "
+                         "clusters of the greedy extraction (implies --extract)")
     ap.add_argument("--weighted", choices=["epochs", "detections"], default=None,
                     help="also time the weighted vote of the same catalog (likelihood weights "
                          "of the detections' SNR, threshold N_min x the mean weight)")
@@ -303,7 +306,7 @@ def main():
                      "ops": "int16x2 packed" if info.get("packed") else "int32",
                      "lds_atomic_frac": votes / (kernel_ms * 1e-3) / LDS_ATOMIC_PEAK},
     }
-    if args.extract:
+    if args.extract or args.refine:
         # Step 3's greedy extraction over the candidates of the last vote
         # (not part of the step above): wall time of the whole call
         ext = []
@@ -317,6 +320,26 @@ def main():
                 ext.append((time.perf_counter() - t1) * 1000.0)
         rec["extract"] = {"ms": float(np.mean(ext)), "n_clusters": int(len(clusters)),
                           "n_cells": n_cand}
+        if args.refine:
+            from paper_2509_26279_amd import synth
+            _, owner = s.extract(wl.n)
+            order = np.argsort(owner, kind="stable")
+            own = owner[order]
+            groups = [order[own == k] for k in range(len(clusters))]
+            starts = synth.mcd_starts(7, 500)
+            ref = []
+            for k in range(args.warmup + args.steps):
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                recs, _, _ = s.refine(x, y, e, groups, starts, subsets=False)
+                if k >= args.warmup:
+                    ref.append((time.perf_counter() - t1) * 1000.0)
+            st = {sas.REFINE_STATUS[int(c)]: int((recs["status"] == c).sum())
+                  for c in np.unique(recs["status"])}
+            rec["refine"] = {"ms": float(np.mean(ref)), "n_clusters": len(groups),
+                             "points": int(sum(len(g) for g in groups)),
+                             "rounds_mean": float(recs["rounds"].mean()) if len(recs) else 0.0,
+                             "status": st, "starts": 500}
     if args.weighted:
         rec["weighted"] = time_weighted(args, wl, v, count_sat)
     if not args.no_cpu_baseline:

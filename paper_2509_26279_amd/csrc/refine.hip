@@ -30,11 +30,11 @@
 namespace sas {
 namespace {
 
-constexpr int RT = 256;             // threads per cluster workgroup
+constexpr int RT = 512;             // threads per cluster workgroup
 constexpr int RW = RT / 64;
 constexpr int kMaxPoints = 512;     // points of one set held in LDS
 constexpr int kMaskWords = kMaxPoints / 32;
-constexpr int kPtsPerLane = kMaxPoints / 64;
+constexpr int kPtsPerLane = kMaxPoints / 64;  // the wave's points per lane, at most
 constexpr int kBest = 10;
 constexpr int kMaxCsteps = 30;
 constexpr int kMaxRounds = 10;
@@ -94,12 +94,13 @@ struct Shared {
 
 // Mean and covariance of the points whose flag is set (lane-held flags of
 // points lane + 64 k), by the wave; all lanes get the result.
+template <int KPL>
 __device__ Cov wave_moments(const Shared &sh, int n, const bool *in, int cnt) {
     const int lane = __lane_id();
     Cov c;
     double a0 = 0, a1 = 0, a2 = 0;
 #pragma unroll
-    for (int k = 0; k < kPtsPerLane; ++k) {
+    for (int k = 0; k < KPL; ++k) {
         const int i = lane + 64 * k;
         if (i < n && in[k]) {
             a0 += sh.zt[i];
@@ -112,7 +113,7 @@ __device__ Cov wave_moments(const Shared &sh, int n, const bool *in, int cnt) {
     c.mu[2] = wave_sum(a2) / cnt;
     double s[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
-    for (int k = 0; k < kPtsPerLane; ++k) {
+    for (int k = 0; k < KPL; ++k) {
         const int i = lane + 64 * k;
         if (i < n && in[k]) {
             const double dt = sh.zt[i] - c.mu[0], dx = sh.zx[i] - c.mu[1], dy = sh.zy[i] - c.mu[2];
@@ -132,13 +133,14 @@ __device__ Cov wave_moments(const Shared &sh, int n, const bool *in, int cnt) {
 // One C-step by the wave: distances from (mu, S^-1) into its d2 row, then
 // in[k] = point lane + 64 k is among the h closest (ties to the lower
 // position).  Returns whether the subset changed.
+template <int KPL>
 __device__ bool c_step(Shared &sh, int n, int h, const Cov &c, bool *in) {
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
     double v[6];
     inv3(c.s, v);
     double *d2 = sh.d2[wave];
 #pragma unroll
-    for (int k = 0; k < kPtsPerLane; ++k) {
+    for (int k = 0; k < KPL; ++k) {
         const int i = lane + 64 * k;
         if (i < n) {
             const double a = sh.zt[i] - c.mu[0], b = sh.zx[i] - c.mu[1], e = sh.zy[i] - c.mu[2];
@@ -149,24 +151,24 @@ __device__ bool c_step(Shared &sh, int n, int h, const Cov &c, bool *in) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    int rank[kPtsPerLane];
-    double mine[kPtsPerLane];
+    int rank[KPL];
+    double mine[KPL];
 #pragma unroll
-    for (int k = 0; k < kPtsPerLane; ++k) {
+    for (int k = 0; k < KPL; ++k) {
         rank[k] = 0;
         mine[k] = (lane + 64 * k < n) ? d2[lane + 64 * k] : 0.0;
     }
     for (int j = 0; j < n; ++j) {
         const double dj = d2[j];
 #pragma unroll
-        for (int k = 0; k < kPtsPerLane; ++k) {
+        for (int k = 0; k < KPL; ++k) {
             const int i = lane + 64 * k;
             rank[k] += (dj < mine[k] || (dj == mine[k] && j < i)) ? 1 : 0;
         }
     }
     bool changed = false;
 #pragma unroll
-    for (int k = 0; k < kPtsPerLane; ++k) {
+    for (int k = 0; k < KPL; ++k) {
         const bool nin = lane + 64 * k < n && rank[k] < h;
         changed |= nin != in[k];
         in[k] = nin;
@@ -177,6 +179,7 @@ __device__ bool c_step(Shared &sh, int n, int h, const Cov &c, bool *in) {
 
 // The first two C-steps of start s (both phases take this same path); the
 // subset flags and its moments on return.  False when the start is dropped.
+template <int KPL>
 __device__ bool start_steps(Shared &sh, int n, int h, const uint32_t *starts, int s, bool *in,
                             Cov &c) {
     const int lane = __lane_id();
@@ -209,10 +212,10 @@ __device__ bool start_steps(Shared &sh, int n, int h, const uint32_t *starts, in
     for (int q = 0; q < 6; ++q) c0.s[q] = s6[q] / 4;
     if (degenerate(c0.s)) return false;
 #pragma unroll
-    for (int k = 0; k < kPtsPerLane; ++k) in[k] = false;
-    c_step(sh, n, h, c0, in);  // 4 points -> h points
-    c = wave_moments(sh, n, in, h);
-    if (!degenerate(c.s) && c_step(sh, n, h, c, in)) c = wave_moments(sh, n, in, h);
+    for (int k = 0; k < KPL; ++k) in[k] = false;
+    c_step<KPL>(sh, n, h, c0, in);  // 4 points -> h points
+    c = wave_moments<KPL>(sh, n, in, h);
+    if (!degenerate(c.s) && c_step<KPL>(sh, n, h, c, in)) c = wave_moments<KPL>(sh, n, in, h);
     (void)lane;
     return true;
 }
@@ -225,6 +228,81 @@ __device__ void sort_into(const int32_t *a, int m, int32_t *out) {
         for (int j = 0; j < m; ++j) r += (a[j] < v || (a[j] == v && j < i)) ? 1 : 0;
         out[r] = v;
     }
+}
+
+// FAST-MCD on the n points in LDS (KPL >= ceil(n / 64) points per lane):
+// the first stage scores every start by the determinant after two C-steps,
+// the kBest lowest (ties to the earlier start) are iterated until the subset
+// holds; their subsets, moments and determinants are left in sh.
+template <int KPL>
+__device__ void mcd_stages(Shared &sh, const RefineArgs &a, int n, int h) {
+    const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
+    (void)tid;
+    // FAST-MCD, first stage: two C-steps from every start
+    for (int s = wave; s < a.n_starts; s += RW) {
+        bool in[KPL];
+        Cov cv;
+        const bool ok = start_steps<KPL>(sh, n, h, a.starts, s, in, cv);
+        if (lane == 0) sh.dets[s] = ok ? det3(cv.s) : INFINITY;
+    }
+    __syncthreads();
+    if (wave == 0) {  // the kBest lowest (det, start)
+        int nt = 0;
+        double last_d = -INFINITY;
+        int last_s = -1;
+        for (; nt < kBest; ++nt) {
+            double bd = INFINITY;
+            int bs = -1;
+            for (int s = lane; s < a.n_starts; s += 64) {
+                const double d = sh.dets[s];
+                const bool after = d > last_d || (d == last_d && s > last_s);
+                if (after && d != INFINITY && (d < bd || (d == bd && s < bs) || bs < 0)) {
+                    bd = d;
+                    bs = s;
+                }
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const double od = __shfl_xor(bd, o, 64);
+                const int os = __shfl_xor(bs, o, 64);
+                if (os >= 0 && (bs < 0 || od < bd || (od == bd && os < bs))) {
+                    bd = od;
+                    bs = os;
+                }
+            }
+            if (bs < 0) break;
+            if (lane == 0) sh.top[nt] = bs;
+            last_d = bd;
+            last_s = bs;
+        }
+        if (lane == 0) sh.n_top = nt;
+    }
+    __syncthreads();
+    const int n_top = sh.n_top;
+    // second stage: the best starts iterated until the subset holds
+    for (int k = wave; k < n_top; k += RW) {
+        bool in[KPL];
+        Cov cv;
+        start_steps<KPL>(sh, n, h, a.starts, sh.top[k], in, cv);
+        for (int it = 0; it < kMaxCsteps; ++it) {
+            if (degenerate(cv.s)) break;
+            if (!c_step<KPL>(sh, n, h, cv, in)) break;
+            cv = wave_moments<KPL>(sh, n, in, h);
+        }
+#pragma unroll
+        for (int q = 0; q < kPtsPerLane; ++q) {
+            const uint64_t b = q < KPL ? __ballot(in[q < KPL ? q : 0]) : 0;
+            if (lane == 0) {
+                sh.mask[k][2 * q] = (uint32_t)b;
+                sh.mask[k][2 * q + 1] = (uint32_t)(b >> 32);
+            }
+        }
+        if (lane == 0) {
+            sh.cov[k] = cv;
+            sh.cdet[k] = det3(cv.s);
+        }
+    }
+    __syncthreads();
 }
 
 __device__ inline bool cell_span(int64_t lo, int64_t hi, int32_t f0, int32_t f1, int cl, int *c0,
@@ -283,73 +361,17 @@ __global__ void __launch_bounds__(RT) k_refine_clusters(RefineArgs a) {
             }
             const int h = (n + 4) / 2;
             __syncthreads();
-            // FAST-MCD, first stage: two C-steps from every start
-            for (int s = wave; s < a.n_starts; s += RW) {
-                bool in[kPtsPerLane];
-                Cov cv;
-                const bool ok = start_steps(sh, n, h, a.starts, s, in, cv);
-                if (lane == 0) sh.dets[s] = ok ? det3(cv.s) : INFINITY;
+            switch ((n + 63) >> 6) {
+            case 1: mcd_stages<1>(sh, a, n, h); break;
+            case 2: mcd_stages<2>(sh, a, n, h); break;
+            case 3:
+            case 4: mcd_stages<4>(sh, a, n, h); break;
+            default: mcd_stages<8>(sh, a, n, h); break;
             }
-            __syncthreads();
-            if (wave == 0) {  // the kBest lowest (det, start)
-                int nt = 0;
-                double last_d = -INFINITY;
-                int last_s = -1;
-                for (; nt < kBest; ++nt) {
-                    double bd = INFINITY;
-                    int bs = -1;
-                    for (int s = lane; s < a.n_starts; s += 64) {
-                        const double d = sh.dets[s];
-                        const bool after = d > last_d || (d == last_d && s > last_s);
-                        if (after && d != INFINITY && (d < bd || (d == bd && s < bs) || bs < 0)) {
-                            bd = d;
-                            bs = s;
-                        }
-                    }
-#pragma unroll
-                    for (int o = 32; o > 0; o >>= 1) {
-                        const double od = __shfl_xor(bd, o, 64);
-                        const int os = __shfl_xor(bs, o, 64);
-                        if (os >= 0 && (bs < 0 || od < bd || (od == bd && os < bs))) {
-                            bd = od;
-                            bs = os;
-                        }
-                    }
-                    if (bs < 0) break;
-                    if (lane == 0) sh.top[nt] = bs;
-                    last_d = bd;
-                    last_s = bs;
-                }
-                if (lane == 0) sh.n_top = nt;
-            }
-            __syncthreads();
             const int n_top = sh.n_top;
             if (n_top == 0) {
                 res.status = SAS_REFINE_NO_START;
                 break;
-            }
-            // second stage: the best starts iterated until the subset holds
-            for (int k = wave; k < n_top; k += RW) {
-                bool in[kPtsPerLane];
-                Cov cv;
-                start_steps(sh, n, h, a.starts, sh.top[k], in, cv);
-                for (int it = 0; it < kMaxCsteps; ++it) {
-                    if (degenerate(cv.s)) break;
-                    if (!c_step(sh, n, h, cv, in)) break;
-                    cv = wave_moments(sh, n, in, h);
-                }
-#pragma unroll
-                for (int q = 0; q < kPtsPerLane; ++q) {
-                    const uint64_t b = __ballot(in[q]);
-                    if (lane == 0) {
-                        sh.mask[k][2 * q] = (uint32_t)b;
-                        sh.mask[k][2 * q + 1] = (uint32_t)(b >> 32);
-                    }
-                }
-                if (lane == 0) {
-                    sh.cov[k] = cv;
-                    sh.cdet[k] = det3(cv.s);
-                }
             }
             __syncthreads();
             int best = 0;
