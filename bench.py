@@ -216,6 +216,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="night workload: planner defaults")
     ap.add_argument("--extract", action="store_true",
                     help="also time the greedy cluster extraction over the step's candidates")
+    ap.add_argument("--extract-rounds", type=int, default=0,
+                    help="parallel rounds of the extraction (0 default, -1 one take at a time)")
     ap.add_argument("--refine", action="store_true",
                     help="also time Steps 4-6 (FAST-MCD refine, gather, iterate) over the "
                          "clusters of the greedy extraction (implies --extract)")
@@ -315,11 +317,11 @@ def main():
             s.peaks()
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            clusters, _ = s.extract(wl.n)
+            clusters, _ = s.extract(wl.n, rounds=args.extract_rounds)
             if k >= args.warmup:
                 ext.append((time.perf_counter() - t1) * 1000.0)
         rec["extract"] = {"ms": float(np.mean(ext)), "n_clusters": int(len(clusters)),
-                          "n_cells": n_cand}
+                          "n_cells": n_cand, "rounds": args.extract_rounds}
         if args.refine:
             from paper_2509_26279_amd import synth
             _, owner = s.extract(wl.n)

@@ -362,16 +362,21 @@ typedef struct {
  *   cluster_of_dev: device int32 [n] by catalog index: the cluster that took
  *                the detection, or -1.
  *   res_dev:     device sas_extract_result.
- * Asynchronous (one workgroup runs the loop), no allocation.  Errors:
- * SAS_E_INVALID (arguments, member_cap >= 2^31, not a dense-path plan),
- * SAS_E_WORKSPACE.
+ *   rounds:      parallel rounds before the loop goes on one take at a time:
+ *                each round takes every cell that beats all open cells
+ *                sharing a live detection with it (the loop would take each
+ *                of them, with the same detections); 0: the default (4),
+ *                -1: none, 1..12.  The result does not depend on it.
+ * Asynchronous, no allocation.  Errors: SAS_E_INVALID (arguments,
+ * member_cap >= 2^31, rounds outside [-1, 12], not a dense-path plan),
+ * SAS_E_UNSUPPORTED (a weighted plan), SAS_E_WORKSPACE.
  */
 sas_status sas_extract_clusters(const sas_plan *plan, const void *workspace, size_t ws_bytes,
                                 int64_t n, const sas_candidate *cand_dev, int64_t n_cand,
                                 int64_t member_cap, void *scratch, size_t scratch_bytes,
                                 sas_candidate *clusters_dev, int64_t cluster_cap,
                                 int32_t *cluster_of_dev, sas_extract_result *res_dev,
-                                void *stream);
+                                int32_t rounds, void *stream);
 
 /* Bytes of scratch sas_extract_clusters needs. */
 sas_status sas_extract_scratch_size(int64_t n, int64_t n_cand, int64_t member_cap,

@@ -1296,7 +1296,7 @@ namespace {
 
 struct ExtractScratch {
     size_t first, blocksum, member, member_epoch, member_cell, inv_first, inv_blocksum,
-        inv_cursor, inv, count, dirty, live, open, total;
+        inv_cursor, inv, count, dirty, live, open, best, slot, taken, perm, counters, total;
 };
 
 ExtractScratch extract_layout(int64_t n, int64_t n_cand, int64_t member_cap) {
@@ -1315,6 +1315,11 @@ ExtractScratch extract_layout(int64_t n, int64_t n_cand, int64_t member_cap) {
     L.dirty = o; o = align_up(o + sizeof(uint32_t) * n_cand);
     L.live = o; o = align_up(o + n);
     L.open = o; o = align_up(o + n_cand);
+    L.best = o; o = align_up(o + sizeof(int32_t) * n);
+    L.slot = o; o = align_up(o + sizeof(int32_t) * n_cand);
+    L.taken = o; o = align_up(o + sizeof(int32_t) * n_cand);
+    L.perm = o; o = align_up(o + sizeof(int32_t) * n_cand);
+    L.counters = o; o = align_up(o + sizeof(int32_t) * kExtractCounters);
     L.total = o;
     return L;
 }
@@ -1338,11 +1343,12 @@ extern "C" sas_status sas_extract_clusters(const sas_plan *p, const void *worksp
                                            int64_t member_cap, void *scratch,
                                            size_t scratch_bytes, sas_candidate *clusters_dev,
                                            int64_t cluster_cap, int32_t *cluster_of_dev,
-                                           sas_extract_result *res_dev, void *stream) {
+                                           sas_extract_result *res_dev, int32_t rounds,
+                                           void *stream) {
     if (!p || n < 0 || n_cand < 0 || n_cand >= kMaxFeatureCands || member_cap < 0 ||
         member_cap > kMaxMembers || cluster_cap < 0 || !res_dev ||
         (n_cand > 0 && !cand_dev) || (cluster_cap > 0 && !clusters_dev) ||
-        (n > 0 && !cluster_of_dev))
+        (n > 0 && !cluster_of_dev) || rounds < -1 || rounds > kExtractRounds)
         return fail(SAS_E_INVALID, "sas_extract_clusters: bad argument");
     if (p->path != SAS_PATH_DENSE)
         return fail(SAS_E_INVALID, "sas_extract_clusters: needs the window index of a dense-path plan");
@@ -1381,10 +1387,16 @@ extern "C" sas_status sas_extract_clusters(const sas_plan *p, const void *worksp
     a.dirty = (uint32_t *)(s + S.dirty);
     a.live = (uint8_t *)(s + S.live);
     a.open = (uint8_t *)(s + S.open);
+    a.best = (int32_t *)(s + S.best);
+    a.slot = (int32_t *)(s + S.slot);
+    a.taken = (int32_t *)(s + S.taken);
+    a.perm = (int32_t *)(s + S.perm);
+    a.counters = (int32_t *)(s + S.counters);
     a.clusters = clusters_dev;
     a.cluster_cap = cluster_cap;
     a.cluster_of = cluster_of_dev;
     a.res = res_dev;
+    a.rounds = rounds == 0 ? kExtractDefaultRounds : rounds < 0 ? 0 : rounds;
     hipError_t e = launch_extract(a, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "sas_extract_clusters: launch");
     return SAS_OK;

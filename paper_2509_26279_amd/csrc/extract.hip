@@ -15,12 +15,22 @@
 //   2. an inverse index (detection -> cells that hold it) by counting sort,
 //      and every cell's count (one wave per cell: distinct epochs through a
 //      256-bit mask in LDS, or the number of live contributors);
-//   3. k_greedy: one workgroup runs the loop.  Each round a block reduction
-//      finds the maximum of the stored counts under the tie rule (cells
-//      below N_min close), the maximum's live contributors are taken (with
-//      the cluster's index) and every open cell that held one of them is
-//      queued; only the queued cells are recounted (one wave each), since the
-//      counts of the others have not changed.
+//   3. parallel rounds: a cell whose key (count, then the tie rule) beats
+//      every open cell sharing a live detection with it is taken by the
+//      sequential loop too, with exactly its current contributors - counts
+//      only fall, so no neighbour can overtake it, and what is taken
+//      elsewhere meanwhile shares none of its detections.  Each round takes
+//      all such local maxima at once (every detection keeps the best open
+//      cell holding it; a cell is a local maximum when it is the best of all
+//      its live detections), removes their detections and recounts;
+//   4. k_greedy: one workgroup finishes whatever the rounds left, one take at
+//      a time.  Each step a block reduction finds the maximum of the stored
+//      counts under the tie rule (cells below N_min close), the maximum's
+//      live contributors are taken and every open cell that held one of
+//      them is queued; only the queued cells are recounted (one wave each);
+//   5. the keys taken by the sequential loop strictly increase (counts only
+//      fall and the tie rule is total), so ranking the clusters by key
+//      restores its order; the owners are renumbered to that order.
 #include <algorithm>
 
 #include "internal.h"
@@ -155,8 +165,10 @@ __global__ void k_inv_init(ExtractArgs a) {
     for (int64_t j = t0; j < a.n; j += stride) {
         a.inv_cursor[j] = 0;
         a.live[j] = 1;
+        a.best[j] = -1;
         a.cluster_of[j] = -1;
     }
+    if (t0 < kExtractCounters) a.counters[t0] = 0;
     for (int64_t k = t0; k < a.n_cand; k += stride) {
         a.open[k] = 1;
         a.dirty[k] = 0;
@@ -217,7 +229,112 @@ __global__ void __launch_bounds__(CT) k_count_all(ExtractArgs a) {
     const int64_t n_waves = ((int64_t)gridDim.x * CT) >> 6;
     for (int64_t k = wave_id; k < a.n_cand; k += n_waves) {
         const int32_t n = recount(a, k, wmask[wave]);
-        if (__lane_id() == 0) a.count[k] = n;
+        if (__lane_id() == 0) {
+            a.count[k] = n;
+            if (n < a.n_min)
+                a.open[k] = 0;
+            else
+                atomicAdd(&a.counters[2], 1);
+        }
+    }
+}
+
+// Whether cell k beats cell c (c < 0: no cell) under the order of the
+// maximum: larger count, then smaller v_idx, by, bx.
+__device__ inline bool cell_better(const ExtractArgs &a, int32_t k, int32_t c) {
+    if (c < 0) return true;
+    const int32_t ck = a.count[k], cc = a.count[c];
+    if (ck != cc) return ck > cc;
+    const sas_candidate &p = a.cand[k], &q = a.cand[c];
+    if (p.v_idx != q.v_idx) return p.v_idx < q.v_idx;
+    if (p.by != q.by) return p.by < q.by;
+    return p.bx < q.bx;
+}
+
+// A parallel round may run: the lists fit and the previous round left an
+// open cell.
+__device__ inline bool round_active(const ExtractArgs &a, int r) {
+    return lists_fit(a) && a.counters[2 + r - 1] > 0;
+}
+
+#define FOR_CELLS(k)                                                                    \
+    const int64_t wave_id = ((int64_t)blockIdx.x * CT + threadIdx.x) >> 6;             \
+    const int64_t n_waves = ((int64_t)gridDim.x * CT) >> 6;                              \
+    for (int64_t k = wave_id; k < a.n_cand; k += n_waves)
+
+// Round r, step 1: every live detection of an open cell keeps the best
+// open cell holding it (compare-and-swap until it holds the better one).
+__global__ void __launch_bounds__(CT) k_round_best(ExtractArgs a, int r) {
+    if (!round_active(a, r)) return;
+    FOR_CELLS(k) {
+        if (a.open[k] != 1) continue;  // wave uniform
+        for (int32_t m = a.first[k] + __lane_id(); m < a.first[k + 1]; m += 64) {
+            const int32_t j = a.member[m];
+            if (!a.live[j]) continue;
+            int32_t cur = a.best[j];
+            while (cell_better(a, (int32_t)k, cur)) {
+                const int32_t old = atomicCAS(&a.best[j], cur, (int32_t)k);
+                if (old == cur) break;
+                cur = old;
+            }
+        }
+    }
+}
+
+// Step 2: a cell that is the best of all its live detections is taken.
+__global__ void __launch_bounds__(CT) k_round_take(ExtractArgs a, int r) {
+    if (!round_active(a, r)) return;
+    FOR_CELLS(k) {
+        if (a.open[k] != 1) continue;
+        bool mine = true;
+        for (int32_t m = a.first[k] + __lane_id(); m < a.first[k + 1]; m += 64) {
+            const int32_t j = a.member[m];
+            if (a.live[j] && a.best[j] != (int32_t)k) mine = false;
+        }
+        if (__all(mine) && __lane_id() == 0) {
+            const int32_t s = atomicAdd(&a.counters[0], 1);
+            a.slot[k] = s;
+            a.taken[s] = (int32_t)k;
+            a.open[k] = 2;
+        }
+    }
+}
+
+// Step 3: the taken cells' live detections leave (their live sets are
+// disjoint: a detection has one best cell).
+__global__ void __launch_bounds__(CT) k_round_kill(ExtractArgs a, int r) {
+    if (!round_active(a, r)) return;
+    FOR_CELLS(k) {
+        if (a.open[k] != 2) continue;
+        const int32_t s = a.slot[k];
+        for (int32_t m = a.first[k] + __lane_id(); m < a.first[k + 1]; m += 64) {
+            const int32_t j = a.member[m];
+            if (!a.live[j]) continue;
+            a.cluster_of[a.cat.sidx[j]] = s;
+            a.live[j] = 0;
+        }
+        if (__lane_id() == 0) a.open[k] = 0;
+    }
+}
+
+// Step 4: recount the open cells, close those below N_min, count the rest,
+// and clear the best cell of their live detections for the next round.
+__global__ void __launch_bounds__(CT) k_round_recount(ExtractArgs a, int r) {
+    __shared__ uint32_t wmask[CT / 64][kSlotWords];
+    if (!round_active(a, r)) return;
+    const int wave = threadIdx.x >> 6;
+    FOR_CELLS(k) {
+        if (a.open[k] != 1) continue;
+        const int32_t n = recount(a, k, wmask[wave]);
+        if (__lane_id() == 0) {
+            a.count[k] = n;
+            if (n < a.n_min)
+                a.open[k] = 0;
+            else
+                atomicAdd(&a.counters[2 + r], 1);
+        }
+        for (int32_t m = a.first[k] + __lane_id(); m < a.first[k + 1]; m += 64)
+            a.best[a.member[m]] = -1;
     }
 }
 
@@ -230,17 +347,8 @@ __global__ void __launch_bounds__(GT) k_greedy(ExtractArgs a) {
     __shared__ Best wbest[GW];
     __shared__ Best best_all;
     const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
-    const int64_t n_members = a.first[a.n_cand];
-    if (n_members > a.member_cap) {  // the lists did not fit: report, extract nothing
-        if (tid == 0) {
-            a.res->n_clusters = 0;
-            a.res->n_members = n_members;
-            a.res->status = SAS_EXTRACT_MEMBERS_FULL;
-        }
-        return;
-    }
-    int64_t n_out = 0;
-    const uint32_t sat = (uint32_t)a.count_sat;
+    if (!lists_fit(a)) return;  // reported by k_finish
+    int32_t n_out = a.counters[0];  // clusters taken by the parallel rounds
     for (;;) {
         // the maximum of the stored counts; cells below N_min close
         Best mine{0, -1, 0, 0, 0};
@@ -274,15 +382,7 @@ __global__ void __launch_bounds__(GT) k_greedy(ExtractArgs a) {
         const Best b = best_all;
         if (b.k < 0) break;  // block uniform
         if (tid == 0) {
-            if (n_out < a.cluster_cap) {
-                const uint32_t cnt = (uint32_t)b.count;
-                uint4 rec;
-                rec.x = b.v;
-                rec.y = (uint32_t)b.bx;
-                rec.z = (uint32_t)b.by;
-                rec.w = (cnt > sat ? sat : cnt) | ((cnt > sat ? 1u : 0u) << 16);
-                *(uint4 *)(a.clusters + n_out) = rec;
-            }
+            a.taken[n_out] = b.k;
             a.open[b.k] = 0;
         }
         // take its live contributors; queue the open cells that held them
@@ -327,11 +427,88 @@ __global__ void __launch_bounds__(GT) k_greedy(ExtractArgs a) {
         ++n_out;
         __syncthreads();
     }
-    if (tid == 0) {
-        a.res->n_clusters = n_out;
-        a.res->n_members = n_members;
-        a.res->status = n_out > a.cluster_cap ? SAS_EXTRACT_CLUSTERS_FULL : 0;
+    if (tid == 0) a.counters[1] = n_out;
+}
+
+// Key of a taken cell for the extraction order: (count at the take, v_idx,
+// by, bx); a beats b when its count is larger, then its v_idx, by, bx smaller.
+struct Key {
+    int32_t count;
+    uint32_t v;
+    int32_t by, bx;
+};
+
+__device__ inline Key key_of(const ExtractArgs &a, int32_t k) {
+    const sas_candidate cd = a.cand[k];
+    return Key{a.count[k], cd.v_idx, cd.by, cd.bx};
+}
+
+__device__ inline bool key_before(const Key &p, const Key &q) {
+    if (p.count != q.count) return p.count > q.count;
+    if (p.v != q.v) return p.v < q.v;
+    if (p.by != q.by) return p.by < q.by;
+    return p.bx < q.bx;
+}
+
+constexpr int kRankTile = 1024;  // keys staged in LDS at a time
+
+// Extraction order: the rank of each cluster's key among all clusters (keys
+// are distinct); the records in that order.  The keys are walked in tiles
+// staged in LDS.
+__global__ void __launch_bounds__(256) k_rank(ExtractArgs a) {
+    __shared__ Key tile[kRankTile];
+    if (!lists_fit(a)) return;
+    const int32_t total = a.counters[1];
+    const uint32_t sat = (uint32_t)a.count_sat;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c0 = (int64_t)blockIdx.x * blockDim.x; c0 < total; c0 += stride) {
+        const int64_t c = c0 + threadIdx.x;  // block uniform loop, per-thread cluster
+        const int32_t k = c < total ? a.taken[c] : 0;
+        const Key mine = key_of(a, k);
+        int32_t r = 0;
+        for (int32_t d0 = 0; d0 < total; d0 += kRankTile) {
+            const int32_t nd = min(kRankTile, total - d0);
+            __syncthreads();
+            for (int32_t i = threadIdx.x; i < nd; i += blockDim.x) tile[i] = key_of(a, a.taken[d0 + i]);
+            __syncthreads();
+            for (int32_t i = 0; i < nd; ++i) r += key_before(tile[i], mine) ? 1 : 0;
+        }
+        if (c >= total) continue;
+        a.perm[c] = r;
+        if (r < a.cluster_cap) {
+            const sas_candidate cd = a.cand[k];
+            const uint32_t cnt = (uint32_t)a.count[k];  // its count when taken
+            uint4 rec;
+            rec.x = cd.v_idx;
+            rec.y = (uint32_t)cd.bx;
+            rec.z = (uint32_t)cd.by;
+            rec.w = (cnt > sat ? sat : cnt) | ((cnt > sat ? 1u : 0u) << 16);
+            *(uint4 *)(a.clusters + r) = rec;
+        }
     }
+}
+
+__global__ void k_renumber(ExtractArgs a) {
+    if (!lists_fit(a)) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+        const int32_t c = a.cluster_of[i];
+        if (c >= 0) a.cluster_of[i] = a.perm[c];
+    }
+}
+
+__global__ void k_finish(ExtractArgs a) {
+    const int64_t n_members = a.first[a.n_cand];
+    if (n_members > a.member_cap) {  // the lists did not fit: nothing was extracted
+        a.res->n_clusters = 0;
+        a.res->n_members = n_members;
+        a.res->status = SAS_EXTRACT_MEMBERS_FULL;
+        return;
+    }
+    const int32_t total = a.counters[1];
+    a.res->n_clusters = total;
+    a.res->n_members = n_members;
+    a.res->status = total > a.cluster_cap ? SAS_EXTRACT_CLUSTERS_FULL : 0;
 }
 
 __global__ void k_contrib_tail(int32_t *first, int64_t n_cand) { first[n_cand] = 0; }
@@ -358,8 +535,19 @@ hipError_t launch_extract(const ExtractArgs &a, hipStream_t stream) {
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_inv_fill, dim3(2048), dim3(256), 0, stream, a);
         hipLaunchKernelGGL(k_count_all, dim3(cell_blocks), dim3(CT), 0, stream, a);
+        for (int r = 1; r <= a.rounds; ++r) {
+            hipLaunchKernelGGL(k_round_best, dim3(cell_blocks), dim3(CT), 0, stream, a, r);
+            hipLaunchKernelGGL(k_round_take, dim3(cell_blocks), dim3(CT), 0, stream, a, r);
+            hipLaunchKernelGGL(k_round_kill, dim3(cell_blocks), dim3(CT), 0, stream, a, r);
+            hipLaunchKernelGGL(k_round_recount, dim3(cell_blocks), dim3(CT), 0, stream, a, r);
+        }
     }
     hipLaunchKernelGGL(k_greedy, dim3(1), dim3(GT), 0, stream, a);
+    const unsigned rank_blocks =
+        (unsigned)std::max<int64_t>(1, std::min<int64_t>((a.n_cand + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_rank, dim3(rank_blocks), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_renumber, dim3(init_blocks), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1), 0, stream, a);
     return hipGetLastError();
 }
 

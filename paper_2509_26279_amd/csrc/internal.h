@@ -172,12 +172,21 @@ struct ExtractArgs {
     int32_t *count;            // [n_cand] current count of each cell
     uint32_t *dirty;           // [n_cand] queued for a recount
     uint8_t *live;             // [n] by sorted position: not yet in a cluster
-    uint8_t *open;             // [n_cand] cell may still reach N_min
+    uint8_t *open;             // [n_cand] 0 closed, 1 open, 2 taken in this round
+    int32_t *best;             // [n] by sorted position: the best open cell holding it, -1
+    int32_t *slot;             // [n_cand] provisional cluster of a cell taken in a round
+    int32_t *taken;            // [n_cand] the cell of each cluster, by provisional index
+    int32_t *perm;             // [n_cand] provisional index -> extraction order
+    int32_t *counters;         // [2 + kExtractRounds + 1] taken so far, total, open after round r
+    int32_t rounds;            // parallel rounds before the sequential finish (<= kExtractRounds)
     sas_candidate *clusters;   // [cluster_cap] in extraction order
     int64_t cluster_cap;
     int32_t *cluster_of;       // [n] by catalog index: cluster or -1
     sas_extract_result *res;
 };
+constexpr int kExtractRounds = 12;  // most parallel rounds before the sequential finish
+constexpr int kExtractDefaultRounds = 4;
+constexpr int kExtractCounters = 2 + kExtractRounds + 1;
 hipError_t launch_extract(const ExtractArgs &a, hipStream_t stream);
 
 // Vetting MLP 32 -> 128 -> 128 -> 1; parameters packed W1 (32 x 128),

@@ -145,7 +145,8 @@ def load():
         "sas_features": (I32, [P, P, SZ, I64, P, P, I64, I32, P, SZ, P, P]),
         "sas_features_scratch_size": (I32, [I64, ctypes.POINTER(ctypes.c_size_t)]),
         "sas_extract_scratch_size": (I32, [I64, I64, I64, ctypes.POINTER(ctypes.c_size_t)]),
-        "sas_extract_clusters": (I32, [P, P, SZ, I64, P, I64, I64, P, SZ, P, I64, P, P, P]),
+        "sas_extract_clusters": (I32, [P, P, SZ, I64, P, I64, I64, P, SZ, P, I64, P, P, I32,
+                                       P]),
         "sas_mlp_create": (I32, [I64, ctypes.c_uint64, P]),
         "sas_mlp_destroy": (I32, [P]),
         "sas_mlp_set_norm": (I32, [P, P, P]),
@@ -366,12 +367,14 @@ class Search:
         n_cand = int(r[0].astype(np.int64) | (r[1].astype(np.int64) << 32))
         return {"n_cand": n_cand, "status": int(r[2]), "n_spilled": int(r[3])}
 
-    def extract(self, n: int, member_cap: int = 0, cluster_cap: int = 0, stream=None):
+    def extract(self, n: int, member_cap: int = 0, cluster_cap: int = 0, rounds: int = 0,
+                stream=None):
         """Step 3 (greedy cluster extraction) over the candidates left in the
         device buffer by the last vote of an n-detection catalog.  Returns
         (clusters as CAND_DTYPE in extraction order, int32 [n] cluster of each
-        detection or -1).  Synchronises; grows member_cap once if the
-        contributor lists did not fit."""
+        detection or -1).  rounds: parallel rounds before the one-at-a-time
+        finish (0 default, -1 none).  Synchronises; grows member_cap once if
+        the contributor lists did not fit."""
         import torch
         r = self.result()
         k = min(r["n_cand"], self.cand.shape[0])
@@ -390,7 +393,7 @@ class Search:
                                                self.cand.data_ptr(), k, member_cap,
                                                scratch.data_ptr(), nb.value, clusters.data_ptr(),
                                                cluster_cap, owner.data_ptr(), res.data_ptr(),
-                                               _stream_handle(stream)))
+                                               int(rounds), _stream_handle(stream)))
             rr = res.cpu().numpy()
             n_clusters = int(rr[0:8].view(np.int64)[0])
             n_members = int(rr[8:16].view(np.int64)[0])

@@ -23,7 +23,8 @@ def _extent(x, y):
     return (int(np.min(x)), int(np.max(x)) + 1, int(np.min(y)), int(np.max(y)) + 1)
 
 
-def _run(x, y, e, t, v, b, n_min, mode="epochs", extent=None, tuning=None, member_cap=0):
+def _run(x, y, e, t, v, b, n_min, mode="epochs", extent=None, tuning=None, member_cap=0,
+         rounds=0):
     x, y, e = np.asarray(x), np.asarray(y), np.asarray(e)
     extent = extent if extent is not None else _extent(x, y)
     plan = sas.Plan(v, t, b, n_min, extent, mode=mode, count_sat=65535, tuning=tuning)
@@ -32,7 +33,7 @@ def _run(x, y, e, t, v, b, n_min, mode="epochs", extent=None, tuning=None, membe
         xd, yd, ed = s.upload(x, y, e)
         s.vote(xd, yd, ed)
         s.peaks()
-        return s.extract(len(x), member_cap=member_cap)
+        return s.extract(len(x), member_cap=member_cap, rounds=rounds)
     finally:
         plan.close()
 
@@ -48,11 +49,15 @@ def _check(got, ref, n):
     assert bad.size == 0, (bad[:5], owner[bad[:5]], want[bad[:5]])
 
 
-def _case(x, y, e, t, v, b, n_min, mode="epochs", extent=None, tuning=None, member_cap=0):
+def _case(x, y, e, t, v, b, n_min, mode="epochs", extent=None, tuning=None, member_cap=0,
+          rounds=(0, -1, 1, 3)):
+    """The oracle's loop against the GPU with parallel rounds (default, a
+    few) and without (one take at a time): identical results."""
     cand = oracle.vote(x, y, e, t, v, b, n_min, mode)
     ref = ox.extract(x, y, e, t, v, b, cand, n_min, mode)
-    got = _run(x, y, e, t, v, b, n_min, mode, extent, tuning, member_cap)
-    _check(got, ref, len(x))
+    for r in rounds:
+        got = _run(x, y, e, t, v, b, n_min, mode, extent, tuning, member_cap, r)
+        _check(got, ref, len(x))
     return ref
 
 
