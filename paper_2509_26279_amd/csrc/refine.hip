@@ -158,7 +158,23 @@ __device__ bool c_step(Shared &sh, int n, int h, const Cov &c, bool *in) {
         rank[k] = 0;
         mine[k] = (lane + 64 * k < n) ? d2[lane + 64 * k] : 0.0;
     }
-    for (int j = 0; j < n; ++j) {
+    // blocks of U distances loaded before they are compared (the loads of a
+    // block are in flight together; fewer when each lane holds many points)
+    constexpr int U = KPL <= 2 ? 8 : 2;
+    int j = 0;
+    for (; j + U <= n; j += U) {
+        double dj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) dj[u] = d2[j + u];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < KPL; ++k) {
+                const int i = lane + 64 * k;
+                rank[k] += (dj[u] < mine[k] || (dj[u] == mine[k] && j + u < i)) ? 1 : 0;
+            }
+    }
+    for (; j < n; ++j) {
         const double dj = d2[j];
 #pragma unroll
         for (int k = 0; k < KPL; ++k) {
