@@ -38,9 +38,11 @@ INT_PEAK_TOPS = N_CU * SIMD_PER_CU * LANES_PER_SIMD * CLOCK_GHZ / 1000.0
 # Packed 16-bit integer ops (v_pk_sub_u16, v_pk_lshrrev_b16, v_dot2_u32_u16):
 # two halves per lane per clock.  Votes of a packed plan run at this rate.
 INT16X2_PEAK_TOPS = 2 * INT_PEAK_TOPS
-# LDS: one 4-byte access per bank per clock, 32 banks per CU
+# LDS: one 4-byte access per bank per clock, 32 banks per CU; an atomic add
+# reads and writes its word, so a 64-lane ds_add_u32 without bank conflicts
+# takes 4 clocks: 16 lane-atomics per CU per clock
 LDS_BANKS = 32
-LDS_ATOMIC_PEAK = N_CU * LDS_BANKS * CLOCK_GHZ * 1e9  # lane atomics per second
+LDS_ATOMIC_PEAK = N_CU * (LDS_BANKS // 2) * CLOCK_GHZ * 1e9  # lane atomics per second
 # Integer operations of one vote on the dense path: x - S_x, y - S_y, the two
 # floor divisions by the cell width (shifts), and the histogram word index
 # (bin row * row pitch + bin column * lanes + lane: one multiply-add and one
