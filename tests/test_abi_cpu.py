@@ -146,3 +146,15 @@ def test_autotune_classes_and_cache(tmp_path):
     assert autotune.load_cache(p) == {}
     autotune.save_cache(p, {k1: {"tuning": {"groups": 1}, "ms": 1.0}})
     assert autotune.load_cache(p)[k1]["tuning"] == {"groups": 1}
+
+
+def test_refine_extract_weighted_argument_errors():
+    """Argument checks that run before any device work (no GPU needed)."""
+    lib = sas.load()
+    # no plan
+    assert lib.sas_refine_clusters(None, None, 0, None, None, None, 0, None, None, 0, 0, None,
+                                   1, 0, None, None, 0, None, None) == sas.SAS_E_INVALID
+    assert lib.sas_vote_weighted(None, None, None, None, None, 0, None, 0, None, None, 0,
+                                 None) == sas.SAS_E_INVALID
+    assert lib.sas_extract_clusters(None, None, 0, 0, None, 0, 0, None, 0, None, 0, None, None,
+                                    0, None) == sas.SAS_E_INVALID
