@@ -53,9 +53,10 @@ OPS_PER_WEIGHTED_VOTE = 7
 VOTE_KERNEL = "k_vote_dense"
 
 
-def _night(n_chips, tune, log):
+def _night(n_chips, tune, log, full_tune=False):
     """The batched night: chips with their own plans, thresholds and
-    autotuned launch shapes (one tuning per chip style)."""
+    autotuned launch shapes (one tuning per shape class: bin width, lattice
+    spacing, grid shape, and epoch and detection counts by powers of two)."""
     import torch
 
     from paper_2509_26279_amd import autotune, sas, synth
@@ -71,13 +72,16 @@ def _night(n_chips, tune, log):
         x = torch.as_tensor(wl.x_q8).cuda()
         y = torch.as_tensor(wl.y_q8).cuda()
         e = torch.as_tensor(wl.epoch).cuda()
-        if tune and p["style"] not in tuned:
-            log("tuning the %s style on chip %d" % (p["style"], p["chip"]))
+        key = autotune.shape_class(wl.binw_q8, sas.grid_spacing(wl.binw_q8, wl.span_q16),
+                                   wl.n_epochs, wl.n, wl.grid.shape)
+        if tune and key not in tuned:
+            log("tuning class %s on chip %d" % (key, p["chip"]))
+            cands = (autotune.candidates({"n_det_hint": wl.n}) if full_tune else
+                     [{}, {"groups": 1}, {"groups": 2}, {"groups": 4}])
             r = autotune.tune(v, wl.t_q16, wl.binw_q8, n_min, wl.extent_q8, x, y, e,
-                              cands=[{}, {"groups": 1}, {"groups": 2}, {"groups": 4}],
-                              log=log)
-            tuned[p["style"]] = r["tuning"]
-        tun = dict(tuned.get(p["style"], {}), n_det_hint=wl.n)
+                              cands=cands, log=log)
+            tuned[key] = {k: v_ for k, v_ in r["tuning"].items() if k != "n_det_hint"}
+        tun = dict(tuned.get(key, {}), n_det_hint=wl.n)
         plan = sas.Plan(v, wl.t_q16, wl.binw_q8, n_min, wl.extent_q8, tuning=tun)
         chips.append({"wl": wl, "v": v, "plan": plan, "x": x, "y": y, "e": e, "n_min": n_min,
                       "style": p["style"]})
@@ -90,7 +94,7 @@ def run_night(args):
 
     from paper_2509_26279_amd import sas
     log = lambda m: print(m, file=sys.stderr, flush=True)
-    chips, tuned = _night(args.chips, not args.no_tune, log)
+    chips, tuned = _night(args.chips, not args.no_tune, log, args.full_tune)
     b = sas.Batch([(c["plan"], c["x"], c["y"], c["e"]) for c in chips], cand_cap=1 << 21)
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
@@ -216,6 +220,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--chips", type=int, default=64, help="night workload: number of chips")
     ap.add_argument("--no-tune", action="store_true", help="night workload: planner defaults")
+    ap.add_argument("--full-tune", action="store_true",
+                    help="night workload: the autotuner's whole candidate list per chip style")
     ap.add_argument("--extract", action="store_true",
                     help="also time the greedy cluster extraction over the step's candidates")
     ap.add_argument("--extract-rounds", type=int, default=0,

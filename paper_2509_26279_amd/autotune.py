@@ -71,7 +71,9 @@ def tune(v, t_q16, binw_q8, n_min, extent_q8, x, y, e, mode="epochs", count_sat=
     base.setdefault("n_det_hint", int(x.numel()))
     ref = None
     table = []
-    for tun in (cands or candidates(base)):
+    # explicit candidates are read relative to the base tuning (the shapes
+    # are timed with the same hints the plans that use them will have)
+    for tun in ([dict(base, **c) for c in cands] if cands else candidates(base)):
         try:
             if "cell_log2_step" in tun:  # relative to the planner's window-index cells
                 tun = dict(tun)
