@@ -743,23 +743,32 @@ __global__ void __launch_bounds__(T) k_refine(DenseArgs a) {
             for (int cy = cy0; cy <= cy1; ++cy) {
                 const int64_t base = ((int64_t)e * c.ncy + cy) * c.ncx;
                 const int32_t j1 = c.off[base + cx1 + 1];
-                for (int32_t jj = c.off[base + cx0]; jj < j1; ++jj) {
-                    const int2 p = c.sxy[jj];
-                    // weighted plans: the index holds 256 x + w
-                    const int32_t px = WM == kRefineCount ? p.x : p.x >> 8;
-                    const uint32_t wt = (uint32_t)p.x & 0xffu;
-                    const int32_t bx = ((px - sx) >> k) - fbx0, by = ((p.y - sy) >> k) - fby0;
-                    if ((uint32_t)bx < (uint32_t)cw && (uint32_t)by < (uint32_t)cw) {
-                        const int bin = by * cw + bx;
-                        if (WM == kRefineWeightDet) {
-                            atomicAdd(&mk[bin * kSlotWords], wt);
-                        } else if (WM == kRefineWeightEpochs) {
-                            if (wt > best[wave][bin][lane]) best[wave][bin][lane] = (uint8_t)wt;
-                            touched |= (uint64_t)1 << bin;
-                        } else if (a.mode_epochs) {
-                            atomicOr(&mk[bin * kSlotWords + (e >> 5)], 1u << (e & 31));
-                        } else {
-                            atomicAdd(&mk[bin * kSlotWords], 1u);
+                // kCopyAhead detections loaded at a time, then binned
+                for (int32_t j0 = c.off[base + cx0]; j0 < j1; j0 += kCopyAhead) {
+                    int2 pq[kCopyAhead];
+#pragma unroll
+                    for (int u = 0; u < kCopyAhead; ++u)
+                        if (j0 + u < j1) pq[u] = c.sxy[j0 + u];
+#pragma unroll
+                    for (int u = 0; u < kCopyAhead; ++u) {
+                        if (j0 + u >= j1) break;
+                        const int2 p = pq[u];
+                        // weighted plans: the index holds 256 x + w
+                        const int32_t px = WM == kRefineCount ? p.x : p.x >> 8;
+                        const uint32_t wt = (uint32_t)p.x & 0xffu;
+                        const int32_t bx = ((px - sx) >> k) - fbx0, by = ((p.y - sy) >> k) - fby0;
+                        if ((uint32_t)bx < (uint32_t)cw && (uint32_t)by < (uint32_t)cw) {
+                            const int bin = by * cw + bx;
+                            if (WM == kRefineWeightDet) {
+                                atomicAdd(&mk[bin * kSlotWords], wt);
+                            } else if (WM == kRefineWeightEpochs) {
+                                if (wt > best[wave][bin][lane]) best[wave][bin][lane] = (uint8_t)wt;
+                                touched |= (uint64_t)1 << bin;
+                            } else if (a.mode_epochs) {
+                                atomicOr(&mk[bin * kSlotWords + (e >> 5)], 1u << (e & 31));
+                            } else {
+                                atomicAdd(&mk[bin * kSlotWords], 1u);
+                            }
                         }
                     }
                 }
