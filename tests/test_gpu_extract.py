@@ -116,3 +116,22 @@ def test_extract_nothing_to_take(gpu):
     clusters, owner = _run(d["x_q8"], d["y_q8"], d["epoch"], d["t_q16"], d["v_q8"],
                            d["binw_q8"], 7)
     assert len(clusters) == 0 and np.all(owner == -1)
+
+
+def test_extract_cluster_capacity_reported(gpu):
+    """Fewer output slots than clusters: the call reports the true number
+    (SAS_EXTRACT_CLUSTERS_FULL) and the binding raises with it."""
+    wl = synth.make_tiny()
+    v = _grid(wl)
+    plan = sas.Plan(v, wl.t_q16, wl.binw_q8, 5, wl.extent_q8)
+    try:
+        s = sas.Search(plan, wl.n, cand_cap=1 << 16)
+        s.vote(*s.upload(wl.x_q8, wl.y_q8, wl.epoch))
+        s.peaks()
+        full, _ = s.extract(wl.n)
+        assert len(full) > 1
+        with pytest.raises(sas.SasError) as ei:
+            s.extract(wl.n, cluster_cap=1)
+        assert ei.value.status == sas.SAS_E_OVERFLOW and str(len(full)) in str(ei.value)
+    finally:
+        plan.close()

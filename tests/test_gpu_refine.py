@@ -184,3 +184,16 @@ def test_edge_cases(gpu):
 
 def sas_status(name):
     return {v: k for k, v in sas.REFINE_STATUS.items()}[name]
+
+
+def test_gather_capacity_truncates(gpu):
+    """A gather capacity below the gathered set: the true count is reported
+    and the first entries (ascending) are written."""
+    x, y, e, t, clusters = _movers_in_noise(8, n_movers=4, outlier_frac=0.2)
+    v = np.array([[0, 0]], np.int32)
+    ext = (0, 800 * 256, 0, 800 * 256)
+    full = gpu_refine(x, y, e, t, v, 1024, 3, clusters, extent=ext)
+    cut = gpu_refine(x, y, e, t, v, 1024, 3, clusters, extent=ext, gather_cap=4)
+    for a, b, ga, gb in zip(full[0], cut[0], full[1], cut[1]):
+        assert int(a["n_gathered"]) == int(b["n_gathered"])
+        assert np.array_equal(gb, ga[:4])
