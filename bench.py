@@ -229,6 +229,8 @@ def main():
     ap.add_argument("--refine", action="store_true",
                     help="also time Steps 4-6 (FAST-MCD refine, gather, iterate) over the "
                          "clusters of the greedy extraction (implies --extract)")
+    ap.add_argument("--refine-starts", type=int, default=500,
+                    help="random starts of FAST-MCD per fit (at most 1024)")
     ap.add_argument("--weighted", choices=["epochs", "detections"], default=None,
                     help="also time the weighted vote of the same catalog (likelihood weights "
                          "of the detections' SNR, threshold N_min x the mean weight)")
@@ -336,7 +338,7 @@ def main():
             order = np.argsort(owner, kind="stable")
             own = owner[order]
             groups = [order[own == k] for k in range(len(clusters))]
-            starts = synth.mcd_starts(7, 500)
+            starts = synth.mcd_starts(7, args.refine_starts)
             ref = []
             for k in range(args.warmup + args.steps):
                 torch.cuda.synchronize()
@@ -349,7 +351,7 @@ def main():
             rec["refine"] = {"ms": float(np.mean(ref)), "n_clusters": len(groups),
                              "points": int(sum(len(g) for g in groups)),
                              "rounds_mean": float(recs["rounds"].mean()) if len(recs) else 0.0,
-                             "status": st, "starts": 500}
+                             "status": st, "starts": args.refine_starts}
     if args.weighted:
         rec["weighted"] = time_weighted(args, wl, v, count_sat)
     if not args.no_cpu_baseline:
