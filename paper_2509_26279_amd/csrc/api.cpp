@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "peaks_sort.h"
 
 namespace sas {
 
@@ -961,19 +962,7 @@ sas_status sas_peaks(const sas_candidate *cand_dev, const sas_vote_result *res_d
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "sas_peaks: copying candidates");
     }
-    auto canon = [](const sas_candidate &a, const sas_candidate &b) {
-        if (a.v_idx != b.v_idx) return a.v_idx < b.v_idx;
-        if (a.by != b.by) return a.by < b.by;
-        return a.bx < b.bx;
-    };
-    if (order == SAS_ORDER_CANONICAL) {
-        std::sort(c.begin(), c.end(), canon);
-    } else {
-        std::sort(c.begin(), c.end(), [&](const sas_candidate &a, const sas_candidate &b) {
-            if (a.count != b.count) return a.count > b.count;
-            return canon(a, b);
-        });
-    }
+    sort_candidates(c, order == SAS_ORDER_BY_COUNT);
     const int64_t k = top_k > 0 ? std::min<int64_t>(top_k, (int64_t)c.size()) : (int64_t)c.size();
     if (k > out_cap || (k > 0 && !out_host)) {
         *n_out = k;

@@ -306,12 +306,15 @@ def vote(plan: Plan, x, y, epoch, cand, res, workspace, stream=None, weight=None
                                         workspace.data_ptr(), ws, _stream_handle(stream)))
 
 
-def peaks(cand, res, order="canonical", top_k=0, stream=None):
-    """Synchronise and return the candidates as a CAND_DTYPE array."""
+def peaks(cand, res, order="canonical", top_k=0, stream=None, out=None):
+    """Synchronise and return the candidates as a CAND_DTYPE array.  out: an
+    optional host CAND_DTYPE array of at least the buffer's capacity, used
+    as the landing area (kept by Search across calls)."""
     lib = load()
     cap = cand.numel() * cand.element_size() // 16
     n = ctypes.c_int64()
-    out = np.zeros(max(cap, 1), dtype=CAND_DTYPE)
+    if out is None or out.dtype != CAND_DTYPE or out.shape[0] < max(cap, 1):
+        out = np.empty(max(cap, 1), dtype=CAND_DTYPE)
     _check(lib.sas_peaks(cand.data_ptr(), res.data_ptr(), cap, ORDERS[order], int(top_k),
                          out.ctypes.data, out.shape[0], ctypes.byref(n), _stream_handle(stream)))
     return out[:n.value].copy()
@@ -336,6 +339,7 @@ class Search:
                               device=device)
         self.cand = torch.empty((max(int(cand_cap), 1), 4), dtype=torch.int32, device=device)
         self.res = torch.zeros(4, dtype=torch.int32, device=device)
+        self._out = None  # host landing array of peaks()
 
     def upload(self, x_q8, y_q8, epoch, weight=None):
         """Device copies of a catalog (and of its weights, when given)."""
@@ -359,7 +363,9 @@ class Search:
         vote(self.plan, x, y, e, self.cand, self.res, self.ws, stream, weight=w)
 
     def peaks(self, order="canonical", top_k=0, stream=None):
-        return peaks(self.cand, self.res, order, top_k, stream)
+        if self._out is None:
+            self._out = np.empty(self.cand.shape[0], dtype=CAND_DTYPE)
+        return peaks(self.cand, self.res, order, top_k, stream, out=self._out)
 
     def result(self) -> dict:
         """The device-side vote result (synchronises): n_cand, status, n_spilled."""
