@@ -114,6 +114,7 @@ struct sas_plan {
     int32_t tile_x = 16, tile_y = 16, vbx = 8, vby = 8, groups = 1, cell_log2 = 11;
     int32_t coarse_log2 = 0, hx = 0, hy = 0, stage_cap = 0, rows = 0, rows_log2 = 0;
     int32_t packed = 0;  // packed 16-bit votes
+    int32_t halves = 0;  // 16-bit histogram counts, two histograms by tile
     int32_t ncx = 1, ncy = 1;
     int64_t n_cells = 0, n_items = 0, n_segments = 0, n_tiles = 0, refine_cap = 0;
     size_t lds_bytes = 0;
@@ -230,6 +231,7 @@ DenseArgs dense_args(const sas_plan *p, const WsLayout &L, char *w, const PrepBu
     a.rows = p->rows;
     a.rows_log2 = p->rows_log2;
     a.packed = p->packed;
+    a.halves = p->halves;
     a.n_min = p->n_min;
     a.count_sat = p->count_sat;
     a.mode_epochs = p->mode == SAS_MODE_EPOCHS ? 1 : 0;
@@ -324,6 +326,8 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     if (tu.refine_cap < 0) return fail(SAS_E_INVALID, "sas_plan_create: refine_cap must be >= 0");
     if (tu.weight_hint < 0 || tu.weight_hint > 255)
         return fail(SAS_E_INVALID, "sas_plan_create: weight_hint must be in [0, 255]");
+    if (tu.half_counts < -1 || tu.half_counts > 1)
+        return fail(SAS_E_INVALID, "sas_plan_create: half_counts must be -1, 0 or 1");
     if (tu.tile_x < 0 || tu.tile_y < 0 || tu.stage_cap < 0 || tu.vblock_x < 0 || tu.vblock_y < 0)
         return fail(SAS_E_INVALID, "sas_plan_create: negative tuning value");
 
@@ -427,7 +431,7 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     auto ceil_cells = [&](int64_t q8) -> int64_t { return (q8 + cellw - 1) >> kc; };
     std::vector<int32_t> seg, seg_v, seg_vel, seg_guard;
     std::vector<int64_t> seg_ky;  // velocity-block row of each segment
-    int64_t guard_x = 0, guard_y = 0, spread_y_max = 0;
+    int64_t guard_x = 0, guard_y = 0, spread_y_max = 0, spread_x_max = 0;
     double spread_x_sum = 0, spread_y_sum = 0;
     {
         int64_t i = 0;
@@ -448,6 +452,7 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
             spread_x_sum += (double)spread_q8((int64_t)vx_hi - vx_lo);
             spread_y_sum += (double)spread_q8((int64_t)vy_hi - vy_lo);
             spread_y_max = std::max(spread_y_max, spread_q8((int64_t)vy_hi - vy_lo));
+            spread_x_max = std::max(spread_x_max, spread_q8((int64_t)vx_hi - vx_lo));
             for (int l = 0; l < NV; ++l) {
                 const bool used = i + l < k;
                 const int32_t u = used ? V[2 * order[i + l]] : vx_lo;
@@ -608,6 +613,24 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
                                   : std::min<int64_t>((int64_t)1 << 26,
                                                       std::max<int64_t>((int64_t)1 << 22,
                                                                         (int64_t)(16 * expected_flags)));
+    // 16-bit histogram counts (lanes j and j + 32 of one word, two histograms
+    // alternating by tile): a count never exceeds the window entries of its
+    // tile, which the kernel checks against 2^16.  The automatic choice wants
+    // the expected entries of a tile (the window grown by the largest block
+    // spread and one index cell on each axis) at 2^13 or fewer.
+    const bool counts = p->dense_mode == kCountDet || p->dense_mode == kCountRef;
+    if (tu.half_counts == 1) {
+        if (G != 1 || !counts || p->path != SAS_PATH_DENSE)
+            return fail(SAS_E_INVALID, "sas_plan_create: half_counts = 1 needs the dense path, "
+                                       "groups = 1 and a counting mode (detections, or coarse "
+                                       "cells)");
+        p->halves = 1;
+    } else if (tu.half_counts == 0 && G == 1 && counts && p->path == SAS_PATH_DENSE &&
+               tu.n_det_hint > 0) {
+        const double wx = (double)TX * cellw + (double)spread_x_max + (double)((int64_t)1 << cl);
+        const double wy = (double)TY * cellw + (double)spread_y_max + (double)((int64_t)1 << cl);
+        p->halves = (double)tu.n_det_hint * wx * wy / std::max(area, 1.0) <= 8192.0 ? 1 : 0;
+    }
     p->tile_x = TX;
     p->tile_y = TY;
     p->vbx = vbx;
@@ -810,6 +833,7 @@ sas_status sas_plan_get_info(const sas_plan *p, sas_plan_info *info) {
     info->stage_cap = p->stage_cap;
     info->lds_bytes = (int32_t)p->lds_bytes;
     info->packed = p->packed;
+    info->half_counts = p->halves;
     return SAS_OK;
 }
 
@@ -946,6 +970,10 @@ sas_status sas_peaks(const sas_candidate *cand_dev, const sas_vote_result *res_d
     if (r.status & SAS_DATA_INTERNAL)
         return fail(SAS_E_DEVICE, "sas_peaks: internal error: a tile window exceeded the plan's "
                                   "run table or guard cells");
+    if (r.status & SAS_DATA_COUNT_RANGE)
+        return fail(SAS_E_OVERFLOW, "sas_peaks: a tile held 2^16 or more window entries for the "
+                                    "plan's 16-bit histogram counts; plan again with "
+                                    "tuning.half_counts = -1");
     if (r.status & SAS_DATA_REFINE_FULL)
         return fail(SAS_E_OVERFLOW, "sas_peaks: more flagged histogram cells than the plan's "
                                     "refinement list holds; raise tuning.refine_cap or use "

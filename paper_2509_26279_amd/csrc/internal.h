@@ -49,6 +49,8 @@ struct DenseArgs {
     int32_t rows;             // index rows a tile window can touch (planner bound)
     int32_t rows_log2;        // run rows per epoch: 2^rows_log2 >= rows
     int32_t packed;           // 1: packed 16-bit votes (stage entries of 4 bytes)
+    int32_t halves;           // 1: 16-bit counts, lanes j and j + 32 share a word; two
+                              //    histograms of hx * hy * 32 words alternate by tile
     int32_t n_min, count_sat;
     int32_t mode_epochs;      // 1: count distinct epochs, 0: count detections
     int32_t weighted;         // 0, or SAS_MODE_WEIGHTED_EPOCHS / _DETECTIONS

@@ -53,7 +53,8 @@ constexpr int NW = T / 64;
 struct Shared {
     int32_t dt[kMaxEpochs];
     int32_t es[4][kMaxEpochs];  // per epoch: S(vx_lo), S(vx_hi), S(vy_lo), S(vy_hi) of the segment
-    int32_t voted[3];           // tile t % 3 has staged detections (set before it is voted)
+    int32_t voted[4];           // window entries staged for tile t % 4 (all waves; summed
+                                // before the tile is voted)
     int32_t sv[64];             // segment: v_idx of each velocity lane (-1: unused)
     int32_t svx[64], svy[64];   // segment: velocity of each lane
     int32_t sg[64];             // segment: left guard cells of each lane, gx | gy << 16
@@ -349,7 +350,14 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
     const int32_t cellw = (int32_t)1 << kc;
     const int32_t W = a.tile_x << kc, H = a.tile_y << kc;  // tile size, Q8
     const uint32_t nmin = (uint32_t)a.n_min;
-    const uint32_t row_bytes = (uint32_t)(a.hx * NV * 4);
+    // 16-bit counts (G = 1, counting modes): velocity lanes j and j + 32 add
+    // 1 and 2^16 to one word of a bin's 32, and tiles alternate between two
+    // histograms of hist_words / 2 words (block uniform)
+    constexpr bool kHalvesOk = G == 1 && (MODE == kCountDet || MODE == kCountRef);
+    const bool hv = kHalvesOk && a.halves != 0;
+    const int NC = hv ? 32 : NV;  // words per bin
+    const uint32_t row_bytes = (uint32_t)(a.hx * NC * 4);
+    const uint32_t cval = hv && j >= 32 ? 65536u : 1u;
     const int LR = a.rows_log2;  // run rows per epoch: 2^LR
     const int32_t vx_lo = a.seg[4 * sg], vx_hi = a.seg[4 * sg + 1];
     const int32_t vy_lo = a.seg[4 * sg + 2], vy_hi = a.seg[4 * sg + 3];
@@ -375,7 +383,9 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
     const int32_t oy = ty0 * cellw;
     // Q8 origin of this lane's histogram row 0: (ty0 - gy) cells
     const uint32_t oy_lane = (uint32_t)(ty0 - my_gy) * (uint32_t)cellw;
-    const uint32_t lane_addr = (uint32_t)(uintptr_t)(lds_u32 *)hist + (uint32_t)(j * 4);
+    const uint32_t lane_addr0 =
+        (uint32_t)(uintptr_t)(lds_u32 *)hist + (uint32_t)((hv ? (j & 31) : j) * 4);
+    uint32_t lane_addr = lane_addr0;  // the current tile's histogram
 
     // Lane shifts of this wave's epochs e = wave + k NW (k < ER), kept in
     // registers for the whole item with the Q8 origin of the lane's
@@ -423,13 +433,13 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         return;
     }
     const us2 kcv = {(unsigned short)kc, (unsigned short)kc};
-    const us2 wts = {(unsigned short)(NV * 4), (unsigned short)row_bytes};
+    const us2 wts = {(unsigned short)(NC * 4), (unsigned short)row_bytes};
     // vote address of lane shift (sx, sy) (full Q8 values; packed: low bits)
     const auto vote_addr = [&](int32_t sx, int32_t sy) __attribute__((always_inline)) {
         if constexpr (PK) {
             return VoteAddr16{__builtin_bit_cast(us2, (uint32_t)sx), kcv, wts, lane_addr};
         } else {
-            return VA{(uint32_t)sx, (uint32_t)sy, row_bytes, lane_addr, kc, LNV + 2};
+            return VA{(uint32_t)sx, (uint32_t)sy, row_bytes, lane_addr, kc, hv ? 7 : LNV + 2};
         }
     };
 
@@ -527,7 +537,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
     runs(txf * cellw);
     if (Mw > 0) {
         stage_chunk(txf * cellw, 0);
-        if (lane == 0) sh.voted[tseq % 3] = 1;
+        if (lane == 0) atomicAdd(&sh.voted[tseq & 3], Mw);
     }
     for (int32_t ti = 0; ti < ntiles; ++ti, ++tseq) {
         const int32_t tx0 = txf + ti * a.tile_x;
@@ -535,6 +545,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         const uint32_t ox_lane = (uint32_t)(tx0 - my_gx) * (uint32_t)cellw;
         const bool next = ti + 1 < ntiles;  // block uniform
         const int32_t oxn = ox + a.tile_x * cellw;
+        if (hv) lane_addr = lane_addr0 + (uint32_t)(tseq & 1) * (uint32_t)(hist_words * 2);
 
         // 2. vote this wave's entries, chunk by chunk (the first is staged)
         if (Mw > wcap && lane == 0) atomicAdd(&a.res->n_spilled, 1);
@@ -548,7 +559,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                 if (n == 0) continue;
                 const int32_t b = __builtin_amdgcn_readlane(my_b, k);
                 vote_run<MODE, G>(wst + b, n, vote_addr(Sx[k], Sy[PK ? 0 : k]),
-                                  MODE == kMask32 ? (1u << e) : 1u, g);
+                                  MODE == kMask32 ? (1u << e) : cval, g);
             }
             for (int k = ER; wave + k * NW < E; ++k) {
                 const int e = wave + k * NW;
@@ -562,7 +573,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                                     : WT ? (int32_t)((uint32_t)sx << 8)
                                          : sx;
                 vote_run<MODE, G>(wst + b, n, vote_addr(sxv, sy),
-                                  MODE == kMask32 ? (1u << e) : 1u, g);
+                                  MODE == kMask32 ? (1u << e) : cval, g);
             }
             __builtin_amdgcn_wave_barrier();  // the stage is read before it is refilled
         }
@@ -571,60 +582,85 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
             runs(oxn);
             if (Mw > 0) {
                 stage_chunk(oxn, 0);
-                if (lane == 0) sh.voted[(tseq + 1) % 3] = 1;
+                if (lane == 0) atomicAdd(&sh.voted[(tseq + 1) & 3], Mw);
             }
         }
         __syncthreads();  // every vote of this tile is in the histogram
-        // The flag of tile t is set after the barrier that ends tile t - 2 and
-        // read between the two barriers of tile t; it is cleared here for
-        // tile t + 2, whose flag was last read before this tile's first barrier.
-        const bool any = sh.voted[tseq % 3] != 0;  // block uniform
-        if (tid == 0) sh.voted[(tseq + 2) % 3] = 0;
+        // The total of tile t is summed before the barrier that ends tile t - 1
+        // and read after the one that ends tile t; slot t + 3 (last read after
+        // the barrier ending tile t - 1, next summed after the one ending tile
+        // t + 1) is cleared here.  With one barrier per tile (16-bit counts)
+        // this tile's read-out overlaps other waves' votes of tile t + 1 and
+        // the summing of tile t + 2, which use the other slots.
+        const int32_t staged = sh.voted[tseq & 3];  // block uniform
+        const bool any = staged != 0;
+        if (tid == 0) {
+            sh.voted[(tseq + 3) & 3] = 0;
+            // a 16-bit count is at most the tile's window entries
+            if (hv && staged >= 65536) atomicOr(&a.res->status, SAS_DATA_COUNT_RANGE);
+        }
 
         // 3. read and clear the histogram; emit or queue interior cells
         if (any) {
-            for (int w0 = 0; w0 < hist_words / 4; w0 += T) {
+            const int rw = hv ? hist_words / 2 : hist_words;  // words of this tile's histogram
+            uint4 *hb = smem4 + (hv ? (tseq & 1) * (hist_words / 8) : 0);
+            // count cnt of lane jj's velocity in bin `bin` (all lanes call)
+            const auto emit = [&](uint32_t cnt, int jj, int bin) __attribute__((always_inline)) {
+                bool ok = false;
+                uint32_t v = 0;
+                int32_t bx = 0, by = 0;
+                if (cnt >= nmin) {
+                    const int iy = bin / a.hx, ix = bin - iy * a.hx;
+                    const int cx = ix - (sh.sg[jj] & 0xffff), cy = iy - (sh.sg[jj] >> 16);
+                    ok = sh.sv[jj] >= 0 && cx >= 0 && cx < a.tile_x && cy >= 0 && cy < a.tile_y;
+                    v = (uint32_t)sh.sv[jj];
+                    bx = tx0 + cx;
+                    by = ty0 + cy;
+                }
+                if (refined_mode<MODE>()) {
+                    const int64_t idx = wave_append(ok, a.refine_count);
+                    if (ok && idx < a.refine_cap) a.refine[idx] = make_int4((int32_t)v, bx, by, 0);
+                } else {
+                    const int64_t idx = wave_append(ok, (unsigned long long *)&a.res->n_cand);
+                    if (ok && idx < a.cand_cap)
+                        write_cand(a.cand, idx, v, bx, by, cnt, (uint32_t)a.count_sat);
+                }
+            };
+            for (int w0 = 0; w0 < rw / 4; w0 += T) {
                 const int w4 = w0 + tid;
                 uint4 h = make_uint4(0, 0, 0, 0);
-                if (w4 < hist_words / 4) {
-                    h = smem4[w4];
-                    smem4[w4] = make_uint4(0, 0, 0, 0);
+                if (w4 < rw / 4) {
+                    h = hb[w4];
+                    hb[w4] = make_uint4(0, 0, 0, 0);
                 }
-                const uint32_t m = max(max(cell_count<MODE>(h.x), cell_count<MODE>(h.y)),
-                                       max(cell_count<MODE>(h.z), cell_count<MODE>(h.w)));
-                if (!__any(m >= nmin)) continue;  // wave uniform
                 const uint32_t hw[4] = {h.x, h.y, h.z, h.w};
+                if (hv) {  // word wi: bin wi / 32, velocity lanes wi % 32 (low), + 32 (high)
+                    uint32_t m = 0;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int wi = 4 * w4 + k;
-                    const uint32_t cnt = cell_count<MODE>(hw[k]);
-                    bool ok = false;
-                    uint32_t v = 0;
-                    int32_t bx = 0, by = 0;
-                    if (cnt >= nmin) {
-                        const int jj = wi & (NV - 1), bin = wi >> LNV;
-                        const int iy = bin / a.hx, ix = bin - iy * a.hx;
-                        const int cx = ix - (sh.sg[jj] & 0xffff), cy = iy - (sh.sg[jj] >> 16);
-                        ok = sh.sv[jj] >= 0 && cx >= 0 && cx < a.tile_x && cy >= 0 &&
-                             cy < a.tile_y;
-                        v = (uint32_t)sh.sv[jj];
-                        bx = tx0 + cx;
-                        by = ty0 + cy;
+                    for (int k = 0; k < 4; ++k) m = max(m, max(hw[k] & 0xffffu, hw[k] >> 16));
+                    if (!__any(m >= nmin)) continue;  // wave uniform
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int wi = 4 * w4 + k;
+                        emit(hw[k] & 0xffffu, wi & 31, wi >> 5);
+                        emit(hw[k] >> 16, (wi & 31) + 32, wi >> 5);
                     }
-                    if (refined_mode<MODE>()) {
-                        const int64_t idx = wave_append(ok, a.refine_count);
-                        if (ok && idx < a.refine_cap)
-                            a.refine[idx] = make_int4((int32_t)v, bx, by, 0);
-                    } else {
-                        const int64_t idx =
-                            wave_append(ok, (unsigned long long *)&a.res->n_cand);
-                        if (ok && idx < a.cand_cap)
-                            write_cand(a.cand, idx, v, bx, by, cnt, (uint32_t)a.count_sat);
+                } else {
+                    const uint32_t m = max(max(cell_count<MODE>(h.x), cell_count<MODE>(h.y)),
+                                           max(cell_count<MODE>(h.z), cell_count<MODE>(h.w)));
+                    if (!__any(m >= nmin)) continue;  // wave uniform
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int wi = 4 * w4 + k;
+                        emit(cell_count<MODE>(hw[k]), wi & (NV - 1), wi >> LNV);
                     }
                 }
             }
         }
-        __syncthreads();  // the histogram is clear before the next tile's votes
+        // the histogram is clear before the next tile's votes; with 16-bit
+        // counts the next tile votes into the other histogram, cleared before
+        // this tile's barrier
+        if (!hv) __syncthreads();
 #pragma unroll
         for (int k = 0; k < ER; ++k) {
             if constexpr (PK) {  // low half only, modulo 2^16
@@ -648,7 +684,7 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
     for (int i = tid; i < hist_words / 4; i += T) smem4[i] = make_uint4(0, 0, 0, 0);
     if (tid < a.cat.n_epochs) sh.dt[tid] = a.cat.dt[tid];
     int32_t tseq = 0;  // tiles done by this workgroup (flag ring of sh.voted)
-    if (tid < 3) sh.voted[tid] = 0;
+    if (tid < 4) sh.voted[tid] = 0;
     // Workgroups are dispatched round-robin over the XCDs (each with its own
     // L2); give XCD x the logical indices [x G / 8, (x + 1) G / 8) so that the
     // workgroups resident on one XCD take neighbouring items.
@@ -676,7 +712,7 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
     const int tid = threadIdx.x;
     for (int i = tid; i < hist_words_max / 4; i += T) smem4[i] = make_uint4(0, 0, 0, 0);
     int32_t tseq = 0, chip_now = -1;  // tseq: tiles done by this workgroup
-    if (tid < 3) sh.voted[tid] = 0;
+    if (tid < 4) sh.voted[tid] = 0;
     const int64_t grid = gridDim.x;  // a multiple of kXcds
     const int64_t logical = (int64_t)(blockIdx.x % kXcds) * (grid / kXcds) + blockIdx.x / kXcds;
     for (int64_t item = logical; item < n_items; item += grid) {

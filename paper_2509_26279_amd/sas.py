@@ -60,7 +60,7 @@ class Tuning(ctypes.Structure):
                 ("cell_log2", ctypes.c_int32), ("sort_vblock", ctypes.c_int32),
                 ("n_det_hint", ctypes.c_int32), ("coarse_log2", ctypes.c_int32),
                 ("refine_cap", ctypes.c_int32), ("packed", ctypes.c_int32),
-                ("weight_hint", ctypes.c_int32)]
+                ("weight_hint", ctypes.c_int32), ("half_counts", ctypes.c_int32)]
 
 
 class BatchChip(ctypes.Structure):
@@ -87,7 +87,8 @@ class PlanInfo(ctypes.Structure):
                 ("mode_variant", ctypes.c_int32), ("n_v", ctypes.c_int64),
                 ("groups", ctypes.c_int32), ("hist_x", ctypes.c_int32),
                 ("hist_y", ctypes.c_int32), ("stage_cap", ctypes.c_int32),
-                ("lds_bytes", ctypes.c_int32), ("packed", ctypes.c_int32)]
+                ("lds_bytes", ctypes.c_int32), ("packed", ctypes.c_int32),
+                ("half_counts", ctypes.c_int32)]
 
 
 _lib = None
@@ -231,10 +232,11 @@ class Plan:
         self._t = np.ascontiguousarray(t_q16, dtype=np.int64)
         self._tuning = None
         if tuning is not None:
-            self._tuning = Tuning(*[int(tuning.get(k, 0)) for k in
-                                    ("tile_x", "tile_y", "vblock_x", "vblock_y", "groups",
-                                     "stage_cap", "cell_log2", "sort_vblock", "n_det_hint",
-                                     "coarse_log2", "refine_cap", "packed", "weight_hint")])
+            keys = [k for k, _ in Tuning._fields_]
+            unknown = sorted(set(tuning) - set(keys))
+            if unknown:
+                raise ValueError("unknown tuning keys: %s" % ", ".join(unknown))
+            self._tuning = Tuning(*[int(tuning.get(k, 0)) for k in keys])
         desc = PlanDesc(self._v.ctypes.data, self._v.shape[0], self._t.shape[0],
                         self._t.ctypes.data, int(binw_q8), int(n_min), MODES[mode],
                         int(count_sat), PATHS[path], (ctypes.c_int32 * 4)(*map(int, extent_q8)),

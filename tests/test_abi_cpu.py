@@ -95,6 +95,8 @@ def _plan_error(**over):
      sas.SAS_E_UNSUPPORTED),
     (dict(mode="weighted_epochs", path="sort"), sas.SAS_E_UNSUPPORTED),
     (dict(mode="weighted_detections", path="sort"), sas.SAS_E_UNSUPPORTED),
+    (dict(tuning=dict(half_counts=2)), sas.SAS_E_INVALID),
+    (dict(tuning=dict(half_counts=-2)), sas.SAS_E_INVALID),
 ])
 def test_plan_argument_errors(over, status):
     assert _plan_error(**over) == status
@@ -158,3 +160,9 @@ def test_refine_extract_weighted_argument_errors():
                                  None) == sas.SAS_E_INVALID
     assert lib.sas_extract_clusters(None, None, 0, 0, None, 0, 0, None, 0, None, 0, None, None,
                                     0, None) == sas.SAS_E_INVALID
+
+
+def test_unknown_tuning_key_rejected():
+    with pytest.raises(ValueError):
+        sas.Plan(np.zeros((1, 2), np.int32), np.arange(4) * 1000, 1024, 2, (0, 4096, 0, 4096),
+                 tuning=dict(half_count=1))

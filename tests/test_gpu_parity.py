@@ -82,10 +82,26 @@ def test_random_adversarial(gpu, seed, mode):
                     dict(tile_x=5, tile_y=3, stage_cap=40, groups=4),
                     dict(tile_x=7, tile_y=9, stage_cap=16, groups=1, vblock_x=5, vblock_y=7),
                     dict(packed=-1), dict(tile_x=5, tile_y=3, stage_cap=40, groups=2, packed=-1),
-                    dict(coarse_log2=2, groups=1, packed=-1)):
+                    dict(coarse_log2=2, groups=1, packed=-1)) + _half_count_tunings(mode):
             g = gpu_vote(d["x_q8"], d["y_q8"], d["epoch"], d["t_q16"], d["v_q8"], d["binw_q8"],
                          n_min, mode, tuning=tun)
             assert_same(g, o)
+
+
+def _half_count_tunings(mode):
+    """16-bit histogram counts forced on: coarse cells (any mode), exact
+    detection counts, small tiles (many tiles per item, so both histograms
+    and every slot of the staged-entry ring are used), small stages
+    (chunks) and the 32-bit vote form."""
+    out = (dict(coarse_log2=2, groups=1, half_counts=1),
+           dict(coarse_log2=1, tile_x=2, tile_y=2, vblock_x=8, vblock_y=8, groups=1, half_counts=1),
+           dict(coarse_log2=1, tile_x=7, tile_y=9, stage_cap=16, groups=1, vblock_x=5,
+                vblock_y=7, half_counts=1),
+           dict(coarse_log2=2, groups=1, packed=-1, half_counts=1))
+    if mode == "detections":
+        out += (dict(coarse_log2=-1, groups=1, half_counts=1),
+                dict(coarse_log2=-1, tile_x=3, tile_y=2, groups=1, half_counts=1, packed=-1))
+    return out
 
 
 @pytest.mark.parametrize("n_epochs,mode", [(20, "epochs"), (100, "epochs"), (100, "detections")])
@@ -102,12 +118,76 @@ def test_overfull_window_is_chunked(gpu, n_epochs, mode):
     for n_min in (1, 15, 60):
         _say(f"chunked E={n_epochs} mode={mode} n_min={n_min}")
         o = oracle.vote(x, y, e, t, v, 1024, n_min, mode)
-        plan = sas.Plan(v, t, 1024, n_min, ext, mode=mode, tuning=dict(stage_cap=1024))
-        srch = sas.Search(plan, len(x), cand_cap=1 << 18)
-        g = srch.run(x, y, e)
-        assert srch.result()["n_spilled"] > 0  # the chunked path did run
+        for tun in (dict(stage_cap=1024), dict(stage_cap=1024, groups=1, half_counts=1)):
+            if tun.get("half_counts") and mode == "epochs" and n_epochs <= 32:
+                tun = dict(tun, coarse_log2=1)  # epoch masks have no 16-bit form
+            plan = sas.Plan(v, t, 1024, n_min, ext, mode=mode, tuning=tun)
+            srch = sas.Search(plan, len(x), cand_cap=1 << 18)
+            g = srch.run(x, y, e)
+            assert srch.result()["n_spilled"] > 0  # the chunked path did run
+            assert plan.info()["half_counts"] == tun.get("half_counts", 0)
+            plan.close()
+            assert_same(g, o)
+
+
+def test_half_counts_choice_and_errors(gpu):
+    """The automatic choice takes 16-bit counts for the wide workload's plan
+    (n_det_hint given) and not without the hint; forcing them where they do
+    not apply is an argument error."""
+    wl = synth.make_wide()
+    v = _grid(wl)[:2000]
+
+    def half_of(tun, t=wl.t_q16, path="auto"):
+        p = sas.Plan(v, t, wl.binw_q8, wl.n_min, wl.extent_q8, tuning=tun, path=path)
+        try:
+            return p.info()["half_counts"]
+        finally:
+            p.close()
+
+    assert half_of(dict(n_det_hint=wl.n)) == 1
+    assert half_of(dict(n_det_hint=wl.n, half_counts=-1)) == 0
+    assert half_of(dict(coarse_log2=2)) == 0
+    # 100 epochs without coarse cells: counts refined into exact bins
+    assert half_of(dict(groups=1, coarse_log2=-1, half_counts=1)) == 1
+    for tun, t, path in ((dict(groups=2, coarse_log2=2, half_counts=1), wl.t_q16, "auto"),
+                         # 20 epochs, single bins: epoch masks, no 16-bit form
+                         (dict(groups=1, coarse_log2=-1, half_counts=1), wl.t_q16[:20], "auto"),
+                         (dict(groups=1, coarse_log2=2, half_counts=1), wl.t_q16, "sort"),
+                         (dict(half_counts=2), wl.t_q16, "auto")):
+        with pytest.raises(sas.SasError):
+            half_of(tun, t, path)
+
+
+def test_half_counts_range_reported(gpu):
+    """A tile whose windows hold 2^16 or more detections cannot use 16-bit
+    counts: the vote reports it and sas_peaks refuses; the same plan with
+    32-bit counts matches the oracle."""
+    rng = np.random.default_rng(11)
+    n = 70000
+    # a 16 px square at (20, 20) px: inside the first tile of every tile row
+    x = (rng.integers(0, 16 * 256, n) + 20 * 256).astype(np.int32)
+    y = (rng.integers(0, 16 * 256, n) + 20 * 256).astype(np.int32)
+    e = rng.integers(0, 4, n).astype(np.uint8)
+    t = np.arange(4, dtype=np.int64) * 4000
+    v = np.array([[i * 256, j * 256] for j in range(-1, 2) for i in range(-1, 2)], np.int32)
+    ext = (0, 128 * 256, 0, 128 * 256)
+    n_min = 300
+    for hc in (1, -1):
+        _say(f"count range half_counts={hc}")
+        plan = sas.Plan(v, t, 1024, n_min, ext, mode="detections",
+                        tuning=dict(groups=1, coarse_log2=-1, half_counts=hc))
+        srch = sas.Search(plan, n, cand_cap=1 << 16)
+        x_d, y_d, e_d = srch.upload(x, y, e)
+        srch.vote(x_d, y_d, e_d)
+        status = srch.result()["status"]
+        if hc == 1:
+            assert status & 16  # SAS_DATA_COUNT_RANGE
+            with pytest.raises(sas.SasError):
+                srch.peaks()
+        else:
+            assert status == 0
+            assert_same(srch.peaks(), oracle.vote(x, y, e, t, v, 1024, n_min, "detections"))
         plan.close()
-        assert_same(g, o)
 
 
 # ---------------------------------------------------------------- full size, sampled
