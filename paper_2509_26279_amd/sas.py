@@ -45,6 +45,17 @@ class SasError(RuntimeError):
         self.status = status
 
 
+# bits of the vote result's status, with the error sas_peaks returns for each
+_DATA_ERRORS = ((1, SAS_E_INVALID, "the catalog holds an epoch index >= n_epochs"),
+                (2, SAS_E_INVALID, "a detection lies outside the plan's footprint"),
+                (8, SAS_E_DEVICE, "internal error: a tile window exceeded the plan's run table "
+                                  "or guard cells"),
+                (16, SAS_E_OVERFLOW, "a tile held 2^16 or more window entries for the plan's "
+                                     "16-bit histogram counts; plan again with half_counts=-1"),
+                (4, SAS_E_OVERFLOW, "more flagged histogram cells than the plan's refinement "
+                                    "list holds"))
+
+
 class GridSpec(ctypes.Structure):
     _fields_ = [("shape", ctypes.c_int32), ("vmin", ctypes.c_double), ("vmax", ctypes.c_double),
                 ("vy_min", ctypes.c_double), ("vy_max", ctypes.c_double),
@@ -369,6 +380,19 @@ class Search:
             self._out = np.empty(self.cand.shape[0], dtype=CAND_DTYPE)
         return peaks(self.cand, self.res, order, top_k, stream, out=self._out)
 
+    def _complete_vote(self) -> int:
+        """Number of candidates of the last vote, after the checks sas_peaks
+        makes: data errors in its status, and more candidates than the buffer
+        holds, raise SasError."""
+        r = self.result()
+        for bit, code, msg in _DATA_ERRORS:
+            if r["status"] & bit:
+                raise SasError(code, "the last vote: " + msg)
+        if r["n_cand"] > self.cand.shape[0]:
+            raise SasError(SAS_E_OVERFLOW, "the last vote found %d candidates, more than the "
+                                           "buffer's %d" % (r["n_cand"], self.cand.shape[0]))
+        return r["n_cand"]
+
     def result(self) -> dict:
         """The device-side vote result (synchronises): n_cand, status, n_spilled."""
         r = self.res.cpu().numpy().view(np.int32)
@@ -384,8 +408,7 @@ class Search:
         finish (0 default, -1 none).  Synchronises; grows member_cap once if
         the contributor lists did not fit."""
         import torch
-        r = self.result()
-        k = min(r["n_cand"], self.cand.shape[0])
+        k = self._complete_vote()
         dev = self.cand.device
         member_cap = int(member_cap or 64 * k + int(n))
         cluster_cap = int(cluster_cap or max(k, 1))
@@ -423,8 +446,7 @@ class Search:
         spacing_q8: the velocity grid's lattice spacing (0: no neighbour
         features)."""
         import torch
-        r = self.result()
-        k = min(r["n_cand"], self.cand.shape[0])
+        k = self._complete_vote()
         feat = torch.empty((max(k, 1), N_FEATURES), dtype=torch.float32, device=self.cand.device)
         nb = features_scratch_size(k) if spacing_q8 else 0
         scratch = torch.empty(max(nb, 1), dtype=torch.uint8, device=self.cand.device)

@@ -118,6 +118,32 @@ def test_extract_nothing_to_take(gpu):
     assert len(clusters) == 0 and np.all(owner == -1)
 
 
+def test_extract_refuses_a_failed_vote(gpu):
+    """Extraction and features run only on a complete candidate list: a
+    catalog error or an overfull candidate buffer from the vote is raised,
+    as sas_peaks would."""
+    wl = synth.make_tiny()
+    v = _grid(wl)
+    plan = sas.Plan(v, wl.t_q16, wl.binw_q8, 5, wl.extent_q8)
+    try:
+        s = sas.Search(plan, wl.n, cand_cap=1 << 16)
+        x = wl.x_q8.copy()
+        x[3] = wl.extent_q8[1] + 4096  # outside the footprint
+        s.vote(*s.upload(x, wl.y_q8, wl.epoch))
+        for call in (lambda: s.extract(wl.n), lambda: s.features(wl.n)):
+            with pytest.raises(sas.SasError) as ei:
+                call()
+            assert ei.value.status == sas.SAS_E_INVALID
+        small = sas.Search(plan, wl.n, cand_cap=2)
+        small.vote(*small.upload(wl.x_q8, wl.y_q8, wl.epoch))
+        assert small.result()["n_cand"] > 2
+        with pytest.raises(sas.SasError) as ei:
+            small.extract(wl.n)
+        assert ei.value.status == sas.SAS_E_OVERFLOW
+    finally:
+        plan.close()
+
+
 def test_extract_cluster_capacity_reported(gpu):
     """Fewer output slots than clusters: the call reports the true number
     (SAS_EXTRACT_CLUSTERS_FULL) and the binding raises with it."""
