@@ -587,8 +587,9 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         }
         __syncthreads();  // every vote of this tile is in the histogram
         // The total of tile t is summed before the barrier that ends tile t - 1
-        // and read after the one that ends tile t; slot t + 3 (last read after
-        // the barrier ending tile t - 1, next summed after the one ending tile
+        // (the first tile of an item: after the item's setup barriers) and read
+        // after the one that ends tile t; slot t + 3 (last read after the
+        // barrier ending tile t - 1, next summed after the one ending tile
         // t + 1) is cleared here.  With one barrier per tile (16-bit counts)
         // this tile's read-out overlaps other waves' votes of tile t + 1 and
         // the summing of tile t + 2, which use the other slots.

@@ -421,6 +421,8 @@ def test_batch_matches_single_chip_votes(gpu):
     chips = _night_chips(6, 0.1)
     styles = {wl.bin_px for wl, *_ in chips}
     assert len(styles) == 2  # both styles present
+    # the wide-style chips take 16-bit counts, the fast-style ones do not
+    assert len({plan.info()["half_counts"] for _, _, plan, *_ in chips}) == 2
     b = sas.Batch([(plan, x, y, e) for _, _, plan, x, y, e in chips], cand_cap=1 << 20)
     b.vote()
     for k, (wl, v, plan, x, y, e) in enumerate(chips):
