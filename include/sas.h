@@ -72,9 +72,6 @@ typedef int32_t sas_status;
 #define SAS_DATA_REFINE_FULL 4 /* more flagged cells than the plan's refinement list holds */
 #define SAS_DATA_INTERNAL 8    /* a tile window exceeded the plan's run table or guard cells
                                   (a library bug; the votes concerned were skipped) */
-#define SAS_DATA_COUNT_RANGE 16 /* a plan with 16-bit histogram counts met a tile with 2^16 or
-                                   more window entries, so its counts may have wrapped: plan
-                                   again with tuning.half_counts = -1 */
 
 const char *sas_status_string(sas_status s);
 /* Message of the calling thread's last failing call ("" if none). */
@@ -181,9 +178,10 @@ typedef struct {
                                    0: weighted plans use single bins unless coarse_log2 > 0 */
     int32_t half_counts;        /* 16-bit histogram counts (plans with groups = 1 that count
                                    detections or refine coarse cells): velocity lanes j and
-                                   j + 32 share a word and two histograms alternate by tile.
-                                   1: on; -1: off; 0: on when n_det_hint puts the expected
-                                   window entries of a tile at 8192 or fewer */
+                                   j + 32 share a word and two histograms alternate by tile;
+                                   a tile whose window entries reach 2^16 is voted with 32-bit
+                                   counts.  0 or 1: on wherever the plan allows it (1 makes a
+                                   plan that does not an error); -1: off */
 } sas_tuning;
 
 /* ------------------------------------------------------------------------

@@ -431,7 +431,7 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     auto ceil_cells = [&](int64_t q8) -> int64_t { return (q8 + cellw - 1) >> kc; };
     std::vector<int32_t> seg, seg_v, seg_vel, seg_guard;
     std::vector<int64_t> seg_ky;  // velocity-block row of each segment
-    int64_t guard_x = 0, guard_y = 0, spread_y_max = 0, spread_x_max = 0;
+    int64_t guard_x = 0, guard_y = 0, spread_y_max = 0;
     double spread_x_sum = 0, spread_y_sum = 0;
     {
         int64_t i = 0;
@@ -452,7 +452,6 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
             spread_x_sum += (double)spread_q8((int64_t)vx_hi - vx_lo);
             spread_y_sum += (double)spread_q8((int64_t)vy_hi - vy_lo);
             spread_y_max = std::max(spread_y_max, spread_q8((int64_t)vy_hi - vy_lo));
-            spread_x_max = std::max(spread_x_max, spread_q8((int64_t)vx_hi - vx_lo));
             for (int l = 0; l < NV; ++l) {
                 const bool used = i + l < k;
                 const int32_t u = used ? V[2 * order[i + l]] : vx_lo;
@@ -615,22 +614,13 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
                                                                         (int64_t)(16 * expected_flags)));
     // 16-bit histogram counts (lanes j and j + 32 of one word, two histograms
     // alternating by tile): a count never exceeds the window entries of its
-    // tile, which the kernel checks against 2^16.  The automatic choice wants
-    // the expected entries of a tile (the window grown by the largest block
-    // spread and one index cell on each axis) at 2^13 or fewer.
+    // tile, and the kernel votes a tile that reaches 2^16 with 32-bit counts.
     const bool counts = p->dense_mode == kCountDet || p->dense_mode == kCountRef;
-    if (tu.half_counts == 1) {
-        if (G != 1 || !counts || p->path != SAS_PATH_DENSE)
-            return fail(SAS_E_INVALID, "sas_plan_create: half_counts = 1 needs the dense path, "
-                                       "groups = 1 and a counting mode (detections, or coarse "
-                                       "cells)");
-        p->halves = 1;
-    } else if (tu.half_counts == 0 && G == 1 && counts && p->path == SAS_PATH_DENSE &&
-               tu.n_det_hint > 0) {
-        const double wx = (double)TX * cellw + (double)spread_x_max + (double)((int64_t)1 << cl);
-        const double wy = (double)TY * cellw + (double)spread_y_max + (double)((int64_t)1 << cl);
-        p->halves = (double)tu.n_det_hint * wx * wy / std::max(area, 1.0) <= 8192.0 ? 1 : 0;
-    }
+    const bool halves_ok = G == 1 && counts && p->path == SAS_PATH_DENSE;
+    if (tu.half_counts == 1 && !halves_ok)
+        return fail(SAS_E_INVALID, "sas_plan_create: half_counts = 1 needs the dense path, "
+                                   "groups = 1 and a counting mode (detections, or coarse cells)");
+    p->halves = tu.half_counts >= 0 && halves_ok ? 1 : 0;
     p->tile_x = TX;
     p->tile_y = TY;
     p->vbx = vbx;
@@ -970,10 +960,6 @@ sas_status sas_peaks(const sas_candidate *cand_dev, const sas_vote_result *res_d
     if (r.status & SAS_DATA_INTERNAL)
         return fail(SAS_E_DEVICE, "sas_peaks: internal error: a tile window exceeded the plan's "
                                   "run table or guard cells");
-    if (r.status & SAS_DATA_COUNT_RANGE)
-        return fail(SAS_E_OVERFLOW, "sas_peaks: a tile held 2^16 or more window entries for the "
-                                    "plan's 16-bit histogram counts; plan again with "
-                                    "tuning.half_counts = -1");
     if (r.status & SAS_DATA_REFINE_FULL)
         return fail(SAS_E_OVERFLOW, "sas_peaks: more flagged histogram cells than the plan's "
                                     "refinement list holds; raise tuning.refine_cap or use "

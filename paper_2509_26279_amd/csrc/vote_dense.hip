@@ -352,12 +352,10 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
     const uint32_t nmin = (uint32_t)a.n_min;
     // 16-bit counts (G = 1, counting modes): velocity lanes j and j + 32 add
     // 1 and 2^16 to one word of a bin's 32, and tiles alternate between two
-    // histograms of hist_words / 2 words (block uniform)
+    // histograms of hist_words / 2 words.  A tile whose window entries could
+    // reach 2^16 is voted in the 32-bit form over both (block uniform).
     constexpr bool kHalvesOk = G == 1 && (MODE == kCountDet || MODE == kCountRef);
     const bool hv = kHalvesOk && a.halves != 0;
-    const int NC = hv ? 32 : NV;  // words per bin
-    const uint32_t row_bytes = (uint32_t)(a.hx * NC * 4);
-    const uint32_t cval = hv && j >= 32 ? 65536u : 1u;
     const int LR = a.rows_log2;  // run rows per epoch: 2^LR
     const int32_t vx_lo = a.seg[4 * sg], vx_hi = a.seg[4 * sg + 1];
     const int32_t vy_lo = a.seg[4 * sg + 2], vy_hi = a.seg[4 * sg + 3];
@@ -383,9 +381,25 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
     const int32_t oy = ty0 * cellw;
     // Q8 origin of this lane's histogram row 0: (ty0 - gy) cells
     const uint32_t oy_lane = (uint32_t)(ty0 - my_gy) * (uint32_t)cellw;
-    const uint32_t lane_addr0 =
-        (uint32_t)(uintptr_t)(lds_u32 *)hist + (uint32_t)((hv ? (j & 31) : j) * 4);
-    uint32_t lane_addr = lane_addr0;  // the current tile's histogram
+    // the current tile's histogram form: 16-bit halves (hvt) or 32-bit words,
+    // its row bytes, the lane's increment, the log2 of a bin's bytes and the
+    // LDS address of the lane's word in bin 0
+    const uint32_t hist_base = (uint32_t)(uintptr_t)(lds_u32 *)hist;
+    bool hvt = false;
+    uint32_t row_bytes = 0, cval = 1, lane_addr = 0;
+    int lbt = 0;
+    us2 wts;  // packed form: (bytes of a bin, row bytes)
+    const auto set_form = [&](bool h, int32_t t) __attribute__((always_inline)) {
+        const int nc = h ? 32 : NV;  // words per bin
+        hvt = h;
+        row_bytes = (uint32_t)(a.hx * nc * 4);
+        cval = h && j >= 32 ? 65536u : 1u;
+        lbt = h ? 7 : LNV + 2;
+        wts = us2{(unsigned short)(nc * 4), (unsigned short)row_bytes};
+        lane_addr = hist_base + (uint32_t)((h ? (j & 31) : j) * 4) +
+                    (h ? (uint32_t)(t & 1) * (uint32_t)(hist_words * 2) : 0u);
+    };
+    set_form(false, 0);
 
     // Lane shifts of this wave's epochs e = wave + k NW (k < ER), kept in
     // registers for the whole item with the Q8 origin of the lane's
@@ -426,20 +440,13 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         const int32_t d = sh.dt[e];
         if (d >= 0) bad |= guard_fails(e, shift_q8(my_vx, d), shift_q8(my_vy, d));
     }
-    if (bad) sh.bad = 1;
-    __syncthreads();
-    if (sh.bad) {  // excluded by the planner's guard cells; block uniform
-        if (tid == 0) atomicOr(&a.res->status, SAS_DATA_INTERNAL);
-        return;
-    }
     const us2 kcv = {(unsigned short)kc, (unsigned short)kc};
-    const us2 wts = {(unsigned short)(NC * 4), (unsigned short)row_bytes};
     // vote address of lane shift (sx, sy) (full Q8 values; packed: low bits)
     const auto vote_addr = [&](int32_t sx, int32_t sy) __attribute__((always_inline)) {
         if constexpr (PK) {
             return VoteAddr16{__builtin_bit_cast(us2, (uint32_t)sx), kcv, wts, lane_addr};
         } else {
-            return VA{(uint32_t)sx, (uint32_t)sy, row_bytes, lane_addr, kc, hv ? 7 : LNV + 2};
+            return VA{(uint32_t)sx, (uint32_t)sy, row_bytes, lane_addr, kc, lbt};
         }
     };
 
@@ -539,13 +546,32 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         stage_chunk(txf * cellw, 0);
         if (lane == 0) atomicAdd(&sh.voted[tseq & 3], Mw);
     }
+    // This barrier publishes the guard check and completes the first tile's
+    // staged total (with 16-bit counts every tile's form follows from it).
+    if (bad) sh.bad = 1;
+    __syncthreads();
+    if (sh.bad) {  // excluded by the planner's guard cells; block uniform
+        if (tid == 0) {
+            atomicOr(&a.res->status, SAS_DATA_INTERNAL);
+            sh.voted[tseq & 3] = 0;  // the first tile is not voted
+        }
+        return;
+    }
+    int32_t staged = sh.voted[tseq & 3];  // this tile's total (block uniform)
     for (int32_t ti = 0; ti < ntiles; ++ti, ++tseq) {
         const int32_t tx0 = txf + ti * a.tile_x;
         const int32_t ox = tx0 * cellw;
         const uint32_t ox_lane = (uint32_t)(tx0 - my_gx) * (uint32_t)cellw;
         const bool next = ti + 1 < ntiles;  // block uniform
         const int32_t oxn = ox + a.tile_x * cellw;
-        if (hv) lane_addr = lane_addr0 + (uint32_t)(tseq & 1) * (uint32_t)(hist_words * 2);
+        if (hv) {
+            // a count is at most the tile's window entries; from 2^16 on the
+            // tile takes the 32-bit form, which spans both histograms, after
+            // the previous tile's read-out
+            const bool h = staged < 65536;
+            if (!h) __syncthreads();
+            set_form(h, tseq);
+        }
 
         // 2. vote this wave's entries, chunk by chunk (the first is staged)
         if (Mw > wcap && lane == 0) atomicAdd(&a.res->n_spilled, 1);
@@ -593,18 +619,14 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         // t + 1) is cleared here.  With one barrier per tile (16-bit counts)
         // this tile's read-out overlaps other waves' votes of tile t + 1 and
         // the summing of tile t + 2, which use the other slots.
-        const int32_t staged = sh.voted[tseq & 3];  // block uniform
         const bool any = staged != 0;
-        if (tid == 0) {
-            sh.voted[(tseq + 3) & 3] = 0;
-            // a 16-bit count is at most the tile's window entries
-            if (hv && staged >= 65536) atomicOr(&a.res->status, SAS_DATA_COUNT_RANGE);
-        }
+        staged = sh.voted[(tseq + 1) & 3];  // the next tile's, complete at this barrier
+        if (tid == 0) sh.voted[(tseq + 3) & 3] = 0;
 
         // 3. read and clear the histogram; emit or queue interior cells
         if (any) {
-            const int rw = hv ? hist_words / 2 : hist_words;  // words of this tile's histogram
-            uint4 *hb = smem4 + (hv ? (tseq & 1) * (hist_words / 8) : 0);
+            const int rw = hvt ? hist_words / 2 : hist_words;  // words of this tile's histogram
+            uint4 *hb = smem4 + (hvt ? (tseq & 1) * (hist_words / 8) : 0);
             // count cnt of lane jj's velocity in bin `bin` (all lanes call)
             const auto emit = [&](uint32_t cnt, int jj, int bin) __attribute__((always_inline)) {
                 bool ok = false;
@@ -635,7 +657,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                     hb[w4] = make_uint4(0, 0, 0, 0);
                 }
                 const uint32_t hw[4] = {h.x, h.y, h.z, h.w};
-                if (hv) {  // word wi: bin wi / 32, velocity lanes wi % 32 (low), + 32 (high)
+                if (hvt) {  // word wi: bin wi / 32, velocity lanes wi % 32 (low), + 32 (high)
                     uint32_t m = 0;
 #pragma unroll
                     for (int k = 0; k < 4; ++k) m = max(m, max(hw[k] & 0xffffu, hw[k] >> 16));
@@ -658,10 +680,10 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                 }
             }
         }
-        // the histogram is clear before the next tile's votes; with 16-bit
-        // counts the next tile votes into the other histogram, cleared before
+        // the histogram is clear before the next tile's votes; after a 16-bit
+        // tile the next one votes into the other histogram, cleared before
         // this tile's barrier
-        if (!hv) __syncthreads();
+        if (!hvt) __syncthreads();
 #pragma unroll
         for (int k = 0; k < ER; ++k) {
             if constexpr (PK) {  // low half only, modulo 2^16

@@ -50,8 +50,6 @@ _DATA_ERRORS = ((1, SAS_E_INVALID, "the catalog holds an epoch index >= n_epochs
                 (2, SAS_E_INVALID, "a detection lies outside the plan's footprint"),
                 (8, SAS_E_DEVICE, "internal error: a tile window exceeded the plan's run table "
                                   "or guard cells"),
-                (16, SAS_E_OVERFLOW, "a tile held 2^16 or more window entries for the plan's "
-                                     "16-bit histogram counts; plan again with half_counts=-1"),
                 (4, SAS_E_OVERFLOW, "more flagged histogram cells than the plan's refinement "
                                     "list holds"))
 

@@ -131,63 +131,64 @@ def test_overfull_window_is_chunked(gpu, n_epochs, mode):
 
 
 def test_half_counts_choice_and_errors(gpu):
-    """The automatic choice takes 16-bit counts for the wide workload's plan
-    (n_det_hint given) and not without the hint; forcing them where they do
-    not apply is an argument error."""
+    """16-bit counts are taken wherever the plan allows them (groups = 1, a
+    counting mode, the dense path) unless switched off; forcing them where
+    they do not apply is an argument error."""
     wl = synth.make_wide()
     v = _grid(wl)[:2000]
 
-    def half_of(tun, t=wl.t_q16, path="auto"):
+    def info_of(tun, t=wl.t_q16, path="auto"):
         p = sas.Plan(v, t, wl.binw_q8, wl.n_min, wl.extent_q8, tuning=tun, path=path)
         try:
-            return p.info()["half_counts"]
+            return p.info()
         finally:
             p.close()
 
-    assert half_of(dict(n_det_hint=wl.n)) == 1
-    assert half_of(dict(n_det_hint=wl.n, half_counts=-1)) == 0
-    assert half_of(dict(coarse_log2=2)) == 0
+    i = info_of(dict(n_det_hint=wl.n))
+    assert i["groups"] == 1 and i["half_counts"] == 1
+    assert info_of(dict(coarse_log2=2))["half_counts"] == 1
+    assert info_of(dict(n_det_hint=wl.n, half_counts=-1))["half_counts"] == 0
+    assert info_of(dict(groups=4, coarse_log2=2))["half_counts"] == 0
+    # 20 epochs in single bins: epoch masks, which have no 16-bit form
+    assert info_of(dict(groups=1, coarse_log2=-1), wl.t_q16[:20])["half_counts"] == 0
     # 100 epochs without coarse cells: counts refined into exact bins
-    assert half_of(dict(groups=1, coarse_log2=-1, half_counts=1)) == 1
+    assert info_of(dict(groups=1, coarse_log2=-1, half_counts=1))["half_counts"] == 1
     for tun, t, path in ((dict(groups=2, coarse_log2=2, half_counts=1), wl.t_q16, "auto"),
-                         # 20 epochs, single bins: epoch masks, no 16-bit form
                          (dict(groups=1, coarse_log2=-1, half_counts=1), wl.t_q16[:20], "auto"),
                          (dict(groups=1, coarse_log2=2, half_counts=1), wl.t_q16, "sort"),
                          (dict(half_counts=2), wl.t_q16, "auto")):
         with pytest.raises(sas.SasError):
-            half_of(tun, t, path)
+            info_of(tun, t, path)
 
 
-def test_half_counts_range_reported(gpu):
-    """A tile whose windows hold 2^16 or more detections cannot use 16-bit
-    counts: the vote reports it and sas_peaks refuses; the same plan with
-    32-bit counts matches the oracle."""
+def test_half_counts_dense_tile_takes_32_bit_form(gpu):
+    """A tile whose windows hold 2^16 or more detections is voted with 32-bit
+    counts by a plan with 16-bit counts: the same candidates as the oracle
+    (and as the plan without 16-bit counts), and no error."""
     rng = np.random.default_rng(11)
     n = 70000
-    # a 16 px square at (20, 20) px: inside the first tile of every tile row
-    x = (rng.integers(0, 16 * 256, n) + 20 * 256).astype(np.int32)
-    y = (rng.integers(0, 16 * 256, n) + 20 * 256).astype(np.int32)
+    # a 2 px square at (20.25, 20.25) px: with shifts below 0.2 px every
+    # detection stays in the 4 px bin (5, 5) at every trial velocity, whose
+    # count (70,000) a 16-bit word would wrap
+    x = (rng.integers(0, 2 * 256, n) + 20 * 256 + 64).astype(np.int32)
+    y = (rng.integers(0, 2 * 256, n) + 20 * 256 + 64).astype(np.int32)
     e = rng.integers(0, 4, n).astype(np.uint8)
     t = np.arange(4, dtype=np.int64) * 4000
     v = np.array([[i * 256, j * 256] for j in range(-1, 2) for i in range(-1, 2)], np.int32)
     ext = (0, 128 * 256, 0, 128 * 256)
     n_min = 300
+    o = oracle.vote(x, y, e, t, v, 1024, n_min, "detections")
+    assert len(o) == len(v) and np.all(o["count"] == 65535) and np.all(o["flags"] == 1)
     for hc in (1, -1):
-        _say(f"count range half_counts={hc}")
+        _say(f"dense tile half_counts={hc}")
         plan = sas.Plan(v, t, 1024, n_min, ext, mode="detections",
                         tuning=dict(groups=1, coarse_log2=-1, half_counts=hc))
+        assert plan.info()["half_counts"] == (1 if hc == 1 else 0)
         srch = sas.Search(plan, n, cand_cap=1 << 16)
-        x_d, y_d, e_d = srch.upload(x, y, e)
-        srch.vote(x_d, y_d, e_d)
-        status = srch.result()["status"]
-        if hc == 1:
-            assert status & 16  # SAS_DATA_COUNT_RANGE
-            with pytest.raises(sas.SasError):
-                srch.peaks()
-        else:
-            assert status == 0
-            assert_same(srch.peaks(), oracle.vote(x, y, e, t, v, 1024, n_min, "detections"))
+        g = srch.run(x, y, e)
+        assert srch.result()["status"] == 0
         plan.close()
+        assert_same(g, o)
 
 
 # ---------------------------------------------------------------- full size, sampled
