@@ -180,8 +180,8 @@ typedef struct {
                                    detections or refine coarse cells): velocity lanes j and
                                    j + 32 share a word and two histograms alternate by tile;
                                    a tile whose window entries reach 2^16 is voted with 32-bit
-                                   counts.  0 or 1: on wherever the plan allows it (1 makes a
-                                   plan that does not an error); -1: off */
+                                   counts.  0: on wherever the plan allows it; 1: on, and an
+                                   error (SAS_E_INVALID) where the plan does not; -1: off */
 } sas_tuning;
 
 /* ------------------------------------------------------------------------
