@@ -179,10 +179,12 @@ def test_half_counts_dense_tile_takes_32_bit_form(gpu):
     n_min = 300
     o = oracle.vote(x, y, e, t, v, 1024, n_min, "detections")
     assert len(o) == len(v) and np.all(o["count"] == 65535) and np.all(o["flags"] == 1)
-    for hc in (1, -1):
-        _say(f"dense tile half_counts={hc}")
+    # default tiles put the square in the first tile of its row; 4 x 4-bin
+    # tiles put it in the second, between 16-bit tiles on both sides
+    for hc, tiles in ((1, {}), (1, dict(tile_x=4, tile_y=4)), (-1, {})):
+        _say(f"dense tile half_counts={hc} {tiles}")
         plan = sas.Plan(v, t, 1024, n_min, ext, mode="detections",
-                        tuning=dict(groups=1, coarse_log2=-1, half_counts=hc))
+                        tuning=dict(groups=1, coarse_log2=-1, half_counts=hc, **tiles))
         assert plan.info()["half_counts"] == (1 if hc == 1 else 0)
         srch = sas.Search(plan, n, cand_cap=1 << 16)
         g = srch.run(x, y, e)
