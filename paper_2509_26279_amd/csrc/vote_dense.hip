@@ -5,14 +5,15 @@
 // of the velocity lattice).  A workgroup takes a (segment, row of tiles); a
 // tile is TX x TY histogram cells (a cell is one bin, or 2^m x 2^m bins for
 // the coarse filter below).  For each tile:
-//   1. per epoch, the exact window of the original frame whose detections can
-//      land in the tile for some velocity of the segment is computed; the
-//      window index (detections grouped by epoch, cell row, cell column) is
-//      read one thread per (epoch, cell row), and a block scan lays the runs
-//      out for a flat copy into a stage in LDS.  The copy keeps only the
-//      detections inside the exact window, grouped by epoch (large windows
-//      are staged in chunks);
-//   2. waves take epochs; lane = (group g < G, velocity j < NV), and the G
+//   1. each wave takes the epochs e = wave (mod 8).  Per epoch, the exact
+//      window of the original frame whose detections can land in the tile
+//      for some velocity of the segment is computed; the window index
+//      (detections grouped by epoch, cell row, cell column) is read one lane
+//      per (epoch, cell row), and wave scans lay the runs out for a copy into
+//      the wave's part of a stage in LDS.  The copy keeps only the detections
+//      inside the exact window, grouped by epoch (large windows are staged in
+//      chunks), and the next tile is staged right after this one's votes;
+//   2. lane = (group g < G, velocity j < NV), and the G
 //      groups vote G staged detections per instruction.  With d = t_e - t0
 //      and S(v) = ceil(v d / 65536), the bin of Step 2,
 //      floor((65536 x - v d) / (65536 b)), equals (x - S(v)) >> log2(b).  The
@@ -22,9 +23,13 @@
 //      multiply-add and an or for the address, and one LDS atomic with no
 //      return value and no bounds check.  The NV words of a bin are
 //      consecutive, so a group's lanes touch NV consecutive banks;
-//   3. one pass over the histogram reads and clears it; interior cells at or
-//      above N_min are emitted (wavefront ballot + one global atomic per
-//      wave) or queued for refinement.
+//   3. after a barrier, one pass over the histogram reads and clears it;
+//      interior cells at or above N_min are emitted (wavefront ballot + one
+//      global atomic per wave) or queued for refinement, and a second
+//      barrier ends the tile.  With 16-bit counts (G = 1, counting variants)
+//      lanes j and j + 32 share a word and tiles alternate between two
+//      histograms, so the second barrier goes; a tile whose window entries
+//      could reach 2^16 uses the 32-bit form.
 // Cell variants:
 //   kMask32  - EPOCHS with E <= 32: epoch bitmask per cell;
 //   kCountDet - DETECTIONS: counter per cell;
