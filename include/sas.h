@@ -361,6 +361,9 @@ typedef struct {
  *   workspace:   the workspace of the last sas_vote of this dense-path plan
  *                on this catalog (n detections): its window index is read.
  *   cand_dev:    device [n_cand] cells reported by that vote (any order).
+ *                The list must be complete: a vote whose result reports a
+ *                data error or more candidates than its buffer held (what
+ *                sas_peaks refuses) gives a wrong extraction.
  *   member_cap:  capacity of the contributor lists (sum over the cells of
  *                their contributors); see res->n_members when exceeded.
  *   scratch:     device, >= sas_extract_scratch_size(n, n_cand, member_cap).
