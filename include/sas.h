@@ -290,6 +290,28 @@ sas_status sas_vote_weighted(const sas_plan *plan, const int32_t *x_q8, const in
                              sas_candidate *cand_dev, int64_t cand_cap, sas_vote_result *res_dev,
                              void *workspace, size_t ws_bytes, void *stream);
 
+/*
+ * sas_vote_static: sas_vote for callers that cannot allocate device memory
+ * or take a workspace (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  The scratch sas_vote keeps in the
+ * caller's workspace lives instead in one static device array of
+ * SAS_STATIC_SCRATCH_BYTES per GPU, owned by the library and held until the
+ * process ends.  The caller still passes the catalog and the outputs, with
+ * the meaning they have in sas_vote; no allocation is made.
+ *   Every call on one GPU shares that GPU's array and leaves its contents
+ *   behind; each call clears what it needs itself.  Calls that overlap on
+ *   one GPU (concurrent streams or threads) race on the array: order them.
+ *   Extraction, features and refinement read a vote's workspace and so need
+ *   sas_vote, not this variant.
+ * Errors (host side, nothing enqueued): those of sas_vote, and
+ * SAS_E_WORKSPACE when sas_vote_workspace_size(plan, n) exceeds
+ * SAS_STATIC_SCRATCH_BYTES (a plan with a smaller tuning.refine_cap may fit).
+ */
+#define SAS_STATIC_SCRATCH_BYTES (64 * 1024 * 1024)
+sas_status sas_vote_static(const sas_plan *plan, const int32_t *x_q8, const int32_t *y_q8,
+                           const uint8_t *epoch, int64_t n, sas_candidate *cand_dev,
+                           int64_t cand_cap, sas_vote_result *res_dev, void *stream);
+
 /* ------------------------------------------------------------------------
  * Batches: many catalogs (e.g. the chips of one night, each with its own
  * plan: grid, epochs, threshold, footprint) voted by one persistent launch

@@ -105,7 +105,7 @@ _lib = None
 EXPORTS = ["sas_status_string", "sas_last_error", "sas_version", "sas_grid_spacing",
            "sas_build_grid", "sas_plan_create", "sas_plan_destroy", "sas_plan_get_info",
            "sas_plan_set_probe", "sas_vote_workspace_size", "sas_vote", "sas_vote_weighted",
-           "sas_peaks",
+           "sas_vote_static", "sas_peaks",
            "sas_threshold_n_min", "sas_batch_workspace_size", "sas_batch_create",
            "sas_batch_destroy", "sas_vote_batch", "sas_batch_set_probe", "sas_features",
            "sas_features_scratch_size", "sas_extract_scratch_size", "sas_extract_clusters",
@@ -142,6 +142,7 @@ def load():
         "sas_vote_workspace_size": (I32, [P, I64, P]),
         "sas_vote": (I32, [P, P, P, P, I64, P, I64, P, P, SZ, P]),
         "sas_vote_weighted": (I32, [P, P, P, P, P, I64, P, I64, P, P, SZ, P]),
+        "sas_vote_static": (I32, [P, P, P, P, I64, P, I64, P, P]),
         "sas_refine_clusters": (I32, [P, P, SZ, P, P, P, I64, P, P, I64, I64, P, I32, I32, P, P,
                                       I32, P, P]),
         "sas_peaks": (I32, [P, P, I64, I32, I64, P, I64, P, P]),
@@ -315,6 +316,18 @@ def vote(plan: Plan, x, y, epoch, cand, res, workspace, stream=None, weight=None
                                         epoch.data_ptr(), weight.data_ptr(), n,
                                         cand.data_ptr(), cap, res.data_ptr(),
                                         workspace.data_ptr(), ws, _stream_handle(stream)))
+
+
+STATIC_SCRATCH_BYTES = 64 * 1024 * 1024
+
+
+def vote_static(plan: Plan, x, y, epoch, cand, res, stream=None):
+    """Enqueue sas_vote_static: sas_vote with the library's static per-GPU
+    scratch array in place of a workspace (no allocation)."""
+    n = int(x.numel())
+    cap = cand.numel() * cand.element_size() // 16
+    _check(load().sas_vote_static(plan.handle, x.data_ptr(), y.data_ptr(), epoch.data_ptr(), n,
+                                  cand.data_ptr(), cap, res.data_ptr(), _stream_handle(stream)))
 
 
 def peaks(cand, res, order="canonical", top_k=0, stream=None, out=None):
