@@ -182,6 +182,11 @@ typedef struct {
                                    a tile whose window entries reach 2^16 is voted with 32-bit
                                    counts.  0: on wherever the plan allows it; 1: on, and an
                                    error (SAS_E_INVALID) where the plan does not; -1: off */
+    int32_t prune;              /* SAS_MODE_EPOCHS plans: 0 skips the tiles of a velocity block
+                                   where fewer than N_min epochs can reach any bin (the window
+                                   of every other epoch misses the footprint), which cannot
+                                   hold a candidate; the output is unchanged.  -1: vote every
+                                   tile.  Other modes never skip tiles. */
 } sas_tuning;
 
 /* ------------------------------------------------------------------------
@@ -240,6 +245,9 @@ typedef struct {
     int32_t lds_bytes;     /* LDS per vote workgroup */
     int32_t packed;        /* 1: votes use packed 16-bit arithmetic */
     int32_t half_counts;   /* 1: 16-bit histogram counts, two histograms by tile */
+    int64_t n_tiles_kept;  /* tiles voted when the catalog's earliest epoch holds a detection
+                              (the rest reach fewer than N_min epochs; tuning.prune) */
+    int64_t n_items_kept;  /* their work items */
 } sas_plan_info;
 sas_status sas_plan_get_info(const sas_plan *plan, sas_plan_info *info);
 
@@ -251,6 +259,99 @@ sas_status sas_plan_get_info(const sas_plan *plan, sas_plan_info *info);
  * events stay owned by the caller.
  */
 sas_status sas_plan_set_probe(sas_plan *plan, void *ev_before, void *ev_after);
+
+/*
+ * sas_plan_set_counter: measurement hook.  Later sas_vote calls with this
+ * plan add to *counter_dev (a device uint64 the caller owns and clears) the
+ * number of 64-lane LDS atomic instructions their vote kernel issues to
+ * cast votes (a run of n staged detections of one epoch takes
+ * ceil(n / groups) of them).  With the kernel time this gives the rate of
+ * the LDS atomic unit.  NULL switches it off.
+ */
+sas_status sas_plan_set_counter(sas_plan *plan, uint64_t *counter_dev);
+
+/* ------------------------------------------------------------------------
+ * Autotuner of the dense path's launch shape (no paper passage: the paper's
+ * implementation runs on CPUs).  A launch shape changes the time of a vote,
+ * never its candidate list; the tuner checks that.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    sas_tuning tuning;  /* the candidate tried */
+    float ms;           /* median time of its vote kernel, -1 when its plan does not fit */
+    int32_t status;     /* SAS_OK, or the sas_plan_create error of this shape */
+} sas_autotune_trial;
+
+/*
+ * sas_autotune_default_candidates: the built-in candidate list around the
+ * planner's choice for desc (its tuning field is the base every candidate
+ * starts from): the planner default, each lane-group count, window-index
+ * cells one step finer and coarser, and five tile shapes per lane-group
+ * count.  *n_out receives the count; SAS_E_OVERFLOW when cap is smaller.
+ * Creates (and destroys) a plan on the current device.
+ */
+sas_status sas_autotune_default_candidates(const sas_plan_desc *desc, sas_tuning *out,
+                                           int32_t cap, int32_t *n_out);
+
+/*
+ * sas_autotune: time each candidate tuning on one catalog and return the
+ * fastest in *best_out.  For every candidate: a plan (desc with that
+ * tuning), one vote whose list is collected in canonical order, then `reps`
+ * votes timed with events around the vote kernel (the median is kept).
+ *   x_q8, y_q8, epoch: device [n]; cands: host [n_cands]; trials_out: host
+ *   [n_cands].
+ * Candidates whose plan does not fit (SAS_E_INVALID or SAS_E_UNSUPPORTED
+ * from sas_plan_create) get ms = -1 and are skipped.  Every other candidate
+ * must give the candidate list of the first one that fits; a difference is
+ * a library bug and returns SAS_E_DEVICE naming the shape.  Allocates
+ * device memory and synchronises `stream`: an offline call.
+ * Errors: SAS_E_INVALID (arguments, no shape fits), SAS_E_UNSUPPORTED
+ * (sort-path or weighted plans), SAS_E_NOMEM, SAS_E_DEVICE, and those of
+ * sas_vote and sas_peaks for the catalog.
+ */
+sas_status sas_autotune(const sas_plan_desc *desc, const int32_t *x_q8, const int32_t *y_q8,
+                        const uint8_t *epoch, int64_t n, const sas_tuning *cands, int32_t n_cands,
+                        int32_t reps, sas_autotune_trial *trials_out, sas_tuning *best_out,
+                        void *stream);
+
+/*
+ * sas_autotune_key: the shape class of a catalog, the key of the tuning
+ * cache: bin width, lattice spacing floor(binw * 65536 / span), and the
+ * epoch count, detection count n and velocity count rounded down to powers
+ * of two, and the mode ("b1024_s256_E64_n262144_V65536_m0").  Host only.
+ */
+sas_status sas_autotune_key(const sas_plan_desc *desc, int64_t n, char *key_out, int64_t cap);
+
+/*
+ * Tuning cache: a text file with one shape class per line,
+ * "<key> name=value ..." (sas_tuning field names; absent fields are 0).
+ * sas_autotune_cache_get sets *found to 1 and fills *out when the key is
+ * present (a missing file is an empty cache); sas_autotune_cache_put adds
+ * or replaces the key's line (lines kept sorted; written through a
+ * temporary file).  Host only.
+ */
+sas_status sas_autotune_cache_get(const char *path, const char *key, sas_tuning *out,
+                                  int32_t *found);
+sas_status sas_autotune_cache_put(const char *path, const char *key, const sas_tuning *tuning);
+
+/* ------------------------------------------------------------------------
+ * Ceilings: rates of the units the dense vote uses, measured on the current
+ * device (no paper passage; the roofline of the vote kernel is stated
+ * against them).  Each figure is the best of a few launches of a kernel that
+ * repeats one kind of instruction on every resident wave.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double lds_atomic_conflict_free; /* lane atomic adds per second, 64 consecutive words per
+                                        wave instruction (no bank conflict) */
+    double lds_atomic_lane_groups;   /* the same with 4 groups of 16 lanes each adding to the
+                                        16 words of one random bin (the G = 4 vote pattern) */
+    double valu_int32_ops;           /* 32-bit integer add / xor lane operations per second */
+    double valu_int16x2_ops;         /* packed 16-bit integer half operations per second */
+    double hbm_copy_bytes_per_s;     /* bytes read plus written per second, 1 GiB device copy */
+} sas_ceilings;
+
+/* Run the measurements on `stream` (allocates 2 GiB and more for its buffers,
+ * frees them, synchronises).  Errors: SAS_E_INVALID, SAS_E_DEVICE. */
+sas_status sas_measure_ceilings(sas_ceilings *out, void *stream);
 
 /* Device workspace needed by sas_vote for a catalog of n detections. */
 sas_status sas_vote_workspace_size(const sas_plan *plan, int64_t n, size_t *bytes);
@@ -358,6 +459,9 @@ sas_status sas_vote_batch(const sas_batch *batch, void *stream);
 /* Measurement hook: record ev_before / ev_after around the batch's vote
  * kernels (first class launch to last) on the call's stream; NULL, NULL off. */
 sas_status sas_batch_set_probe(sas_batch *batch, void *ev_before, void *ev_after);
+/* Measurement hook: later sas_vote_batch calls add their vote kernels' LDS
+ * atomic vote instructions to *counter_dev (as sas_plan_set_counter). */
+sas_status sas_batch_set_counter(sas_batch *batch, uint64_t *counter_dev);
 
 /* ------------------------------------------------------------------------
  * Greedy cluster extraction (Step 3 of Sec. 2.1).
@@ -474,6 +578,21 @@ sas_status sas_mlp_set_norm(sas_mlp *mlp, const float *mean_host, const float *s
  * (n = 20865; resets the optimiser state).  Synchronous. */
 sas_status sas_mlp_get_params(const sas_mlp *mlp, float *host, int64_t cap, int64_t *n_out);
 sas_status sas_mlp_set_params(sas_mlp *mlp, const float *host, int64_t n);
+/*
+ * Checkpoints (no paper passage): everything a resumed training needs, so
+ * that training resumed from a checkpoint continues bit for bit as the
+ * uninterrupted run would.  sas_mlp_save writes, to host memory, a 256-byte
+ * text header (one JSON object padded with spaces and ending in a newline:
+ * format "sas_mlp", version 1, parameter and input counts, the AdamW step
+ * count and the creation seed) followed by float32 little-endian arrays:
+ * the FP32 master parameters, the AdamW first and second moments (20865
+ * each), and the input mean and std (32 each).  Two-call protocol: *n_out
+ * receives the size; a smaller cap returns SAS_E_OVERFLOW.  sas_mlp_load
+ * restores all of it (and the bf16 working weights) into a network of any
+ * max_batch; SAS_E_INVALID for a wrong size or header.  Both synchronous.
+ */
+sas_status sas_mlp_save(const sas_mlp *mlp, void *host, int64_t cap, int64_t *n_out);
+sas_status sas_mlp_load(sas_mlp *mlp, const void *host, int64_t n);
 /* Logits of n rows (any n; processed max_batch rows at a time). */
 sas_status sas_mlp_forward(const sas_mlp *mlp, const float *x_dev, int64_t n, float *logits_dev,
                            void *stream);

@@ -10,7 +10,9 @@ Network 32 -> 128 -> 128 -> 1 with ReLU (derivative 0 at 0):
 with W1, W2 also used as q(W).  q is rounding to bfloat16 (round to nearest
 even of the float32 value); with bf16=False q is the identity and the whole
 computation is exact FP64 (used to check the gradient by finite
-differences).
+differences).  The rounding points are named (POINTS); `points` selects
+which of them round (all by default), so that a test can show that each of
+them is visible at the GPU comparison's tolerance.
 
 Loss: mean over the batch of binary cross-entropy with logits and a weight
 pw on positives,  l = pw y softplus(-z) + (1 - y) softplus(z).
@@ -56,41 +58,53 @@ def bf16(a):
     return r.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+# every bf16 rounding point: the standardised input, the three weight
+# matrices, the two hidden activations, the logit gradient and the two
+# back-propagated activation gradients
+POINTS = ("a0", "W1", "h1", "W2", "h2", "W3", "g3", "d2", "d1")
+
+
 def _q(a, on):
     return bf16(a) if on else np.asarray(a, dtype=np.float64)
+
+
+def _on(bf16_on, points, name):
+    return bf16_on and (points is None or name in points)
 
 
 def softplus(z):
     return np.maximum(z, 0.0) + np.log1p(np.exp(-np.abs(z)))
 
 
-def forward(params, x, mu, sd, bf16_on=True):
+def forward(params, x, mu, sd, bf16_on=True, points=None):
     """Logits and the intermediate activations."""
     P = unpack(params)
+    q = lambda a, name: _q(a, _on(bf16_on, points, name))
     sd = np.where(np.asarray(sd, np.float64) == 0, 1.0, np.asarray(sd, np.float64))
-    a0 = _q((np.asarray(x, np.float64) - np.asarray(mu, np.float64)) / sd, bf16_on)
-    h1 = _q(np.maximum(a0 @ _q(P["W1"], bf16_on) + P["b1"], 0.0), bf16_on)
-    h2 = _q(np.maximum(h1 @ _q(P["W2"], bf16_on) + P["b2"], 0.0), bf16_on)
-    z = h2 @ _q(P["W3"], bf16_on) + P["b3"][0]
+    a0 = q((np.asarray(x, np.float64) - np.asarray(mu, np.float64)) / sd, "a0")
+    h1 = q(np.maximum(a0 @ q(P["W1"], "W1") + P["b1"], 0.0), "h1")
+    h2 = q(np.maximum(h1 @ q(P["W2"], "W2") + P["b2"], 0.0), "h2")
+    z = h2 @ q(P["W3"], "W3") + P["b3"][0]
     return z, (a0, h1, h2)
 
 
-def loss_and_grad(params, x, y, mu, sd, pos_weight=1.0, bf16_on=True):
+def loss_and_grad(params, x, y, mu, sd, pos_weight=1.0, bf16_on=True, points=None):
     """Mean loss and the gradient (packed like the parameters)."""
     P = unpack(params)
+    q = lambda a, name: _q(a, _on(bf16_on, points, name))
     y = np.asarray(y, np.float64)
-    z, (a0, h1, h2) = forward(params, x, mu, sd, bf16_on)
+    z, (a0, h1, h2) = forward(params, x, mu, sd, bf16_on, points)
     B = z.shape[0]
     loss = float(np.mean(pos_weight * y * softplus(-z) + (1 - y) * softplus(z)))
     sig = 1.0 / (1.0 + np.exp(-z))
     dz = (sig * (pos_weight * y + 1 - y) - pos_weight * y) / B
-    g3 = _q(dz, bf16_on)
+    g3 = q(dz, "g3")
     dW3 = h2.T @ g3
     db3 = np.array([g3.sum()])
-    d2 = _q(np.outer(g3, _q(P["W3"], bf16_on)) * (h2 > 0), bf16_on)
+    d2 = q(np.outer(g3, q(P["W3"], "W3")) * (h2 > 0), "d2")
     dW2 = h1.T @ d2
     db2 = d2.sum(axis=0)
-    d1 = _q((d2 @ _q(P["W2"], bf16_on).T) * (h1 > 0), bf16_on)
+    d1 = q((d2 @ q(P["W2"], "W2").T) * (h1 > 0), "d1")
     dW1 = a0.T @ d1
     db1 = d1.sum(axis=0)
     return loss, pack({"W1": dW1, "b1": db1, "W2": dW2, "b2": db2, "W3": dW3, "b3": db3})

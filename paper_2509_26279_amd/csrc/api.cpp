@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <memory>
 #include <cstdio>
@@ -117,6 +118,10 @@ struct sas_plan {
     int32_t halves = 0;  // 16-bit histogram counts, two histograms by tile
     int32_t ncx = 1, ncy = 1;
     int64_t n_cells = 0, n_items = 0, n_segments = 0, n_tiles = 0, refine_cap = 0;
+    // items [0, n_items_kept) are the tiles that can hold a candidate when the
+    // earliest epoch e_first holds a detection; the rest are voted otherwise
+    int64_t n_items_kept = 0, n_tiles_kept = 0;
+    int32_t e_first = 0;
     size_t lds_bytes = 0;
     int32_t *d_vel = nullptr, *d_seg = nullptr, *d_seg_v = nullptr, *d_seg_vel = nullptr;
     int32_t *d_seg_guard = nullptr, *d_items = nullptr;
@@ -129,6 +134,7 @@ struct sas_plan {
     int32_t sort_vblock = 0;
     int32_t *d_sort_vel = nullptr, *d_sort_vidx = nullptr;
     hipEvent_t probe[2] = {nullptr, nullptr};
+    unsigned long long *counter = nullptr;  // device: LDS atomic vote instructions (probe)
     int64_t *d_t = nullptr;
     std::vector<void *> allocs;
 };
@@ -243,12 +249,15 @@ DenseArgs dense_args(const sas_plan *p, const WsLayout &L, char *w, const PrepBu
     a.seg_guard = p->d_seg_guard;
     a.items = p->d_items;
     a.n_items = p->n_items;
+    a.n_items_kept = p->n_items_kept;
+    a.e_first = p->e_first;
     a.refine = (int4 *)(w + L.refine);
     a.refine_count = pb.refine_count;
     a.refine_cap = refines(p->dense_mode) ? p->refine_cap : 0;
     a.cand = cand;
     a.cand_cap = cand_cap;
     a.res = res;
+    a.atomics = p->counter;
     return a;
 }
 
@@ -330,6 +339,8 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
         return fail(SAS_E_INVALID, "sas_plan_create: half_counts must be -1, 0 or 1");
     if (tu.tile_x < 0 || tu.tile_y < 0 || tu.stage_cap < 0 || tu.vblock_x < 0 || tu.vblock_y < 0)
         return fail(SAS_E_INVALID, "sas_plan_create: negative tuning value");
+    if (tu.prune < -1 || tu.prune > 0)
+        return fail(SAS_E_INVALID, "sas_plan_create: prune must be 0 or -1");
 
     // Cell size of the histogram.  A cell of 2^m x 2^m bins counts the
     // detections of all its bins; only cells reaching N_min are refined into
@@ -642,11 +653,31 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     // in the segment's box and dt in [0, span] lie inside the convex hull of
     // the footprint's corners and their shifts by the box corners times span.
     // Every tile row gets the x range of that hull.
+    //
+    // Coverage.  In EPOCHS mode a bin's count is at most the number of epochs
+    // whose detections can reach it.  For a tile of a segment, epoch e can
+    // contribute only if its exact window (the tile shifted by S(v, d_e) over
+    // the segment's box, as the kernel stages it) meets the footprint; a tile
+    // with fewer than N_min such epochs holds no candidate and is not voted.
+    // d_e is taken from the earliest scheduled epoch e_first; when that epoch
+    // holds no detection the reference epoch is later, and the kernel votes
+    // the skipped tiles too (they follow the kept items in the list).
     const __int128 B = (__int128)1 << (16 + kc);  // one histogram cell in Q24
     const __int128 lim_bins = (__int128)1 << 29;
-    std::vector<int32_t> items;
-    int64_t n_tiles = 0;
+    const bool prune = tu.prune == 0 && d->mode == SAS_MODE_EPOCHS && p->path == SAS_PATH_DENSE;
+    int32_t e_first = 0;
+    for (int e = 1; e < d->n_epochs; ++e)
+        if (d->t_q16[e] < d->t_q16[e_first]) e_first = e;
+    std::vector<int64_t> dq(d->n_epochs);
+    for (int e = 0; e < d->n_epochs; ++e) dq[e] = d->t_q16[e] - d->t_q16[e_first];
+    const int64_t TWq = (int64_t)TX << kc, THq = (int64_t)TY << kc;  // tile size, Q8
+    auto shift_of = [](int64_t v, int64_t dd) { return (v * dd + 65535) >> 16; };  // floor
+    std::vector<int32_t> items, tail;  // kept items, then the skipped tiles' items
+    int64_t n_tiles = 0, n_tiles_kept = 0;
+    std::vector<std::array<int64_t, 3>> rows_of_seg;  // (tile row r, first, last tile column)
+    std::vector<int32_t> cov;
     for (int64_t sg = 0; sg < n_seg && p->path == SAS_PATH_DENSE; ++sg) {
+        rows_of_seg.clear();
         const int32_t vx_lo = seg[4 * sg], vx_hi = seg[4 * sg + 1];
         const int32_t vy_lo = seg[4 * sg + 2], vy_hi = seg[4 * sg + 3];
         std::vector<std::pair<__int128, __int128>> pts;
@@ -674,16 +705,75 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
                 if (v <= -lim_bins || v >= lim_bins)
                     return fail(SAS_E_UNSUPPORTED, "sas_plan_create: projected bins exceed +-2^29");
             const int64_t t0x = floor_div(bxl, TX), t1x = floor_div(bxh, TX);
-            items.insert(items.end(), {(int32_t)sg, (int32_t)(r * TY), (int32_t)(t0x * TX),
-                                       (int32_t)(t1x - t0x + 1)});
+            rows_of_seg.push_back({r, t0x, t1x});
             n_tiles += t1x - t0x + 1;
         }
+        if (rows_of_seg.empty()) continue;
+        // coverage of every (tile row, tile column) of the segment: per epoch
+        // the rows and columns whose window meets the footprint form a
+        // rectangle; a 2-D difference array sums them
+        const int64_t ra0 = rows_of_seg.front()[0], ra1 = rows_of_seg.back()[0];
+        int64_t ka0 = rows_of_seg[0][1], ka1 = rows_of_seg[0][2];
+        for (const auto &q : rows_of_seg) { ka0 = std::min(ka0, q[1]); ka1 = std::max(ka1, q[2]); }
+        const int64_t nr = ra1 - ra0 + 1, nk = ka1 - ka0 + 1;
+        const bool seg_prune = prune && nr * nk <= ((int64_t)1 << 22);
+        if (seg_prune) {
+            cov.assign((size_t)((nr + 1) * (nk + 1)), 0);
+            for (int e = 0; e < d->n_epochs; ++e) {
+                const int64_t s0 = shift_of(vx_lo, dq[e]), s1 = shift_of(vx_hi, dq[e]);
+                const int64_t s2 = shift_of(vy_lo, dq[e]), s3 = shift_of(vy_hi, dq[e]);
+                // window rows [oy + s2, oy + s3 + TH) meet [y0, y1): oy = r TH
+                const int64_t rb = std::max(ra0, floor_div((__int128)ex[2] - s3 - THq, THq) + 1);
+                const int64_t re = std::min(ra1, floor_div((__int128)ex[3] - s2 - 1, THq));
+                // window columns [ox + s0, ox + s1 + TW) meet [x0, x1): ox = k TW
+                const int64_t kb = std::max(ka0, floor_div((__int128)ex[0] - s1 - TWq, TWq) + 1);
+                const int64_t ke = std::min(ka1, floor_div((__int128)ex[1] - s0 - 1, TWq));
+                if (rb > re || kb > ke) continue;
+                const int64_t r0i = rb - ra0, r1i = re - ra0 + 1, k0i = kb - ka0, k1i = ke - ka0 + 1;
+                cov[r0i * (nk + 1) + k0i] += 1;
+                cov[r0i * (nk + 1) + k1i] -= 1;
+                cov[r1i * (nk + 1) + k0i] -= 1;
+                cov[r1i * (nk + 1) + k1i] += 1;
+            }
+            for (int64_t i = 0; i < nr; ++i)
+                for (int64_t k = 0; k < nk; ++k) {
+                    int32_t &c = cov[i * (nk + 1) + k];
+                    if (i > 0) c += cov[(i - 1) * (nk + 1) + k];
+                    if (k > 0) c += cov[i * (nk + 1) + k - 1];
+                    if (i > 0 && k > 0) c -= cov[(i - 1) * (nk + 1) + k - 1];
+                }
+        }
+        for (const auto &q : rows_of_seg) {
+            const int64_t r = q[0], t0x = q[1], t1x = q[2];
+            int64_t k0 = t0x, k1 = t1x;  // kept tile columns [k0, k1]
+            if (seg_prune) {
+                const int32_t *row = &cov[(r - ra0) * (nk + 1)];  // column k at row[k - ka0]
+                while (k0 <= t1x && row[k0 - ka0] < d->n_min) ++k0;
+                while (k1 >= k0 && row[k1 - ka0] < d->n_min) --k1;
+            }
+            auto push = [&](std::vector<int32_t> &dst, int64_t a, int64_t b) {
+                if (a > b) return;
+                dst.insert(dst.end(), {(int32_t)sg, (int32_t)(r * TY), (int32_t)(a * TX),
+                                       (int32_t)(b - a + 1)});
+            };
+            push(items, k0, k1);
+            n_tiles_kept += std::max<int64_t>(0, k1 - k0 + 1);
+            if (k0 > k1) {
+                push(tail, t0x, t1x);
+            } else {
+                push(tail, t0x, k0 - 1);
+                push(tail, k1 + 1, t1x);
+            }
+        }
     }
-    {   // Work order: segments of one velocity-block row share their y shifts,
-        // so (block row, band of tile rows, segment, tile row) keeps the
-        // windows of neighbouring items in one band of the catalog; the
-        // kernel gives each XCD a contiguous range of this order, so the
-        // workgroups resident on one XCD read from one L2-sized band.
+    // Work order: segments of one velocity-block row share their y shifts,
+    // so (block row, band of tile rows, segment, tile row) keeps the windows
+    // of neighbouring items in one band of the catalog; the kernel gives each
+    // XCD a contiguous range of this order, so the workgroups resident on one
+    // XCD read from one L2-sized band.  The kept items and the tail are
+    // ordered separately.
+    for (std::vector<int32_t> *list : {&items, &tail}) {
+        std::vector<int32_t> &items = *list;
         const int64_t n_it = (int64_t)items.size() / 4;
         const int64_t band = 4 * (int64_t)TY;
         std::vector<int64_t> idx(n_it);
@@ -699,8 +789,12 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
         items.swap(sorted);
     }
     p->n_segments = n_seg;
+    p->n_items_kept = (int64_t)items.size() / 4;
+    items.insert(items.end(), tail.begin(), tail.end());
     p->n_items = (int64_t)items.size() / 4;
     p->n_tiles = n_tiles;
+    p->n_tiles_kept = n_tiles_kept;
+    p->e_first = e_first;
     if (p->n_items >= ((int64_t)1 << 31))
         return fail(SAS_E_UNSUPPORTED, "sas_plan_create: too many work items");
 
@@ -807,6 +901,8 @@ sas_status sas_plan_get_info(const sas_plan *p, sas_plan_info *info) {
     if (!p || !info) return fail(SAS_E_INVALID, "sas_plan_get_info: null argument");
     info->n_items = p->n_items;
     info->n_tiles = p->n_tiles;
+    info->n_items_kept = p->n_items_kept;
+    info->n_tiles_kept = p->n_tiles_kept;
     info->n_blocks = p->path == SAS_PATH_SORT ? (int64_t)p->sort_blocks.size() : p->n_segments;
     info->path = p->path;
     info->tile_x = p->tile_x;
@@ -833,6 +929,12 @@ sas_status sas_plan_set_probe(sas_plan *p, void *ev_before, void *ev_after) {
         return fail(SAS_E_INVALID, "sas_plan_set_probe: give both events or neither");
     p->probe[0] = (hipEvent_t)ev_before;
     p->probe[1] = (hipEvent_t)ev_after;
+    return SAS_OK;
+}
+
+sas_status sas_plan_set_counter(sas_plan *p, uint64_t *counter_dev) {
+    if (!p) return fail(SAS_E_INVALID, "sas_plan_set_counter: null plan");
+    p->counter = (unsigned long long *)counter_dev;
     return SAS_OK;
 }
 
@@ -999,7 +1101,7 @@ struct sas_batch {
     struct Class {
         int mode = 0, groups = 1, packed = 0;
         int32_t *d_items5 = nullptr;
-        int64_t n_items = 0;
+        int64_t n_items = 0, n_kept = 0;
         int32_t hist_words_max = 0;
         size_t lds = 0;
     };
@@ -1009,6 +1111,7 @@ struct sas_batch {
     char *ws = nullptr;
     std::vector<void *> allocs;
     hipEvent_t probe[2] = {nullptr, nullptr};
+    unsigned long long *counter = nullptr;
 };
 
 namespace {
@@ -1095,14 +1198,16 @@ sas_status sas_batch_create(const sas_batch_chip *chips, int32_t n_chips, void *
     for (int32_t c = 0; c < n_chips; ++c) {
         const sas_plan *p = chips[c].plan;
         const double dens = (double)chips[c].n / p->footprint_cells;  // detections per cell
-        chip_cost[c] = (double)p->n_tiles *
+        chip_cost[c] = (double)p->n_tiles_kept *
                        ((double)p->tile_x * p->tile_y * dens * (64 / p->groups) + 4096.0);
     }
     std::vector<int32_t> chip_order(n_chips);
     for (int32_t c = 0; c < n_chips; ++c) chip_order[c] = c;
     std::stable_sort(chip_order.begin(), chip_order.end(),
                      [&](int32_t u, int32_t w) { return chip_cost[u] > chip_cost[w]; });
-    std::vector<std::vector<It>> per_class(kMaxBatchClasses);
+    // Per class: every chip's kept items (chip-major), then every chip's
+    // skipped tiles (voted only for a chip whose earliest epoch is empty).
+    std::vector<std::vector<It>> per_class(kMaxBatchClasses), tails(kMaxBatchClasses);
     for (int32_t c : chip_order) {
         const sas_plan *p = chips[c].plan;
         if (chips[c].n == 0 || p->n_items == 0) continue;
@@ -1115,13 +1220,16 @@ sas_status sas_batch_create(const sas_batch_chip *chips, int32_t n_chips, void *
             it.v[2] = src[1];
             it.v[3] = src[2];
             it.v[4] = src[3];
-            per_class[k].push_back(it);
+            (q < p->n_items_kept ? per_class[k] : tails[k]).push_back(it);
         }
     }
     for (int k = 0; k < kMaxBatchClasses; ++k) {
-        if (per_class[k].empty()) continue;
+        if (per_class[k].empty() && tails[k].empty()) continue;
+        const int64_t n_kept = (int64_t)per_class[k].size();
+        per_class[k].insert(per_class[k].end(), tails[k].begin(), tails[k].end());
         const std::vector<It> &v = per_class[k];
         sas_batch::Class cl;
+        cl.n_kept = n_kept;
         cl.mode = k / 6;
         cl.groups = (k / 2 % 3 == 0) ? 1 : (k / 2 % 3 == 1) ? 2 : 4;
         cl.packed = k % 2;
@@ -1184,6 +1292,12 @@ sas_status sas_batch_set_probe(sas_batch *b, void *ev_before, void *ev_after) {
     return SAS_OK;
 }
 
+sas_status sas_batch_set_counter(sas_batch *b, uint64_t *counter_dev) {
+    if (!b) return fail(SAS_E_INVALID, "sas_batch_set_counter: null batch");
+    b->counter = (unsigned long long *)counter_dev;
+    return SAS_OK;
+}
+
 sas_status sas_vote_batch(const sas_batch *b, void *stream) {
     if (!b) return fail(SAS_E_INVALID, "sas_vote_batch: null batch");
     hipStream_t s = (hipStream_t)stream;
@@ -1206,8 +1320,9 @@ sas_status sas_vote_batch(const sas_batch *b, void *stream) {
         // persistent: as many workgroups as fit on the device at once
         const int per_cu = std::max<int>(1, (int)(kLdsPerCU / (cl.lds + dense_static_lds_bytes())));
         const int grid = (int)std::min<int64_t>(cl.n_items, (int64_t)n_cu * per_cu);
-        e = launch_vote_dense_batch(cl.mode, cl.groups, cl.packed, b->d_args, cl.d_items5,
-                                    cl.n_items, cl.hist_words_max, cl.lds, grid, s);
+        e = launch_vote_dense_batch(cl.mode, cl.groups, cl.packed, b->d_args,
+                                    (int32_t)b->chips.size(), cl.d_items5, cl.n_items, cl.n_kept,
+                                    cl.hist_words_max, cl.lds, grid, b->counter, s);
         if (e != hipSuccess) return hip_fail(e, "sas_vote_batch: vote launch");
     }
     if (b->probe[1] && (e = hipEventRecord(b->probe[1], s)) != hipSuccess)

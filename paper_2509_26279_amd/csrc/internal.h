@@ -61,12 +61,16 @@ struct DenseArgs {
     const int32_t *seg_guard; // [n_seg][NV] left guard cells gx | gy << 16
     const int32_t *items;     // [n_items][4] segment, ty0, first tx0, number of tiles
     int64_t n_items;
+    int64_t n_items_kept;     // items [0, n_items_kept) suffice when epoch e_first (the
+    int32_t e_first;          // earliest scheduled) holds a detection; the rest hold only
+                              // tiles that fewer than N_min epochs can reach from it
     int4 *refine;             // [refine_cap] queued (v_idx, cell x, cell y, 0)
     unsigned long long *refine_count;
     int64_t refine_cap;
     sas_candidate *cand;
     int64_t cand_cap;
     sas_vote_result *res;
+    unsigned long long *atomics;  // or null: adds the LDS atomic vote instructions issued
 };
 
 // Workspace carve-up for the preparation stage.
@@ -236,11 +240,12 @@ hipError_t mlp_refresh(const MlpBuffers &b, hipStream_t s);
 hipError_t launch_vote_dense(int mode, int groups, const DenseArgs &a, hipStream_t stream,
                              hipEvent_t ev0, hipEvent_t ev1);
 // One persistent launch over the merged items (chip, segment, ty0, txf,
-// ntiles) of many chips of one kernel class.
+// ntiles) of many chips of one kernel class: every chip's kept items first
+// (n_kept of them), then the tiles skipped by coverage.
 hipError_t launch_vote_dense_batch(int mode, int groups, int packed, const DenseArgs *chips_dev,
-                                   const int32_t *items5_dev, int64_t n_items,
-                                   int32_t hist_words_max, size_t lds, int grid,
-                                   hipStream_t stream);
+                                   int32_t n_chips, const int32_t *items5_dev, int64_t n_items,
+                                   int64_t n_kept, int32_t hist_words_max, size_t lds, int grid,
+                                   unsigned long long *atomics, hipStream_t stream);
 hipError_t launch_refine(const DenseArgs &a, hipStream_t stream);
 size_t dense_lds_bytes(int groups, int hx, int hy, int stage_cap, int packed);
 size_t dense_static_lds_bytes();

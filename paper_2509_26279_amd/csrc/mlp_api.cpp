@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -20,6 +21,7 @@ using namespace sas;
 struct sas_mlp {
     int64_t max_batch = 0;
     int64_t step = 0;
+    uint64_t seed = 0;
     MlpBuffers b{};
     std::vector<void *> allocs;
 };
@@ -68,6 +70,7 @@ sas_status sas_mlp_create(int64_t max_batch, uint64_t seed, sas_mlp **out) {
     *out = nullptr;
     std::unique_ptr<sas_mlp> m(new sas_mlp());
     m->max_batch = max_batch;
+    m->seed = seed;
     const size_t B = (size_t)max_batch, H = kMlpHidden;
     const size_t nz = (size_t)((max_batch + kMlpSplitK - 1) / kMlpSplitK);
     MlpBuffers &b = m->b;
@@ -141,6 +144,79 @@ sas_status sas_mlp_set_params(sas_mlp *m, const float *host, int64_t n) {
     if (!m || !host || n != kMlpParams)
         return mfail(SAS_E_INVALID, "sas_mlp_set_params: needs 20865 values");
     return upload_params(m, host);
+}
+
+// Checkpoint: a text header of kCkptHeader bytes (one JSON object, padded
+// with spaces, ending in a newline), then float32 little-endian arrays:
+// masters p, AdamW moments m and v (kMlpParams each), mean and std (kMlpIn
+// each).  The header holds the format, the counts, the step and the seed.
+constexpr int64_t kCkptHeader = 256;
+constexpr int64_t kCkptFloats = 3 * (int64_t)kMlpParams + 2 * kMlpIn;
+constexpr int64_t kCkptBytes = kCkptHeader + 4 * kCkptFloats;
+
+sas_status sas_mlp_save(const sas_mlp *m, void *host, int64_t cap, int64_t *n_out) {
+    if (!m || !n_out) return mfail(SAS_E_INVALID, "sas_mlp_save: null argument");
+    *n_out = kCkptBytes;
+    if (cap < kCkptBytes || !host)
+        return mfail(SAS_E_OVERFLOW, "sas_mlp_save: cap below the checkpoint size in *n_out");
+    char *out = (char *)host;
+    std::string head = "{\"format\": \"sas_mlp\", \"version\": 1, \"params\": " +
+                       std::to_string(kMlpParams) + ", \"inputs\": " + std::to_string(kMlpIn) +
+                       ", \"step\": " + std::to_string(m->step) + ", \"seed\": " +
+                       std::to_string(m->seed) +
+                       ", \"layout\": \"float32 le: p, adam_m, adam_v, mean, std\"}";
+    head.resize(kCkptHeader - 1, ' ');
+    head.push_back('\n');
+    std::memcpy(out, head.data(), kCkptHeader);
+    float *f = (float *)(out + kCkptHeader);
+    const struct {
+        const float *src;
+        int64_t n;
+    } parts[] = {{m->b.p, kMlpParams}, {m->b.m, kMlpParams}, {m->b.v, kMlpParams},
+                 {m->b.mu, kMlpIn}, {m->b.sd, kMlpIn}};
+    for (const auto &pt : parts) {
+        if (hipMemcpy(f, pt.src, sizeof(float) * pt.n, hipMemcpyDeviceToHost) != hipSuccess)
+            return mfail(SAS_E_DEVICE, "sas_mlp_save: copy");
+        f += pt.n;
+    }
+    return SAS_OK;
+}
+
+sas_status sas_mlp_load(sas_mlp *m, const void *host, int64_t n) {
+    if (!m || !host) return mfail(SAS_E_INVALID, "sas_mlp_load: null argument");
+    if (n != kCkptBytes) return mfail(SAS_E_INVALID, "sas_mlp_load: not a checkpoint of this size");
+    const char *in = (const char *)host;
+    const std::string head(in, kCkptHeader);
+    long long step = -1, params = -1, inputs = -1, version = -1;
+    unsigned long long seed = 0;
+    const size_t ps = head.find("\"step\": "), pp = head.find("\"params\": "),
+                 pi = head.find("\"inputs\": "), pv = head.find("\"version\": "),
+                 pd = head.find("\"seed\": ");
+    static const std::string kPrefix = "{\"format\": \"sas_mlp\",";
+    if (head.compare(0, kPrefix.size(), kPrefix) != 0 || ps == std::string::npos ||
+        pp == std::string::npos || pi == std::string::npos || pv == std::string::npos ||
+        pd == std::string::npos || head.back() != '\n' ||
+        std::sscanf(head.c_str() + ps + 8, "%lld", &step) != 1 ||
+        std::sscanf(head.c_str() + pp + 10, "%lld", &params) != 1 ||
+        std::sscanf(head.c_str() + pi + 10, "%lld", &inputs) != 1 ||
+        std::sscanf(head.c_str() + pv + 11, "%lld", &version) != 1 ||
+        std::sscanf(head.c_str() + pd + 8, "%llu", &seed) != 1)
+        return mfail(SAS_E_INVALID, "sas_mlp_load: bad checkpoint header");
+    if (version != 1 || params != kMlpParams || inputs != kMlpIn || step < 0)
+        return mfail(SAS_E_INVALID, "sas_mlp_load: checkpoint of another network or version");
+    const float *f = (const float *)(in + kCkptHeader);
+    float *dst[] = {m->b.p, m->b.m, m->b.v, m->b.mu, m->b.sd};
+    const int64_t cnt[] = {kMlpParams, kMlpParams, kMlpParams, kMlpIn, kMlpIn};
+    for (int k = 0; k < 5; ++k) {
+        if (hipMemcpy(dst[k], f, sizeof(float) * cnt[k], hipMemcpyHostToDevice) != hipSuccess)
+            return mfail(SAS_E_DEVICE, "sas_mlp_load: upload");
+        f += cnt[k];
+    }
+    if (mlp_refresh(m->b, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+        return mfail(SAS_E_DEVICE, "sas_mlp_load: refreshing the bf16 weights");
+    m->step = step;
+    m->seed = seed;
+    return SAS_OK;
 }
 
 sas_status sas_mlp_forward(const sas_mlp *m, const float *x_dev, int64_t n, float *logits_dev,

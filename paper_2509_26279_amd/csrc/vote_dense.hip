@@ -332,9 +332,10 @@ __device__ __attribute__((always_inline)) inline int32_t run_part(
 // One work item: a segment and a row of ntiles tiles starting at tile column
 // txf (cells), tile row ty0.  The histogram is all zero on entry and on exit;
 // sh.dt holds the catalog's d_e.
+// n_instr (wave uniform) counts the wave's LDS atomic vote instructions.
 template <int MODE, int G, bool PK>
 __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t sg, int32_t ty0,
-                          int32_t txf, int32_t ntiles, int32_t &tseq) {
+                          int32_t txf, int32_t ntiles, int32_t &tseq, uint32_t &n_instr) {
     constexpr int NV = 64 / G;
     constexpr int LNV = G == 1 ? 6 : G == 2 ? 5 : 4;
     constexpr bool WT = weighted_mode<MODE>();
@@ -589,6 +590,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                 const int32_t n = __builtin_amdgcn_readlane(my_n, k);
                 if (n == 0) continue;
                 const int32_t b = __builtin_amdgcn_readlane(my_b, k);
+                n_instr += (uint32_t)(n + G - 1) / G;
                 vote_run<MODE, G>(wst + b, n, vote_addr(Sx[k], Sy[PK ? 0 : k]),
                                   MODE == kMask32 ? (1u << e) : cval, g);
             }
@@ -597,6 +599,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                 const int32_t n = __builtin_amdgcn_readlane(my_n, k);
                 if (n == 0) continue;
                 const int32_t b = __builtin_amdgcn_readlane(my_b, k);
+                n_instr += (uint32_t)(n + G - 1) / G;
                 const int32_t d = sh.dt[e];
                 const int32_t sx = shift_q8(my_vx, d) + (int32_t)ox_lane;
                 const int32_t sy = shift_q8(my_vy, d) + (int32_t)oy_lane;
@@ -718,10 +721,17 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
     // workgroups resident on one XCD take neighbouring items.
     const int64_t grid = gridDim.x;  // a multiple of kXcds
     const int64_t logical = (int64_t)(blockIdx.x % kXcds) * (grid / kXcds) + blockIdx.x / kXcds;
-    for (int64_t item = logical; item < a.n_items; item += grid) {
+    // The items past n_items_kept hold tiles that fewer than N_min epochs
+    // reach when the reference epoch is the earliest scheduled one; they are
+    // voted only when that epoch holds no detection (then t0 is later).
+    const int64_t n_walk = a.cat.dt[a.e_first] == 0 ? a.n_items_kept : a.n_items;
+    uint32_t n_instr = 0;
+    for (int64_t item = logical; item < n_walk; item += grid) {
         const int32_t *it = a.items + 4 * item;
-        vote_item<MODE, G, PK>(a, sh, smem4, it[0], it[1], it[2], it[3], tseq);
+        vote_item<MODE, G, PK>(a, sh, smem4, it[0], it[1], it[2], it[3], tseq, n_instr);
     }
+    if (a.atomics && __lane_id() == 0 && n_instr)
+        atomicAdd(a.atomics, (unsigned long long)n_instr);
 }
 
 // Many catalogs in one persistent launch (one workgroup per resident slot):
@@ -730,23 +740,34 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
 // kernel walks its items, and each item reads its chip's parameters from
 // chips[].  Every chip of the launch uses this kernel's cell variant and lane
 // groups (and vote form); hist_words_max covers the largest histogram among
-// them.
+// them.  Items [0, n_kept) are every chip's kept items; the rest hold tiles
+// that fewer than N_min epochs reach (see k_vote_dense), voted only for the
+// chips whose earliest scheduled epoch holds no detection.
 template <int MODE, int G, bool PK>
 __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_vote_dense_batch(const DenseArgs *__restrict__ chips,
+                                                         int32_t n_chips,
                                                          const int32_t *__restrict__ items5,
-                                                         int64_t n_items, int32_t hist_words_max) {
+                                                         int64_t n_items, int64_t n_kept,
+                                                         int32_t hist_words_max,
+                                                         unsigned long long *atomics) {
     extern __shared__ uint4 smem4[];
     __shared__ Shared sh;
     const int tid = threadIdx.x;
     for (int i = tid; i < hist_words_max / 4; i += T) smem4[i] = make_uint4(0, 0, 0, 0);
     int32_t tseq = 0, chip_now = -1;  // tseq: tiles done by this workgroup
     if (tid < 4) sh.voted[tid] = 0;
+    int later_t0 = 0;  // some chip's reference epoch is later than its earliest epoch
+    for (int c = tid; c < n_chips; c += T) later_t0 |= chips[c].cat.dt[chips[c].e_first] != 0;
+    later_t0 = __syncthreads_or(later_t0);
+    const int64_t n_walk = later_t0 ? n_items : n_kept;
+    uint32_t n_instr = 0;  // LDS atomic vote instructions of this wave
     const int64_t grid = gridDim.x;  // a multiple of kXcds
     const int64_t logical = (int64_t)(blockIdx.x % kXcds) * (grid / kXcds) + blockIdx.x / kXcds;
-    for (int64_t item = logical; item < n_items; item += grid) {
+    for (int64_t item = logical; item < n_walk; item += grid) {
         const int32_t *it = items5 + 5 * item;
         const int chip = it[0];
         const DenseArgs &a = chips[chip];
+        if (item >= n_kept && a.cat.dt[a.e_first] == 0) continue;  // block uniform
         if (chip != chip_now) {
             __syncthreads();  // the previous item no longer reads sh.dt or the stage
             if (tid < a.cat.n_epochs) sh.dt[tid] = a.cat.dt[tid];
@@ -755,8 +776,9 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
             for (int i = tid; i < hw / 4; i += T) smem4[i] = make_uint4(0, 0, 0, 0);
             chip_now = chip;
         }
-        vote_item<MODE, G, PK>(a, sh, smem4, it[1], it[2], it[3], it[4], tseq);
+        vote_item<MODE, G, PK>(a, sh, smem4, it[1], it[2], it[3], it[4], tseq, n_instr);
     }
+    if (atomics && __lane_id() == 0 && n_instr) atomicAdd(atomics, (unsigned long long)n_instr);
 }
 
 // Exact bins of a queued cell: for velocity v and the cell's 2^m x 2^m
@@ -898,37 +920,43 @@ hipError_t launch_m(int groups, const DenseArgs &a, size_t lds, hipStream_t s, h
     }
 }
 
+struct BatchLaunch {
+    const DenseArgs *chips;
+    int32_t n_chips;
+    const int32_t *items5;
+    int64_t n_items, n_kept;
+    int32_t hist_words_max;
+    size_t lds;
+    int grid;
+    unsigned long long *atomics;
+};
+
 template <int MODE, int G, bool PK>
-hipError_t launch_batch_mg(const DenseArgs *chips, const int32_t *items5, int64_t n_items,
-                           int32_t hist_words_max, size_t lds, int grid, hipStream_t stream) {
+hipError_t launch_batch_mg(const BatchLaunch &b, hipStream_t stream) {
     static size_t lds_set = 0;
-    hipError_t e = set_lds_limit((const void *)k_vote_dense_batch<MODE, G, PK>, lds, &lds_set);
+    hipError_t e = set_lds_limit((const void *)k_vote_dense_batch<MODE, G, PK>, b.lds, &lds_set);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_vote_dense_batch<MODE, G, PK>), dim3(grid), dim3(T), lds, stream,
-                       chips, items5, n_items, hist_words_max);
+    hipLaunchKernelGGL((k_vote_dense_batch<MODE, G, PK>), dim3(b.grid), dim3(T), b.lds, stream,
+                       b.chips, b.n_chips, b.items5, b.n_items, b.n_kept, b.hist_words_max,
+                       b.atomics);
     return hipGetLastError();
 }
 
 template <int MODE, bool PK>
-hipError_t launch_batch_m(int groups, const DenseArgs *chips, const int32_t *items5,
-                          int64_t n_items, int32_t hwm, size_t lds, int grid, hipStream_t s) {
+hipError_t launch_batch_m(int groups, const BatchLaunch &b, hipStream_t s) {
     switch (groups) {
-    case 1: return launch_batch_mg<MODE, 1, PK>(chips, items5, n_items, hwm, lds, grid, s);
-    case 2: return launch_batch_mg<MODE, 2, PK>(chips, items5, n_items, hwm, lds, grid, s);
-    default: return launch_batch_mg<MODE, 4, PK>(chips, items5, n_items, hwm, lds, grid, s);
+    case 1: return launch_batch_mg<MODE, 1, PK>(b, s);
+    case 2: return launch_batch_mg<MODE, 2, PK>(b, s);
+    default: return launch_batch_mg<MODE, 4, PK>(b, s);
     }
 }
 
 template <bool PK>
-hipError_t launch_batch_p(int mode, int groups, const DenseArgs *chips, const int32_t *items5,
-                          int64_t n_items, int32_t hwm, size_t lds, int grid, hipStream_t s) {
+hipError_t launch_batch_p(int mode, int groups, const BatchLaunch &b, hipStream_t s) {
     switch (mode) {
-    case kMask32:
-        return launch_batch_m<kMask32, PK>(groups, chips, items5, n_items, hwm, lds, grid, s);
-    case kCountDet:
-        return launch_batch_m<kCountDet, PK>(groups, chips, items5, n_items, hwm, lds, grid, s);
-    default:
-        return launch_batch_m<kCountRef, PK>(groups, chips, items5, n_items, hwm, lds, grid, s);
+    case kMask32: return launch_batch_m<kMask32, PK>(groups, b, s);
+    case kCountDet: return launch_batch_m<kCountDet, PK>(groups, b, s);
+    default: return launch_batch_m<kCountRef, PK>(groups, b, s);
     }
 }
 
@@ -960,15 +988,14 @@ size_t dense_lds_bytes(int groups, int hx, int hy, int stage_cap, int packed) {
 size_t dense_static_lds_bytes() { return sizeof(Shared); }
 
 hipError_t launch_vote_dense_batch(int mode, int groups, int packed, const DenseArgs *chips_dev,
-                                   const int32_t *items5_dev, int64_t n_items,
-                                   int32_t hist_words_max, size_t lds, int grid,
-                                   hipStream_t stream) {
+                                   int32_t n_chips, const int32_t *items5_dev, int64_t n_items,
+                                   int64_t n_kept, int32_t hist_words_max, size_t lds, int grid,
+                                   unsigned long long *atomics, hipStream_t stream) {
     if (n_items <= 0) return hipSuccess;
-    grid = (grid + kXcds - 1) / kXcds * kXcds;
-    return packed ? launch_batch_p<true>(mode, groups, chips_dev, items5_dev, n_items,
-                                         hist_words_max, lds, grid, stream)
-                  : launch_batch_p<false>(mode, groups, chips_dev, items5_dev, n_items,
-                                          hist_words_max, lds, grid, stream);
+    const BatchLaunch b{chips_dev, n_chips, items5_dev, n_items, n_kept, hist_words_max, lds,
+                        (grid + kXcds - 1) / kXcds * kXcds, atomics};
+    return packed ? launch_batch_p<true>(mode, groups, b, stream)
+                  : launch_batch_p<false>(mode, groups, b, stream);
 }
 
 hipError_t launch_refine(const DenseArgs &a, hipStream_t stream) {

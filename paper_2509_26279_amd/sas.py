@@ -69,7 +69,8 @@ class Tuning(ctypes.Structure):
                 ("cell_log2", ctypes.c_int32), ("sort_vblock", ctypes.c_int32),
                 ("n_det_hint", ctypes.c_int32), ("coarse_log2", ctypes.c_int32),
                 ("refine_cap", ctypes.c_int32), ("packed", ctypes.c_int32),
-                ("weight_hint", ctypes.c_int32), ("half_counts", ctypes.c_int32)]
+                ("weight_hint", ctypes.c_int32), ("half_counts", ctypes.c_int32),
+                ("prune", ctypes.c_int32)]
 
 
 class BatchChip(ctypes.Structure):
@@ -87,6 +88,10 @@ class PlanDesc(ctypes.Structure):
                 ("tuning", ctypes.c_void_p)]
 
 
+class AutotuneTrial(ctypes.Structure):
+    _fields_ = [("tuning", Tuning), ("ms", ctypes.c_float), ("status", ctypes.c_int32)]
+
+
 class PlanInfo(ctypes.Structure):
     _fields_ = [("n_items", ctypes.c_int64), ("n_tiles", ctypes.c_int64),
                 ("n_blocks", ctypes.c_int64),
@@ -97,21 +102,26 @@ class PlanInfo(ctypes.Structure):
                 ("groups", ctypes.c_int32), ("hist_x", ctypes.c_int32),
                 ("hist_y", ctypes.c_int32), ("stage_cap", ctypes.c_int32),
                 ("lds_bytes", ctypes.c_int32), ("packed", ctypes.c_int32),
-                ("half_counts", ctypes.c_int32)]
+                ("half_counts", ctypes.c_int32), ("n_tiles_kept", ctypes.c_int64),
+                ("n_items_kept", ctypes.c_int64)]
 
 
 _lib = None
 
 EXPORTS = ["sas_status_string", "sas_last_error", "sas_version", "sas_grid_spacing",
            "sas_build_grid", "sas_plan_create", "sas_plan_destroy", "sas_plan_get_info",
-           "sas_plan_set_probe", "sas_vote_workspace_size", "sas_vote", "sas_vote_weighted",
+           "sas_plan_set_probe", "sas_plan_set_counter", "sas_batch_set_counter",
+           "sas_vote_workspace_size", "sas_vote", "sas_vote_weighted",
            "sas_vote_static", "sas_peaks",
            "sas_threshold_n_min", "sas_batch_workspace_size", "sas_batch_create",
            "sas_batch_destroy", "sas_vote_batch", "sas_batch_set_probe", "sas_features",
            "sas_features_scratch_size", "sas_extract_scratch_size", "sas_extract_clusters",
            "sas_refine_clusters",
+           "sas_autotune", "sas_autotune_default_candidates", "sas_autotune_key",
+           "sas_autotune_cache_get", "sas_autotune_cache_put",
+           "sas_measure_ceilings",
            "sas_mlp_create", "sas_mlp_destroy", "sas_mlp_set_norm", "sas_mlp_get_params",
-           "sas_mlp_set_params", "sas_mlp_forward", "sas_mlp_grad", "sas_mlp_train_step"]
+           "sas_mlp_set_params", "sas_mlp_save", "sas_mlp_load", "sas_mlp_forward", "sas_mlp_grad", "sas_mlp_train_step"]
 
 
 def load():
@@ -139,6 +149,8 @@ def load():
         "sas_plan_destroy": (I32, [P]),
         "sas_plan_get_info": (I32, [P, P]),
         "sas_plan_set_probe": (I32, [P, P, P]),
+        "sas_plan_set_counter": (I32, [P, P]),
+        "sas_batch_set_counter": (I32, [P, P]),
         "sas_vote_workspace_size": (I32, [P, I64, P]),
         "sas_vote": (I32, [P, P, P, P, I64, P, I64, P, P, SZ, P]),
         "sas_vote_weighted": (I32, [P, P, P, P, P, I64, P, I64, P, P, SZ, P]),
@@ -158,11 +170,19 @@ def load():
         "sas_extract_scratch_size": (I32, [I64, I64, I64, ctypes.POINTER(ctypes.c_size_t)]),
         "sas_extract_clusters": (I32, [P, P, SZ, I64, P, I64, I64, P, SZ, P, I64, P, P, I32,
                                        P]),
+        "sas_autotune": (I32, [P, P, P, P, I64, P, I32, I32, P, P, P]),
+        "sas_autotune_default_candidates": (I32, [P, P, I32, P]),
+        "sas_autotune_key": (I32, [P, I64, ctypes.c_char_p, I64]),
+        "sas_autotune_cache_get": (I32, [ctypes.c_char_p, ctypes.c_char_p, P, P]),
+        "sas_autotune_cache_put": (I32, [ctypes.c_char_p, ctypes.c_char_p, P]),
+        "sas_measure_ceilings": (I32, [P, P]),
         "sas_mlp_create": (I32, [I64, ctypes.c_uint64, P]),
         "sas_mlp_destroy": (I32, [P]),
         "sas_mlp_set_norm": (I32, [P, P, P]),
         "sas_mlp_get_params": (I32, [P, P, I64, P]),
         "sas_mlp_set_params": (I32, [P, P, I64]),
+        "sas_mlp_save": (I32, [P, P, I64, P]),
+        "sas_mlp_load": (I32, [P, P, I64]),
         "sas_mlp_forward": (I32, [P, P, I64, P, P]),
         "sas_mlp_grad": (I32, [P, P, P, I64, ctypes.c_float, P, P, P]),
         "sas_mlp_train_step": (I32, [P, P, P, I64, ctypes.c_float, ctypes.c_float,
@@ -232,27 +252,45 @@ def threshold_n_min(n_epochs: int, mu: float, n_stacks: float, n_false: float = 
 
 # --------------------------------------------------------------------------- plans
 
+def tuning_struct(tuning) -> Tuning:
+    """A sas_tuning from a dict of its fields (absent fields 0)."""
+    keys = [k for k, _ in Tuning._fields_]
+    unknown = sorted(set(tuning) - set(keys))
+    if unknown:
+        raise ValueError("unknown tuning keys: %s" % ", ".join(unknown))
+    return Tuning(*[int(tuning.get(k, 0)) for k in keys])
+
+
+def tuning_dict(t: Tuning) -> dict:
+    """The nonzero fields of a sas_tuning."""
+    return {k: int(getattr(t, k)) for k, _ in Tuning._fields_ if getattr(t, k)}
+
+
+class _Desc:
+    """A sas_plan_desc with the arrays it points to kept alive."""
+
+    def __init__(self, velocities, t_q16, binw_q8, n_min, extent_q8, mode="epochs",
+                 count_sat=65535, path="auto", tuning=None):
+        self.v = np.ascontiguousarray(velocities, dtype=np.int32).reshape(-1, 2)
+        self.t = np.ascontiguousarray(t_q16, dtype=np.int64)
+        self.tuning = tuning_struct(tuning) if tuning is not None else None
+        self.desc = PlanDesc(self.v.ctypes.data, self.v.shape[0], self.t.shape[0],
+                             self.t.ctypes.data, int(binw_q8), int(n_min), MODES[mode],
+                             int(count_sat), PATHS[path],
+                             (ctypes.c_int32 * 4)(*map(int, extent_q8)),
+                             ctypes.addressof(self.tuning) if self.tuning is not None else None)
+
+
 class Plan:
     """A work decomposition for one (velocity set, epochs, parameters, footprint)."""
 
     def __init__(self, velocities, t_q16, binw_q8, n_min, extent_q8, mode="epochs",
                  count_sat=65535, path="auto", tuning=None):
         lib = load()
-        self._v = np.ascontiguousarray(velocities, dtype=np.int32).reshape(-1, 2)
-        self._t = np.ascontiguousarray(t_q16, dtype=np.int64)
-        self._tuning = None
-        if tuning is not None:
-            keys = [k for k, _ in Tuning._fields_]
-            unknown = sorted(set(tuning) - set(keys))
-            if unknown:
-                raise ValueError("unknown tuning keys: %s" % ", ".join(unknown))
-            self._tuning = Tuning(*[int(tuning.get(k, 0)) for k in keys])
-        desc = PlanDesc(self._v.ctypes.data, self._v.shape[0], self._t.shape[0],
-                        self._t.ctypes.data, int(binw_q8), int(n_min), MODES[mode],
-                        int(count_sat), PATHS[path], (ctypes.c_int32 * 4)(*map(int, extent_q8)),
-                        ctypes.addressof(self._tuning) if self._tuning is not None else None)
+        d = _Desc(velocities, t_q16, binw_q8, n_min, extent_q8, mode, count_sat, path, tuning)
+        self._v, self._t, self._tuning = d.v, d.t, d.tuning
         self._p = ctypes.c_void_p()
-        _check(lib.sas_plan_create(ctypes.byref(desc), ctypes.byref(self._p)))
+        _check(lib.sas_plan_create(ctypes.byref(d.desc), ctypes.byref(self._p)))
         self.mode = mode
         self.weighted = MODES[mode] >= 2
         self.n_v = self._v.shape[0]
@@ -274,6 +312,12 @@ class Plan:
         h1 = ctypes.c_void_p(ev_after.cuda_event) if ev_after is not None else None
         _check(load().sas_plan_set_probe(self._p, h0, h1))
 
+    def set_counter(self, counter=None):
+        """Later votes add their LDS atomic vote instructions to `counter`, a
+        device int64 tensor of one element (None: off)."""
+        _check(load().sas_plan_set_counter(self._p, counter.data_ptr() if counter is not None
+                                           else None))
+
     def workspace_size(self, n: int) -> int:
         out = ctypes.c_size_t()
         _check(load().sas_vote_workspace_size(self._p, int(n), ctypes.byref(out)))
@@ -289,6 +333,71 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+# --------------------------------------------------------------------------- autotuner
+
+class Ceilings(ctypes.Structure):
+    _fields_ = [("lds_atomic_conflict_free", ctypes.c_double),
+                ("lds_atomic_lane_groups", ctypes.c_double),
+                ("valu_int32_ops", ctypes.c_double), ("valu_int16x2_ops", ctypes.c_double),
+                ("hbm_copy_bytes_per_s", ctypes.c_double)]
+
+
+def measure_ceilings(stream=None) -> dict:
+    """Measured rates of the LDS atomics, integer VALU and HBM (sas_measure_ceilings)."""
+    c = Ceilings()
+    _check(load().sas_measure_ceilings(ctypes.byref(c), _stream_handle(stream)))
+    return {k: float(getattr(c, k)) for k, _ in Ceilings._fields_}
+
+
+def autotune_key(velocities, t_q16, binw_q8, n_min, extent_q8, n, mode="epochs") -> str:
+    """Shape class of a catalog (sas_autotune_key)."""
+    d = _Desc(velocities, t_q16, binw_q8, n_min, extent_q8, mode)
+    buf = ctypes.create_string_buffer(160)
+    _check(load().sas_autotune_key(ctypes.byref(d.desc), int(n), buf, 160))
+    return buf.value.decode()
+
+
+def autotune_default_candidates(velocities, t_q16, binw_q8, n_min, extent_q8, mode="epochs",
+                                count_sat=65535, base=None) -> list:
+    """The library's built-in candidate tunings around the planner's choice."""
+    d = _Desc(velocities, t_q16, binw_q8, n_min, extent_q8, mode, count_sat, "auto", base or {})
+    out = (Tuning * 64)()
+    n = ctypes.c_int32()
+    _check(load().sas_autotune_default_candidates(ctypes.byref(d.desc), out, 64,
+                                                  ctypes.byref(n)))
+    return [tuning_dict(out[k]) for k in range(n.value)]
+
+
+def autotune(velocities, t_q16, binw_q8, n_min, extent_q8, x, y, epoch, cands, reps=3,
+             mode="epochs", count_sat=65535, stream=None):
+    """sas_autotune over the candidate tunings (dicts): (best tuning dict,
+    [(tuning dict, ms or None, status)])."""
+    d = _Desc(velocities, t_q16, binw_q8, n_min, extent_q8, mode, count_sat)
+    arr = (Tuning * len(cands))(*[tuning_struct(c) for c in cands])
+    trials = (AutotuneTrial * len(cands))()
+    best = Tuning()
+    _check(load().sas_autotune(ctypes.byref(d.desc), x.data_ptr(), y.data_ptr(), epoch.data_ptr(),
+                               int(x.numel()), arr, len(cands), int(reps), trials,
+                               ctypes.byref(best), _stream_handle(stream)))
+    table = [(tuning_dict(t.tuning), float(t.ms) if t.ms >= 0 else None, int(t.status))
+             for t in trials]
+    return tuning_dict(best), table
+
+
+def autotune_cache_get(path: str, key: str):
+    """The cached tuning dict of a shape class, or None."""
+    t = Tuning()
+    found = ctypes.c_int32()
+    _check(load().sas_autotune_cache_get(path.encode(), key.encode(), ctypes.byref(t),
+                                         ctypes.byref(found)))
+    return tuning_dict(t) if found.value else None
+
+
+def autotune_cache_put(path: str, key: str, tuning: dict) -> None:
+    t = tuning_struct(tuning)
+    _check(load().sas_autotune_cache_put(path.encode(), key.encode(), ctypes.byref(t)))
 
 
 def _stream_handle(stream):
@@ -555,6 +664,12 @@ class Batch:
         h1 = ctypes.c_void_p(ev_after.cuda_event) if ev_after is not None else None
         _check(load().sas_batch_set_probe(self._b, h0, h1))
 
+    def set_counter(self, counter=None):
+        """Later votes add their LDS atomic vote instructions to `counter`, a
+        device int64 tensor of one element (None: off)."""
+        _check(load().sas_batch_set_counter(self._b, counter.data_ptr() if counter is not None
+                                            else None))
+
     def peaks(self, k: int, order="canonical", top_k=0, stream=None):
         return peaks(self.cand[k], self.res[k], order, top_k, stream)
 
@@ -598,6 +713,22 @@ class MLP:
     def set_params(self, p):
         p = np.ascontiguousarray(p, dtype=np.float32)
         _check(load().sas_mlp_set_params(self._m, p.ctypes.data, p.shape[0]))
+
+    def save(self) -> bytes:
+        """Checkpoint (sas_mlp_save): header, masters, AdamW moments, norm."""
+        n = ctypes.c_int64()
+        lib = load()
+        st = lib.sas_mlp_save(self._m, None, 0, ctypes.byref(n))
+        if st not in (SAS_OK, SAS_E_OVERFLOW):
+            _check(st)
+        buf = ctypes.create_string_buffer(n.value)
+        _check(lib.sas_mlp_save(self._m, buf, n.value, ctypes.byref(n)))
+        return buf.raw[:n.value]
+
+    def load(self, blob: bytes):
+        """Restore a checkpoint written by save() (sas_mlp_load)."""
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        _check(load().sas_mlp_load(self._m, buf, len(blob)))
 
     def forward(self, x, stream=None):
         import torch

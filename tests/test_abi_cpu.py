@@ -20,13 +20,25 @@ def _declared():
     return sorted(set(re.findall(r"^\w[\w\s\*]*?\b(sas_\w+)\s*\(", txt, re.M)))
 
 
+def _exported():
+    """Names of the sas_* functions the built library exports (dynamic symbols)."""
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", sas.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    return sorted({ln.split()[-1] for ln in out.splitlines()
+                   if len(ln.split()) == 3 and ln.split()[1] == "T"
+                   and ln.split()[-1].startswith("sas_")})
+
+
 def test_library_exports_every_declared_symbol():
     lib = sas.load()
     names = _declared()
     assert "sas_vote" in names and "sas_peaks" in names and "sas_build_grid" in names
     for n in names:
         assert hasattr(lib, n), n
-    assert set(names) <= set(sas.EXPORTS) | set(names)
+    # the header, the library's exported functions and the binding's list agree
+    assert set(_exported()) == set(names), sorted(set(_exported()) ^ set(names))
+    assert set(sas.EXPORTS) == set(names), sorted(set(sas.EXPORTS) ^ set(names))
     assert "gfx950" in sas.version()
 
 
@@ -137,17 +149,30 @@ def test_batch_argument_errors():
 
 def test_autotune_classes_and_cache(tmp_path):
     from paper_2509_26279_amd import autotune
-    k1 = autotune.shape_class(1024, 256, 100, 309460, "sector")
-    assert k1 == autotune.shape_class(1024, 256, 127, 300000, "sector")
-    assert k1 != autotune.shape_class(1024, 256, 128, 300000, "sector")
-    assert k1 != autotune.shape_class(4096, 2048, 100, 309460, "disk")
-    cands = autotune.candidates({"n_det_hint": 5})
-    assert {} not in cands and all(c["n_det_hint"] == 5 for c in cands)
-    assert {c.get("groups") for c in cands} == {None, 1, 2, 4}
-    p = str(tmp_path / "tune.json")
-    assert autotune.load_cache(p) == {}
-    autotune.save_cache(p, {k1: {"tuning": {"groups": 1}, "ms": 1.0}})
-    assert autotune.load_cache(p)[k1]["tuning"] == {"groups": 1}
+    v = np.zeros((84351, 2), np.int32)
+    t100 = np.arange(100) * 262144 // 99  # 4 h in Q16
+    ext = (0, 2048 * 256, 0, 4096 * 256)
+    k1 = autotune.shape_class(v, t100, 1024, 25, ext, 309460)
+    assert k1 == "b1024_s256_E64_n262144_V65536_m0", k1
+    t127 = np.arange(127) * 262144 // 126  # same span, more epochs in the same octave
+    assert k1 == autotune.shape_class(v, t127, 1024, 25, ext, 300000)
+    assert k1 != autotune.shape_class(v, np.arange(128) * 262144 // 127, 1024, 25, ext, 300000)
+    assert k1 != autotune.shape_class(v, t100, 4096, 25, ext, 309460)
+    assert k1 != autotune.shape_class(v[:1000], t100, 1024, 25, ext, 309460)
+    assert k1 != autotune.shape_class(v, t100, 1024, 25, ext, 309460, mode="detections")
+    p = str(tmp_path / "tune.txt")
+    assert autotune.cached(k1, p) is None  # no file: empty cache
+    autotune.store(k1, {"groups": 1, "tile_x": 12}, p)
+    autotune.store("b4096_other", {}, p)
+    autotune.store(k1, {"groups": 2, "n_det_hint": 5}, p)  # replaces the line
+    assert autotune.cached(k1, p) == {"groups": 2, "n_det_hint": 5}
+    assert autotune.cached("b4096_other", p) == {}
+    assert open(p).read().splitlines() == ["b1024_s256_E64_n262144_V65536_m0 groups=2 "
+                                           "n_det_hint=5", "b4096_other"]
+    with open(p, "a") as f:
+        f.write("bad_line groups=1 nonsense=3\n")
+    with pytest.raises(sas.SasError):
+        autotune.cached("bad_line", p)
 
 
 def test_refine_extract_weighted_argument_errors():

@@ -121,11 +121,21 @@ def test_overfull_window_is_chunked(gpu, n_epochs, mode):
         for tun in (dict(stage_cap=1024), dict(stage_cap=1024, groups=1, half_counts=1)):
             if tun.get("half_counts") and mode == "epochs" and n_epochs <= 32:
                 tun = dict(tun, coarse_log2=1)  # epoch masks have no 16-bit form
-            plan = sas.Plan(v, t, 1024, n_min, ext, mode=mode, tuning=tun)
+            # every tile voted (prune = -1), so that the chunked path runs even
+            # where no bin can reach N_min distinct epochs
+            plan = sas.Plan(v, t, 1024, n_min, ext, mode=mode, tuning=dict(tun, prune=-1))
             srch = sas.Search(plan, len(x), cand_cap=1 << 18)
             g = srch.run(x, y, e)
             assert srch.result()["n_spilled"] > 0  # the chunked path did run
             assert plan.info()["half_counts"] == tun.get("half_counts", 0)
+            plan.close()
+            assert_same(g, o)
+            # with coverage pruning: nothing to vote once N_min exceeds the epochs
+            plan = sas.Plan(v, t, 1024, n_min, ext, mode=mode, tuning=tun)
+            info = plan.info()
+            if mode == "epochs" and n_min > n_epochs:
+                assert info["n_tiles_kept"] == 0 and info["n_tiles"] > 0
+            g = sas.Search(plan, len(x), cand_cap=1 << 18).run(x, y, e)
             plan.close()
             assert_same(g, o)
 
@@ -494,6 +504,20 @@ def test_autotuner_keeps_outputs(gpu):
     g = gpu_vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v, wl.binw_q8, wl.n_min, "epochs", 255,
                  wl.extent_q8, tuning=r["tuning"])
     assert_same(g, o)
+
+
+def test_autotune_default_candidates(gpu):
+    """The library's candidate list starts from the base tuning and covers
+    every lane-group count."""
+    from paper_2509_26279_amd import autotune
+    wl = synth.make_tiny()
+    v = _grid(wl)
+    cands = autotune.candidates(v, wl.t_q16, wl.binw_q8, wl.n_min, wl.extent_q8,
+                                {"n_det_hint": 5}, count_sat=255)
+    assert cands[0] == {"n_det_hint": 5}
+    assert all(c["n_det_hint"] == 5 for c in cands)
+    assert {c.get("groups") for c in cands} == {None, 1, 2, 4}
+    assert any("cell_log2" in c for c in cands) and any("tile_x" in c for c in cands)
 
 
 # ---------------------------------------------------------------- candidate features

@@ -64,3 +64,25 @@ def test_adamw_first_step():
     # step 1: m_hat = g, v_hat = g^2, so the update is lr (sign(g) + wd p) for g != 0
     np.testing.assert_allclose(p1[:2], p[:2] - 0.01 * (np.sign(g[:2]) * (1 / (1 + 1e-8 / np.abs(g[:2]))) + 0.1 * p[:2]))
     assert p1[2] == pytest.approx(0.5 - 0.01 * 0.1 * 0.5)
+
+
+def test_each_rounding_point_is_resolved_by_the_gpu_tolerance():
+    """The GPU comparison (tests/test_gpu_mlp.py) allows a relative L2 error
+    of TOL on the logits and on each gradient block.  Leaving out any one
+    bf16 rounding point of the reference moves the logits (forward points)
+    or some gradient block by more than 5 TOL on every gradient case, so a
+    kernel that misses or misplaces a rounding point cannot pass."""
+    from mlp_case import BLOCKS, GRAD_CASES, TOL, case, rel_l2
+    for B, pw in GRAD_CASES:
+        p, x, y, mu, sd = case(100 + B, B)
+        z, _ = M.forward(p, x, mu, sd)
+        _, g = M.loss_and_grad(p, x, y, mu, sd, pos_weight=pw)
+        for pt in M.POINTS:
+            keep = tuple(q for q in M.POINTS if q != pt)
+            z2, _ = M.forward(p, x, mu, sd, points=keep)
+            _, g2 = M.loss_and_grad(p, x, y, mu, sd, pos_weight=pw, points=keep)
+            shift = max([rel_l2(z2, z)] + [rel_l2(g2[a:b], g[a:b]) for _, a, b in BLOCKS])
+            assert shift > 5 * TOL, (B, pt, shift)
+        # and the full set of points is the default
+        z3, _ = M.forward(p, x, mu, sd, points=M.POINTS)
+        assert np.array_equal(z3, z)
