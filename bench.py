@@ -1,23 +1,25 @@
 """Benchmark of the voting transform on one MI355X.
 
-A step is one pass of the hot path over one chip's catalog, already resident
-in HBM: sas_vote (reference epoch, window index, dense LDS vote over the
-whole velocity grid) followed by sas_peaks (device -> host candidates in
-canonical order).  Default workload: the wide-field chip (2048x4096 px,
-100 epochs over 4 h, 3000 noise detections per epoch plus 200 movers, 4 px
-bins, sector grid of 84,351 velocities, N_min = 25).
+A step is one pass of the hot path over the workload's catalogs, already
+resident in HBM: the vote (reference epoch, window index, dense LDS vote over
+the whole velocity grid of every chip, refinement of flagged cells) followed
+by sas_peaks of every chip (device -> host candidates in canonical order).
 
---workload night runs the batched night instead: 64 chips (seeded wide or
-fast style, 5e4-5e5 detections, 40-120 epochs, each with its own grid and
-threshold) voted by one batched launch per kernel class, with launch shapes
-chosen by the autotuner per chip style.
+Default workload: the batched night, the largest single-GPU configuration:
+64 chips (seeded wide or fast style, 5e4-5e5 detections, 40-120 epochs, each
+with its own velocity grid and threshold) voted by one persistent launch per
+kernel class, captured once as a HIP graph and replayed every step; launch
+shapes come from the committed tuning cache (no tuning in the timed run).
+--workload wide|fast|tiny runs one chip's sas_vote + sas_peaks instead.
 
-Prints one JSON line (rank 0).  --gpus above 1 is refused: the benchmark
-measures one GPU.
+Prints one JSON line.  --gpus above 1 is refused: the benchmark measures one
+GPU.  --ceilings prints the measured unit rates instead (LDS atomics, integer
+VALU, HBM copy).
 """
 from __future__ import annotations
 
 import argparse
+import concurrent.futures as cf
 import json
 import os
 import sys
@@ -35,57 +37,105 @@ SIMD_PER_CU, LANES_PER_SIMD = 4, 16
 # CU (the published 157.3 TFLOP/s fp32 vector peak counts an FMA as 2 and
 # packed fp32 as 2 more)
 INT_PEAK_TOPS = N_CU * SIMD_PER_CU * LANES_PER_SIMD * CLOCK_GHZ / 1000.0
-# Packed 16-bit integer ops (v_pk_sub_u16, v_pk_lshrrev_b16, v_dot2_u32_u16):
-# two halves per lane per clock.  Votes of a packed plan run at this rate.
+# Packed 16-bit integer ops: two halves per lane per clock.
 INT16X2_PEAK_TOPS = 2 * INT_PEAK_TOPS
 # LDS: one 4-byte access per bank per clock, 32 banks per CU; an atomic add
 # reads and writes its word, so a 64-lane ds_add_u32 without bank conflicts
-# takes 4 clocks: 16 lane-atomics per CU per clock
+# takes 4 clocks: 16 lane-atomics per CU per clock.  Each vote is one lane
+# of one LDS atomic instruction.
 LDS_BANKS = 32
 LDS_ATOMIC_PEAK = N_CU * (LDS_BANKS // 2) * CLOCK_GHZ * 1e9  # lane atomics per second
 # Integer operations of one vote on the dense path: x - S_x, y - S_y, the two
 # floor divisions by the cell width (shifts), and the histogram word index
-# (bin row * row pitch + bin column * lanes + lane: one multiply-add and one
-# shift-add).  The count increment itself is the LDS atomic.
+# (one multiply-add and one shift-add).  The count increment is the atomic.
 OPS_PER_VOTE = 6
-# A weighted vote also takes its weight out of the staged entry (one and).
 OPS_PER_WEIGHTED_VOTE = 7
 VOTE_KERNEL = "k_vote_dense"
+BATCH_KERNEL = "k_vote_dense_batch"
 
 
-def _night(n_chips, tune, log, full_tune=False):
-    """The batched night: chips with their own plans, thresholds and
-    autotuned launch shapes (one tuning per shape class: bin width, lattice
-    spacing, grid shape, and epoch and detection counts by powers of two)."""
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _lds_roofline(kernel, instr, kernel_s, votes, alu_peak_tops, traffic):
+    """Roofline of a vote kernel against the LDS atomic unit: `instr`
+    64-lane atomic vote instructions (device counter) over the kernel time.
+    The algorithmic rate (N |V| votes over the same time) is reported next
+    to it: coverage pruning skips tiles that cannot hold a candidate, so the
+    kernel issues fewer lane atomics than N |V|."""
+    lanes = 64.0 * instr
+    achieved = lanes / kernel_s
+    return {"bound": "lds_atomic", "achieved": achieved, "peak": LDS_ATOMIC_PEAK,
+            "unit": "lane-atomics/s", "frac": achieved / LDS_ATOMIC_PEAK, "traffic": traffic,
+            "kernel": kernel, "lane_atomics_per_launch": lanes,
+            "algorithmic_votes_per_launch": votes,
+            "algorithmic_votes_per_s": votes / kernel_s,
+            "algorithmic_frac": votes / kernel_s / LDS_ATOMIC_PEAK,
+            "alu_frac": OPS_PER_VOTE * lanes / kernel_s / (alu_peak_tops * 1e12),
+            "ops_per_vote": OPS_PER_VOTE}
+
+
+# --------------------------------------------------------------------------- night
+
+def _night_setup(n_chips, cache, retune, tune_set="small"):
+    """Chips of the night with their thresholds and plans; launch shapes
+    from the tuning cache (retune: tune each shape class on its first chip
+    and store the choice)."""
+    import numpy as np
     import torch
 
     from paper_2509_26279_amd import autotune, sas, synth
-    chips, tuned = [], {}
+    specs = []
     for p in synth.night_chip_params(4, n_chips):
         wl = synth.make_night_chip(p, 0)
         v = sas.grid_from_spec(wl.grid, wl.binw_q8, wl.span_q16)
         n_min = wl.n_min
-        if p["style"] == "fast":  # threshold rule of Sec. 2.2 for this chip
+        if p["style"] == "fast":  # the threshold rule of Sec. 2.2 for this chip
             area = float(wl.width_px * wl.height_px)
             mu = wl.n / wl.n_epochs * wl.bin_px ** 2 / area
             n_min = sas.threshold_n_min(wl.n_epochs, mu, len(v) * area / wl.bin_px ** 2)
-        x = torch.as_tensor(wl.x_q8).cuda()
-        y = torch.as_tensor(wl.y_q8).cuda()
-        e = torch.as_tensor(wl.epoch).cuda()
-        key = autotune.shape_class(wl.binw_q8, sas.grid_spacing(wl.binw_q8, wl.span_q16),
-                                   wl.n_epochs, wl.n, wl.grid.shape)
-        if tune and key not in tuned:
-            log("tuning class %s on chip %d" % (key, p["chip"]))
-            cands = (autotune.candidates({"n_det_hint": wl.n}) if full_tune else
-                     [{}, {"groups": 1}, {"groups": 2}, {"groups": 4}])
-            r = autotune.tune(v, wl.t_q16, wl.binw_q8, n_min, wl.extent_q8, x, y, e,
-                              cands=cands, log=log)
-            tuned[key] = {k: v_ for k, v_ in r["tuning"].items() if k != "n_det_hint"}
-        tun = dict(tuned.get(key, {}), n_det_hint=wl.n)
-        plan = sas.Plan(v, wl.t_q16, wl.binw_q8, n_min, wl.extent_q8, tuning=tun)
-        chips.append({"wl": wl, "v": v, "plan": plan, "x": x, "y": y, "e": e, "n_min": n_min,
+        key = autotune.shape_class(v, wl.t_q16, wl.binw_q8, n_min, wl.extent_q8, wl.n)
+        specs.append({"p": p, "wl": wl, "v": v, "n_min": n_min, "key": key,
                       "style": p["style"]})
-    return chips, tuned
+    tuned, missing = {}, []
+    for c in specs:
+        if c["key"] in tuned:
+            continue
+        t = None if retune else autotune.cached(c["key"], cache)
+        if t is None and not retune:
+            missing.append(c["key"])  # planner defaults
+        if t is None and retune:
+            wl = c["wl"]
+            log("tuning class %s on chip %d" % (c["key"], c["p"]["chip"]))
+            x = torch.as_tensor(wl.x_q8).cuda()
+            y = torch.as_tensor(wl.y_q8).cuda()
+            e = torch.as_tensor(wl.epoch).cuda()
+            # small: the planner's choice and each lane-group count; full: the
+            # library's whole candidate list around the planner's choice
+            cands = [{}, {"groups": 1}, {"groups": 2}, {"groups": 4}] if tune_set == "small" \
+                else None
+            r = autotune.tune(c["v"], wl.t_q16, wl.binw_q8, c["n_min"], wl.extent_q8, x, y, e,
+                              base={"n_det_hint": wl.n}, cands=cands, reps=2, log=log)
+            t = {k: v_ for k, v_ in r["tuning"].items() if k != "n_det_hint"}
+            autotune.store(c["key"], t, cache)
+        tuned[c["key"]] = t or {}
+
+    def make_plan(c):
+        wl = c["wl"]
+        tun = dict(tuned[c["key"]], n_det_hint=wl.n)
+        return sas.Plan(c["v"], wl.t_q16, wl.binw_q8, c["n_min"], wl.extent_q8, tuning=tun)
+
+    # plans are host analyses (the library releases the interpreter lock)
+    with cf.ThreadPoolExecutor(max_workers=8) as ex:
+        plans = list(ex.map(make_plan, specs))
+    for c, plan in zip(specs, plans):
+        wl = c["wl"]
+        c["plan"] = plan
+        c["x"] = torch.as_tensor(wl.x_q8).cuda()
+        c["y"] = torch.as_tensor(wl.y_q8).cuda()
+        c["e"] = torch.as_tensor(wl.epoch).cuda()
+    return specs, tuned, missing
 
 
 def run_night(args):
@@ -93,38 +143,61 @@ def run_night(args):
     import torch
 
     from paper_2509_26279_amd import sas
-    log = lambda m: print(m, file=sys.stderr, flush=True)
-    chips, tuned = _night(args.chips, not args.no_tune, log, args.full_tune)
+    t_setup = time.perf_counter()
+    chips, tuned, missing = _night_setup(args.chips, args.cache, args.retune, args.tune_set)
     b = sas.Batch([(c["plan"], c["x"], c["y"], c["e"]) for c in chips], cand_cap=1 << 21)
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
+    for _ in range(max(args.warmup, 1)):
         b.vote()
-        for k in range(len(chips)):
-            b.peaks(k)
+        eager = [b.peaks(k) for k in range(len(chips))]
     torch.cuda.synchronize()
+    graph = None
+    if not args.no_graph:  # one capture of the whole batch, replayed per step
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            b.vote(stream=torch.cuda.current_stream())
+        graph.replay()
+        for k in range(len(chips)):
+            if not np.array_equal(b.peaks(k), eager[k]):
+                raise RuntimeError("graph replay of chip %d differs from the eager vote" % k)
+    setup_s = time.perf_counter() - t_setup
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_cand = 0
+    for _ in range(args.steps):
+        if graph is not None:
+            graph.replay()
+        else:
+            b.vote()
+        n_cand = sum(len(b.peaks(k)) for k in range(len(chips)))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1000.0 / args.steps
+    # the vote kernels alone, on the launch stream: events and the LDS atomic
+    # counter of the same launches, eager, after the timed region
+    counter = torch.zeros(1, dtype=torch.int64, device="cuda")
+    reps = 2
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
+           for _ in range(reps)]
     for a, z in evs:
         a.record(stream)
         z.record(stream)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    n_cand = 0
-    for k in range(args.steps):
-        b.set_probe(evs[k][0], evs[k][1])
+    b.set_counter(counter)
+    for a, z in evs:
+        b.set_probe(a, z)
         b.vote()
-        n_cand = sum(len(b.peaks(c)) for c in range(len(chips)))
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     b.set_probe(None, None)
+    b.set_counter(None)
     kernel_ms = float(np.mean([a.elapsed_time(z) for a, z in evs]))
-    ms_step = wall * 1000.0 / args.steps
+    instr = float(counter.item()) / reps
     votes = float(sum(c["wl"].n * len(c["v"]) for c in chips))
-    achieved = OPS_PER_VOTE * votes / (kernel_ms * 1e-3) / 1e12
-    # the peak of the night's vote mix: each chip's votes at its plan's rate
-    peak = votes / sum(c["wl"].n * len(c["v"]) /
-                       (INT16X2_PEAK_TOPS if c["plan"].info()["packed"] else INT_PEAK_TOPS)
-                       for c in chips)
+    # the ALU peak of the night's vote mix: each chip's votes at its plan's rate
+    alu_peak = votes / sum(c["wl"].n * len(c["v"]) /
+                           (INT16X2_PEAK_TOPS if c["plan"].info()["packed"] else INT_PEAK_TOPS)
+                           for c in chips)
+    infos = [c["plan"].info() for c in chips]
     n_fast = sum(c["style"] == "fast" for c in chips)
     rec = {
         "metric": "detection-velocity votes/s per chip", "value": votes / (ms_step * 1e-3),
@@ -132,34 +205,41 @@ def run_night(args):
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": "night: %d chips (%d wide-style, %d fast-style), detections "
-                               "log-uniform 5e4-5e5, 40-120 epochs, one batched launch"
+                               "log-uniform 5e4-5e5, 40-120 epochs, one batched launch per "
+                               "kernel class, replayed as a captured graph"
                                % (len(chips), len(chips) - n_fast, n_fast),
+                   "n_chips": len(chips),
                    "n_detections": int(sum(c["wl"].n for c in chips)),
+                   "n_velocities": int(sum(len(c["v"]) for c in chips)),
                    "votes": votes, "parallelism": "single-gpu"},
+        "per_ccd_chip": {"ms": ms_step / len(chips), "chips_per_s": len(chips) / (wall /
+                                                                                    args.steps),
+                         "votes_per_s_mean_chip": votes / len(chips) / (ms_step * 1e-3)},
         "candidates_per_s": n_cand / (ms_step * 1e-3), "n_candidates": n_cand,
-        "vote_kernels_ms": kernel_ms, "tuned": tuned,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
-                     "unit": "Tops/s", "frac": achieved / peak, "traffic": None,
-                     "kernel": "k_vote_dense_batch", "ops_per_vote": OPS_PER_VOTE},
+        "vote_kernels_ms": kernel_ms, "graph": graph is not None,
+        "tiles": int(sum(i["n_tiles"] for i in infos)),
+        "tiles_voted": int(sum(i["n_tiles_kept"] for i in infos)),
+        "tuning_cache": os.path.relpath(args.cache, ROOT), "tuned_classes": len(tuned),
+        "untuned_classes": missing, "setup_s": setup_s,
+        "roofline": _lds_roofline(BATCH_KERNEL, instr, kernel_ms * 1e-3, votes, alu_peak,
+                                  None),
     }
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(chips[0]["wl"], chips[0]["v"], args.cpu_seconds,
-                                           chips[0]["n_min"])
+        rec["cpu_baseline"] = cpu_baseline_night(chips, args.cpu_seconds)
     b.close()
     for c in chips:
         c["plan"].close()
     print(json.dumps(rec), flush=True)
 
 
+# --------------------------------------------------------------------------- one chip
+
 def _workload(name):
     from paper_2509_26279_amd import synth
-    if name == "wide":
-        return synth.make_wide()
-    if name == "fast":
-        return synth.make_fast()
-    if name == "tiny":
-        return synth.make_tiny()
-    raise SystemExit("unknown workload " + name)
+    makers = {"wide": synth.make_wide, "fast": synth.make_fast, "tiny": synth.make_tiny}
+    if name not in makers:
+        raise SystemExit("unknown workload " + name)
+    return makers[name]()
 
 
 def _kernel_source_hash():
@@ -183,72 +263,11 @@ def _traffic(workload):
     return t.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(wl, v, seconds, n_min=None):
-    """The oracle as it stands, on the host cores, over a seeded velocity sample."""
-    import numpy as np
-
-    import oracle
-    threads = len(os.sched_getaffinity(0))
-    if os.environ.get("OMP_NUM_THREADS"):
-        threads = min(threads, int(os.environ["OMP_NUM_THREADS"]))
-    rng = np.random.default_rng(0)
-    probe = np.sort(rng.choice(len(v), size=min(threads, len(v)), replace=False))
-    t0 = time.perf_counter()
-    n_min = wl.n_min if n_min is None else n_min
-    oracle.vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v[probe], wl.binw_q8, n_min,
-                "epochs", 255, threads=threads)
-    dt = time.perf_counter() - t0
-    k = int(max(threads, min(len(v), threads * round(seconds / max(dt, 1e-3)))))
-    sample = np.sort(rng.choice(len(v), size=k, replace=False))
-    t0 = time.perf_counter()
-    c = oracle.vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v[sample], wl.binw_q8, n_min,
-                    "epochs", 255, threads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": wl.n * k / dt, "unit": "votes/s", "cores": threads, "kind": "oracle",
-            "sample": "%d of %d velocities (seeded), full catalog of %d detections, %.1f s"
-                      % (k, len(v), wl.n, dt),
-            "candidates": int(len(c))}
-
-
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="wide")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--chips", type=int, default=64, help="night workload: number of chips")
-    ap.add_argument("--no-tune", action="store_true", help="night workload: planner defaults")
-    ap.add_argument("--full-tune", action="store_true",
-                    help="night workload: the autotuner's whole candidate list per chip style")
-    ap.add_argument("--extract", action="store_true",
-                    help="also time the greedy cluster extraction over the step's candidates")
-    ap.add_argument("--extract-rounds", type=int, default=0,
-                    help="parallel rounds of the extraction (0 default, -1 one take at a time)")
-    ap.add_argument("--refine", action="store_true",
-                    help="also time Steps 4-6 (FAST-MCD refine, gather, iterate) over the "
-                         "clusters of the greedy extraction (implies --extract)")
-    ap.add_argument("--refine-starts", type=int, default=500,
-                    help="random starts of FAST-MCD per fit (at most 1024)")
-    ap.add_argument("--weighted", choices=["epochs", "detections"], default=None,
-                    help="also time the weighted vote of the same catalog (likelihood weights "
-                         "of the detections' SNR, threshold N_min x the mean weight)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU; --gpus %d is not supported" % args.gpus,
-              file=sys.stderr)
-        sys.exit(2)
-
-    if args.workload == "night":
-        run_night(args)
-        return
-
+def run_chip(args):
     import numpy as np
     import torch
 
     from paper_2509_26279_amd import sas
-
     wl = _workload(args.workload)
     v = sas.grid_from_spec(wl.grid, wl.binw_q8, wl.span_q16)
     count_sat = 255 if wl.count_dtype == "u8" else 65535
@@ -258,20 +277,20 @@ def main():
     s = sas.Search(plan, wl.n, cand_cap=1 << 22)
     x, y, e = s.upload(wl.x_q8, wl.y_q8, wl.epoch)
     stream = torch.cuda.current_stream()
-
     for _ in range(args.warmup):
         s.vote(x, y, e)
         out = s.peaks()
     torch.cuda.synchronize()
-
-    # events around the whole step (vote + peaks) and, through the plan's
-    # probe, around the vote kernel alone on the stream it is launched on
+    # events around the vote kernel alone (the plan's probe, on its launch
+    # stream) and the LDS atomic counter, around every timed step
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
-    for a, b in evs:  # create the underlying HIP events
+    for a, b in evs:
         a.record(stream)
         b.record(stream)
+    counter = torch.zeros(1, dtype=torch.int64, device="cuda")
     torch.cuda.synchronize()
+    plan.set_counter(counter)
     t0 = time.perf_counter()
     for k in range(args.steps):
         plan.set_probe(evs[k][0], evs[k][1])
@@ -280,88 +299,82 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     plan.set_probe(None, None)
+    plan.set_counter(None)
     kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    instr = float(counter.item()) / args.steps
     ms_step = wall * 1000.0 / args.steps
     votes = float(wl.n) * len(v)
-    n_cand = len(out)
-
-    achieved = OPS_PER_VOTE * votes / (kernel_ms * 1e-3) / 1e12
     peak = INT16X2_PEAK_TOPS if info.get("packed") else INT_PEAK_TOPS
     rec = {
-        "metric": "detection-velocity votes/s per chip",
-        "value": votes / (ms_step * 1e-3),
-        "unit": "votes/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic",
+        "metric": "detection-velocity votes/s per chip", "value": votes / (ms_step * 1e-3),
+        "unit": "votes/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": "%s chip: %dx%d px, %d epochs over %.0f h, %d detections, "
                                "%d velocities, %.0f px bins, N_min %d"
                                % (wl.name, wl.width_px, wl.height_px, wl.n_epochs, wl.span_h,
                                   wl.n, len(v), wl.bin_px, wl.n_min),
                    "n_detections": wl.n, "n_velocities": int(len(v)),
                    "n_epochs": wl.n_epochs, "parallelism": "single-gpu"},
-        "candidates_per_s": n_cand / (ms_step * 1e-3),
-        "n_candidates": n_cand,
-        "vote_kernel_ms": kernel_ms,
-        "vote_kernel_votes_per_s": votes / (kernel_ms * 1e-3),
+        "candidates_per_s": len(out) / (ms_step * 1e-3), "n_candidates": len(out),
+        "vote_kernel_ms": kernel_ms, "vote_kernel_votes_per_s": votes / (kernel_ms * 1e-3),
         "plan": info,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
-                     "unit": "Tops/s", "frac": achieved / peak,
-                     "traffic": _traffic(wl.name), "kernel": VOTE_KERNEL,
-                     "ops_per_vote": OPS_PER_VOTE,
-                     "ops": "int16x2 packed" if info.get("packed") else "int32",
-                     "lds_atomic_frac": votes / (kernel_ms * 1e-3) / LDS_ATOMIC_PEAK},
+        "roofline": _lds_roofline(VOTE_KERNEL, instr, kernel_ms * 1e-3, votes, peak,
+                                  _traffic(wl.name)),
     }
     if args.extract or args.refine:
-        # Step 3's greedy extraction over the candidates of the last vote
-        # (not part of the step above): wall time of the whole call
-        ext = []
-        for k in range(args.warmup + args.steps):
-            s.vote(x, y, e)
-            s.peaks()
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            clusters, _ = s.extract(wl.n, rounds=args.extract_rounds)
-            if k >= args.warmup:
-                ext.append((time.perf_counter() - t1) * 1000.0)
-        rec["extract"] = {"ms": float(np.mean(ext)), "n_clusters": int(len(clusters)),
-                          "n_cells": n_cand, "rounds": args.extract_rounds}
-        if args.refine:
-            from paper_2509_26279_amd import synth
-            _, owner = s.extract(wl.n)
-            order = np.argsort(owner, kind="stable")
-            own = owner[order]
-            groups = [order[own == k] for k in range(len(clusters))]
-            starts = synth.mcd_starts(7, args.refine_starts)
-            ref = []
-            for k in range(args.warmup + args.steps):
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                recs, _, _ = s.refine(x, y, e, groups, starts, subsets=False)
-                if k >= args.warmup:
-                    ref.append((time.perf_counter() - t1) * 1000.0)
-            st = {sas.REFINE_STATUS[int(c)]: int((recs["status"] == c).sum())
-                  for c in np.unique(recs["status"])}
-            rec["refine"] = {"ms": float(np.mean(ref)), "n_clusters": len(groups),
-                             "points": int(sum(len(g) for g in groups)),
-                             "rounds_mean": float(recs["rounds"].mean()) if len(recs) else 0.0,
-                             "status": st, "starts": args.refine_starts}
+        rec.update(time_extract_refine(args, wl, s, x, y, e, len(out)))
     if args.weighted:
-        rec["weighted"] = time_weighted(args, wl, v, count_sat)
+        rec["weighted"] = time_weighted(args, wl, v)
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(wl, v, args.cpu_seconds)
+        rec["cpu_baseline"] = cpu_baseline([(wl, v, wl.n_min)], args.cpu_seconds)
     plan.close()
     print(json.dumps(rec), flush=True)
 
 
-def time_weighted(args, wl, v, count_sat):
-    """The step of main() with a weighted plan (not the headline value)."""
+def time_extract_refine(args, wl, s, x, y, e, n_cand):
+    """Step 3's greedy extraction (and Steps 4-6) over the candidates of the
+    last vote: wall time of the whole call (not part of the step above)."""
+    import numpy as np
+    import torch
+
+    from paper_2509_26279_amd import sas, synth
+    out = {}
+    ext = []
+    for k in range(args.warmup + args.steps):
+        s.vote(x, y, e)
+        s.peaks()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        clusters, _ = s.extract(wl.n, rounds=args.extract_rounds)
+        if k >= args.warmup:
+            ext.append((time.perf_counter() - t1) * 1000.0)
+    out["extract"] = {"ms": float(np.mean(ext)), "n_clusters": int(len(clusters)),
+                      "n_cells": n_cand, "rounds": args.extract_rounds}
+    if args.refine:
+        _, owner = s.extract(wl.n)
+        order = np.argsort(owner, kind="stable")
+        own = owner[order]
+        groups = [order[own == k] for k in range(len(clusters))]
+        starts = synth.mcd_starts(7, args.refine_starts)
+        ref = []
+        for k in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            recs, _, _ = s.refine(x, y, e, groups, starts, subsets=False)
+            if k >= args.warmup:
+                ref.append((time.perf_counter() - t1) * 1000.0)
+        st = {sas.REFINE_STATUS[int(c)]: int((recs["status"] == c).sum())
+              for c in np.unique(recs["status"])}
+        out["refine"] = {"ms": float(np.mean(ref)), "n_clusters": len(groups),
+                         "points": int(sum(len(g) for g in groups)),
+                         "rounds_mean": float(recs["rounds"].mean()) if len(recs) else 0.0,
+                         "status": st, "starts": args.refine_starts}
+    return out
+
+
+def time_weighted(args, wl, v):
+    """The step of run_chip() with a weighted plan (not the headline value)."""
     import numpy as np
     import torch
 
@@ -405,6 +418,103 @@ def time_weighted(args, wl, v, count_sat):
                          "unit": "Tops/s", "frac": achieved / INT_PEAK_TOPS,
                          "kernel": VOTE_KERNEL, "ops_per_vote": OPS_PER_WEIGHTED_VOTE,
                          "ops": "int32"}}
+
+
+# --------------------------------------------------------------------------- CPU baseline
+
+def _threads():
+    threads = len(os.sched_getaffinity(0))
+    if os.environ.get("OMP_NUM_THREADS"):
+        threads = min(threads, int(os.environ["OMP_NUM_THREADS"]))
+    return threads
+
+
+def cpu_baseline(items, seconds):
+    """The oracle as it stands, on the host cores, over seeded velocity
+    samples of the given (workload, grid, threshold) items, about `seconds`
+    of work in all; votes/s over the whole sample."""
+    import numpy as np
+
+    import oracle
+    threads = _threads()
+    per = seconds / len(items)
+    votes, total_s, parts = 0.0, 0.0, []
+    for wl, v, n_min in items:
+        rng = np.random.default_rng(0)
+        probe = np.sort(rng.choice(len(v), size=min(threads, len(v)), replace=False))
+        t0 = time.perf_counter()
+        oracle.vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v[probe], wl.binw_q8, n_min,
+                    "epochs", 65535, threads=threads)
+        dt = time.perf_counter() - t0
+        k = int(max(threads, min(len(v), threads * round(per / max(dt, 1e-3)))))
+        sample = np.sort(rng.choice(len(v), size=k, replace=False))
+        t0 = time.perf_counter()
+        oracle.vote(wl.x_q8, wl.y_q8, wl.epoch, wl.t_q16, v[sample], wl.binw_q8, n_min,
+                    "epochs", 65535, threads=threads)
+        dt = time.perf_counter() - t0
+        votes += float(wl.n) * k
+        total_s += dt
+        parts.append("%s: %d of %d velocities, %d detections, %.1f s"
+                     % (wl.name, k, len(v), wl.n, dt))
+    return {"value": votes / total_s, "unit": "votes/s", "cores": threads, "kind": "oracle",
+            "sample": "seeded velocity samples over whole catalogs; " + "; ".join(parts)}
+
+
+def cpu_baseline_night(chips, seconds):
+    """The oracle on the first two chips of each style of the night."""
+    pick = [c for c in chips if c["style"] == "fast"][:2] + \
+        [c for c in chips if c["style"] == "wide"][:2]
+    return cpu_baseline([(c["wl"], c["v"], c["n_min"]) for c in pick], seconds)
+
+
+# --------------------------------------------------------------------------- main
+
+def main():
+    from paper_2509_26279_amd import autotune
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="night", choices=["night", "wide", "fast", "tiny"])
+    ap.add_argument("--cpu-seconds", type=float, default=16.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--chips", type=int, default=64, help="night: number of chips")
+    ap.add_argument("--cache", default=autotune.CACHE, help="night: tuning cache file")
+    ap.add_argument("--retune", action="store_true",
+                    help="night: tune every shape class (library autotuner) and store the "
+                         "choices in --cache before the timed run")
+    ap.add_argument("--tune-set", choices=["small", "full"], default="small",
+                    help="night --retune: candidate launch shapes per class")
+    ap.add_argument("--no-graph", action="store_true", help="night: eager launches per step")
+    ap.add_argument("--ceilings", action="store_true",
+                    help="print the measured unit rates (LDS atomics, integer VALU, HBM copy)")
+    ap.add_argument("--extract", action="store_true",
+                    help="one chip: also time the greedy cluster extraction")
+    ap.add_argument("--extract-rounds", type=int, default=0,
+                    help="parallel rounds of the extraction (0 default, -1 one take at a time)")
+    ap.add_argument("--refine", action="store_true",
+                    help="one chip: also time Steps 4-6 over the extraction's clusters")
+    ap.add_argument("--refine-starts", type=int, default=500,
+                    help="random starts of FAST-MCD per fit (at most 1024)")
+    ap.add_argument("--weighted", choices=["epochs", "detections"], default=None,
+                    help="one chip: also time the weighted vote of the same catalog")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU; --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    if args.ceilings:
+        from paper_2509_26279_amd import sas
+        c = sas.measure_ceilings()
+        c.update({"lds_atomic_peak": LDS_ATOMIC_PEAK, "valu_int32_peak": INT_PEAK_TOPS * 1e12,
+                  "valu_int16x2_peak": INT16X2_PEAK_TOPS * 1e12,
+                  "hbm_peak_bytes_per_s": HBM_PEAK_GBS * 1e9})
+        print(json.dumps({"ceilings": c}), flush=True)
+        return
+    if args.workload == "night":
+        run_night(args)
+    else:
+        run_chip(args)
 
 
 if __name__ == "__main__":
