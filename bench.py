@@ -19,7 +19,6 @@ VALU, HBM copy).
 from __future__ import annotations
 
 import argparse
-import concurrent.futures as cf
 import json
 import os
 import sys
@@ -78,73 +77,14 @@ def _lds_roofline(kernel, instr, kernel_s, votes, alu_peak_tops, traffic):
 
 # --------------------------------------------------------------------------- night
 
-def _night_setup(n_chips, cache, retune, tune_set="small"):
-    """Chips of the night with their thresholds and plans; launch shapes
-    from the tuning cache (retune: tune each shape class on its first chip
-    and store the choice)."""
-    import numpy as np
-    import torch
-
-    from paper_2509_26279_amd import autotune, sas, synth
-    specs = []
-    for p in synth.night_chip_params(4, n_chips):
-        wl = synth.make_night_chip(p, 0)
-        v = sas.grid_from_spec(wl.grid, wl.binw_q8, wl.span_q16)
-        n_min = wl.n_min
-        if p["style"] == "fast":  # the threshold rule of Sec. 2.2 for this chip
-            area = float(wl.width_px * wl.height_px)
-            mu = wl.n / wl.n_epochs * wl.bin_px ** 2 / area
-            n_min = sas.threshold_n_min(wl.n_epochs, mu, len(v) * area / wl.bin_px ** 2)
-        key = autotune.shape_class(v, wl.t_q16, wl.binw_q8, n_min, wl.extent_q8, wl.n)
-        specs.append({"p": p, "wl": wl, "v": v, "n_min": n_min, "key": key,
-                      "style": p["style"]})
-    tuned, missing = {}, []
-    for c in specs:
-        if c["key"] in tuned:
-            continue
-        t = None if retune else autotune.cached(c["key"], cache)
-        if t is None and not retune:
-            missing.append(c["key"])  # planner defaults
-        if t is None and retune:
-            wl = c["wl"]
-            log("tuning class %s on chip %d" % (c["key"], c["p"]["chip"]))
-            x = torch.as_tensor(wl.x_q8).cuda()
-            y = torch.as_tensor(wl.y_q8).cuda()
-            e = torch.as_tensor(wl.epoch).cuda()
-            # small: the planner's choice and each lane-group count; full: the
-            # library's whole candidate list around the planner's choice
-            cands = [{}, {"groups": 1}, {"groups": 2}, {"groups": 4}] if tune_set == "small" \
-                else None
-            r = autotune.tune(c["v"], wl.t_q16, wl.binw_q8, c["n_min"], wl.extent_q8, x, y, e,
-                              base={"n_det_hint": wl.n}, cands=cands, reps=2, log=log)
-            t = {k: v_ for k, v_ in r["tuning"].items() if k != "n_det_hint"}
-            autotune.store(c["key"], t, cache)
-        tuned[c["key"]] = t or {}
-
-    def make_plan(c):
-        wl = c["wl"]
-        tun = dict(tuned[c["key"]], n_det_hint=wl.n)
-        return sas.Plan(c["v"], wl.t_q16, wl.binw_q8, c["n_min"], wl.extent_q8, tuning=tun)
-
-    # plans are host analyses (the library releases the interpreter lock)
-    with cf.ThreadPoolExecutor(max_workers=8) as ex:
-        plans = list(ex.map(make_plan, specs))
-    for c, plan in zip(specs, plans):
-        wl = c["wl"]
-        c["plan"] = plan
-        c["x"] = torch.as_tensor(wl.x_q8).cuda()
-        c["y"] = torch.as_tensor(wl.y_q8).cuda()
-        c["e"] = torch.as_tensor(wl.epoch).cuda()
-    return specs, tuned, missing
-
-
 def run_night(args):
     import numpy as np
     import torch
 
     from paper_2509_26279_amd import sas
     t_setup = time.perf_counter()
-    chips, tuned, missing = _night_setup(args.chips, args.cache, args.retune, args.tune_set)
+    from paper_2509_26279_amd import night
+    chips, tuned, missing = night.setup(args.chips, args.cache, args.retune, args.tune_set, log)
     b = sas.Batch([(c["plan"], c["x"], c["y"], c["e"]) for c in chips], cand_cap=1 << 21)
     stream = torch.cuda.current_stream()
     for _ in range(max(args.warmup, 1)):
@@ -222,7 +162,7 @@ def run_night(args):
         "tuning_cache": os.path.relpath(args.cache, ROOT), "tuned_classes": len(tuned),
         "untuned_classes": missing, "setup_s": setup_s,
         "roofline": _lds_roofline(BATCH_KERNEL, instr, kernel_ms * 1e-3, votes, alu_peak,
-                                  None),
+                                  _traffic("night", BATCH_KERNEL)),
     }
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline_night(chips, args.cpu_seconds)
@@ -249,10 +189,10 @@ def _kernel_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def _traffic(workload):
+def _traffic(workload, kernel=VOTE_KERNEL):
     """HBM bytes per vote-kernel launch from the committed PMC summary, or
     None when there is none or the kernel source changed since."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (VOTE_KERNEL, workload))
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
     try:
         with open(path) as f:
             t = json.load(f)
@@ -326,6 +266,8 @@ def run_chip(args):
         rec.update(time_extract_refine(args, wl, s, x, y, e, len(out)))
     if args.weighted:
         rec["weighted"] = time_weighted(args, wl, v)
+    if args.sort_sample:
+        rec["sort_path"] = time_sort_path(args, wl, v, count_sat, x, y, e)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline([(wl, v, wl.n_min)], args.cpu_seconds)
     plan.close()
@@ -370,6 +312,48 @@ def time_extract_refine(args, wl, s, x, y, e, n_cand):
                          "points": int(sum(len(g) for g in groups)),
                          "rounds_mean": float(recs["rounds"].mean()) if len(recs) else 0.0,
                          "status": st, "starts": args.refine_starts}
+    return out
+
+
+def time_sort_path(args, wl, v, count_sat, x, y, e):
+    """The sort-by-bin-key path against the dense path on a seeded block of
+    the grid (not the headline value): vote-kernel time of each, identical
+    candidate lists required."""
+    import numpy as np
+    import torch
+
+    from paper_2509_26279_amd import sas
+    rng = np.random.default_rng(11)
+    k = min(args.sort_sample, len(v))
+    start = int(rng.integers(0, len(v) - k + 1))
+    vs = v[start:start + k]  # consecutive velocities: one block of the lattice
+    out = {"velocities": k, "first_v_idx": start, "n_detections": wl.n}
+    lists = {}
+    for path in ("sort", "dense"):
+        plan = sas.Plan(vs, wl.t_q16, wl.binw_q8, wl.n_min, wl.extent_q8, count_sat=count_sat,
+                        path=path, tuning={"n_det_hint": wl.n})
+        s = sas.Search(plan, wl.n, cand_cap=1 << 22)
+        s.vote(x, y, e)
+        lists[path] = s.peaks()
+        ts = []
+        for _ in range(max(args.steps, 2)):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            b.record()
+            torch.cuda.synchronize()
+            plan.set_probe(a, b)
+            s.vote(x, y, e)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        plan.set_probe(None, None)
+        info = plan.info()
+        plan.close()
+        ms = float(np.median(ts))
+        out[path] = {"ms": ms, "votes_per_s": wl.n * k / (ms * 1e-3), "blocks": info["n_blocks"]}
+    if not np.array_equal(lists["sort"], lists["dense"]):
+        raise RuntimeError("sort and dense paths disagree on the sampled block")
+    out["n_candidates"] = int(len(lists["dense"]))
+    out["dense_over_sort"] = out["sort"]["ms"] / out["dense"]["ms"]
     return out
 
 
@@ -496,6 +480,9 @@ def main():
                     help="one chip: also time Steps 4-6 over the extraction's clusters")
     ap.add_argument("--refine-starts", type=int, default=500,
                     help="random starts of FAST-MCD per fit (at most 1024)")
+    ap.add_argument("--sort-sample", type=int, default=0,
+                    help="one chip: also time the sort-by-bin-key path on this many consecutive "
+                         "velocities of the grid, against the dense path")
     ap.add_argument("--weighted", choices=["epochs", "detections"], default=None,
                     help="one chip: also time the weighted vote of the same catalog")
     args = ap.parse_args()

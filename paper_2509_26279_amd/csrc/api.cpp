@@ -1215,12 +1215,13 @@ sas_status sas_batch_create(const sas_batch_chip *chips, int32_t n_chips, void *
         for (int64_t q = 0; q < p->n_items; ++q) {
             It it;
             const int32_t *src = &p->h_items[4 * q];
-            it.v[0] = c;
+            const bool kept = q < p->n_items_kept;
+            it.v[0] = kept ? c : ~c;  // skipped tiles carry ~chip
             it.v[1] = src[0];
             it.v[2] = src[1];
             it.v[3] = src[2];
             it.v[4] = src[3];
-            (q < p->n_items_kept ? per_class[k] : tails[k]).push_back(it);
+            (kept ? per_class[k] : tails[k]).push_back(it);
         }
     }
     for (int k = 0; k < kMaxBatchClasses; ++k) {
@@ -1319,7 +1320,8 @@ sas_status sas_vote_batch(const sas_batch *b, void *stream) {
         const sas_batch::Class &cl = b->classes[k];
         // persistent: as many workgroups as fit on the device at once
         const int per_cu = std::max<int>(1, (int)(kLdsPerCU / (cl.lds + dense_static_lds_bytes())));
-        const int grid = (int)std::min<int64_t>(cl.n_items, (int64_t)n_cu * per_cu);
+        const int grid = (int)std::max<int64_t>(
+            1, std::min<int64_t>(cl.n_kept, (int64_t)n_cu * per_cu));
         e = launch_vote_dense_batch(cl.mode, cl.groups, cl.packed, b->d_args,
                                     (int32_t)b->chips.size(), cl.d_items5, cl.n_items, cl.n_kept,
                                     cl.hist_words_max, cl.lds, grid, b->counter, s);

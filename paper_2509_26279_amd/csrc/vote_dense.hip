@@ -64,6 +64,8 @@ struct Shared {
     int32_t svx[64], svy[64];   // segment: velocity of each lane
     int32_t sg[64];             // segment: left guard cells of each lane, gx | gy << 16
     int32_t bad;
+    int32_t count_on;           // measurement: count the LDS atomic vote instructions
+    unsigned long long n_instr; // their number in this workgroup
 };
 
 // Epochs per wave whose lane shifts stay in registers over a work item (two
@@ -332,10 +334,9 @@ __device__ __attribute__((always_inline)) inline int32_t run_part(
 // One work item: a segment and a row of ntiles tiles starting at tile column
 // txf (cells), tile row ty0.  The histogram is all zero on entry and on exit;
 // sh.dt holds the catalog's d_e.
-// n_instr (wave uniform) counts the wave's LDS atomic vote instructions.
 template <int MODE, int G, bool PK>
 __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t sg, int32_t ty0,
-                          int32_t txf, int32_t ntiles, int32_t &tseq, uint32_t &n_instr) {
+                          int32_t txf, int32_t ntiles, int32_t &tseq) {
     constexpr int NV = 64 / G;
     constexpr int LNV = G == 1 ? 6 : G == 2 ? 5 : 4;
     constexpr bool WT = weighted_mode<MODE>();
@@ -542,6 +543,11 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         my_b = lane < KW ? (qk < 64 ? b0 : b1) : t0 + t1;
         const int32_t nb = __shfl(my_b, min(lane + 1, 63), 64);
         my_n = lane < KW ? nb - my_b : 0;
+        if (sh.count_on) {  // measurement: the chunk's votes take ceil(n / G) instructions per epoch
+            int32_t tot;
+            wave_scan((my_n + G - 1) / G, &tot);
+            if (lane == 0 && tot) atomicAdd(&sh.n_instr, (unsigned long long)tot);
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -590,7 +596,6 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                 const int32_t n = __builtin_amdgcn_readlane(my_n, k);
                 if (n == 0) continue;
                 const int32_t b = __builtin_amdgcn_readlane(my_b, k);
-                n_instr += (uint32_t)(n + G - 1) / G;
                 vote_run<MODE, G>(wst + b, n, vote_addr(Sx[k], Sy[PK ? 0 : k]),
                                   MODE == kMask32 ? (1u << e) : cval, g);
             }
@@ -599,7 +604,6 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                 const int32_t n = __builtin_amdgcn_readlane(my_n, k);
                 if (n == 0) continue;
                 const int32_t b = __builtin_amdgcn_readlane(my_b, k);
-                n_instr += (uint32_t)(n + G - 1) / G;
                 const int32_t d = sh.dt[e];
                 const int32_t sx = shift_q8(my_vx, d) + (int32_t)ox_lane;
                 const int32_t sy = shift_q8(my_vy, d) + (int32_t)oy_lane;
@@ -716,6 +720,10 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
     if (tid < a.cat.n_epochs) sh.dt[tid] = a.cat.dt[tid];
     int32_t tseq = 0;  // tiles done by this workgroup (flag ring of sh.voted)
     if (tid < 4) sh.voted[tid] = 0;
+    if (tid == 0) {
+        sh.count_on = a.atomics != nullptr;
+        sh.n_instr = 0;
+    }
     // Workgroups are dispatched round-robin over the XCDs (each with its own
     // L2); give XCD x the logical indices [x G / 8, (x + 1) G / 8) so that the
     // workgroups resident on one XCD take neighbouring items.
@@ -725,14 +733,15 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
     // reach when the reference epoch is the earliest scheduled one; they are
     // voted only when that epoch holds no detection (then t0 is later).
     const int64_t n_walk = a.cat.dt[a.e_first] == 0 ? a.n_items_kept : a.n_items;
-    uint32_t n_instr = 0;
     for (int64_t item = logical; item < n_walk; item += grid) {
         const int32_t *it = a.items + 4 * item;
-        vote_item<MODE, G, PK>(a, sh, smem4, it[0], it[1], it[2], it[3], tseq, n_instr);
+        vote_item<MODE, G, PK>(a, sh, smem4, it[0], it[1], it[2], it[3], tseq);
     }
-    if (a.atomics && __lane_id() == 0 && n_instr)
-        atomicAdd(a.atomics, (unsigned long long)n_instr);
+    __syncthreads();
+    if (tid == 0 && sh.count_on && sh.n_instr) atomicAdd(a.atomics, sh.n_instr);
 }
+
+constexpr int64_t kBatchRun = 64;  // rounds of an XCD's block of items in the batched walk
 
 // Many catalogs in one persistent launch (one workgroup per resident slot):
 // the merged items (items5: chip, segment, ty0, txf, ntiles; chip-major, each
@@ -741,8 +750,9 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
 // chips[].  Every chip of the launch uses this kernel's cell variant and lane
 // groups (and vote form); hist_words_max covers the largest histogram among
 // them.  Items [0, n_kept) are every chip's kept items; the rest hold tiles
-// that fewer than N_min epochs reach (see k_vote_dense), voted only for the
-// chips whose earliest scheduled epoch holds no detection.
+// that fewer than N_min epochs reach (see k_vote_dense), with the chip stored
+// as ~chip, voted only for the chips whose earliest scheduled epoch holds no
+// detection.
 template <int MODE, int G, bool PK>
 __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_vote_dense_batch(const DenseArgs *__restrict__ chips,
                                                          int32_t n_chips,
@@ -756,18 +766,30 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
     for (int i = tid; i < hist_words_max / 4; i += T) smem4[i] = make_uint4(0, 0, 0, 0);
     int32_t tseq = 0, chip_now = -1;  // tseq: tiles done by this workgroup
     if (tid < 4) sh.voted[tid] = 0;
+    if (tid == 0) {
+        sh.count_on = atomics != nullptr;
+        sh.n_instr = 0;
+    }
     int later_t0 = 0;  // some chip's reference epoch is later than its earliest epoch
     for (int c = tid; c < n_chips; c += T) later_t0 |= chips[c].cat.dt[chips[c].e_first] != 0;
     later_t0 = __syncthreads_or(later_t0);
     const int64_t n_walk = later_t0 ? n_items : n_kept;
-    uint32_t n_instr = 0;  // LDS atomic vote instructions of this wave
-    const int64_t grid = gridDim.x;  // a multiple of kXcds
-    const int64_t logical = (int64_t)(blockIdx.x % kXcds) * (grid / kXcds) + blockIdx.x / kXcds;
-    for (int64_t item = logical; item < n_walk; item += grid) {
+    // Each XCD walks blocks of kBatchRun x (its resident workgroups)
+    // consecutive items, blocks interleaved over the XCDs: the workgroups of
+    // one XCD take neighbouring items, round after round, so the catalog
+    // regions of consecutive rounds overlap in that XCD's L2.
+    const int64_t per_xcd = gridDim.x / kXcds;  // gridDim.x is a multiple of kXcds
+    const int64_t xcd = blockIdx.x % kXcds, w = blockIdx.x / kXcds;
+    const int64_t run = per_xcd * kBatchRun;
+    for (int64_t b0 = xcd * run; b0 < n_walk; b0 += kXcds * run)
+    for (int64_t item = b0 + w, b1 = min(b0 + run, n_walk); item < b1; item += per_xcd) {
         const int32_t *it = items5 + 5 * item;
-        const int chip = it[0];
+        int chip = it[0];
+        if (chip < 0) {  // skipped tiles of chip ~chip: block uniform
+            chip = ~chip;
+            if (chips[chip].cat.dt[chips[chip].e_first] == 0) continue;
+        }
         const DenseArgs &a = chips[chip];
-        if (item >= n_kept && a.cat.dt[a.e_first] == 0) continue;  // block uniform
         if (chip != chip_now) {
             __syncthreads();  // the previous item no longer reads sh.dt or the stage
             if (tid < a.cat.n_epochs) sh.dt[tid] = a.cat.dt[tid];
@@ -776,9 +798,10 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
             for (int i = tid; i < hw / 4; i += T) smem4[i] = make_uint4(0, 0, 0, 0);
             chip_now = chip;
         }
-        vote_item<MODE, G, PK>(a, sh, smem4, it[1], it[2], it[3], it[4], tseq, n_instr);
+        vote_item<MODE, G, PK>(a, sh, smem4, it[1], it[2], it[3], it[4], tseq);
     }
-    if (atomics && __lane_id() == 0 && n_instr) atomicAdd(atomics, (unsigned long long)n_instr);
+    __syncthreads();
+    if (tid == 0 && sh.count_on && sh.n_instr) atomicAdd(atomics, sh.n_instr);
 }
 
 // Exact bins of a queued cell: for velocity v and the cell's 2^m x 2^m
@@ -901,7 +924,10 @@ hipError_t launch_mg(const DenseArgs &a, size_t lds, hipStream_t stream, hipEven
     static size_t lds_set = 0;  // dynamic LDS limit raised so far for this kernel
     hipError_t e = set_lds_limit((const void *)k_vote_dense<MODE, G, PK>, lds, &lds_set);
     if (e != hipSuccess) return e;
-    const int64_t want = a.n_items < kMaxVoteGrid ? a.n_items : kMaxVoteGrid;
+    // sized by the kept items (those walked unless the reference epoch is a
+    // later one), so that the XCD-contiguous walk spreads them over all XCDs
+    const int64_t kept = a.n_items_kept > 0 ? a.n_items_kept : 1;
+    const int64_t want = kept < kMaxVoteGrid ? kept : kMaxVoteGrid;
     const dim3 grid((unsigned)((want + kXcds - 1) / kXcds * kXcds)), block(T);
     if (ev0 && (e = hipEventRecord(ev0, stream)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_vote_dense<MODE, G, PK>), grid, block, lds, stream, a);

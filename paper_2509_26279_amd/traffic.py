@@ -16,6 +16,10 @@ copy calibrate them (bytes copied / bytes the counter reports).
 (run the program with the repository root as the working directory or on
 PYTHONPATH).  The summary records the hash of the kernel source it was taken
 on; the benchmark reports the traffic only while that hash matches.
+
+Workload "night" votes the batched night once (k_vote_dense_batch, one
+dispatch per kernel class): its traffic is the sum over those dispatches,
+written to profiles/traffic_k_vote_dense_batch_night.json.
 """
 from __future__ import annotations
 
@@ -36,6 +40,10 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
+def kernel_of(workload: str) -> str:
+    return "k_vote_dense_batch" if workload == "night" else KERNEL
+
+
 def run(workload: str) -> None:
     import torch
 
@@ -46,6 +54,17 @@ def run(workload: str) -> None:
     dst.copy_(src)  # calibration: COPY_BYTES read, COPY_BYTES written
     torch.cuda.synchronize()
     del src, dst
+    if workload == "night":
+        from . import night
+        chips, _, _ = night.setup()
+        b = sas.Batch([(c["plan"], c["x"], c["y"], c["e"]) for c in chips], cand_cap=1 << 21)
+        b.vote()
+        n = sum(len(b.peaks(k)) for k in range(len(chips)))
+        b.close()
+        for c in chips:
+            c["plan"].close()
+        print("traffic run: night, %d candidates" % n, flush=True)
+        return
     wl = getattr(synth, "make_" + workload)()
     v = sas.grid_from_spec(wl.grid, wl.binw_q8, wl.span_q16)
     plan = sas.Plan(v, wl.t_q16, wl.binw_q8, wl.n_min, wl.extent_q8,
@@ -65,32 +84,37 @@ def _rows(d: str):
             yield from csv.DictReader(fh)
 
 
-def _counter(d: str, name: str):
+def _counter(d: str, name: str, kernel: str = KERNEL):
     """(copy KiB, vote KiB) for one counter: the largest copy-like dispatch
-    and the vote kernel's dispatch."""
+    and the vote kernel's dispatch (the batch kernel: the sum over its
+    dispatches, one per kernel class, of the single batched vote)."""
     copy_kib, vote_kib = 0.0, None
     for r in _rows(d):
         if r.get("Counter_Name") != name:
             continue
         k = r.get("Kernel_Name", "")
         val = float(r["Counter_Value"])
-        if KERNEL in k:
-            vote_kib = val if vote_kib is None else max(vote_kib, val)
+        if kernel + "<" in k:
+            if kernel == KERNEL:
+                vote_kib = val if vote_kib is None else max(vote_kib, val)
+            else:
+                vote_kib = val + (vote_kib or 0.0)
         elif "copy" in k.lower() or "elementwise" in k.lower():
             copy_kib = max(copy_kib, val)
     return copy_kib, vote_kib
 
 
 def summarize(workload: str, fetch_dir: str, write_dir: str, out: str) -> dict:
-    cf, vf = _counter(fetch_dir, "FETCH_SIZE")
-    cw, vw = _counter(write_dir, "WRITE_SIZE")
+    kernel = kernel_of(workload)
+    cf, vf = _counter(fetch_dir, "FETCH_SIZE", kernel)
+    cw, vw = _counter(write_dir, "WRITE_SIZE", kernel)
     if not cf or not cw or vf is None or vw is None:
         raise SystemExit("counters missing: copy fetch %s write %s, vote fetch %s write %s"
                          % (cf, cw, vf, vw))
     kf = COPY_BYTES / (cf * 1024.0)
     kw = COPY_BYTES / (cw * 1024.0)
     rec = {
-        "kernel": KERNEL,
+        "kernel": kernel,
         "workload": workload,
         "fetch_kib": vf, "write_kib": vw,
         "copy_bytes": COPY_BYTES, "copy_fetch_kib": cf, "copy_write_kib": cw,

@@ -27,6 +27,10 @@ used with fewer false candidates:
 Recall counts findable movers (at least N_min epochs on the chip) with at
 least one selected candidate matched to them; false positives are selected
 candidates matched to no mover.
+
+Two protocols: fast-style chips (pool at N_pool = 19, mostly mover ghosts)
+and wide-style chips (pool threshold from the threshold rule of Sec. 2.2,
+noise candidates dominating, about 1e6 candidates over 12 chips).
 """
 from __future__ import annotations
 
@@ -290,6 +294,38 @@ def fast_protocol(members=5, epochs=60, log=None, train=TRAIN_SEEDS, val=VAL_SEE
                     members=members, epochs=epochs, log=log)
 
 
+# Seeds of the wide-style protocol: noise-dominated pools of the wide chip.
+WIDE_TRAIN_SEEDS = tuple(range(400, 408))
+WIDE_VAL_SEEDS = (410, 411)
+WIDE_TEST_SEEDS = (420, 421)
+# Pool threshold: the threshold rule (Sec. 2.2) at this many expected noise
+# candidates per chip (N_pool = 7 on the wide chip: about 9e4 noise
+# candidates per chip, 1.1e6 over the protocol's 12 chips).
+WIDE_POOL_FALSE = 1e5
+
+
+def pool_threshold(wl, v, n_false):
+    """The threshold rule of Sec. 2.2 (sas_threshold_n_min) for this chip's
+    noise density and grid at n_false expected noise candidates."""
+    area = float(wl.width_px * wl.height_px)
+    mu = wl.n / wl.n_epochs * wl.bin_px ** 2 / area
+    return sas.threshold_n_min(wl.n_epochs, mu, len(v) * area / wl.bin_px ** 2, n_false)
+
+
+def wide_protocol(members=5, epochs=60, log=None, train=WIDE_TRAIN_SEEDS, val=WIDE_VAL_SEEDS,
+                  test=WIDE_TEST_SEEDS, n_false=WIDE_POOL_FALSE):
+    """The protocol on wide-style chips (slow movers, 100 epochs, 4 px bins):
+    pools at N_pool from the threshold rule, dominated by noise candidates;
+    the plain threshold is the workload's N_min = 25."""
+    from . import synth
+    wl = synth.make_wide(train[0])
+    n_pool = pool_threshold(wl, sas.grid_from_spec(wl.grid, wl.binw_q8, wl.span_q16), n_false)
+    out = evaluate(train, val, test, n_pool, wl.n_min, synth.make_wide, members=members,
+                   epochs=epochs, log=log)
+    out["pool_false_target"] = n_false
+    return out
+
+
 if __name__ == "__main__":
     import json
     import sys
@@ -299,6 +335,10 @@ if __name__ == "__main__":
     def _log(msg):
         print("%7.1fs %s" % (time.time() - t_start, msg), file=sys.stderr, flush=True)
 
-    out = fast_protocol(log=_log)
-    out["plain_curve"] = {str(k): v for k, v in out["plain_curve"].items()}
-    print(json.dumps(out), flush=True)
+    for name, proto in (("fast", fast_protocol), ("wide", wide_protocol)):
+        if len(sys.argv) > 1 and sys.argv[1] != name:
+            continue
+        out = proto(log=_log)
+        out["plain_curve"] = {str(k): v for k, v in out["plain_curve"].items()}
+        out["protocol"] = name
+        print(json.dumps(out), flush=True)
