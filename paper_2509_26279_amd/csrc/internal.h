@@ -19,6 +19,14 @@ constexpr int kXcds = 8;                   // MI355X: accelerator dies, one L2 e
 
 constexpr int kRefineGrid = 2048;          // workgroups of the refinement launch
 
+// Staging loads of the vote kernels: kCopyAhead detections of a run at a
+// time, the first group unconditionally.  A lane whose run is empty or
+// already staged loads from the run's end, so up to kCopyAhead detections
+// past the last one are read: the sorted detections are followed by that
+// much slack in the workspace.
+constexpr int kCopyAhead = 4;
+constexpr size_t kSortedSlackBytes = kCopyAhead * 2 * sizeof(int32_t);
+
 // Histogram variants of the dense path.
 enum DenseMode : int {
     kMask32 = 0,    // EPOCHS, E <= 32, single bins: epoch bitmask per cell, emitted directly

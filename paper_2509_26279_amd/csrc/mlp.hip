@@ -1,5 +1,5 @@
 // Vetting MLP 32 -> 128 -> 128 -> 1 on gfx950: bf16 operands on the matrix
-// cores (v_mfma_f32_16x16x16_bf16), FP32 accumulation.
+// cores (v_mfma_f32_16x16x32_bf16), FP32 accumulation.
 //
 // Forward:   a0 = q((x - mu) / sd);  h1 = q(relu(a0 q(W1) + b1));
 //            h2 = q(relu(h1 q(W2) + b2));  z = h2 q(W3) + b3
@@ -15,7 +15,7 @@
 namespace sas {
 namespace {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 __device__ inline uint16_t f2bf(float f) {
@@ -61,10 +61,12 @@ struct Gemm {
 
 constexpr int GT = 256;  // 4 waves, each a 32 x 32 quarter of the 64 x 64 tile
 
+constexpr int GK = 32;   // K of one v_mfma_f32_16x16x32_bf16
+
 template <int EPI>
 __global__ void __launch_bounds__(GT) k_gemm(Gemm g) {
-    __shared__ uint16_t As[64][16 + 2];
-    __shared__ uint16_t Bs[16][64 + 2];
+    __shared__ uint16_t As[64][GK + 2];
+    __shared__ uint16_t Bs[GK][64 + 2];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
     const int kb = blockIdx.z * g.k_chunk, ke = min(g.K, kb + g.k_chunk);
@@ -75,27 +77,31 @@ __global__ void __launch_bounds__(GT) k_gemm(Gemm g) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
-    for (int k0 = kb; k0 < ke; k0 += 16) {
-        for (int q = tid; q < 64 * 16; q += GT) {
-            const int r = q >> 4, kk = q & 15, m = m0 + r, k = k0 + kk;
+    for (int k0 = kb; k0 < ke; k0 += GK) {
+        for (int q = tid; q < 64 * GK; q += GT) {
+            const int r = q / GK, kk = q % GK, m = m0 + r, k = k0 + kk;
             As[r][kk] = (m < g.M && k < ke) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : 0;
         }
-        for (int q = tid; q < 16 * 64; q += GT) {
+        for (int q = tid; q < GK * 64; q += GT) {
             const int kk = q >> 6, cc = q & 63, k = k0 + kk, n = n0 + cc;
             Bs[kk][cc] = (k < ke && n < g.N) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : 0;
         }
         __syncthreads();
+        // operands of a 16 x 16 x 32 product: lane holds row (or column)
+        // lane % 16 at k = 8 (lane / 16) + j, j < 8
 #pragma unroll
         for (int ti = 0; ti < 2; ++ti) {
-            v4s a;
+            v8bf a;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) a[j] = (short)As[wm + 16 * ti + r16][4 * q4 + j];
+            for (int j = 0; j < 8; ++j)
+                a[j] = __builtin_bit_cast(__bf16, As[wm + 16 * ti + r16][8 * q4 + j]);
 #pragma unroll
             for (int tj = 0; tj < 2; ++tj) {
-                v4s b;
+                v8bf b;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) b[j] = (short)Bs[4 * q4 + j][wn + 16 * tj + r16];
-                acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[ti][tj], 0, 0, 0);
+                for (int j = 0; j < 8; ++j)
+                    b[j] = __builtin_bit_cast(__bf16, Bs[8 * q4 + j][wn + 16 * tj + r16]);
+                acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[ti][tj], 0, 0, 0);
             }
         }
         __syncthreads();

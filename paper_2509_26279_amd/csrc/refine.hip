@@ -14,7 +14,7 @@
 //
 // One workgroup per cluster (grid-stride over clusters).  The point set
 // (at most kMaxPoints) lives in LDS as t (h since t0), x, y (px) in FP64;
-// the four waves take the starts; a C-step ranks the distances exactly
+// the eight waves take the starts; a C-step ranks the distances exactly
 // (each point counts the points before it, ties to the lower position), so
 // the chosen subset does not depend on any reduction order.
 //

@@ -240,7 +240,8 @@ __device__ inline void vote_run(const typename V::Entry *st, int32_t n, const V 
     if (G > 1 && i + g < n) vote_block<MODE, G, 1>(st + i, g, va, val);
 }
 
-constexpr int kCopyAhead = 4;  // detections of a run loaded at once
+static_assert(kSortedSlackBytes >= kCopyAhead * sizeof(int2),
+              "the workspace slack after the sorted detections covers a full staging load");
 
 // Window-index row r of epoch e for the item's tile row at oy: the index of
 // its cell column 0, or -1 when the epoch's window misses the footprint in y
@@ -499,12 +500,13 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         int2 q[2][kCopyAhead];
 #pragma unroll
         for (int s2 = 0; s2 < 2; ++s2) {
-            // clamped to the run: a run staged by earlier chunks gives jb = je =
-            // rlen, so the loads below stay within kCopyAhead - 1 of its end
+            // clamped to the run: a run staged by earlier chunks (or empty) gives
+            // jb = je = rlen, so the loads below start at most at its end
             jb[s2] = min(rlen[s2], max(0, c0 - rpre[s2]));
             je[s2] = max(jb[s2], min(rlen[s2], c1 - rpre[s2]));
-            // unconditional loads: at most kCopyAhead - 1 detections past the run,
-            // inside the slack that follows the detections in the workspace
+            // unconditional loads: at most kCopyAhead detections past the run,
+            // inside the kSortedSlackBytes that follow the detections in the
+            // workspace
             const int2 *src = c.sxy + (rsrc[s2] + jb[s2]);
 #pragma unroll
             for (int u = 0; u < kCopyAhead; ++u) q[s2][u] = src[u];

@@ -299,8 +299,9 @@ WIDE_TRAIN_SEEDS = tuple(range(400, 408))
 WIDE_VAL_SEEDS = (410, 411)
 WIDE_TEST_SEEDS = (420, 421)
 # Pool threshold: the threshold rule (Sec. 2.2) at this many expected noise
-# candidates per chip (N_pool = 7 on the wide chip: about 9e4 noise
-# candidates per chip, 1.1e6 over the protocol's 12 chips).
+# candidates per chip.  It gives N_pool = 8 on the wide chip, where the pools
+# hold about 2.3e5 candidates per chip (2.8e6 over the protocol's 12 chips),
+# about 99.8% of them unmatched to any mover.
 WIDE_POOL_FALSE = 1e5
 
 
