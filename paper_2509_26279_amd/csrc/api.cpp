@@ -178,8 +178,7 @@ WsLayout ws_layout(const sas_plan *p, int64_t n) {
     L.blocksum = o; o = align_up(o + sizeof(int32_t) * nb);
     L.cellid = o; o = align_up(o + sizeof(int32_t) * nn);
     L.rank = o; o = align_up(o + sizeof(int32_t) * nn);
-    // the vote kernel may read up to kCopyAhead detections past a run
-    L.sxy = o; o = align_up(o + 2 * sizeof(int32_t) * nn + kSortedSlackBytes);
+    L.sxy = o; o = align_up(o + 2 * sizeof(int32_t) * nn);
     L.sidx = o; o = align_up(o + sizeof(int32_t) * nn);
     L.present = o; o = align_up(o + sizeof(int32_t) * kMaxEpochs);
     L.dt = o; o = align_up(o + sizeof(int32_t) * kMaxEpochs);

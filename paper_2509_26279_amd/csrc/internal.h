@@ -19,13 +19,9 @@ constexpr int kXcds = 8;                   // MI355X: accelerator dies, one L2 e
 
 constexpr int kRefineGrid = 2048;          // workgroups of the refinement launch
 
-// Staging loads of the vote kernels: kCopyAhead detections of a run at a
-// time, the first group unconditionally.  A lane whose run is empty or
-// already staged loads from the run's end, so up to kCopyAhead detections
-// past the last one are read: the sorted detections are followed by that
-// much slack in the workspace.
+// Detections of a window-index run that the refinement kernel loads at a
+// time (each load bounded by the run's end).
 constexpr int kCopyAhead = 4;
-constexpr size_t kSortedSlackBytes = kCopyAhead * 2 * sizeof(int32_t);
 
 // Histogram variants of the dense path.
 enum DenseMode : int {

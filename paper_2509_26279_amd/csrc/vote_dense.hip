@@ -8,11 +8,12 @@
 //   1. each wave takes the epochs e = wave (mod 8).  Per epoch, the exact
 //      window of the original frame whose detections can land in the tile
 //      for some velocity of the segment is computed; the window index
-//      (detections grouped by epoch, cell row, cell column) is read one lane
-//      per (epoch, cell row), and wave scans lay the runs out for a copy into
-//      the wave's part of a stage in LDS.  The copy keeps only the detections
-//      inside the exact window, grouped by epoch (large windows are staged in
-//      chunks), and the next tile is staged right after this one's votes;
+//      (detections grouped by epoch, cell row, cell column) gives one run of
+//      detections per (epoch, cell row), and a wave scan lays the runs end to
+//      end.  The wave then reads that sequence 64 consecutive entries at a
+//      time (coalesced) and packs the detections inside the exact window into
+//      its part of a stage in LDS, grouped by epoch (large windows are staged
+//      in chunks); the next tile is staged right after this one's votes;
 //   2. lane = (group g < G, velocity j < NV), and the G
 //      groups vote G staged detections per instruction.  With d = t_e - t0
 //      and S(v) = ceil(v d / 65536), the bin of Step 2,
@@ -57,12 +58,13 @@ constexpr int NW = T / 64;
 
 struct Shared {
     int32_t dt[kMaxEpochs];
-    int32_t es[4][kMaxEpochs];  // per epoch: S(vx_lo), S(vx_hi), S(vy_lo), S(vy_hi) of the segment
+    int4 es[kMaxEpochs];        // per epoch: S(vx_lo), S(vx_hi), S(vy_lo), S(vy_hi) of the segment
     int32_t voted[4];           // window entries staged for tile t % 4 (all waves; summed
                                 // before the tile is voted)
     int32_t sv[64];             // segment: v_idx of each velocity lane (-1: unused)
     int32_t svx[64], svy[64];   // segment: velocity of each lane
     int32_t sg[64];             // segment: left guard cells of each lane, gx | gy << 16
+    int32_t heads[NW][64];      // per wave: marks of the runs that start in the block being staged
     int32_t bad;
     int32_t count_on;           // measurement: count the LDS atomic vote instructions
     unsigned long long n_instr; // their number in this workgroup
@@ -70,8 +72,8 @@ struct Shared {
 
 // Epochs per wave whose lane shifts stay in registers over a work item (two
 // registers each, or one packed).
-constexpr int kEpochRegs = 10;
-constexpr int kEpochRegsPacked = 12;  // packed: one register per epoch
+constexpr int kEpochRegs = 8;
+constexpr int kEpochRegsPacked = 8;  // packed: one register per epoch
 
 // ceil(v * d / 65536) for d >= 0: the shift v (t_e - t0) in Q8 pixels,
 // rounded so that the floor of the shifted position is exact.
@@ -240,9 +242,6 @@ __device__ inline void vote_run(const typename V::Entry *st, int32_t n, const V 
     if (G > 1 && i + g < n) vote_block<MODE, G, 1>(st + i, g, va, val);
 }
 
-static_assert(kSortedSlackBytes >= kCopyAhead * sizeof(int2),
-              "the workspace slack after the sorted detections covers a full staging load");
-
 // Window-index row r of epoch e for the item's tile row at oy: the index of
 // its cell column 0, or -1 when the epoch's window misses the footprint in y
 // or touches fewer rows (tile independent).
@@ -250,7 +249,7 @@ __device__ __attribute__((always_inline)) inline int32_t window_row(
     const DenseArgs &a, const Shared &sh, int e, int r, int32_t oy, int32_t H) {
     const PreparedCatalog &c = a.cat;
     if (sh.dt[e] < 0) return -1;
-    const int32_t ylo = oy + sh.es[2][e], yhi = oy + sh.es[3][e] + H;
+    const int32_t ylo = oy + sh.es[e].z, yhi = oy + sh.es[e].w + H;
     int cy0, cy1;
     if (!cell_span(ylo, yhi, c.y0, c.y1, c.cell_log2, &cy0, &cy1)) return -1;
     if (r == 0 && cy1 - cy0 + 1 > a.rows)  // excluded by the planner
@@ -268,7 +267,7 @@ __device__ __attribute__((always_inline)) inline void window_run(
     end = 0;
     if (row < 0) return;
     int cx0, cx1;
-    if (!cell_span(oxw + sh.es[0][e], oxw + sh.es[1][e] + W, c.x0, c.x1, c.cell_log2, &cx0,
+    if (!cell_span(oxw + sh.es[e].x, oxw + sh.es[e].y + W, c.x0, c.x1, c.cell_log2, &cx0,
                    &cx1))
         return;
     src = c.off[row + cx0];
@@ -300,35 +299,17 @@ struct Window {
 __device__ __attribute__((always_inline)) inline Window window_of(const Shared &sh, int e,
                                                                  int32_t oxw, int32_t oy,
                                                                  int32_t W, int32_t H) {
-    return Window{oxw + sh.es[0][e], oxw + sh.es[1][e] + W, oy + sh.es[2][e],
-                  oy + sh.es[3][e] + H};
+    const int4 s = sh.es[e];
+    return Window{oxw + s.x, oxw + s.y + W, oy + s.z, oy + s.w + H};
 }
 
-// One lane's part [jb, je) of a window-index run (source src): the
-// detections inside the window w, counted (write = false) or appended at
-// dst (write = true).  kCopyAhead loads at a time.
+// A staged entry: the detection (x, y), or its packed low halves.
 __device__ inline void put_entry(int2 *dst, int2 q) { *dst = q; }
 __device__ inline void put_entry(uint32_t *dst, int2 q) { *dst = pack16(q.x, q.y); }
 
-template <bool WRITE, class Entry>
-__device__ __attribute__((always_inline)) inline int32_t run_part(
-    const PreparedCatalog &c, int32_t src, int32_t jb, int32_t je, Window w, Entry *dst) {
-    int32_t n = 0;
-    for (int32_t jj = jb; jj < je; jj += kCopyAhead) {
-        int2 q[kCopyAhead];
-#pragma unroll
-        for (int u = 0; u < kCopyAhead; ++u)
-            if (jj + u < je) q[u] = c.sxy[src + jj + u];
-#pragma unroll
-        for (int u = 0; u < kCopyAhead; ++u) {
-            if (jj + u < je && w.holds(q[u])) {
-                if (WRITE) put_entry(dst + n, q[u]);
-                ++n;
-            }
-        }
-    }
-    return n;
-}
+// Blocks of 64 window-index entries whose loads a wave issues before testing
+// any of them.
+constexpr int kStageBlocks = 2;
 
 // Dynamic LDS: histogram [HY][HX][NV] words, then the stage (int2), one
 // part of stage_cap / NW detections per wave.
@@ -377,10 +358,9 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
     }
     if (tid < E) {  // shifts of the segment's box edges
         const int32_t d = sh.dt[tid];
-        sh.es[0][tid] = d >= 0 ? shift_q8(vx_lo, d) : 0;
-        sh.es[1][tid] = d >= 0 ? shift_q8(vx_hi, d) : 0;
-        sh.es[2][tid] = d >= 0 ? shift_q8(vy_lo, d) : 0;
-        sh.es[3][tid] = d >= 0 ? shift_q8(vy_hi, d) : 0;
+        sh.es[tid] = d >= 0 ? make_int4(shift_q8(vx_lo, d), shift_q8(vx_hi, d), shift_q8(vy_lo, d),
+                                        shift_q8(vy_hi, d))
+                            : make_int4(0, 0, 0, 0);
     }
     if (tid == 0) sh.bad = 0;
     __syncthreads();
@@ -420,10 +400,10 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
     bool bad = false;
     const auto guard_fails = [&](int e, int64_t sxe, int64_t sye) __attribute__((always_inline)) {
         const int64_t gxq = (int64_t)my_gx << kc, gyq = (int64_t)my_gy << kc;
-        return (int64_t)sh.es[0][e] - sxe - 1 + gxq < 0 ||
-               (int64_t)sh.es[2][e] - sye - 1 + gyq < 0 ||
-               (int64_t)sh.es[1][e] - sxe + W - 1 + gxq >= ((int64_t)a.hx << kc) ||
-               (int64_t)sh.es[3][e] - sye + H - 1 + gyq >= ((int64_t)a.hy << kc);
+        const int4 s = sh.es[e];
+        return (int64_t)s.x - sxe - 1 + gxq < 0 || (int64_t)s.z - sye - 1 + gyq < 0 ||
+               (int64_t)s.y - sxe + W - 1 + gxq >= ((int64_t)a.hx << kc) ||
+               (int64_t)s.w - sye + H - 1 + gyq >= ((int64_t)a.hy << kc);
     };
 #pragma unroll
     for (int k = 0; k < ER; ++k) {
@@ -467,82 +447,113 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
     const int nq = KW << LR;  // <= 128 (planner)
     const int32_t wcap = a.stage_cap / NW;
     Entry *wst = stage + wave * wcap;
-    int32_t rsrc[2], rlen[2], rpre[2];
+    int32_t rsb[2], rlen[2], rpre[2];  // per slot: run source - position, length, position
     int32_t Mw = 0;              // this wave's window-index entries of the tile (wave uniform)
     int32_t my_b = 0, my_n = 0;  // lane k < KW: stage start and count of epoch k
     int32_t rowb[2];             // window-index row of each slot's pair (-1: none)
-    int qe[2];                   // epoch of each slot's pair (clamped for empty slots)
+    // epoch of slot s2's pair (clamped for empty slots)
+    const auto pair_epoch = [&](int s2) __attribute__((always_inline)) {
+        return wave + NW * min((s2 * 64 + lane) >> LR, max(KW - 1, 0));
+    };
 #pragma unroll
     for (int s2 = 0; s2 < 2; ++s2) {
         const int q = s2 * 64 + lane;
-        qe[s2] = wave + NW * min(q >> LR, max(KW - 1, 0));
-        rowb[s2] = q < nq ? window_row(a, sh, qe[s2], q & ((1 << LR) - 1), oy, H) : -1;
+        rowb[s2] = q < nq ? window_row(a, sh, pair_epoch(s2), q & ((1 << LR) - 1), oy, H) : -1;
     }
 
     const auto runs = [&](int32_t oxw) __attribute__((always_inline)) {
-        int32_t end[2];
+        int32_t src[2], end[2];
 #pragma unroll
-        for (int s2 = 0; s2 < 2; ++s2) window_run(c, sh, qe[s2], rowb[s2], oxw, W, rsrc[s2], end[s2]);
+        for (int s2 = 0; s2 < 2; ++s2)
+            window_run(c, sh, pair_epoch(s2), rowb[s2], oxw, W, src[s2], end[s2]);
         int32_t t0, t1;
-        rlen[0] = end[0] - rsrc[0];
-        rlen[1] = end[1] - rsrc[1];
+        rlen[0] = end[0] - src[0];
+        rlen[1] = end[1] - src[1];
         rpre[0] = wave_scan(rlen[0], &t0);
         rpre[1] = t0 + wave_scan(rlen[1], &t1);
+        rsb[0] = src[0] - rpre[0];
+        rsb[1] = src[1] - rpre[1];
         Mw = t0 + t1;
     };
-    // the entries [c0, c0 + wcap) of the wave's runs (in pair order) that lie
-    // in their epoch's exact window, packed into the wave's stage
+    // The entries [c0, c0 + wcap) of the wave's runs (in pair order) that lie
+    // in their epoch's exact window, packed into the wave's stage.  Lane l
+    // takes entries c0 + 64 i + l, so that the loads of a block of 64 entries
+    // read a few consecutive stretches of the index.  The pair owning an
+    // entry is the last non-empty run starting at or before it: each block's
+    // run starts are marked in the wave's row of sh.heads (pair + 1), and a
+    // lane takes the nearest mark at or below it, else the previous block's
+    // owner.  kStageBlocks blocks are loaded before any is tested.
+    int32_t *const hd = sh.heads[wave];
     const auto stage_chunk = [&](int32_t oxw, int32_t c0) __attribute__((always_inline)) {
-        const int32_t c1 = c0 + wcap;
-        int32_t jb[2], je[2], nk[2];
-        uint32_t km[2];  // which of the first kCopyAhead detections are kept
-        Window w[2];
-        int2 q[2][kCopyAhead];
-#pragma unroll
-        for (int s2 = 0; s2 < 2; ++s2) {
-            // clamped to the run: a run staged by earlier chunks (or empty) gives
-            // jb = je = rlen, so the loads below start at most at its end
-            jb[s2] = min(rlen[s2], max(0, c0 - rpre[s2]));
-            je[s2] = max(jb[s2], min(rlen[s2], c1 - rpre[s2]));
-            // unconditional loads: at most kCopyAhead detections past the run,
-            // inside the kSortedSlackBytes that follow the detections in the
-            // workspace
-            const int2 *src = c.sxy + (rsrc[s2] + jb[s2]);
-#pragma unroll
-            for (int u = 0; u < kCopyAhead; ++u) q[s2][u] = src[u];
+        const int32_t c1 = min(c0 + wcap, Mw);
+        const bool two = nq > 64;  // slot 1 holds pairs (wave uniform)
+        // owner of entry c0: its run may have started in an earlier chunk
+        int32_t own;
+        {
+            const uint64_t m0 = __ballot(rpre[0] <= c0 && c0 < rpre[0] + rlen[0]);
+            const uint64_t m1 = __ballot(rpre[1] <= c0 && c0 < rpre[1] + rlen[1]);
+            own = m0 ? __builtin_ctzll(m0) : m1 ? 64 + __builtin_ctzll(m1) : 0;
         }
-#pragma unroll
-        for (int s2 = 0; s2 < 2; ++s2) {
-            w[s2] = window_of(sh, qe[s2], oxw, oy, W, H);
-            if (WT) {  // the index holds 256 x + w
-                w[s2].x0 = (int32_t)((uint32_t)w[s2].x0 << 8);
-                w[s2].x1 = (int32_t)((uint32_t)w[s2].x1 << 8);
-            }
-            km[s2] = 0;
-#pragma unroll
-            for (int u = 0; u < kCopyAhead; ++u)
-                km[s2] |= (uint32_t)(jb[s2] + u < je[s2] && w[s2].holds(q[s2][u])) << u;
-            nk[s2] = __popc(km[s2]) +
-                     run_part<false>(c, rsrc[s2], jb[s2] + kCopyAhead, je[s2], w[s2],
-                                     (Entry *)nullptr);
-        }
-        int32_t t0, t1;
-        int32_t start[2];  // packed position of the lane's first kept detection, per slot
-        start[0] = wave_scan(nk[0], &t0);
-        start[1] = t0 + wave_scan(nk[1], &t1);
-#pragma unroll
-        for (int s2 = 0; s2 < 2; ++s2) {
-            int32_t at = start[s2];
-#pragma unroll
-            for (int u = 0; u < kCopyAhead; ++u)
-                if ((km[s2] >> u) & 1u) put_entry(wst + at++, q[s2][u]);
-            run_part<true>(c, rsrc[s2], jb[s2] + kCopyAhead, je[s2], w[s2], wst + at);
-        }
-        // lane k < KW: the packed start of epoch k is the kept prefix at pair k << LR
+        // lane k < KW: position of epoch k's first entry, clamped to the chunk
         const int qk = min(lane, 31) << LR;
-        const int32_t b0 = __shfl(start[0], qk & 63, 64);
-        const int32_t b1 = __shfl(start[1], qk & 63, 64);
-        my_b = lane < KW ? (qk < 64 ? b0 : b1) : t0 + t1;
+        const int32_t pk0 = __shfl(rpre[0], qk & 63, 64), pk1 = __shfl(rpre[1], qk & 63, 64);
+        const int32_t pk = min(max(lane < KW ? (qk < 64 ? pk0 : pk1) : Mw, c0), c1);
+        int32_t mb = 0, kept = 0;
+        for (int32_t b0 = c0; b0 < c1; b0 += kStageBlocks * 64) {
+            int2 ent[kStageBlocks];
+            int32_t ek[kStageBlocks];
+#pragma unroll
+            for (int u = 0; u < kStageBlocks; ++u) {
+                const int32_t P0 = b0 + 64 * u, p = P0 + lane;
+                ent[u] = make_int2(0, 0);
+                ek[u] = 0;
+                if (P0 >= c1) break;  // wave uniform
+                if (rlen[0] > 0 && (uint32_t)(rpre[0] - P0) < 64u) hd[rpre[0] - P0] = lane + 1;
+                if (two && rlen[1] > 0 && (uint32_t)(rpre[1] - P0) < 64u)
+                    hd[rpre[1] - P0] = lane + 65;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const int32_t h = hd[lane];
+                hd[lane] = 0;
+                const uint64_t marks = __ballot(h != 0) & ((2ull << lane) - 1);
+                const int32_t hq = __shfl(h, marks ? 63 - __builtin_clzll(marks) : 0, 64) - 1;
+                const int32_t q = marks ? hq : own;
+                own = __builtin_amdgcn_readlane(q, 63);
+                int32_t sb = __shfl(rsb[0], q & 63, 64);
+                if (two) {
+                    const int32_t sbh = __shfl(rsb[1], q & 63, 64);
+                    sb = q < 64 ? sb : sbh;
+                }
+                if (p < c1) {
+                    ent[u] = c.sxy[p + sb];
+                    ek[u] = q >> LR;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kStageBlocks; ++u) {
+                const int32_t P0 = b0 + 64 * u;
+                if (P0 >= c1) break;  // wave uniform
+                Window w = window_of(sh, wave + NW * ek[u], oxw, oy, W, H);
+                if (WT) {  // the index holds 256 x + w
+                    w.x0 = (int32_t)((uint32_t)w.x0 << 8);
+                    w.x1 = (int32_t)((uint32_t)w.x1 << 8);
+                }
+                const bool keep = P0 + lane < c1 && w.holds(ent[u]);
+                const uint64_t km = __ballot(keep);
+                if (keep) {
+                    const uint32_t at = __builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+                    put_entry(wst + kept + (int32_t)at, ent[u]);
+                }
+                if (pk < c1 && (uint32_t)(pk - P0) < 64u)
+                    mb = kept + __popcll(km & ((1ull << (pk - P0)) - 1));
+                kept += __popcll(km);
+            }
+        }
+        if (pk >= c1) mb = kept;
+        // lane k < KW: stage start and count of epoch k's entries
+        my_b = mb;
         const int32_t nb = __shfl(my_b, min(lane + 1, 63), 64);
         my_n = lane < KW ? nb - my_b : 0;
         if (sh.count_on) {  // measurement: the chunk's votes take ceil(n / G) instructions per epoch
@@ -722,6 +733,7 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
     if (tid < a.cat.n_epochs) sh.dt[tid] = a.cat.dt[tid];
     int32_t tseq = 0;  // tiles done by this workgroup (flag ring of sh.voted)
     if (tid < 4) sh.voted[tid] = 0;
+    sh.heads[tid >> 6][tid & 63] = 0;  // each wave's own row, clear between blocks
     if (tid == 0) {
         sh.count_on = a.atomics != nullptr;
         sh.n_instr = 0;
@@ -768,6 +780,7 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
     for (int i = tid; i < hist_words_max / 4; i += T) smem4[i] = make_uint4(0, 0, 0, 0);
     int32_t tseq = 0, chip_now = -1;  // tseq: tiles done by this workgroup
     if (tid < 4) sh.voted[tid] = 0;
+    sh.heads[tid >> 6][tid & 63] = 0;  // each wave's own row, clear between blocks
     if (tid == 0) {
         sh.count_on = atomics != nullptr;
         sh.n_instr = 0;
