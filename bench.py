@@ -208,14 +208,30 @@ def run_chip(args):
     import torch
 
     from paper_2509_26279_amd import sas
+    from paper_2509_26279_amd import autotune
     wl = _workload(args.workload)
     v = sas.grid_from_spec(wl.grid, wl.binw_q8, wl.span_q16)
     count_sat = 255 if wl.count_dtype == "u8" else 65535
+    # launch shape of the chip's shape class from the tuning cache (the
+    # planner's own choice when the class is not cached; --retune times it)
+    key = autotune.shape_class(v, wl.t_q16, wl.binw_q8, wl.n_min, wl.extent_q8, wl.n)
+    xt = torch.as_tensor(wl.x_q8).cuda()
+    yt = torch.as_tensor(wl.y_q8).cuda()
+    et = torch.as_tensor(wl.epoch).cuda()
+    tun = None if args.retune else autotune.cached(key, args.cache)
+    if tun is None and args.retune:
+        cands = [{}, {"groups": 1}, {"groups": 2}, {"groups": 4}] if args.tune_set == "small" \
+            else None
+        r = autotune.tune(v, wl.t_q16, wl.binw_q8, wl.n_min, wl.extent_q8, xt, yt, et,
+                          count_sat=count_sat, base={"n_det_hint": wl.n}, cands=cands, reps=2,
+                          log=log)
+        tun = {k: v_ for k, v_ in r["tuning"].items() if k != "n_det_hint"}
+        autotune.store(key, tun, args.cache)
     plan = sas.Plan(v, wl.t_q16, wl.binw_q8, wl.n_min, wl.extent_q8, count_sat=count_sat,
-                    tuning={"n_det_hint": wl.n})
+                    tuning=dict(tun or {}, n_det_hint=wl.n))
     info = plan.info()
     s = sas.Search(plan, wl.n, cand_cap=1 << 22)
-    x, y, e = s.upload(wl.x_q8, wl.y_q8, wl.epoch)
+    x, y, e = xt, yt, et
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
         s.vote(x, y, e)
@@ -258,7 +274,8 @@ def run_chip(args):
                    "n_epochs": wl.n_epochs, "parallelism": "single-gpu"},
         "candidates_per_s": len(out) / (ms_step * 1e-3), "n_candidates": len(out),
         "vote_kernel_ms": kernel_ms, "vote_kernel_votes_per_s": votes / (kernel_ms * 1e-3),
-        "plan": info,
+        "plan": info, "tuning_class": key, "tuning": tun or {},
+        "tuning_cache": os.path.relpath(args.cache, ROOT),
         "roofline": _lds_roofline(VOTE_KERNEL, instr, kernel_ms * 1e-3, votes, peak,
                                   _traffic(wl.name)),
     }
@@ -463,12 +480,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=16.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--chips", type=int, default=64, help="night: number of chips")
-    ap.add_argument("--cache", default=autotune.CACHE, help="night: tuning cache file")
+    ap.add_argument("--cache", default=autotune.CACHE, help="tuning cache file (launch shapes per shape class)")
     ap.add_argument("--retune", action="store_true",
-                    help="night: tune every shape class (library autotuner) and store the "
-                         "choices in --cache before the timed run")
+                    help="tune every shape class of the workload (library autotuner) and "
+                         "store the choices in --cache before the timed run")
     ap.add_argument("--tune-set", choices=["small", "full"], default="small",
-                    help="night --retune: candidate launch shapes per class")
+                    help="--retune: candidate launch shapes per class")
     ap.add_argument("--no-graph", action="store_true", help="night: eager launches per step")
     ap.add_argument("--ceilings", action="store_true",
                     help="print the measured unit rates (LDS atomics, integer VALU, HBM copy)")
