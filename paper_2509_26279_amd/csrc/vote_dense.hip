@@ -66,6 +66,8 @@ struct Shared {
     int32_t sg[64];             // segment: left guard cells of each lane, gx | gy << 16
     int32_t heads[NW][64];      // per wave: marks of the runs that start in the block being staged
     int32_t bad;
+    int32_t spill[2];           // tile t % 2 was staged in chunks (set by its waves)
+    int32_t n_spill;            // tiles staged in chunks, not yet added to the result
     int32_t count_on;           // measurement: count the LDS atomic vote instructions
     unsigned long long n_instr; // their number in this workgroup
 };
@@ -599,7 +601,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         }
 
         // 2. vote this wave's entries, chunk by chunk (the first is staged)
-        if (Mw > wcap && lane == 0) atomicAdd(&a.res->n_spilled, 1);
+        if (Mw > wcap && lane == 0) sh.spill[tseq & 1] = 1;
         for (int32_t c0 = 0; c0 < Mw; c0 += wcap) {
             if (c0 > 0) stage_chunk(ox, c0);
 #pragma unroll
@@ -646,7 +648,16 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         // the summing of tile t + 2, which use the other slots.
         const bool any = staged != 0;
         staged = sh.voted[(tseq + 1) & 3];  // the next tile's, complete at this barrier
-        if (tid == 0) sh.voted[(tseq + 3) & 3] = 0;
+        if (tid == 0) {
+            sh.voted[(tseq + 3) & 3] = 0;
+            // a spill flag is set before the barrier ending its tile and
+            // cleared here, before the barrier ending the next one (after
+            // which the flag's next tile sets it)
+            if (sh.spill[tseq & 1]) {
+                ++sh.n_spill;
+                sh.spill[tseq & 1] = 0;
+            }
+        }
 
         // 3. read and clear the histogram; emit or queue interior cells
         if (any) {
@@ -737,6 +748,8 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
     if (tid == 0) {
         sh.count_on = a.atomics != nullptr;
         sh.n_instr = 0;
+        sh.spill[0] = sh.spill[1] = 0;
+        sh.n_spill = 0;
     }
     // Workgroups are dispatched round-robin over the XCDs (each with its own
     // L2); give XCD x the logical indices [x G / 8, (x + 1) G / 8) so that the
@@ -753,6 +766,9 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
     }
     __syncthreads();
     if (tid == 0 && sh.count_on && sh.n_instr) atomicAdd(a.atomics, sh.n_instr);
+    // one add per workgroup: the count of every chunked tile to one global
+    // word would serialise at that word's L2 channel
+    if (tid == 0 && sh.n_spill) atomicAdd(&a.res->n_spilled, sh.n_spill);
 }
 
 constexpr int64_t kBatchRun = 64;  // rounds of an XCD's block of items in the batched walk
@@ -784,6 +800,8 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
     if (tid == 0) {
         sh.count_on = atomics != nullptr;
         sh.n_instr = 0;
+        sh.spill[0] = sh.spill[1] = 0;
+        sh.n_spill = 0;
     }
     int later_t0 = 0;  // some chip's reference epoch is later than its earliest epoch
     for (int c = tid; c < n_chips; c += T) later_t0 |= chips[c].cat.dt[chips[c].e_first] != 0;
@@ -807,6 +825,10 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
         const DenseArgs &a = chips[chip];
         if (chip != chip_now) {
             __syncthreads();  // the previous item no longer reads sh.dt or the stage
+            if (tid == 0 && sh.n_spill) {  // the previous chip's chunked tiles
+                atomicAdd(&chips[chip_now].res->n_spilled, sh.n_spill);
+                sh.n_spill = 0;
+            }
             if (tid < a.cat.n_epochs) sh.dt[tid] = a.cat.dt[tid];
             // this chip's histogram may cover what was the previous chip's stage
             const int hw = a.hx * a.hy * (64 / G);
@@ -817,6 +839,7 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
     }
     __syncthreads();
     if (tid == 0 && sh.count_on && sh.n_instr) atomicAdd(atomics, sh.n_instr);
+    if (tid == 0 && sh.n_spill) atomicAdd(&chips[chip_now].res->n_spilled, sh.n_spill);
 }
 
 // Exact bins of a queued cell: for velocity v and the cell's 2^m x 2^m
