@@ -163,7 +163,7 @@ bool is_weighted(int32_t mode) {
 bool refines(int dense_mode) { return dense_mode == kCountRef || dense_mode == kWeightRef; }
 
 struct WsLayout {
-    size_t count, blocksum, cellid, rank, sxy, sidx, present, dt, refine_count, refine;
+    size_t count, offT, blocksum, cellid, rank, sxy, sidx, present, dt, refine_count, refine;
     size_t keys, keys_alt, hist, hist_blocksum;  // sort path
     size_t total;
 };
@@ -175,6 +175,7 @@ WsLayout ws_layout(const sas_plan *p, int64_t n) {
     const int64_t nb = (n_count + kScanTile - 1) / kScanTile;
     const size_t nn = (size_t)std::max<int64_t>(n, 1);
     L.count = o; o = align_up(o + sizeof(int32_t) * n_count);
+    L.offT = o; o = align_up(o + sizeof(int32_t) * (size_t)p->n_epochs * (p->ncx + 1) * p->ncy);
     L.blocksum = o; o = align_up(o + sizeof(int32_t) * nb);
     L.cellid = o; o = align_up(o + sizeof(int32_t) * nn);
     L.rank = o; o = align_up(o + sizeof(int32_t) * nn);
@@ -200,6 +201,7 @@ WsLayout ws_layout(const sas_plan *p, int64_t n) {
 PrepBuffers prep_buffers(const WsLayout &L, char *w) {
     PrepBuffers pb;
     pb.count = (int32_t *)(w + L.count);
+    pb.offT = (int32_t *)(w + L.offT);
     pb.blocksum = (int32_t *)(w + L.blocksum);
     pb.cellid = (int32_t *)(w + L.cellid);
     pb.rank = (int32_t *)(w + L.rank);
@@ -217,6 +219,7 @@ DenseArgs dense_args(const sas_plan *p, const WsLayout &L, char *w, const PrepBu
     a.cat.sxy = pb.sxy;
     a.cat.sidx = pb.sidx;
     a.cat.off = pb.count;
+    a.cat.offT = pb.offT;
     a.cat.dt = pb.dt;
     a.cat.n_epochs = p->n_epochs;
     a.cat.ncx = p->ncx;
@@ -551,7 +554,8 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     if (cl > 30) return fail(SAS_E_UNSUPPORTED, "sas_plan_create: footprint too large");
     const int64_t ncx = ncells_of(cl, ex[0], ex[1]), ncy = ncells_of(cl, ex[2], ex[3]);
     const int64_t n_cells = (int64_t)d->n_epochs * ncx * ncy;
-    if (n_cells >= ((int64_t)1 << 30))
+    // the column-major copy of the offsets holds E (ncx + 1) ncy words
+    if (n_cells >= ((int64_t)1 << 30) || (int64_t)d->n_epochs * (ncx + 1) * ncy >= ((int64_t)1 << 30))
         return fail(SAS_E_INVALID, "sas_plan_create: window index too large; raise cell_log2");
     const int rows_log2 = log2_ceil(rows_bound(cl, TY));
     const size_t hist_bytes = (size_t)HX * HY * NV * 4;

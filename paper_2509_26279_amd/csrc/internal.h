@@ -37,6 +37,10 @@ struct PreparedCatalog {
     const int2 *sxy;      // [n_valid] (x, y), Q8; weighted plans: (256 x + w, y)
     const int32_t *sidx;  // [n_valid] catalog index of each detection
     const int32_t *off;   // [n_cells + 1] CSR offsets; cell = (e * ncy + cy) * ncx + cx
+    const int32_t *offT;  // [E][ncx + 1][ncy] the same offsets by column:
+                          // offT[(e * (ncx + 1) + cx) * ncy + cy] = off[(e * ncy + cy) * ncx + cx]
+                          // (cx = ncx: the end of row cy), so that consecutive rows of one
+                          // column are adjacent
     const int32_t *dt;    // [E] t[e] - t0, Q16 h; -1 for epochs without detections
     int32_t n_epochs;
     int32_t ncx, ncy, cell_log2;
@@ -80,6 +84,7 @@ struct DenseArgs {
 // Workspace carve-up for the preparation stage.
 struct PrepBuffers {
     int32_t *count;     // [n_cells + 1] -> offsets after the scan
+    int32_t *offT;      // [E][ncx + 1][ncy] offsets by column (PreparedCatalog::offT)
     int32_t *blocksum;  // [scan blocks]
     int32_t *cellid;    // [n]
     int32_t *rank;      // [n]

@@ -150,6 +150,20 @@ __global__ void k_prep_reftime(const int64_t *t, const int32_t *present, int32_t
     if (e < n_epochs) dt[e] = (present[e] && t0 != LLONG_MAX) ? (int32_t)(t[e] - t0) : -1;
 }
 
+// Offsets by column: offT[(e (ncx + 1) + cx) ncy + cy] = off[(e ncy + cy) ncx + cx]
+// for cx in [0, ncx] (cx = ncx reads the start of the next row, the end of
+// row cy).  Threads run over offT in order, so its writes are coalesced.
+__global__ void k_prep_offsets_by_column(const int32_t *__restrict__ off, int32_t *__restrict__ offT,
+                                         int32_t n_epochs, int32_t ncx, int32_t ncy) {
+    const int64_t total = (int64_t)n_epochs * (ncx + 1) * ncy;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const int64_t cy = i % ncy, rest = i / ncy;
+        const int64_t cx = rest % (ncx + 1), e = rest / (ncx + 1);
+        offT[i] = off[(e * ncy + cy) * ncx + cx];
+    }
+}
+
 __global__ void k_prep_scatter(const int32_t *__restrict__ x, const int32_t *__restrict__ y,
                                const uint8_t *__restrict__ weight, int64_t n,
                                const int32_t *__restrict__ cellid,
@@ -203,6 +217,14 @@ hipError_t launch_prep(const int32_t *x, const int32_t *y, const uint8_t *epoch,
     hipLaunchKernelGGL(k_scan_blocksums, dim3(1), dim3(kScanThreads), 0, stream, pb.blocksum, nb);
     hipLaunchKernelGGL(k_scan_add, dim3(blocks_for(n_count, 256)), dim3(256), 0, stream,
                        pb.count, n_count, pb.blocksum);
+    {
+        const int64_t total = (int64_t)n_epochs * (ncx + 1) * ncy;
+        unsigned tb = blocks_for(total, 256);
+        if (tb > 4096) tb = 4096;
+        if (tb > 0)
+            hipLaunchKernelGGL(k_prep_offsets_by_column, dim3(tb), dim3(256), 0, stream,
+                               pb.count, pb.offT, n_epochs, ncx, ncy);
+    }
     hipLaunchKernelGGL(k_prep_reftime, dim3(1), dim3(kMaxEpochs), 0, stream, t_dev, pb.present,
                        n_epochs, pb.dt);
     if (n > 0) {

@@ -245,8 +245,10 @@ __device__ inline void vote_run(const typename V::Entry *st, int32_t n, const V 
 }
 
 // Window-index row r of epoch e for the item's tile row at oy: the index of
-// its cell column 0, or -1 when the epoch's window misses the footprint in y
-// or touches fewer rows (tile independent).
+// its cell column 0 in the offsets by column (offT), or -1 when the epoch's
+// window misses the footprint in y or touches fewer rows (tile independent).
+// The lanes of one epoch hold consecutive rows, so their offsets are
+// adjacent words.
 __device__ __attribute__((always_inline)) inline int32_t window_row(
     const DenseArgs &a, const Shared &sh, int e, int r, int32_t oy, int32_t H) {
     const PreparedCatalog &c = a.cat;
@@ -257,7 +259,7 @@ __device__ __attribute__((always_inline)) inline int32_t window_row(
     if (r == 0 && cy1 - cy0 + 1 > a.rows)  // excluded by the planner
         atomicOr(&a.res->status, SAS_DATA_INTERNAL);
     if (cy0 + r > cy1) return -1;
-    return (e * c.ncy + cy0 + r) * c.ncx;  // < 2^30 cells (planner)
+    return e * (c.ncx + 1) * c.ncy + cy0 + r;  // < 2^30 words (planner)
 }
 
 // Run of that row for the tile whose Q8 x origin is oxw: source offset and
@@ -272,8 +274,8 @@ __device__ __attribute__((always_inline)) inline void window_run(
     if (!cell_span(oxw + sh.es[e].x, oxw + sh.es[e].y + W, c.x0, c.x1, c.cell_log2, &cx0,
                    &cx1))
         return;
-    src = c.off[row + cx0];
-    end = c.off[row + cx1 + 1];
+    src = c.offT[row + cx0 * c.ncy];
+    end = c.offT[row + (cx1 + 1) * c.ncy];
 }
 
 // Exclusive scan over the 64 lanes of a wave; *total gets the sum.
