@@ -176,12 +176,16 @@ typedef struct {
     int32_t weight_hint;        /* weighted plans: typical weight of a detection (1..255); with
                                    n_det_hint it lets coarse_log2 = 0 choose coarse cells.
                                    0: weighted plans use single bins unless coarse_log2 > 0 */
-    int32_t half_counts;        /* 16-bit histogram counts (plans with groups = 1 that count
-                                   detections or refine coarse cells): velocity lanes j and
-                                   j + 32 share a word and two histograms alternate by tile;
-                                   a tile whose window entries reach 2^16 is voted with 32-bit
-                                   counts.  0: on wherever the plan allows it; 1: on, and an
-                                   error (SAS_E_INVALID) where the plan does not; -1: off */
+    int32_t half_counts;        /* 16-bit histogram counts (dense plans that count detections,
+                                   more than 32 epochs, or coarse cells): velocity lanes j and
+                                   j + NV / 2 of a block of NV = 64 / groups share a word.
+                                   groups = 1: two histograms alternate by tile, and a tile
+                                   whose window entries reach 2^16 is voted with 32-bit counts;
+                                   groups 2 and 4: one histogram in half the LDS (larger
+                                   tiles), and such a tile is voted in two passes of half the
+                                   lanes each with 32-bit counts.  0: on wherever the plan
+                                   allows it; 1: on, and an error (SAS_E_INVALID) where the plan
+                                   does not; -1: off */
     int32_t prune;              /* SAS_MODE_EPOCHS plans: 0 skips the tiles of a velocity block
                                    where fewer than N_min epochs can reach any bin (the window
                                    of every other epoch misses the footprint), which cannot
@@ -244,7 +248,8 @@ typedef struct {
     int32_t stage_cap;
     int32_t lds_bytes;     /* LDS per vote workgroup */
     int32_t packed;        /* 1: votes use packed 16-bit arithmetic */
-    int32_t half_counts;   /* 1: 16-bit histogram counts, two histograms by tile */
+    int32_t half_counts;   /* 16-bit histogram counts: 1, two histograms by tile; 2, one
+                              histogram (groups 2 and 4); 0, 32-bit counts */
     int64_t n_tiles_kept;  /* tiles voted when the catalog's earliest epoch holds a detection
                               (the rest reach fewer than N_min epochs; tuning.prune) */
     int64_t n_items_kept;  /* their work items */

@@ -508,6 +508,22 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
         while (((int64_t)1 << l) < v) ++l;
         return l;
     };
+    // 16-bit histogram counts for the counting cell variants on the dense
+    // path (a count never exceeds the window entries of its tile, and the
+    // kernel votes a tile that reaches 2^16 with 32-bit counts): with one
+    // lane group, two histograms alternating by tile in the LDS of one 32-bit
+    // histogram (halves = 1); with more, one histogram in half the LDS
+    // (halves = 2), so that tiles get larger.
+    const bool counts_mode =
+        !weighted && (m > 0 || d->mode == SAS_MODE_DETECTIONS ||
+                      (d->mode == SAS_MODE_EPOCHS && d->n_epochs > 32));
+    const bool dense_path = d->path == SAS_PATH_AUTO || d->path == SAS_PATH_DENSE;
+    if (tu.half_counts == 1 && !(counts_mode && dense_path))
+        return fail(SAS_E_INVALID, "sas_plan_create: half_counts = 1 needs the dense path and a "
+                                   "counting cell variant (detections, more than 32 epochs, or "
+                                   "coarse cells)");
+    const int halves = tu.half_counts >= 0 && counts_mode && dense_path ? (G == 1 ? 1 : 2) : 0;
+    const int64_t bin_words = halves == 2 ? NV / 2 : NV;  // LDS words of a histogram bin
     // tile shape: the largest interior under the histogram budget with the
     // best ratio of interior to window area (exact windows: the window adds
     // the average spread of a block to each side length)
@@ -515,7 +531,7 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     // and a row's words fit a 16-bit weight
     auto packs = [&](int64_t tx, int64_t ty) {
         return !weighted && tu.packed >= 0 && ((tx + guard_x) << kc) <= 65536 &&
-               ((ty + guard_y) << kc) <= 65536 && (tx + guard_x) * NV * 4 <= 65535;
+               ((ty + guard_y) << kc) <= 65536 && (tx + guard_x) * bin_words * 4 <= 65535;
     };
     int32_t TX = tu.tile_x, TY = tu.tile_y;
     if (!TX || !TY) {
@@ -526,7 +542,7 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
                 if (tu.tile_y && ty != tu.tile_y) continue;
                 // the stage of a packed tile takes half the bytes
                 const size_t hist_budget = lds_target * (packs(tx, ty) ? 17 : 15) / 20;
-                const size_t hb = (size_t)(tx + guard_x) * (ty + guard_y) * NV * 4;
+                const size_t hb = (size_t)(tx + guard_x) * (ty + guard_y) * bin_words * 4;
                 if (hb > hist_budget) continue;
                 const double wx = tx + 0.5 * spread_x_avg / cellw + 0.5;
                 const double wy = ty + 0.5 * spread_y_avg / cellw + 0.5;
@@ -558,10 +574,10 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     if (n_cells >= ((int64_t)1 << 30) || (int64_t)d->n_epochs * (ncx + 1) * ncy >= ((int64_t)1 << 30))
         return fail(SAS_E_INVALID, "sas_plan_create: window index too large; raise cell_log2");
     const int rows_log2 = log2_ceil(rows_bound(cl, TY));
-    const size_t hist_bytes = (size_t)HX * HY * NV * 4;
+    const size_t hist_bytes = (size_t)HX * HY * bin_words * 4;
     int64_t stage_cap = tu.stage_cap;
     if (!stage_cap) {
-        const size_t fixed = dense_lds_bytes(G, (int)HX, (int)HY, 0, packed);
+        const size_t fixed = dense_lds_bytes(G, (int)HX, (int)HY, 0, packed, halves);
         const size_t room = lds_target > fixed ? (lds_target - fixed) / entry_bytes : 0;
         int64_t want = (int64_t)room;
         if (tu.n_det_hint > 0) {
@@ -574,7 +590,7 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     // one part per wave of the workgroup, at least two detections each
     stage_cap = std::max<int64_t>((stage_cap + kVoteWaves - 1) / kVoteWaves * kVoteWaves,
                                   2 * kVoteWaves);
-    const size_t lds = dense_lds_bytes(G, (int)HX, (int)HY, (int)stage_cap, packed);
+    const size_t lds = dense_lds_bytes(G, (int)HX, (int)HY, (int)stage_cap, packed, halves);
     if (HX > 65535 || HY > 65535 || hist_bytes > lds_cap || lds > lds_cap)
         return fail(SAS_E_INVALID, "sas_plan_create: tile + guard cells + stage exceed the LDS of "
                                    "a workgroup; lower tile_x, tile_y, stage_cap or vblock");
@@ -626,15 +642,7 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
                                   : std::min<int64_t>((int64_t)1 << 26,
                                                       std::max<int64_t>((int64_t)1 << 22,
                                                                         (int64_t)(16 * expected_flags)));
-    // 16-bit histogram counts (lanes j and j + 32 of one word, two histograms
-    // alternating by tile): a count never exceeds the window entries of its
-    // tile, and the kernel votes a tile that reaches 2^16 with 32-bit counts.
-    const bool counts = p->dense_mode == kCountDet || p->dense_mode == kCountRef;
-    const bool halves_ok = G == 1 && counts && p->path == SAS_PATH_DENSE;
-    if (tu.half_counts == 1 && !halves_ok)
-        return fail(SAS_E_INVALID, "sas_plan_create: half_counts = 1 needs the dense path, "
-                                   "groups = 1 and a counting mode (detections, or coarse cells)");
-    p->halves = tu.half_counts >= 0 && halves_ok ? 1 : 0;
+    p->halves = halves;
     p->tile_x = TX;
     p->tile_y = TY;
     p->vbx = vbx;
@@ -1243,9 +1251,10 @@ sas_status sas_batch_create(const sas_batch_chip *chips, int32_t n_chips, void *
         for (int32_t c = 0; c < n_chips; ++c) {
             const sas_plan *p = chips[c].plan;
             if (batch_class(p) != k) continue;
-            cl.hist_words_max = std::max(cl.hist_words_max, p->hx * p->hy * (64 / p->groups));
+            cl.hist_words_max = std::max(cl.hist_words_max, p->hx * p->hy * (64 / p->groups) /
+                                                                (p->halves == 2 ? 2 : 1));
             cl.lds = std::max(cl.lds, dense_lds_bytes(p->groups, p->hx, p->hy, p->stage_cap,
-                                                      p->packed));
+                                                      p->packed, p->halves));
         }
         cl.n_items = (int64_t)v.size();
         void *d = nullptr;

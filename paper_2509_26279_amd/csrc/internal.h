@@ -57,8 +57,9 @@ struct DenseArgs {
     int32_t rows;             // index rows a tile window can touch (planner bound)
     int32_t rows_log2;        // run rows per epoch: 2^rows_log2 >= rows
     int32_t packed;           // 1: packed 16-bit votes (stage entries of 4 bytes)
-    int32_t halves;           // 1: 16-bit counts, lanes j and j + 32 share a word; two
-                              //    histograms of hx * hy * 32 words alternate by tile
+    int32_t halves;           // 16-bit counts, lanes j and j + NV / 2 share a word: 1, two
+                              // histograms of hx * hy * NV / 2 words alternate by tile;
+                              // 2, one such histogram (its LDS is half a 32-bit one)
     int32_t n_min, count_sat;
     int32_t mode_epochs;      // 1: count distinct epochs, 0: count detections
     int32_t weighted;         // 0, or SAS_MODE_WEIGHTED_EPOCHS / _DETECTIONS
@@ -256,7 +257,7 @@ hipError_t launch_vote_dense_batch(int mode, int groups, int packed, const Dense
                                    int64_t n_kept, int32_t hist_words_max, size_t lds, int grid,
                                    unsigned long long *atomics, hipStream_t stream);
 hipError_t launch_refine(const DenseArgs &a, hipStream_t stream);
-size_t dense_lds_bytes(int groups, int hx, int hy, int stage_cap, int packed);
+size_t dense_lds_bytes(int groups, int hx, int hy, int stage_cap, int packed, int halves);
 size_t dense_static_lds_bytes();
 
 // Refine / Gather / iterate (Steps 4-6) per cluster.

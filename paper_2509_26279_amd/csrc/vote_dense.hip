@@ -332,8 +332,9 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
     typedef typename VA::Entry Entry;
     constexpr int ER = PK ? kEpochRegsPacked : kEpochRegs;
     uint32_t *hist = (uint32_t *)smem4;
-    const int hist_words = a.hx * a.hy * NV;
-    Entry *stage = (Entry *)(hist + hist_words);
+    const int hist_words = a.hx * a.hy * NV;  // words of a 32-bit histogram
+    // halves = 2 plans hold half of that
+    Entry *stage = (Entry *)(hist + (a.halves == 2 ? hist_words / 2 : hist_words));
 
     const PreparedCatalog &c = a.cat;
     const int E = c.n_epochs;
@@ -343,12 +344,17 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
     const int32_t cellw = (int32_t)1 << kc;
     const int32_t W = a.tile_x << kc, H = a.tile_y << kc;  // tile size, Q8
     const uint32_t nmin = (uint32_t)a.n_min;
-    // 16-bit counts (G = 1, counting modes): velocity lanes j and j + 32 add
-    // 1 and 2^16 to one word of a bin's 32, and tiles alternate between two
-    // histograms of hist_words / 2 words.  A tile whose window entries could
-    // reach 2^16 is voted in the 32-bit form over both (block uniform).
-    constexpr bool kHalvesOk = G == 1 && (MODE == kCountDet || MODE == kCountRef);
-    const bool hv = kHalvesOk && a.halves != 0;
+    // 16-bit counts (counting modes): velocity lanes j and j + NV / 2 add 1
+    // and 2^16 to one word of a bin's NV / 2.  halves = 1 (G = 1): tiles
+    // alternate between two such histograms in the LDS of one 32-bit
+    // histogram, and a tile whose window entries could reach 2^16 is voted in
+    // the 32-bit form over both.  halves = 2: one such histogram in half the
+    // LDS (so the planner's tiles are larger), and a tile whose entries could
+    // reach 2^16 is voted twice with 32-bit counts, by the lanes j < NV / 2
+    // and then by the others, each pass read out on its own (block uniform).
+    constexpr bool kHalvesOk = MODE == kCountDet || MODE == kCountRef;
+    const bool hv = G == 1 && kHalvesOk && a.halves == 1;  // the planner's forms by lane groups
+    const bool hs = G > 1 && kHalvesOk && a.halves == 2;
     const int LR = a.rows_log2;  // run rows per epoch: 2^LR
     const int32_t vx_lo = a.seg[4 * sg], vx_hi = a.seg[4 * sg + 1];
     const int32_t vy_lo = a.seg[4 * sg + 2], vy_hi = a.seg[4 * sg + 3];
@@ -373,25 +379,34 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
     const int32_t oy = ty0 * cellw;
     // Q8 origin of this lane's histogram row 0: (ty0 - gy) cells
     const uint32_t oy_lane = (uint32_t)(ty0 - my_gy) * (uint32_t)cellw;
-    // the current tile's histogram form: 16-bit halves (hvt) or 32-bit words,
-    // its row bytes, the lane's increment, the log2 of a bin's bytes and the
-    // LDS address of the lane's word in bin 0
+    // The current tile's histogram form (block uniform):
+    //   kForm32: 32-bit counts, NV words per bin;
+    //   kFormHalves: 16-bit halves, NV / 2 words per bin (halves = 1: the
+    //     histogram of tile t % 2; halves = 2: the only one);
+    //   kFormHalfLanes: 32-bit counts of the lanes j with j / (NV / 2) equal to
+    //     the pass, NV / 2 words per bin (the other lanes add 0);
+    // with its row bytes, the lane's increment, the log2 of a bin's bytes and
+    // the LDS address of the lane's word in bin 0.
+    enum { kForm32 = 0, kFormHalves = 1, kFormHalfLanes = 2 };
     const uint32_t hist_base = (uint32_t)(uintptr_t)(lds_u32 *)hist;
-    bool hvt = false;
+    int form = kForm32, fpass = 0;
     uint32_t row_bytes = 0, cval = 1, lane_addr = 0;
     int lbt = 0;
     us2 wts;  // packed form: (bytes of a bin, row bytes)
-    const auto set_form = [&](bool h, int32_t t) __attribute__((always_inline)) {
-        const int nc = h ? 32 : NV;  // words per bin
-        hvt = h;
+    const auto set_form = [&](int f, int32_t t, int pass) __attribute__((always_inline)) {
+        const int nc = f == kForm32 ? NV : NV / 2;  // words per bin
+        form = f;
+        fpass = pass;
         row_bytes = (uint32_t)(a.hx * nc * 4);
-        cval = h && j >= 32 ? 65536u : 1u;
-        lbt = h ? 7 : LNV + 2;
+        const bool hi = j >= NV / 2;
+        cval = f == kFormHalves ? (hi ? 65536u : 1u) : f == kFormHalfLanes ? (hi == (pass != 0) ? 1u : 0u)
+                                                                          : 1u;
+        lbt = f == kForm32 ? LNV + 2 : LNV + 1;
         wts = us2{(unsigned short)(nc * 4), (unsigned short)row_bytes};
-        lane_addr = hist_base + (uint32_t)((h ? (j & 31) : j) * 4) +
-                    (h ? (uint32_t)(t & 1) * (uint32_t)(hist_words * 2) : 0u);
+        lane_addr = hist_base + (uint32_t)((f == kForm32 ? j : (j & (NV / 2 - 1))) * 4) +
+                    (f == kFormHalves && hv ? (uint32_t)(t & 1) * (uint32_t)(hist_words * 2) : 0u);
     };
-    set_form(false, 0);
+    set_form(hs ? kFormHalves : kForm32, 0, 0);
 
     // Lane shifts of this wave's epochs e = wave + k NW (k < ER), kept in
     // registers for the whole item with the Q8 origin of the lane's
@@ -599,13 +614,19 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
             // the previous tile's read-out
             const bool h = staged < 65536;
             if (!h) __syncthreads();
-            set_form(h, tseq);
+            set_form(h ? kFormHalves : kForm32, tseq, 0);
         }
-
-        // 2. vote this wave's entries, chunk by chunk (the first is staged)
+        // halves = 2: from 2^16 entries on, two passes of half the lanes
+        const int npass = hs && staged >= 65536 ? 2 : 1;
+        const bool any = staged != 0;
         if (Mw > wcap && lane == 0) sh.spill[tseq & 1] = 1;
+        for (int pass = 0; pass < npass; ++pass) {
+        if (hs) set_form(npass == 2 ? kFormHalfLanes : kFormHalves, tseq, pass);
+
+        // 2. vote this wave's entries, chunk by chunk (the first is staged;
+        // a second pass stages it again when later chunks replaced it)
         for (int32_t c0 = 0; c0 < Mw; c0 += wcap) {
-            if (c0 > 0) stage_chunk(ox, c0);
+            if (c0 > 0 || (pass > 0 && Mw > wcap)) stage_chunk(ox, c0);
 #pragma unroll
             for (int k = 0; k < ER; ++k) {
                 const int e = wave + k * NW;
@@ -632,39 +653,42 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
             }
             __builtin_amdgcn_wave_barrier();  // the stage is read before it is refilled
         }
+        const bool last = pass == npass - 1;
         // the next tile's runs and first chunk, while other waves still vote
-        if (next) {
+        if (last && next) {
             runs(oxn);
             if (Mw > 0) {
                 stage_chunk(oxn, 0);
                 if (lane == 0) atomicAdd(&sh.voted[(tseq + 1) & 3], Mw);
             }
         }
-        __syncthreads();  // every vote of this tile is in the histogram
+        __syncthreads();  // every vote of this tile (pass) is in the histogram
         // The total of tile t is summed before the barrier that ends tile t - 1
         // (the first tile of an item: after the item's setup barriers) and read
         // after the one that ends tile t; slot t + 3 (last read after the
         // barrier ending tile t - 1, next summed after the one ending tile
-        // t + 1) is cleared here.  With one barrier per tile (16-bit counts)
-        // this tile's read-out overlaps other waves' votes of tile t + 1 and
-        // the summing of tile t + 2, which use the other slots.
-        const bool any = staged != 0;
-        staged = sh.voted[(tseq + 1) & 3];  // the next tile's, complete at this barrier
-        if (tid == 0) {
-            sh.voted[(tseq + 3) & 3] = 0;
-            // a spill flag is set before the barrier ending its tile and
-            // cleared here, before the barrier ending the next one (after
-            // which the flag's next tile sets it)
-            if (sh.spill[tseq & 1]) {
-                ++sh.n_spill;
-                sh.spill[tseq & 1] = 0;
+        // t + 1) is cleared here.  With one barrier per tile (16-bit counts in
+        // two histograms) this tile's read-out overlaps other waves' votes of
+        // tile t + 1 and the summing of tile t + 2, which use the other slots.
+        if (last) {
+            staged = sh.voted[(tseq + 1) & 3];  // the next tile's, complete at this barrier
+            if (tid == 0) {
+                sh.voted[(tseq + 3) & 3] = 0;
+                // a spill flag is set before the barrier ending its tile and
+                // cleared here, before the barrier ending the next one (after
+                // which the flag's next tile sets it)
+                if (sh.spill[tseq & 1]) {
+                    ++sh.n_spill;
+                    sh.spill[tseq & 1] = 0;
+                }
             }
         }
 
         // 3. read and clear the histogram; emit or queue interior cells
         if (any) {
-            const int rw = hvt ? hist_words / 2 : hist_words;  // words of this tile's histogram
-            uint4 *hb = smem4 + (hvt ? (tseq & 1) * (hist_words / 8) : 0);
+            // words of this tile's histogram, and its first word
+            const int rw = form == kForm32 ? hist_words : hist_words / 2;
+            uint4 *hb = smem4 + (form == kFormHalves && hv ? (tseq & 1) * (hist_words / 8) : 0);
             // count cnt of lane jj's velocity in bin `bin` (all lanes call)
             const auto emit = [&](uint32_t cnt, int jj, int bin) __attribute__((always_inline)) {
                 bool ok = false;
@@ -695,7 +719,8 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                     hb[w4] = make_uint4(0, 0, 0, 0);
                 }
                 const uint32_t hw[4] = {h.x, h.y, h.z, h.w};
-                if (hvt) {  // word wi: bin wi / 32, velocity lanes wi % 32 (low), + 32 (high)
+                if (form == kFormHalves) {  // word wi: bin wi / (NV / 2), velocity lanes
+                                            // wi % (NV / 2) (low half) and that + NV / 2
                     uint32_t m = 0;
 #pragma unroll
                     for (int k = 0; k < 4; ++k) m = max(m, max(hw[k] & 0xffffu, hw[k] >> 16));
@@ -703,8 +728,17 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         const int wi = 4 * w4 + k;
-                        emit(hw[k] & 0xffffu, wi & 31, wi >> 5);
-                        emit(hw[k] >> 16, (wi & 31) + 32, wi >> 5);
+                        emit(hw[k] & 0xffffu, wi & (NV / 2 - 1), wi >> (LNV - 1));
+                        emit(hw[k] >> 16, (wi & (NV / 2 - 1)) + NV / 2, wi >> (LNV - 1));
+                    }
+                } else if (form == kFormHalfLanes) {  // word wi: bin wi / (NV / 2), velocity
+                                                      // lane wi % (NV / 2) + the pass's half
+                    const uint32_t m = max(max(h.x, h.y), max(h.z, h.w));
+                    if (!__any(m >= nmin)) continue;  // wave uniform
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int wi = 4 * w4 + k;
+                        emit(hw[k], (wi & (NV / 2 - 1)) + fpass * (NV / 2), wi >> (LNV - 1));
                     }
                 } else {
                     const uint32_t m = max(max(cell_count<MODE>(h.x), cell_count<MODE>(h.y)),
@@ -718,10 +752,11 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                 }
             }
         }
-        // the histogram is clear before the next tile's votes; after a 16-bit
-        // tile the next one votes into the other histogram, cleared before
-        // this tile's barrier
-        if (!hvt) __syncthreads();
+        // the histogram is clear before the next tile's (pass's) votes; after
+        // a 16-bit tile of two histograms the next one votes into the other
+        // histogram, cleared before this tile's barrier
+        if (!(hv && form == kFormHalves)) __syncthreads();
+        }  // passes
 #pragma unroll
         for (int k = 0; k < ER; ++k) {
             if constexpr (PK) {  // low half only, modulo 2^16
@@ -741,7 +776,7 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
     extern __shared__ uint4 smem4[];
     __shared__ Shared sh;
     const int tid = threadIdx.x;
-    const int hist_words = a.hx * a.hy * (64 / G);
+    const int hist_words = a.hx * a.hy * (64 / G) / (a.halves == 2 ? 2 : 1);  // as allocated
     for (int i = tid; i < hist_words / 4; i += T) smem4[i] = make_uint4(0, 0, 0, 0);
     if (tid < a.cat.n_epochs) sh.dt[tid] = a.cat.dt[tid];
     int32_t tseq = 0;  // tiles done by this workgroup (flag ring of sh.voted)
@@ -833,7 +868,7 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_v
             }
             if (tid < a.cat.n_epochs) sh.dt[tid] = a.cat.dt[tid];
             // this chip's histogram may cover what was the previous chip's stage
-            const int hw = a.hx * a.hy * (64 / G);
+            const int hw = a.hx * a.hy * (64 / G) / (a.halves == 2 ? 2 : 1);
             for (int i = tid; i < hw / 4; i += T) smem4[i] = make_uint4(0, 0, 0, 0);
             chip_now = chip;
         }
@@ -1045,8 +1080,9 @@ hipError_t launch_w(int mode, int groups, const DenseArgs &a, size_t lds, hipStr
 
 }  // namespace
 
-size_t dense_lds_bytes(int groups, int hx, int hy, int stage_cap, int packed) {
-    size_t b = (size_t)hx * hy * (64 / groups) * sizeof(uint32_t);   // histogram
+size_t dense_lds_bytes(int groups, int hx, int hy, int stage_cap, int packed, int halves) {
+    // histogram: 32-bit words, or 16-bit counts in one histogram (halves = 2)
+    size_t b = (size_t)hx * hy * (64 / groups) * (halves == 2 ? 2 : sizeof(uint32_t));
     b += (size_t)stage_cap * (packed ? sizeof(uint32_t) : sizeof(int2));  // stage (NW parts)
     return (b + 15) & ~(size_t)15;
 }
@@ -1078,7 +1114,7 @@ hipError_t launch_refine(const DenseArgs &a, hipStream_t stream) {
 hipError_t launch_vote_dense(int mode, int groups, const DenseArgs &a, hipStream_t stream,
                              hipEvent_t ev0, hipEvent_t ev1) {
     if (a.n_items <= 0) return hipSuccess;
-    const size_t lds = dense_lds_bytes(groups, a.hx, a.hy, a.stage_cap, a.packed);
+    const size_t lds = dense_lds_bytes(groups, a.hx, a.hy, a.stage_cap, a.packed, a.halves);
     if (mode == kWeightDet || mode == kWeightRef) {
         if (a.packed) return hipErrorInvalidValue;  // excluded by the planner
         return launch_w(mode, groups, a, lds, stream, ev0, ev1);

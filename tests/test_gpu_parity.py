@@ -92,16 +92,28 @@ def _half_count_tunings(mode):
     """16-bit histogram counts forced on: coarse cells (any mode), exact
     detection counts, small tiles (many tiles per item, so both histograms
     and every slot of the staged-entry ring are used), small stages
-    (chunks) and the 32-bit vote form."""
+    (chunks) and the 32-bit vote form; two histograms by tile (one lane
+    group) and one histogram (two and four lane groups)."""
     out = (dict(coarse_log2=2, groups=1, half_counts=1),
            dict(coarse_log2=1, tile_x=2, tile_y=2, vblock_x=8, vblock_y=8, groups=1, half_counts=1),
            dict(coarse_log2=1, tile_x=7, tile_y=9, stage_cap=16, groups=1, vblock_x=5,
                 vblock_y=7, half_counts=1),
-           dict(coarse_log2=2, groups=1, packed=-1, half_counts=1))
+           dict(coarse_log2=2, groups=1, packed=-1, half_counts=1),
+           dict(coarse_log2=2, groups=2, half_counts=1),
+           dict(coarse_log2=1, tile_x=3, tile_y=2, stage_cap=16, groups=4, half_counts=1),
+           dict(coarse_log2=2, groups=4, packed=-1, half_counts=1))
     if mode == "detections":
         out += (dict(coarse_log2=-1, groups=1, half_counts=1),
-                dict(coarse_log2=-1, tile_x=3, tile_y=2, groups=1, half_counts=1, packed=-1))
+                dict(coarse_log2=-1, tile_x=3, tile_y=2, groups=1, half_counts=1, packed=-1),
+                dict(coarse_log2=-1, groups=2, half_counts=1),
+                dict(coarse_log2=-1, tile_x=3, tile_y=2, groups=4, half_counts=1, packed=-1))
     return out
+
+
+def _expected_halves(info, counting):
+    """The planner's 16-bit count form for a counting plan: two histograms
+    with one lane group, one histogram with more."""
+    return 0 if not counting else (1 if info["groups"] == 1 else 2)
 
 
 @pytest.mark.parametrize("n_epochs,mode", [(20, "epochs"), (100, "epochs"), (100, "detections")])
@@ -118,7 +130,8 @@ def test_overfull_window_is_chunked(gpu, n_epochs, mode):
     for n_min in (1, 15, 60):
         _say(f"chunked E={n_epochs} mode={mode} n_min={n_min}")
         o = oracle.vote(x, y, e, t, v, 1024, n_min, mode)
-        for tun in (dict(stage_cap=1024), dict(stage_cap=1024, groups=1, half_counts=1)):
+        for tun in (dict(stage_cap=1024), dict(stage_cap=1024, groups=1, half_counts=1),
+                    dict(stage_cap=1024, groups=4, half_counts=1)):
             if tun.get("half_counts") and mode == "epochs" and n_epochs <= 32:
                 tun = dict(tun, coarse_log2=1)  # epoch masks have no 16-bit form
             # every tile voted (prune = -1), so that the chunked path runs even
@@ -127,7 +140,8 @@ def test_overfull_window_is_chunked(gpu, n_epochs, mode):
             srch = sas.Search(plan, len(x), cand_cap=1 << 18)
             g = srch.run(x, y, e)
             assert srch.result()["n_spilled"] > 0  # the chunked path did run
-            assert plan.info()["half_counts"] == tun.get("half_counts", 0)
+            counting = mode == "detections" or n_epochs > 32 or tun.get("coarse_log2", 0) > 0
+            assert plan.info()["half_counts"] == _expected_halves(plan.info(), counting)
             plan.close()
             assert_same(g, o)
             # with coverage pruning: nothing to vote once N_min exceeds the epochs
@@ -141,9 +155,10 @@ def test_overfull_window_is_chunked(gpu, n_epochs, mode):
 
 
 def test_half_counts_choice_and_errors(gpu):
-    """16-bit counts are taken wherever the plan allows them (groups = 1, a
-    counting mode, the dense path) unless switched off; forcing them where
-    they do not apply is an argument error."""
+    """16-bit counts are taken wherever the plan allows them (a counting cell
+    variant on the dense path: two histograms with one lane group, one with
+    more) unless switched off; forcing them where they do not apply is an
+    argument error."""
     wl = synth.make_wide()
     v = _grid(wl)[:2000]
 
@@ -158,13 +173,15 @@ def test_half_counts_choice_and_errors(gpu):
     assert i["groups"] == 1 and i["half_counts"] == 1
     assert info_of(dict(coarse_log2=2))["half_counts"] == 1
     assert info_of(dict(n_det_hint=wl.n, half_counts=-1))["half_counts"] == 0
-    assert info_of(dict(groups=4, coarse_log2=2))["half_counts"] == 0
+    assert info_of(dict(groups=4, coarse_log2=2))["half_counts"] == 2
+    assert info_of(dict(groups=2, coarse_log2=2, half_counts=1))["half_counts"] == 2
+    assert info_of(dict(groups=2, coarse_log2=2, half_counts=-1))["half_counts"] == 0
     # 20 epochs in single bins: epoch masks, which have no 16-bit form
     assert info_of(dict(groups=1, coarse_log2=-1), wl.t_q16[:20])["half_counts"] == 0
     # 100 epochs without coarse cells: counts refined into exact bins
     assert info_of(dict(groups=1, coarse_log2=-1, half_counts=1))["half_counts"] == 1
-    for tun, t, path in ((dict(groups=2, coarse_log2=2, half_counts=1), wl.t_q16, "auto"),
-                         (dict(groups=1, coarse_log2=-1, half_counts=1), wl.t_q16[:20], "auto"),
+    for tun, t, path in ((dict(groups=1, coarse_log2=-1, half_counts=1), wl.t_q16[:20], "auto"),
+                         (dict(groups=4, coarse_log2=-1, half_counts=1), wl.t_q16[:20], "auto"),
                          (dict(groups=1, coarse_log2=2, half_counts=1), wl.t_q16, "sort"),
                          (dict(half_counts=2), wl.t_q16, "auto")):
         with pytest.raises(sas.SasError):
@@ -191,11 +208,12 @@ def test_half_counts_dense_tile_takes_32_bit_form(gpu):
     assert len(o) == len(v) and np.all(o["count"] == 65535) and np.all(o["flags"] == 1)
     # default tiles put the square in the first tile of its row; 4 x 4-bin
     # tiles put it in the second, between 16-bit tiles on both sides
-    for hc, tiles in ((1, {}), (1, dict(tile_x=4, tile_y=4)), (-1, {})):
-        _say(f"dense tile half_counts={hc} {tiles}")
+    for hc, gr, tiles in ((1, 1, {}), (1, 1, dict(tile_x=4, tile_y=4)), (-1, 1, {}),
+                          (1, 2, {}), (1, 4, dict(tile_x=4, tile_y=4)), (1, 4, {})):
+        _say(f"dense tile half_counts={hc} groups={gr} {tiles}")
         plan = sas.Plan(v, t, 1024, n_min, ext, mode="detections",
-                        tuning=dict(groups=1, coarse_log2=-1, half_counts=hc, **tiles))
-        assert plan.info()["half_counts"] == (1 if hc == 1 else 0)
+                        tuning=dict(groups=gr, coarse_log2=-1, half_counts=hc, **tiles))
+        assert plan.info()["half_counts"] == (0 if hc != 1 else 1 if gr == 1 else 2)
         srch = sas.Search(plan, n, cand_cap=1 << 16)
         g = srch.run(x, y, e)
         assert srch.result()["status"] == 0
