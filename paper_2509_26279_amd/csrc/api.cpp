@@ -391,7 +391,7 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     int G = tu.groups;
     if (G == 0) {
         const double spread8 = 7.0 * (double)d->binw_q8 / (double)cellw;  // 8 steps, in cells
-        G = spread8 <= 2.0 ? 1 : spread8 <= 4.0 ? 2 : 4;
+        G = spread8 <= 2.0 ? 1 : 2;
     }
     if (G != 1 && G != 2 && G != 4)
         return fail(SAS_E_INVALID, "sas_plan_create: groups must be 1, 2 or 4");
