@@ -338,7 +338,10 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
 
     const PreparedCatalog &c = a.cat;
     const int E = c.n_epochs;
-    const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
+    const int tid = threadIdx.x, lane = __lane_id();
+    // the wave index in a scalar register: the per-epoch and per-chunk
+    // decisions that depend on it are then scalar branches
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = G == 1 ? 0 : lane >> LNV, j = lane & (NV - 1);
     const int kc = a.log2b + a.coarse_log2;
     const int32_t cellw = (int32_t)1 << kc;
