@@ -452,7 +452,7 @@ def test_batch_matches_single_chip_votes(gpu):
     chips = _night_chips(6, 0.1)
     styles = {wl.bin_px for wl, *_ in chips}
     assert len(styles) == 2  # both styles present
-    # the wide-style chips take 16-bit counts, the fast-style ones do not
+    # the wide-style chips take two 16-bit histograms, the fast-style ones one
     assert len({plan.info()["half_counts"] for _, _, plan, *_ in chips}) == 2
     b = sas.Batch([(plan, x, y, e) for _, _, plan, x, y, e in chips], cand_cap=1 << 20)
     b.vote()
@@ -470,6 +470,34 @@ def test_batch_matches_single_chip_votes(gpu):
             assert_same(got[np.isin(got["v_idx"], idx)], o)
     b.close()
     for c in chips:
+        c[2].close()
+
+
+def test_batch_mixes_count_forms_in_one_kernel_class(gpu):
+    """Chips of one kernel class (cell variant, lane groups, vote form) with
+    and without 16-bit counts in one batch: each chip's histogram and stage
+    are laid out by its own plan; every list equals its single-chip vote."""
+    every = _night_chips(8, 0.1)
+    chips = [c for c in every if c[0].bin_px > 4][:3]
+    assert len(chips) == 3
+    wl, v, plan, x, y, e = chips[0]
+    plan32 = sas.Plan(v, wl.t_q16, wl.binw_q8, wl.n_min, wl.extent_q8,
+                      tuning=dict(n_det_hint=wl.n, half_counts=-1))
+    plans = [plan32] + [c[2] for c in chips]
+    infos = [p.info() for p in plans]
+    assert {i["half_counts"] for i in infos} == {0, 2}
+    assert len({(i["groups"], i["packed"]) for i in infos}) == 1  # one kernel class
+    items = [(plan32, x, y, e)] + [(c[2], c[3], c[4], c[5]) for c in chips]
+    b = sas.Batch(items, cand_cap=1 << 20)
+    b.vote()
+    for k, (p, xk, yk, ek) in enumerate(items):
+        s = sas.Search(p, int(xk.numel()), cand_cap=1 << 20)
+        s.vote(xk, yk, ek)
+        _say(f"mixed batch chip {k}: half_counts {infos[k]['half_counts']}, {len(s.peaks())} records")
+        assert_same(b.peaks(k), s.peaks())
+    b.close()
+    plan32.close()
+    for c in every:
         c[2].close()
 
 
