@@ -402,8 +402,9 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         fpass = pass;
         row_bytes = (uint32_t)(a.hx * nc * 4);
         const bool hi = j >= NV / 2;
-        cval = f == kFormHalves ? (hi ? 65536u : 1u) : f == kFormHalfLanes ? (hi == (pass != 0) ? 1u : 0u)
-                                                                          : 1u;
+        cval = f == kFormHalves      ? (hi ? 65536u : 1u)
+               : f == kFormHalfLanes ? (hi == (pass != 0) ? 1u : 0u)
+                                     : 1u;
         lbt = f == kForm32 ? LNV + 2 : LNV + 1;
         wts = us2{(unsigned short)(nc * 4), (unsigned short)row_bytes};
         lane_addr = hist_base + (uint32_t)((f == kForm32 ? j : (j & (NV / 2 - 1))) * 4) +
@@ -624,141 +625,143 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         const bool any = staged != 0;
         if (Mw > wcap && lane == 0) sh.spill[tseq & 1] = 1;
         for (int pass = 0; pass < npass; ++pass) {
-        if (hs) set_form(npass == 2 ? kFormHalfLanes : kFormHalves, tseq, pass);
+            if (hs) set_form(npass == 2 ? kFormHalfLanes : kFormHalves, tseq, pass);
 
-        // 2. vote this wave's entries, chunk by chunk (the first is staged;
-        // a second pass stages it again when later chunks replaced it)
-        for (int32_t c0 = 0; c0 < Mw; c0 += wcap) {
-            if (c0 > 0 || (pass > 0 && Mw > wcap)) stage_chunk(ox, c0);
+            // 2. vote this wave's entries, chunk by chunk (the first is staged;
+            // a second pass stages it again when later chunks replaced it)
+            for (int32_t c0 = 0; c0 < Mw; c0 += wcap) {
+                if (c0 > 0 || (pass > 0 && Mw > wcap)) stage_chunk(ox, c0);
 #pragma unroll
-            for (int k = 0; k < ER; ++k) {
-                const int e = wave + k * NW;
-                if (e >= E) break;
-                const int32_t n = __builtin_amdgcn_readlane(my_n, k);
-                if (n == 0) continue;
-                const int32_t b = __builtin_amdgcn_readlane(my_b, k);
-                vote_run<MODE, G>(wst + b, n, vote_addr(Sx[k], Sy[PK ? 0 : k]),
-                                  MODE == kMask32 ? (1u << e) : cval, g);
+                for (int k = 0; k < ER; ++k) {
+                    const int e = wave + k * NW;
+                    if (e >= E) break;
+                    const int32_t n = __builtin_amdgcn_readlane(my_n, k);
+                    if (n == 0) continue;
+                    const int32_t b = __builtin_amdgcn_readlane(my_b, k);
+                    vote_run<MODE, G>(wst + b, n, vote_addr(Sx[k], Sy[PK ? 0 : k]),
+                                      MODE == kMask32 ? (1u << e) : cval, g);
+                }
+                for (int k = ER; wave + k * NW < E; ++k) {
+                    const int e = wave + k * NW;
+                    const int32_t n = __builtin_amdgcn_readlane(my_n, k);
+                    if (n == 0) continue;
+                    const int32_t b = __builtin_amdgcn_readlane(my_b, k);
+                    const int32_t d = sh.dt[e];
+                    const int32_t sx = shift_q8(my_vx, d) + (int32_t)ox_lane;
+                    const int32_t sy = shift_q8(my_vy, d) + (int32_t)oy_lane;
+                    const int32_t sxv = PK   ? (int32_t)pack16(sx, sy)
+                                        : WT ? (int32_t)((uint32_t)sx << 8)
+                                             : sx;
+                    vote_run<MODE, G>(wst + b, n, vote_addr(sxv, sy),
+                                      MODE == kMask32 ? (1u << e) : cval, g);
+                }
+                __builtin_amdgcn_wave_barrier();  // the stage is read before it is refilled
             }
-            for (int k = ER; wave + k * NW < E; ++k) {
-                const int e = wave + k * NW;
-                const int32_t n = __builtin_amdgcn_readlane(my_n, k);
-                if (n == 0) continue;
-                const int32_t b = __builtin_amdgcn_readlane(my_b, k);
-                const int32_t d = sh.dt[e];
-                const int32_t sx = shift_q8(my_vx, d) + (int32_t)ox_lane;
-                const int32_t sy = shift_q8(my_vy, d) + (int32_t)oy_lane;
-                const int32_t sxv = PK   ? (int32_t)pack16(sx, sy)
-                                    : WT ? (int32_t)((uint32_t)sx << 8)
-                                         : sx;
-                vote_run<MODE, G>(wst + b, n, vote_addr(sxv, sy),
-                                  MODE == kMask32 ? (1u << e) : cval, g);
-            }
-            __builtin_amdgcn_wave_barrier();  // the stage is read before it is refilled
-        }
-        const bool last = pass == npass - 1;
-        // the next tile's runs and first chunk, while other waves still vote
-        if (last && next) {
-            runs(oxn);
-            if (Mw > 0) {
-                stage_chunk(oxn, 0);
-                if (lane == 0) atomicAdd(&sh.voted[(tseq + 1) & 3], Mw);
-            }
-        }
-        __syncthreads();  // every vote of this tile (pass) is in the histogram
-        // The total of tile t is summed before the barrier that ends tile t - 1
-        // (the first tile of an item: after the item's setup barriers) and read
-        // after the one that ends tile t; slot t + 3 (last read after the
-        // barrier ending tile t - 1, next summed after the one ending tile
-        // t + 1) is cleared here.  With one barrier per tile (16-bit counts in
-        // two histograms) this tile's read-out overlaps other waves' votes of
-        // tile t + 1 and the summing of tile t + 2, which use the other slots.
-        if (last) {
-            staged = sh.voted[(tseq + 1) & 3];  // the next tile's, complete at this barrier
-            if (tid == 0) {
-                sh.voted[(tseq + 3) & 3] = 0;
-                // a spill flag is set before the barrier ending its tile and
-                // cleared here, before the barrier ending the next one (after
-                // which the flag's next tile sets it)
-                if (sh.spill[tseq & 1]) {
-                    ++sh.n_spill;
-                    sh.spill[tseq & 1] = 0;
+            const bool last = pass == npass - 1;
+            // the next tile's runs and first chunk, while other waves still vote
+            if (last && next) {
+                runs(oxn);
+                if (Mw > 0) {
+                    stage_chunk(oxn, 0);
+                    if (lane == 0) atomicAdd(&sh.voted[(tseq + 1) & 3], Mw);
                 }
             }
-        }
+            __syncthreads();  // every vote of this tile (pass) is in the histogram
+            // The total of tile t is summed before the barrier that ends tile t - 1
+            // (the first tile of an item: after the item's setup barriers) and read
+            // after the one that ends tile t; slot t + 3 (last read after the
+            // barrier ending tile t - 1, next summed after the one ending tile
+            // t + 1) is cleared here.  With one barrier per tile (16-bit counts in
+            // two histograms) this tile's read-out overlaps other waves' votes of
+            // tile t + 1 and the summing of tile t + 2, which use the other slots.
+            if (last) {
+                staged = sh.voted[(tseq + 1) & 3];  // the next tile's, complete at this barrier
+                if (tid == 0) {
+                    sh.voted[(tseq + 3) & 3] = 0;
+                    // a spill flag is set before the barrier ending its tile and
+                    // cleared here, before the barrier ending the next one (after
+                    // which the flag's next tile sets it)
+                    if (sh.spill[tseq & 1]) {
+                        ++sh.n_spill;
+                        sh.spill[tseq & 1] = 0;
+                    }
+                }
+            }
 
-        // 3. read and clear the histogram; emit or queue interior cells
-        if (any) {
-            // words of this tile's histogram, and its first word
-            const int rw = form == kForm32 ? hist_words : hist_words / 2;
-            uint4 *hb = smem4 + (form == kFormHalves && hv ? (tseq & 1) * (hist_words / 8) : 0);
-            // count cnt of lane jj's velocity in bin `bin` (all lanes call)
-            const auto emit = [&](uint32_t cnt, int jj, int bin) __attribute__((always_inline)) {
-                bool ok = false;
-                uint32_t v = 0;
-                int32_t bx = 0, by = 0;
-                if (cnt >= nmin) {
-                    const int iy = bin / a.hx, ix = bin - iy * a.hx;
-                    const int cx = ix - (sh.sg[jj] & 0xffff), cy = iy - (sh.sg[jj] >> 16);
-                    ok = sh.sv[jj] >= 0 && cx >= 0 && cx < a.tile_x && cy >= 0 && cy < a.tile_y;
-                    v = (uint32_t)sh.sv[jj];
-                    bx = tx0 + cx;
-                    by = ty0 + cy;
-                }
-                if (refined_mode<MODE>()) {
-                    const int64_t idx = wave_append(ok, a.refine_count);
-                    if (ok && idx < a.refine_cap) a.refine[idx] = make_int4((int32_t)v, bx, by, 0);
-                } else {
-                    const int64_t idx = wave_append(ok, (unsigned long long *)&a.res->n_cand);
-                    if (ok && idx < a.cand_cap)
-                        write_cand(a.cand, idx, v, bx, by, cnt, (uint32_t)a.count_sat);
-                }
-            };
-            for (int w0 = 0; w0 < rw / 4; w0 += T) {
-                const int w4 = w0 + tid;
-                uint4 h = make_uint4(0, 0, 0, 0);
-                if (w4 < rw / 4) {
-                    h = hb[w4];
-                    hb[w4] = make_uint4(0, 0, 0, 0);
-                }
-                const uint32_t hw[4] = {h.x, h.y, h.z, h.w};
-                if (form == kFormHalves) {  // word wi: bin wi / (NV / 2), velocity lanes
-                                            // wi % (NV / 2) (low half) and that + NV / 2
-                    uint32_t m = 0;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) m = max(m, max(hw[k] & 0xffffu, hw[k] >> 16));
-                    if (!__any(m >= nmin)) continue;  // wave uniform
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const int wi = 4 * w4 + k;
-                        emit(hw[k] & 0xffffu, wi & (NV / 2 - 1), wi >> (LNV - 1));
-                        emit(hw[k] >> 16, (wi & (NV / 2 - 1)) + NV / 2, wi >> (LNV - 1));
+            // 3. read and clear the histogram; emit or queue interior cells
+            if (any) {
+                // words of this tile's histogram, and its first word
+                const int rw = form == kForm32 ? hist_words : hist_words / 2;
+                uint4 *hb = smem4 + (form == kFormHalves && hv ? (tseq & 1) * (hist_words / 8) : 0);
+                // count cnt of lane jj's velocity in bin `bin` (all lanes call)
+                const auto emit = [&](uint32_t cnt, int jj,
+                                      int bin) __attribute__((always_inline)) {
+                    bool ok = false;
+                    uint32_t v = 0;
+                    int32_t bx = 0, by = 0;
+                    if (cnt >= nmin) {
+                        const int iy = bin / a.hx, ix = bin - iy * a.hx;
+                        const int cx = ix - (sh.sg[jj] & 0xffff), cy = iy - (sh.sg[jj] >> 16);
+                        ok = sh.sv[jj] >= 0 && cx >= 0 && cx < a.tile_x && cy >= 0 && cy < a.tile_y;
+                        v = (uint32_t)sh.sv[jj];
+                        bx = tx0 + cx;
+                        by = ty0 + cy;
                     }
-                } else if (form == kFormHalfLanes) {  // word wi: bin wi / (NV / 2), velocity
-                                                      // lane wi % (NV / 2) + the pass's half
-                    const uint32_t m = max(max(h.x, h.y), max(h.z, h.w));
-                    if (!__any(m >= nmin)) continue;  // wave uniform
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const int wi = 4 * w4 + k;
-                        emit(hw[k], (wi & (NV / 2 - 1)) + fpass * (NV / 2), wi >> (LNV - 1));
+                    if (refined_mode<MODE>()) {
+                        const int64_t idx = wave_append(ok, a.refine_count);
+                        if (ok && idx < a.refine_cap)
+                            a.refine[idx] = make_int4((int32_t)v, bx, by, 0);
+                    } else {
+                        const int64_t idx = wave_append(ok, (unsigned long long *)&a.res->n_cand);
+                        if (ok && idx < a.cand_cap)
+                            write_cand(a.cand, idx, v, bx, by, cnt, (uint32_t)a.count_sat);
                     }
-                } else {
-                    const uint32_t m = max(max(cell_count<MODE>(h.x), cell_count<MODE>(h.y)),
-                                           max(cell_count<MODE>(h.z), cell_count<MODE>(h.w)));
-                    if (!__any(m >= nmin)) continue;  // wave uniform
+                };
+                for (int w0 = 0; w0 < rw / 4; w0 += T) {
+                    const int w4 = w0 + tid;
+                    uint4 h = make_uint4(0, 0, 0, 0);
+                    if (w4 < rw / 4) {
+                        h = hb[w4];
+                        hb[w4] = make_uint4(0, 0, 0, 0);
+                    }
+                    const uint32_t hw[4] = {h.x, h.y, h.z, h.w};
+                    if (form == kFormHalves) {  // word wi: bin wi / (NV / 2), velocity lanes
+                                                // wi % (NV / 2) (low half) and that + NV / 2
+                        uint32_t m = 0;
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const int wi = 4 * w4 + k;
-                        emit(cell_count<MODE>(hw[k]), wi & (NV - 1), wi >> LNV);
+                        for (int k = 0; k < 4; ++k) m = max(m, max(hw[k] & 0xffffu, hw[k] >> 16));
+                        if (!__any(m >= nmin)) continue;  // wave uniform
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const int wi = 4 * w4 + k;
+                            emit(hw[k] & 0xffffu, wi & (NV / 2 - 1), wi >> (LNV - 1));
+                            emit(hw[k] >> 16, (wi & (NV / 2 - 1)) + NV / 2, wi >> (LNV - 1));
+                        }
+                    } else if (form == kFormHalfLanes) {  // word wi: bin wi / (NV / 2), velocity
+                                                          // lane wi % (NV / 2) + the pass's half
+                        const uint32_t m = max(max(h.x, h.y), max(h.z, h.w));
+                        if (!__any(m >= nmin)) continue;  // wave uniform
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const int wi = 4 * w4 + k;
+                            emit(hw[k], (wi & (NV / 2 - 1)) + fpass * (NV / 2), wi >> (LNV - 1));
+                        }
+                    } else {
+                        const uint32_t m = max(max(cell_count<MODE>(h.x), cell_count<MODE>(h.y)),
+                                               max(cell_count<MODE>(h.z), cell_count<MODE>(h.w)));
+                        if (!__any(m >= nmin)) continue;  // wave uniform
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const int wi = 4 * w4 + k;
+                            emit(cell_count<MODE>(hw[k]), wi & (NV - 1), wi >> LNV);
+                        }
                     }
                 }
             }
-        }
-        // the histogram is clear before the next tile's (pass's) votes; after
-        // a 16-bit tile of two histograms the next one votes into the other
-        // histogram, cleared before this tile's barrier
-        if (!(hv && form == kFormHalves)) __syncthreads();
+            // the histogram is clear before the next tile's (pass's) votes; after
+            // a 16-bit tile of two histograms the next one votes into the other
+            // histogram, cleared before this tile's barrier
+            if (!(hv && form == kFormHalves)) __syncthreads();
         }  // passes
 #pragma unroll
         for (int k = 0; k < ER; ++k) {
