@@ -179,11 +179,12 @@ typedef struct {
     int32_t half_counts;        /* 16-bit histogram counts (dense plans that count detections,
                                    more than 32 epochs, or coarse cells): velocity lanes j and
                                    j + NV / 2 of a block of NV = 64 / groups share a word.
-                                   groups = 1: two histograms alternate by tile, and a tile
-                                   whose window entries reach 2^16 is voted with 32-bit counts;
-                                   groups 2 and 4: one histogram in half the LDS (larger
-                                   tiles), and such a tile is voted in two passes of half the
-                                   lanes each with 32-bit counts.  0: on wherever the plan
+                                   One lane group with 32-bit votes: two histograms alternate
+                                   by tile, and a tile whose window entries reach 2^16 is voted
+                                   with 32-bit counts; otherwise one histogram in half the LDS
+                                   (larger tiles, or three workgroups per CU for one lane group
+                                   with packed votes), and such a tile is voted in two passes
+                                   of half the lanes each with 32-bit counts.  0: on wherever the plan
                                    allows it; 1: on, and an error (SAS_E_INVALID) where the plan
                                    does not; -1: off */
     int32_t prune;              /* SAS_MODE_EPOCHS plans: 0 skips the tiles of a velocity block
@@ -248,8 +249,8 @@ typedef struct {
     int32_t stage_cap;
     int32_t lds_bytes;     /* LDS per vote workgroup */
     int32_t packed;        /* 1: votes use packed 16-bit arithmetic */
-    int32_t half_counts;   /* 16-bit histogram counts: 1, two histograms by tile; 2, one
-                              histogram (groups 2 and 4); 0, 32-bit counts */
+    int32_t half_counts;   /* 16-bit histogram counts: 1, two histograms by tile (one lane
+                              group, 32-bit votes); 2, one histogram; 0, 32-bit counts */
     int64_t n_tiles_kept;  /* tiles voted when the catalog's earliest epoch holds a detection
                               (the rest reach fewer than N_min epochs; tuning.prune) */
     int64_t n_items_kept;  /* their work items */

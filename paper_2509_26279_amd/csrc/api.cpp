@@ -492,11 +492,13 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     const double spread_x_avg = n_seg ? spread_x_sum / n_seg : 0.0;  // Q8, at the last epoch
     const double spread_y_avg = n_seg ? spread_y_sum / n_seg : 0.0;
 
-    // LDS budget of one workgroup: two workgroups per CU unless the tuning
-    // asks for more.
+    // LDS budget of one workgroup: two workgroups per CU, three for plans with
+    // one lane group and packed votes (their kernels keep 80 registers, so
+    // that six waves share a SIMD).
     const size_t lds_static = dense_static_lds_bytes();
     const size_t lds_cap = (size_t)kLdsPerCU - lds_static;
-    const size_t lds_target = (size_t)kLdsPerCU / 2 - 2048 - lds_static;  // 2 per CU, with slack
+    const size_t lds_target2 = (size_t)kLdsPerCU / 2 - 2048 - lds_static;
+    const size_t lds_target3 = (size_t)kLdsPerCU / 3 - 2048 - lds_static;
     int cl = tu.cell_log2;
     if (cl < 0 || cl > 30) return fail(SAS_E_INVALID, "sas_plan_create: cell_log2 out of range");
     auto ncells_of = [&](int c, int64_t lo, int64_t hi) { return ((hi - lo) + (1LL << c) - 1) >> c; };
@@ -510,10 +512,11 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
     };
     // 16-bit histogram counts for the counting cell variants on the dense
     // path (a count never exceeds the window entries of its tile, and the
-    // kernel votes a tile that reaches 2^16 with 32-bit counts): with one
-    // lane group, two histograms alternating by tile in the LDS of one 32-bit
-    // histogram (halves = 1); with more, one histogram in half the LDS
-    // (halves = 2), so that tiles get larger.
+    // kernel votes a tile that reaches 2^16 with 32-bit counts): one
+    // histogram in half the LDS of a 32-bit one (halves = 2), so that tiles
+    // get larger or more workgroups fit; one lane group with 32-bit votes
+    // instead keeps two histograms alternating by tile in that LDS
+    // (halves = 1).
     const bool counts_mode =
         !weighted && (m > 0 || d->mode == SAS_MODE_DETECTIONS ||
                       (d->mode == SAS_MODE_EPOCHS && d->n_epochs > 32));
@@ -522,27 +525,33 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
         return fail(SAS_E_INVALID, "sas_plan_create: half_counts = 1 needs the dense path and a "
                                    "counting cell variant (detections, more than 32 epochs, or "
                                    "coarse cells)");
-    const int halves = tu.half_counts >= 0 && counts_mode && dense_path ? (G == 1 ? 1 : 2) : 0;
-    const int64_t bin_words = halves == 2 ? NV / 2 : NV;  // LDS words of a histogram bin
-    // tile shape: the largest interior under the histogram budget with the
-    // best ratio of interior to window area (exact windows: the window adds
-    // the average spread of a block to each side length)
+    const bool half_ok = tu.half_counts >= 0 && counts_mode && dense_path;
+    auto halves_of = [&](bool pk) { return half_ok ? (G == 1 && !pk ? 1 : 2) : 0; };
+    // LDS words of a histogram bin
+    auto bin_words_of = [&](bool pk) -> int64_t { return halves_of(pk) == 2 ? NV / 2 : NV; };
     // packed 16-bit votes: a histogram row and column span at most 2^16 Q8 px
     // and a row's words fit a 16-bit weight
     auto packs = [&](int64_t tx, int64_t ty) {
         return !weighted && tu.packed >= 0 && ((tx + guard_x) << kc) <= 65536 &&
-               ((ty + guard_y) << kc) <= 65536 && (tx + guard_x) * bin_words * 4 <= 65535;
+               ((ty + guard_y) << kc) <= 65536 && (tx + guard_x) * bin_words_of(true) * 4 <= 65535;
     };
+    // tile shape: the largest interior under the histogram budget with the
+    // best ratio of interior to window area (exact windows: the window adds
+    // the average spread of a block to each side length); one lane group
+    // looks at packed tiles at three workgroups per CU first
+    const bool three_ok = G == 1 && !weighted && tu.packed >= 0;
     int32_t TX = tu.tile_x, TY = tu.tile_y;
-    if (!TX || !TY) {
+    auto search = [&](size_t target, bool packed_only) {
         double best = -1.0;
         for (int ty = 1; ty <= 128; ++ty)
             for (int tx = 1; tx <= 128; ++tx) {
                 if (tu.tile_x && tx != tu.tile_x) continue;
                 if (tu.tile_y && ty != tu.tile_y) continue;
+                const bool pk = packs(tx, ty);
+                if (packed_only && !pk) continue;
                 // the stage of a packed tile takes half the bytes
-                const size_t hist_budget = lds_target * (packs(tx, ty) ? 17 : 15) / 20;
-                const size_t hb = (size_t)(tx + guard_x) * (ty + guard_y) * bin_words * 4;
+                const size_t hist_budget = target * (pk ? 17 : 15) / 20;
+                const size_t hb = (size_t)(tx + guard_x) * (ty + guard_y) * bin_words_of(pk) * 4;
                 if (hb > hist_budget) continue;
                 const double wx = tx + 0.5 * spread_x_avg / cellw + 0.5;
                 const double wy = ty + 0.5 * spread_y_avg / cellw + 0.5;
@@ -553,15 +562,25 @@ sas_status sas_plan_create(const sas_plan_desc *d, sas_plan **plan_out) {
                     TY = ty;
                 }
             }
-        if (best < 0) {
+        return best >= 0;
+    };
+    bool three = false;  // three workgroups per CU
+    if (!TX || !TY) {
+        three = three_ok && search(lds_target3, true);
+        if (!three && !search(lds_target2, false)) {
             TX = tu.tile_x ? tu.tile_x : 1;
             TY = tu.tile_y ? tu.tile_y : 1;
         }
+    } else {
+        three = three_ok && packs(TX, TY);
     }
+    const size_t lds_target = three ? lds_target3 : lds_target2;
     if (TX < 1 || TY < 1 || TX > 4096 || TY > 4096)
         return fail(SAS_E_INVALID, "sas_plan_create: tile_x and tile_y must be in [1, 4096]");
     const int64_t HX = TX + guard_x, HY = TY + guard_y;
     const int packed = packs(TX, TY) ? 1 : 0;
+    const int halves = halves_of(packed != 0);
+    const int64_t bin_words = bin_words_of(packed != 0);
     const size_t entry_bytes = packed ? sizeof(uint32_t) : sizeof(int2);
     if (!cl) cl = kc + 1;  // window-index cells of 2 x 2 histogram cells
     while (ncells_of(cl, ex[0], ex[1]) > 32767 || ncells_of(cl, ex[2], ex[3]) > 32767 ||

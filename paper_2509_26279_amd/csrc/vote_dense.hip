@@ -77,6 +77,14 @@ struct Shared {
 constexpr int kEpochRegs = 8;
 constexpr int kEpochRegsPacked = 8;  // packed: one register per epoch
 
+// Waves per SIMD the vote kernels are compiled for: 4 (128 registers, two
+// workgroups of 8 waves per CU); 6 (80 registers, three workgroups) for one
+// lane group with packed votes, whose LDS the planner sizes for three.
+template <int G, bool PK>
+constexpr int kWavesPerSimd = G == 1 && PK ? 6 : 4;
+// Epoch shifts kept in registers by those kernels.
+constexpr int kEpochRegsPacked6 = 4;
+
 // ceil(v * d / 65536) for d >= 0: the shift v (t_e - t0) in Q8 pixels,
 // rounded so that the floor of the shifted position is exact.
 __device__ inline int32_t shift_q8(int32_t v, int32_t d) {
@@ -330,7 +338,8 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
     typedef typename std::conditional<
         PK, VoteAddr16, typename std::conditional<WT, VoteAddr32W, VoteAddr32>::type>::type VA;
     typedef typename VA::Entry Entry;
-    constexpr int ER = PK ? kEpochRegsPacked : kEpochRegs;
+    constexpr int ER = !PK ? kEpochRegs : kWavesPerSimd<G, PK> == 6 ? kEpochRegsPacked6
+                                                                    : kEpochRegsPacked;
     uint32_t *hist = (uint32_t *)smem4;
     const int hist_words = a.hx * a.hy * NV;  // words of a 32-bit histogram
     // halves = 2 plans hold half of that
@@ -348,16 +357,19 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
     const int32_t W = a.tile_x << kc, H = a.tile_y << kc;  // tile size, Q8
     const uint32_t nmin = (uint32_t)a.n_min;
     // 16-bit counts (counting modes): velocity lanes j and j + NV / 2 add 1
-    // and 2^16 to one word of a bin's NV / 2.  halves = 1 (G = 1): tiles
-    // alternate between two such histograms in the LDS of one 32-bit
-    // histogram, and a tile whose window entries could reach 2^16 is voted in
-    // the 32-bit form over both.  halves = 2: one such histogram in half the
-    // LDS (so the planner's tiles are larger), and a tile whose entries could
-    // reach 2^16 is voted twice with 32-bit counts, by the lanes j < NV / 2
-    // and then by the others, each pass read out on its own (block uniform).
+    // and 2^16 to one word of a bin's NV / 2.  halves = 1 (G = 1, 32-bit
+    // votes): tiles alternate between two such histograms in the LDS of one
+    // 32-bit histogram, and a tile whose window entries could reach 2^16 is
+    // voted in the 32-bit form over both.  halves = 2: one such histogram in
+    // half the LDS (larger tiles, or three workgroups per CU), and a tile
+    // whose entries could reach 2^16 is voted twice with 32-bit counts, by the
+    // lanes j < NV / 2 and then by the others, each pass read out on its own
+    // (block uniform).
     constexpr bool kHalvesOk = MODE == kCountDet || MODE == kCountRef;
-    const bool hv = G == 1 && kHalvesOk && a.halves == 1;  // the planner's forms by lane groups
-    const bool hs = G > 1 && kHalvesOk && a.halves == 2;
+    // the planner's forms: two histograms only for one lane group with
+    // 32-bit votes, one histogram for the rest
+    const bool hv = G == 1 && !PK && kHalvesOk && a.halves == 1;
+    const bool hs = (G > 1 || PK) && kHalvesOk && a.halves == 2;
     const int LR = a.rows_log2;  // run rows per epoch: 2^LR
     const int32_t vx_lo = a.seg[4 * sg], vx_hi = a.seg[4 * sg + 1];
     const int32_t vy_lo = a.seg[4 * sg + 2], vy_hi = a.seg[4 * sg + 3];
@@ -778,7 +790,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
 // Dynamic LDS: histogram [HY][HX][NV] words, then the stage (int2, or one
 // packed word per detection), one part of stage_cap / NW detections per wave.
 template <int MODE, int G, bool PK>
-__global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_vote_dense(DenseArgs a) {
+__global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(kWavesPerSimd<G, PK>))) k_vote_dense(DenseArgs a) {
     extern __shared__ uint4 smem4[];
     __shared__ Shared sh;
     const int tid = threadIdx.x;
@@ -827,7 +839,7 @@ constexpr int64_t kBatchRun = 64;  // rounds of an XCD's block of items in the b
 // as ~chip, voted only for the chips whose earliest scheduled epoch holds no
 // detection.
 template <int MODE, int G, bool PK>
-__global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) k_vote_dense_batch(const DenseArgs *__restrict__ chips,
+__global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(kWavesPerSimd<G, PK>))) k_vote_dense_batch(const DenseArgs *__restrict__ chips,
                                                          int32_t n_chips,
                                                          const int32_t *__restrict__ items5,
                                                          int64_t n_items, int64_t n_kept,

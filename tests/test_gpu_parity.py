@@ -110,10 +110,10 @@ def _half_count_tunings(mode):
     return out
 
 
-def _expected_halves(info, counting):
+def _expected_halves(info, counting=True):
     """The planner's 16-bit count form for a counting plan: two histograms
-    with one lane group, one histogram with more."""
-    return 0 if not counting else (1 if info["groups"] == 1 else 2)
+    for one lane group with 32-bit votes, one histogram otherwise."""
+    return 0 if not counting else (1 if info["groups"] == 1 and not info["packed"] else 2)
 
 
 @pytest.mark.parametrize("n_epochs,mode", [(20, "epochs"), (100, "epochs"), (100, "detections")])
@@ -170,8 +170,11 @@ def test_half_counts_choice_and_errors(gpu):
             p.close()
 
     i = info_of(dict(n_det_hint=wl.n))
-    assert i["groups"] == 1 and i["half_counts"] == 1
-    assert info_of(dict(coarse_log2=2))["half_counts"] == 1
+    assert i["groups"] == 1 and i["half_counts"] == _expected_halves(i) == 2  # packed
+    i = info_of(dict(coarse_log2=2))
+    assert i["half_counts"] == _expected_halves(i)
+    i = info_of(dict(coarse_log2=2, groups=1, packed=-1))
+    assert i["half_counts"] == 1 and not i["packed"]
     assert info_of(dict(n_det_hint=wl.n, half_counts=-1))["half_counts"] == 0
     assert info_of(dict(groups=4, coarse_log2=2))["half_counts"] == 2
     assert info_of(dict(groups=2, coarse_log2=2, half_counts=1))["half_counts"] == 2
@@ -179,7 +182,8 @@ def test_half_counts_choice_and_errors(gpu):
     # 20 epochs in single bins: epoch masks, which have no 16-bit form
     assert info_of(dict(groups=1, coarse_log2=-1), wl.t_q16[:20])["half_counts"] == 0
     # 100 epochs without coarse cells: counts refined into exact bins
-    assert info_of(dict(groups=1, coarse_log2=-1, half_counts=1))["half_counts"] == 1
+    i = info_of(dict(groups=1, coarse_log2=-1, half_counts=1))
+    assert i["half_counts"] == _expected_halves(i)
     for tun, t, path in ((dict(groups=1, coarse_log2=-1, half_counts=1), wl.t_q16[:20], "auto"),
                          (dict(groups=4, coarse_log2=-1, half_counts=1), wl.t_q16[:20], "auto"),
                          (dict(groups=1, coarse_log2=2, half_counts=1), wl.t_q16, "sort"),
@@ -209,11 +213,12 @@ def test_half_counts_dense_tile_takes_32_bit_form(gpu):
     # default tiles put the square in the first tile of its row; 4 x 4-bin
     # tiles put it in the second, between 16-bit tiles on both sides
     for hc, gr, tiles in ((1, 1, {}), (1, 1, dict(tile_x=4, tile_y=4)), (-1, 1, {}),
+                          (1, 1, dict(packed=-1)), (1, 1, dict(packed=-1, tile_x=4, tile_y=4)),
                           (1, 2, {}), (1, 4, dict(tile_x=4, tile_y=4)), (1, 4, {})):
         _say(f"dense tile half_counts={hc} groups={gr} {tiles}")
         plan = sas.Plan(v, t, 1024, n_min, ext, mode="detections",
                         tuning=dict(groups=gr, coarse_log2=-1, half_counts=hc, **tiles))
-        assert plan.info()["half_counts"] == (0 if hc != 1 else 1 if gr == 1 else 2)
+        assert plan.info()["half_counts"] == (0 if hc != 1 else _expected_halves(plan.info()))
         srch = sas.Search(plan, n, cand_cap=1 << 16)
         g = srch.run(x, y, e)
         assert srch.result()["status"] == 0
@@ -452,8 +457,9 @@ def test_batch_matches_single_chip_votes(gpu):
     chips = _night_chips(6, 0.1)
     styles = {wl.bin_px for wl, *_ in chips}
     assert len(styles) == 2  # both styles present
-    # the wide-style chips take two 16-bit histograms, the fast-style ones one
-    assert len({plan.info()["half_counts"] for _, _, plan, *_ in chips}) == 2
+    # two kernel classes: one lane group with packed votes (three workgroups
+    # per CU) for the wide-style chips, two lane groups for the fast-style ones
+    assert len({(plan.info()["groups"], plan.info()["packed"]) for _, _, plan, *_ in chips}) == 2
     b = sas.Batch([(plan, x, y, e) for _, _, plan, x, y, e in chips], cand_cap=1 << 20)
     b.vote()
     for k, (wl, v, plan, x, y, e) in enumerate(chips):
