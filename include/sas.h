@@ -184,9 +184,9 @@ typedef struct {
                                    with 32-bit counts; otherwise one histogram in half the LDS
                                    (larger tiles, or three workgroups per CU for one lane group
                                    with packed votes), and such a tile is voted in two passes
-                                   of half the lanes each with 32-bit counts.  0: on wherever the plan
-                                   allows it; 1: on, and an error (SAS_E_INVALID) where the plan
-                                   does not; -1: off */
+                                   of half the lanes each with 32-bit counts.  0: on wherever
+                                   the plan allows it; 1: on, and an error (SAS_E_INVALID) where
+                                   the plan does not; -1: off */
     int32_t prune;              /* SAS_MODE_EPOCHS plans: 0 skips the tiles of a velocity block
                                    where fewer than N_min epochs can reach any bin (the window
                                    of every other epoch misses the footprint), which cannot
