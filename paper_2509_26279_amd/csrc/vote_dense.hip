@@ -27,10 +27,12 @@
 //   3. after a barrier, one pass over the histogram reads and clears it;
 //      interior cells at or above N_min are emitted (wavefront ballot + one
 //      global atomic per wave) or queued for refinement, and a second
-//      barrier ends the tile.  With 16-bit counts (G = 1, counting variants)
-//      lanes j and j + 32 share a word and tiles alternate between two
-//      histograms, so the second barrier goes; a tile whose window entries
-//      could reach 2^16 uses the 32-bit form.
+//      barrier ends the tile.  With 16-bit counts (counting variants) lanes
+//      j and j + NV / 2 share a word: one lane group with 32-bit votes keeps
+//      two histograms that alternate by tile, so the second barrier goes;
+//      the other plans keep one histogram in half the LDS (larger tiles, or
+//      a third workgroup per CU for one lane group with packed votes).  A
+//      tile whose window entries could reach 2^16 takes 32-bit counts.
 // Cell variants:
 //   kMask32  - EPOCHS with E <= 32: epoch bitmask per cell;
 //   kCountDet - DETECTIONS: counter per cell;
