@@ -288,17 +288,21 @@ __device__ __attribute__((always_inline)) inline void window_run(
     end = c.offT[row + (cx1 + 1) * c.ncy];
 }
 
-// Exclusive scan over the 64 lanes of a wave; *total gets the sum.
+// Exclusive scan over the 64 lanes of a wave (all lanes active); *total gets
+// the sum.  Data-parallel primitive moves only, no LDS round trips: a
+// Hillis-Steele scan inside each row of 16 lanes (row shifts by 1, 2, 4, 8;
+// lanes shifted in from outside the row add 0), then lane 15 of rows 0 and 2
+// is broadcast into rows 1 and 3, and lane 31 into rows 2 and 3.
 __device__ __attribute__((always_inline)) inline int32_t wave_scan(int32_t v, int32_t *total) {
-    const int lane = __lane_id();
-    int32_t incl = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int32_t o = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += o;
-    }
-    *total = __shfl(incl, 63, 64);
-    return incl - v;
+    int32_t x = v;
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    *total = __builtin_amdgcn_readlane(x, 63);
+    return x - v;
 }
 
 // Exact window of epoch e for the tile whose Q8 origin is (oxw, oy).
@@ -536,11 +540,12 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         const int32_t pk0 = __shfl(rpre[0], qk & 63, 64), pk1 = __shfl(rpre[1], qk & 63, 64);
         const int32_t pk = min(max(lane < KW ? (qk < 64 ? pk0 : pk1) : Mw, c0), c1);
         int32_t mb = 0, kept = 0;
-        for (int32_t b0 = c0; b0 < c1; b0 += kStageBlocks * 64) {
-            int2 ent[kStageBlocks];
-            int32_t ek[kStageBlocks];
+        constexpr int SB = kWavesPerSimd<G, PK> == 6 ? 1 : kStageBlocks;
+        for (int32_t b0 = c0; b0 < c1; b0 += SB * 64) {
+            int2 ent[SB];
+            int32_t ek[SB];
 #pragma unroll
-            for (int u = 0; u < kStageBlocks; ++u) {
+            for (int u = 0; u < SB; ++u) {
                 const int32_t P0 = b0 + 64 * u, p = P0 + lane;
                 ent[u] = make_int2(0, 0);
                 ek[u] = 0;
@@ -568,7 +573,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                 }
             }
 #pragma unroll
-            for (int u = 0; u < kStageBlocks; ++u) {
+            for (int u = 0; u < SB; ++u) {
                 const int32_t P0 = b0 + 64 * u;
                 if (P0 >= c1) break;  // wave uniform
                 Window w = window_of(sh, wave + NW * ek[u], oxw, oy, W, H);
