@@ -305,6 +305,19 @@ __device__ __attribute__((always_inline)) inline int32_t wave_scan(int32_t v, in
     return x - v;
 }
 
+// Inclusive maximum scan of non-negative values over the 64 lanes of a wave
+// (all lanes active), by the same moves as wave_scan.
+__device__ __attribute__((always_inline)) inline int32_t wave_max_scan(int32_t v) {
+    int32_t x = v;
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false));  // row_shr:1
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false));  // row_shr:2
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false));  // row_shr:4
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false));  // row_shr:8
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return x;
+}
+
 // Exact window of epoch e for the tile whose Q8 origin is (oxw, oy).
 struct Window {
     int32_t x0, x1, y0, y1;
@@ -558,9 +571,9 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 const int32_t h = hd[lane];
                 hd[lane] = 0;
-                const uint64_t marks = __ballot(h != 0) & ((2ull << lane) - 1);
-                const int32_t hq = __shfl(h, marks ? 63 - __builtin_clzll(marks) : 0, 64) - 1;
-                const int32_t q = marks ? hq : own;
+                // marks grow with the position: the scan's maximum is the last one
+                const int32_t hm = wave_max_scan(h);
+                const int32_t q = hm ? hm - 1 : own;
                 own = __builtin_amdgcn_readlane(q, 63);
                 int32_t sb = __shfl(rsb[0], q & 63, 64);
                 if (two) {
