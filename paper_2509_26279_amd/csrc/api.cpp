@@ -163,7 +163,8 @@ bool is_weighted(int32_t mode) {
 bool refines(int dense_mode) { return dense_mode == kCountRef || dense_mode == kWeightRef; }
 
 struct WsLayout {
-    size_t count, offT, blocksum, cellid, rank, sxy, sidx, present, dt, refine_count, refine;
+    size_t count, offT, blocksum, cellid, rank, sxy, sidx, present, dt, refine_count, item_queue,
+        refine;
     size_t keys, keys_alt, hist, hist_blocksum;  // sort path
     size_t total;
 };
@@ -184,6 +185,7 @@ WsLayout ws_layout(const sas_plan *p, int64_t n) {
     L.present = o; o = align_up(o + sizeof(int32_t) * kMaxEpochs);
     L.dt = o; o = align_up(o + sizeof(int32_t) * kMaxEpochs);
     L.refine_count = o; o = align_up(o + sizeof(unsigned long long));
+    L.item_queue = o; o = align_up(o + sizeof(unsigned long long) * kXcds);
     L.refine = o;
     o = align_up(o + sizeof(int4) * (p->path == SAS_PATH_DENSE && refines(p->dense_mode)
                                          ? p->refine_cap : 1));
@@ -210,6 +212,7 @@ PrepBuffers prep_buffers(const WsLayout &L, char *w) {
     pb.present = (int32_t *)(w + L.present);
     pb.dt = (int32_t *)(w + L.dt);
     pb.refine_count = (unsigned long long *)(w + L.refine_count);
+    pb.item_queue = (unsigned long long *)(w + L.item_queue);
     return pb;
 }
 
@@ -255,6 +258,7 @@ DenseArgs dense_args(const sas_plan *p, const WsLayout &L, char *w, const PrepBu
     a.e_first = p->e_first;
     a.refine = (int4 *)(w + L.refine);
     a.refine_count = pb.refine_count;
+    a.item_queue = pb.item_queue;
     a.refine_cap = refines(p->dense_mode) ? p->refine_cap : 0;
     a.cand = cand;
     a.cand_cap = cand_cap;

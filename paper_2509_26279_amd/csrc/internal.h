@@ -13,7 +13,6 @@ constexpr int kVoteThreads = 512;          // threads per vote workgroup
 constexpr int kVoteWaves = kVoteThreads / 64;
 constexpr int kMaxWavePairs = 128;         // (epoch, index row) pairs of one wave's windows
 constexpr int kSlotWords = kMaxEpochs / 32;
-constexpr int64_t kMaxVoteGrid = 1 << 16;  // workgroups of one vote launch (grid-stride)
 constexpr int kLdsPerCU = 160 * 1024;      // gfx950
 constexpr int kXcds = 8;                   // MI355X: accelerator dies, one L2 each
 
@@ -76,6 +75,8 @@ struct DenseArgs {
     int4 *refine;             // [refine_cap] queued (v_idx, cell x, cell y, 0)
     unsigned long long *refine_count;
     int64_t refine_cap;
+    unsigned long long *item_queue;  // [kXcds] items taken from each XCD's range (zeroed
+                                     // by the preparation)
     sas_candidate *cand;
     int64_t cand_cap;
     sas_vote_result *res;
@@ -94,6 +95,7 @@ struct PrepBuffers {
     int32_t *present;   // [E]
     int32_t *dt;        // [E]
     unsigned long long *refine_count;
+    unsigned long long *item_queue;  // [kXcds]
 };
 
 constexpr int kScanThreads = 1024;

@@ -52,7 +52,8 @@ __device__ int32_t block_exclusive_scan(int32_t v, int32_t *total) {
 }
 
 __global__ void k_prep_zero(int32_t *count, int64_t n_count, int32_t *present, int32_t n_epochs,
-                            sas_vote_result *res, unsigned long long *refine_count) {
+                            sas_vote_result *res, unsigned long long *refine_count,
+                            unsigned long long *item_queue) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_count; i += stride)
         count[i] = 0;
@@ -64,6 +65,7 @@ __global__ void k_prep_zero(int32_t *count, int64_t n_count, int32_t *present, i
             res->n_spilled = 0;
             *refine_count = 0;
         }
+        if (threadIdx.x < kXcds) item_queue[threadIdx.x] = 0;
     }
 }
 
@@ -205,7 +207,7 @@ hipError_t launch_prep(const int32_t *x, const int32_t *y, const uint8_t *epoch,
     unsigned zb = blocks_for(n_count, 256);
     if (zb > 4096) zb = 4096;
     hipLaunchKernelGGL(k_prep_zero, dim3(zb), dim3(256), 0, stream, pb.count, n_count,
-                       pb.present, n_epochs, res, pb.refine_count);
+                       pb.present, n_epochs, res, pb.refine_count, pb.item_queue);
     if (n > 0) {
         hipLaunchKernelGGL(k_prep_count, dim3(blocks_for(n, 256)), dim3(256), 0, stream, x, y,
                            epoch, n, n_epochs, ncx, ncy, cell_log2, ext[0], ext[1], ext[2],

@@ -48,6 +48,7 @@
 // the low byte), so the weight rides along with the position through the
 // staging unchanged: the window's x bounds are scaled by 256 too, and the
 // bin of (256 x + w) - 256 S shifted by log2(b) + 8 is the bin of x - S.
+#include <algorithm>
 #include <type_traits>
 
 #include "internal.h"
@@ -72,6 +73,7 @@ struct Shared {
     int32_t n_spill;            // tiles staged in chunks, not yet added to the result
     int32_t count_on;           // measurement: count the LDS atomic vote instructions
     unsigned long long n_instr; // their number in this workgroup
+    unsigned long long ticket;  // the item queue's answer to this workgroup
 };
 
 // Epochs per wave whose lane shifts stay in registers over a work item (two
@@ -826,18 +828,30 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(kWavesPe
         sh.spill[0] = sh.spill[1] = 0;
         sh.n_spill = 0;
     }
-    // Workgroups are dispatched round-robin over the XCDs (each with its own
-    // L2); give XCD x the logical indices [x G / 8, (x + 1) G / 8) so that the
-    // workgroups resident on one XCD take neighbouring items.
-    const int64_t grid = gridDim.x;  // a multiple of kXcds
-    const int64_t logical = (int64_t)(blockIdx.x % kXcds) * (grid / kXcds) + blockIdx.x / kXcds;
     // The items past n_items_kept hold tiles that fewer than N_min epochs
     // reach when the reference epoch is the earliest scheduled one; they are
     // voted only when that epoch holds no detection (then t0 is later).
     const int64_t n_walk = a.cat.dt[a.e_first] == 0 ? a.n_items_kept : a.n_items;
-    for (int64_t item = logical; item < n_walk; item += grid) {
-        const int32_t *it = a.items + 4 * item;
-        vote_item<MODE, G, PK>(a, sh, smem4, it[0], it[1], it[2], it[3], tseq);
+    // Persistent workgroups (as many as are resident) take items from queues:
+    // XCD x's range is [x n / 8, (x + 1) n / 8) of the L2-friendly item order
+    // and workgroups are dispatched round-robin over the XCDs (each with its
+    // own L2), so a workgroup first takes its own XCD's items, one atomic
+    // ticket each, then helps with the other ranges in turn.  Every ticket
+    // below a range's size is one item, taken once; every workgroup ends after
+    // one ticket past the end of each range.
+    const int x0 = blockIdx.x % kXcds;
+    for (int k = 0; k < kXcds; ++k) {
+        const int x = (x0 + k) % kXcds;
+        const int64_t lo = x * n_walk / kXcds, n_x = (x + 1) * n_walk / kXcds - lo;
+        for (;;) {
+            __syncthreads();  // every thread has read the previous ticket
+            if (tid == 0) sh.ticket = atomicAdd(&a.item_queue[x], 1ull);
+            __syncthreads();
+            const int64_t t = (int64_t)sh.ticket;  // block uniform
+            if (t >= n_x) break;
+            const int32_t *it = a.items + 4 * (lo + t);
+            vote_item<MODE, G, PK>(a, sh, smem4, it[0], it[1], it[2], it[3], tseq);
+        }
     }
     __syncthreads();
     if (tid == 0 && sh.count_on && sh.n_instr) atomicAdd(a.atomics, sh.n_instr);
@@ -1037,11 +1051,18 @@ hipError_t launch_mg(const DenseArgs &a, size_t lds, hipStream_t stream, hipEven
     static size_t lds_set = 0;  // dynamic LDS limit raised so far for this kernel
     hipError_t e = set_lds_limit((const void *)k_vote_dense<MODE, G, PK>, lds, &lds_set);
     if (e != hipSuccess) return e;
-    // sized by the kept items (those walked unless the reference epoch is a
-    // later one), so that the XCD-contiguous walk spreads them over all XCDs
+    // persistent: the workgroups resident at once (LDS and waves per SIMD),
+    // at most one per kept item (those walked unless the reference epoch is
+    // a later one); the item queues balance the work
+    int dev = 0, n_cu = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t per_cu = std::max<int64_t>(
+        1, std::min<int64_t>(kLdsPerCU / (int64_t)(lds + sizeof(Shared)),
+                             kWavesPerSimd<G, PK> * 4 / NW));
     const int64_t kept = a.n_items_kept > 0 ? a.n_items_kept : 1;
-    const int64_t want = kept < kMaxVoteGrid ? kept : kMaxVoteGrid;
-    const dim3 grid((unsigned)((want + kXcds - 1) / kXcds * kXcds)), block(T);
+    const int64_t want = std::min<int64_t>(kept, (int64_t)n_cu * per_cu);
+    const dim3 grid((unsigned)want), block(T);
     if (ev0 && (e = hipEventRecord(ev0, stream)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_vote_dense<MODE, G, PK>), grid, block, lds, stream, a);
     if (ev1 && (e = hipEventRecord(ev1, stream)) != hipSuccess) return e;
