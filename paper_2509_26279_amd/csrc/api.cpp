@@ -1146,6 +1146,7 @@ struct sas_batch {
     std::vector<void *> allocs;
     hipEvent_t probe[2] = {nullptr, nullptr};
     unsigned long long *counter = nullptr;
+    unsigned long long *queues = nullptr;  // [classes][kXcds] item queues
 };
 
 namespace {
@@ -1295,8 +1296,17 @@ sas_status sas_batch_create(const sas_batch_chip *chips, int32_t n_chips, void *
         cl.d_items5 = (int32_t *)d;
         bt->classes.push_back(cl);
     }
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, sizeof(unsigned long long) * kXcds *
+                                     std::max<size_t>(1, bt->classes.size()));
+    if (e != hipSuccess) {
+        for (void *a : bt->allocs) hipFree(a);
+        return fail(SAS_E_NOMEM, "sas_batch_create: item queues");
+    }
+    bt->allocs.push_back(q);
+    bt->queues = (unsigned long long *)q;
     void *d = nullptr;
-    hipError_t e = hipMalloc(&d, sizeof(DenseArgs) * n_chips);
+    e = hipMalloc(&d, sizeof(DenseArgs) * n_chips);
     if (e != hipSuccess) {
         for (void *a : bt->allocs) hipFree(a);
         return fail(SAS_E_NOMEM, "sas_batch_create: chip table");
@@ -1348,18 +1358,12 @@ sas_status sas_vote_batch(const sas_batch *b, void *stream) {
     }
     if (b->probe[0] && (e = hipEventRecord(b->probe[0], s)) != hipSuccess)
         return hip_fail(e, "sas_vote_batch: probe");
-    int dev = 0, n_cu = 256;
-    if (hipGetDevice(&dev) == hipSuccess)
-        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
     for (size_t k = 0; k < b->classes.size(); ++k) {
         const sas_batch::Class &cl = b->classes[k];
-        // persistent: as many workgroups as fit on the device at once
-        const int per_cu = std::max<int>(1, (int)(kLdsPerCU / (cl.lds + dense_static_lds_bytes())));
-        const int grid = (int)std::max<int64_t>(
-            1, std::min<int64_t>(cl.n_kept, (int64_t)n_cu * per_cu));
         e = launch_vote_dense_batch(cl.mode, cl.groups, cl.packed, b->d_args,
                                     (int32_t)b->chips.size(), cl.d_items5, cl.n_items, cl.n_kept,
-                                    cl.hist_words_max, cl.lds, grid, b->counter, s);
+                                    cl.hist_words_max, cl.lds, b->queues + kXcds * k,
+                                    b->counter, s);
         if (e != hipSuccess) return hip_fail(e, "sas_vote_batch: vote launch");
     }
     if (b->probe[1] && (e = hipEventRecord(b->probe[1], s)) != hipSuccess)

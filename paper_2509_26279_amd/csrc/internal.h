@@ -253,11 +253,13 @@ hipError_t launch_vote_dense(int mode, int groups, const DenseArgs &a, hipStream
                              hipEvent_t ev0, hipEvent_t ev1);
 // One persistent launch over the merged items (chip, segment, ty0, txf,
 // ntiles) of many chips of one kernel class: every chip's kept items first
-// (n_kept of them), then the tiles skipped by coverage.
+// (n_kept of them), then the tiles skipped by coverage.  queue: kXcds device
+// counters of this launch's own, zeroed on the stream before the vote kernel.
 hipError_t launch_vote_dense_batch(int mode, int groups, int packed, const DenseArgs *chips_dev,
                                    int32_t n_chips, const int32_t *items5_dev, int64_t n_items,
-                                   int64_t n_kept, int32_t hist_words_max, size_t lds, int grid,
-                                   unsigned long long *atomics, hipStream_t stream);
+                                   int64_t n_kept, int32_t hist_words_max, size_t lds,
+                                   unsigned long long *queue, unsigned long long *atomics,
+                                   hipStream_t stream);
 hipError_t launch_refine(const DenseArgs &a, hipStream_t stream);
 size_t dense_lds_bytes(int groups, int hx, int hy, int stage_cap, int packed, int halves);
 size_t dense_static_lds_bytes();

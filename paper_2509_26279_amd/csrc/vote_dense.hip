@@ -860,12 +860,11 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(kWavesPe
     if (tid == 0 && sh.n_spill) atomicAdd(&a.res->n_spilled, sh.n_spill);
 }
 
-constexpr int64_t kBatchRun = 64;  // rounds of an XCD's block of items in the batched walk
-
 // Many catalogs in one persistent launch (one workgroup per resident slot):
 // the merged items (items5: chip, segment, ty0, txf, ntiles; chip-major, each
-// chip in its own L2-friendly order) are walked like the single-catalog
-// kernel walks its items, and each item reads its chip's parameters from
+// chip in its own L2-friendly order) are taken from per-XCD queues like the
+// single-catalog kernel takes its items (so an XCD's range holds few chips),
+// and each item reads its chip's parameters from
 // chips[].  Every chip of the launch uses this kernel's cell variant and lane
 // groups (and vote form); hist_words_max covers the largest histogram among
 // them.  Items [0, n_kept) are every chip's kept items; the rest hold tiles
@@ -878,6 +877,7 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(kWavesPe
                                                          const int32_t *__restrict__ items5,
                                                          int64_t n_items, int64_t n_kept,
                                                          int32_t hist_words_max,
+                                                         unsigned long long *queue,
                                                          unsigned long long *atomics) {
     extern __shared__ uint4 smem4[];
     __shared__ Shared sh;
@@ -896,16 +896,17 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(kWavesPe
     for (int c = tid; c < n_chips; c += T) later_t0 |= chips[c].cat.dt[chips[c].e_first] != 0;
     later_t0 = __syncthreads_or(later_t0);
     const int64_t n_walk = later_t0 ? n_items : n_kept;
-    // Each XCD walks blocks of kBatchRun x (its resident workgroups)
-    // consecutive items, blocks interleaved over the XCDs: the workgroups of
-    // one XCD take neighbouring items, round after round, so the catalog
-    // regions of consecutive rounds overlap in that XCD's L2.
-    const int64_t per_xcd = gridDim.x / kXcds;  // gridDim.x is a multiple of kXcds
-    const int64_t xcd = blockIdx.x % kXcds, w = blockIdx.x / kXcds;
-    const int64_t run = per_xcd * kBatchRun;
-    for (int64_t b0 = xcd * run; b0 < n_walk; b0 += kXcds * run)
-    for (int64_t item = b0 + w, b1 = min(b0 + run, n_walk); item < b1; item += per_xcd) {
-        const int32_t *it = items5 + 5 * item;
+    const int x0 = blockIdx.x % kXcds;
+    for (int k = 0; k < kXcds; ++k) {
+      const int x = (x0 + k) % kXcds;
+      const int64_t lo = x * n_walk / kXcds, n_x = (x + 1) * n_walk / kXcds - lo;
+      for (;;) {
+        __syncthreads();  // every thread has read the previous ticket
+        if (tid == 0) sh.ticket = atomicAdd(&queue[x], 1ull);
+        __syncthreads();
+        const int64_t t = (int64_t)sh.ticket;  // block uniform
+        if (t >= n_x) break;
+        const int32_t *it = items5 + 5 * (lo + t);
         int chip = it[0];
         if (chip < 0) {  // skipped tiles of chip ~chip: block uniform
             chip = ~chip;
@@ -925,6 +926,7 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(kWavesPe
             chip_now = chip;
         }
         vote_item<MODE, G, PK>(a, sh, smem4, it[1], it[2], it[3], it[4], tseq);
+      }
     }
     __syncthreads();
     if (tid == 0 && sh.count_on && sh.n_instr) atomicAdd(atomics, sh.n_instr);
@@ -1045,24 +1047,27 @@ hipError_t set_lds_limit(const void *fn, size_t lds, size_t *lds_set) {
     return hipSuccess;
 }
 
-template <int MODE, int G, bool PK>
-hipError_t launch_mg(const DenseArgs &a, size_t lds, hipStream_t stream, hipEvent_t ev0,
-                     hipEvent_t ev1) {
-    static size_t lds_set = 0;  // dynamic LDS limit raised so far for this kernel
-    hipError_t e = set_lds_limit((const void *)k_vote_dense<MODE, G, PK>, lds, &lds_set);
-    if (e != hipSuccess) return e;
-    // persistent: the workgroups resident at once (LDS and waves per SIMD),
-    // at most one per kept item (those walked unless the reference epoch is
-    // a later one); the item queues balance the work
+// Persistent vote launches: the workgroups resident at once (LDS and waves
+// per SIMD), at most one per kept item (those walked unless the reference
+// epoch is a later one); the item queues balance the work.
+template <int G, bool PK>
+int64_t resident_grid(size_t lds, int64_t kept) {
     int dev = 0, n_cu = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
     const int64_t per_cu = std::max<int64_t>(
         1, std::min<int64_t>(kLdsPerCU / (int64_t)(lds + sizeof(Shared)),
                              kWavesPerSimd<G, PK> * 4 / NW));
-    const int64_t kept = a.n_items_kept > 0 ? a.n_items_kept : 1;
-    const int64_t want = std::min<int64_t>(kept, (int64_t)n_cu * per_cu);
-    const dim3 grid((unsigned)want), block(T);
+    return std::min<int64_t>(std::max<int64_t>(kept, 1), (int64_t)n_cu * per_cu);
+}
+
+template <int MODE, int G, bool PK>
+hipError_t launch_mg(const DenseArgs &a, size_t lds, hipStream_t stream, hipEvent_t ev0,
+                     hipEvent_t ev1) {
+    static size_t lds_set = 0;  // dynamic LDS limit raised so far for this kernel
+    hipError_t e = set_lds_limit((const void *)k_vote_dense<MODE, G, PK>, lds, &lds_set);
+    if (e != hipSuccess) return e;
+    const dim3 grid((unsigned)resident_grid<G, PK>(lds, a.n_items_kept)), block(T);
     if (ev0 && (e = hipEventRecord(ev0, stream)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_vote_dense<MODE, G, PK>), grid, block, lds, stream, a);
     if (ev1 && (e = hipEventRecord(ev1, stream)) != hipSuccess) return e;
@@ -1087,18 +1092,25 @@ struct BatchLaunch {
     int64_t n_items, n_kept;
     int32_t hist_words_max;
     size_t lds;
-    int grid;
+    unsigned long long *queue;
     unsigned long long *atomics;
 };
+
+__global__ void k_zero_queue(unsigned long long *queue) {
+    if (threadIdx.x < kXcds) queue[threadIdx.x] = 0;
+}
 
 template <int MODE, int G, bool PK>
 hipError_t launch_batch_mg(const BatchLaunch &b, hipStream_t stream) {
     static size_t lds_set = 0;
     hipError_t e = set_lds_limit((const void *)k_vote_dense_batch<MODE, G, PK>, b.lds, &lds_set);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_vote_dense_batch<MODE, G, PK>), dim3(b.grid), dim3(T), b.lds, stream,
-                       b.chips, b.n_chips, b.items5, b.n_items, b.n_kept, b.hist_words_max,
-                       b.atomics);
+    // a fill kernel, not a memset: the launch may be captured in a graph
+    hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(64), 0, stream, b.queue);
+    const int64_t grid = resident_grid<G, PK>(b.lds, b.n_kept);
+    hipLaunchKernelGGL((k_vote_dense_batch<MODE, G, PK>), dim3((unsigned)grid), dim3(T), b.lds,
+                       stream, b.chips, b.n_chips, b.items5, b.n_items, b.n_kept,
+                       b.hist_words_max, b.queue, b.atomics);
     return hipGetLastError();
 }
 
@@ -1150,11 +1162,12 @@ size_t dense_static_lds_bytes() { return sizeof(Shared); }
 
 hipError_t launch_vote_dense_batch(int mode, int groups, int packed, const DenseArgs *chips_dev,
                                    int32_t n_chips, const int32_t *items5_dev, int64_t n_items,
-                                   int64_t n_kept, int32_t hist_words_max, size_t lds, int grid,
-                                   unsigned long long *atomics, hipStream_t stream) {
+                                   int64_t n_kept, int32_t hist_words_max, size_t lds,
+                                   unsigned long long *queue, unsigned long long *atomics,
+                                   hipStream_t stream) {
     if (n_items <= 0) return hipSuccess;
     const BatchLaunch b{chips_dev, n_chips, items5_dev, n_items, n_kept, hist_words_max, lds,
-                        (grid + kXcds - 1) / kXcds * kXcds, atomics};
+                        queue, atomics};
     return packed ? launch_batch_p<true>(mode, groups, b, stream)
                   : launch_batch_p<false>(mode, groups, b, stream);
 }
