@@ -517,11 +517,17 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         rowb[s2] = q < nq ? window_row(a, sh, pair_epoch(s2), q & ((1 << LR) - 1), oy, H) : -1;
     }
 
-    const auto runs = [&](int32_t oxw) __attribute__((always_inline)) {
-        int32_t src[2], end[2];
+    // a tile's run bounds (window-index offsets), loaded ahead of the scans
+    int32_t src[2], end[2];
+    const auto run_bounds = [&](int32_t oxw) __attribute__((always_inline)) {
 #pragma unroll
         for (int s2 = 0; s2 < 2; ++s2)
             window_run(c, sh, pair_epoch(s2), rowb[s2], oxw, W, src[s2], end[s2]);
+    };
+    const auto runs = [&]() __attribute__((always_inline)) {
+        // the bounds are consumed here and no earlier: nothing that waits for
+        // their loads is moved above the votes they overlap
+        asm volatile("" : "+v"(src[0]), "+v"(end[0]), "+v"(src[1]), "+v"(end[1]));
         int32_t t0, t1;
         rlen[0] = end[0] - src[0];
         rlen[1] = end[1] - src[1];
@@ -623,7 +629,8 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     };
 
-    runs(txf * cellw);
+    run_bounds(txf * cellw);
+    runs();
     if (Mw > 0) {
         stage_chunk(txf * cellw, 0);
         if (lane == 0) atomicAdd(&sh.voted[tseq & 3], Mw);
@@ -646,6 +653,8 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         const uint32_t ox_lane = (uint32_t)(tx0 - my_gx) * (uint32_t)cellw;
         const bool next = ti + 1 < ntiles;  // block uniform
         const int32_t oxn = ox + a.tile_x * cellw;
+        // the next tile's run bounds load while this tile is voted
+        if (next) run_bounds(oxn);
         if (hv) {
             // a count is at most the tile's window entries; from 2^16 on the
             // tile takes the 32-bit form, which spans both histograms, after
@@ -694,7 +703,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
             const bool last = pass == npass - 1;
             // the next tile's runs and first chunk, while other waves still vote
             if (last && next) {
-                runs(oxn);
+                runs();
                 if (Mw > 0) {
                     stage_chunk(oxn, 0);
                     if (lane == 0) atomicAdd(&sh.voted[(tseq + 1) & 3], Mw);
