@@ -524,7 +524,11 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         for (int s2 = 0; s2 < 2; ++s2)
             window_run(c, sh, pair_epoch(s2), rowb[s2], oxw, W, src[s2], end[s2]);
     };
+    // Wave priorities: the window runs and the staging gate the next tile
+    // and run at priority 2, the read-out at 1; the votes, which other waves
+    // of the CU keep issuing, at 0.
     const auto runs = [&]() __attribute__((always_inline)) {
+        __builtin_amdgcn_s_setprio(2);
         // the bounds are consumed here and no earlier: nothing that waits for
         // their loads is moved above the votes they overlap
         asm volatile("" : "+v"(src[0]), "+v"(end[0]), "+v"(src[1]), "+v"(end[1]));
@@ -547,6 +551,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
     // owner.  kStageBlocks blocks are loaded before any is tested.
     int32_t *const hd = sh.heads[wave];
     const auto stage_chunk = [&](int32_t oxw, int32_t c0) __attribute__((always_inline)) {
+        __builtin_amdgcn_s_setprio(2);
         const int32_t c1 = min(c0 + wcap, Mw);
         const bool two = nq > 64;  // slot 1 holds pairs (wave uniform)
         // owner of entry c0: its run may have started in an earlier chunk
@@ -627,6 +632,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        __builtin_amdgcn_s_setprio(0);
     };
 
     run_bounds(txf * cellw);
@@ -733,6 +739,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
 
             // 3. read and clear the histogram; emit or queue interior cells
             if (any) {
+                __builtin_amdgcn_s_setprio(1);
                 // words of this tile's histogram, and its first word
                 const int rw = form == kForm32 ? hist_words : hist_words / 2;
                 uint4 *hb = smem4 + (form == kFormHalves && hv ? (tseq & 1) * (hist_words / 8) : 0);
@@ -801,6 +808,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                     }
                 }
             }
+            __builtin_amdgcn_s_setprio(0);
             // the histogram is clear before the next tile's (pass's) votes; after
             // a 16-bit tile of two histograms the next one votes into the other
             // histogram, cleared before this tile's barrier
