@@ -95,14 +95,33 @@ __device__ inline int32_t shift_q8(int32_t v, int32_t d) {
     return (int32_t)(((int64_t)v * (int64_t)d + 65535) >> 16);
 }
 
+// Device memory reached through the pointers of the argument struct.  The
+// batched kernel reads that struct from a table in device memory, where the
+// compiler cannot tell the pointers' address space; flat accesses count
+// against the LDS wait counter as well, so every LDS wait of the kernel would
+// also wait for the catalog loads in flight.  Accesses through gmem() are
+// global accesses.
+template <class T>
+__device__ __attribute__((always_inline)) inline __attribute__((address_space(1))) T *gmem(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+// The HIP vector types are classes whose operators take generic objects:
+// 8- and 16-byte records go through plain vector types.
+typedef int32_t gv2i __attribute__((ext_vector_type(2)));
+typedef uint32_t gv4u __attribute__((ext_vector_type(4)));
+__device__ __attribute__((always_inline)) inline int2 load_g(const int2 *p) {
+    const gv2i v = *gmem((const gv2i *)p);
+    return make_int2(v.x, v.y);
+}
+__device__ __attribute__((always_inline)) inline void store_g(void *p, uint32_t x, uint32_t y,
+                                                              uint32_t z, uint32_t w) {
+    *gmem((gv4u *)p) = gv4u{x, y, z, w};
+}
+
 __device__ inline void write_cand(sas_candidate *cand, int64_t idx, uint32_t v_idx, int32_t bx,
                                   int32_t by, uint32_t cnt, uint32_t sat) {
-    uint4 rec;
-    rec.x = v_idx;
-    rec.y = (uint32_t)bx;
-    rec.z = (uint32_t)by;
-    rec.w = (cnt > sat ? sat : cnt) | ((cnt > sat ? 1u : 0u) << 16);
-    *(uint4 *)(cand + idx) = rec;
+    store_g(cand + idx, v_idx, (uint32_t)bx, (uint32_t)by,
+            (cnt > sat ? sat : cnt) | ((cnt > sat ? 1u : 0u) << 16));
 }
 
 // Wave-aggregated append: one global atomic per wave; returns the slot of
@@ -111,7 +130,9 @@ __device__ inline int64_t wave_append(bool ok, unsigned long long *counter) {
     const uint64_t mask = __ballot(ok);
     if (mask == 0) return 0;
     unsigned long long base = 0;
-    if (__lane_id() == 0) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
+    if (__lane_id() == 0)
+        base = __hip_atomic_fetch_add(gmem(counter), (unsigned long long)__popcll(mask),
+                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     base = __shfl(base, 0, 64);
     const uint32_t pre = __builtin_amdgcn_mbcnt_hi(
         (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -269,7 +290,8 @@ __device__ __attribute__((always_inline)) inline int32_t window_row(
     int cy0, cy1;
     if (!cell_span(ylo, yhi, c.y0, c.y1, c.cell_log2, &cy0, &cy1)) return -1;
     if (r == 0 && cy1 - cy0 + 1 > a.rows)  // excluded by the planner
-        atomicOr(&a.res->status, SAS_DATA_INTERNAL);
+        __hip_atomic_fetch_or(gmem(&a.res->status), (int32_t)SAS_DATA_INTERNAL, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT);
     if (cy0 + r > cy1) return -1;
     return e * (c.ncx + 1) * c.ncy + cy0 + r;  // < 2^30 words (planner)
 }
@@ -286,8 +308,8 @@ __device__ __attribute__((always_inline)) inline void window_run(
     if (!cell_span(oxw + sh.es[e].x, oxw + sh.es[e].y + W, c.x0, c.x1, c.cell_log2, &cx0,
                    &cx1))
         return;
-    src = c.offT[row + cx0 * c.ncy];
-    end = c.offT[row + (cx1 + 1) * c.ncy];
+    src = gmem(c.offT)[row + cx0 * c.ncy];
+    end = gmem(c.offT)[row + (cx1 + 1) * c.ncy];
 }
 
 // Exclusive scan over the 64 lanes of a wave (all lanes active); *total gets
@@ -392,15 +414,15 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
     const bool hv = G == 1 && !PK && kHalvesOk && a.halves == 1;
     const bool hs = (G > 1 || PK) && kHalvesOk && a.halves == 2;
     const int LR = a.rows_log2;  // run rows per epoch: 2^LR
-    const int32_t vx_lo = a.seg[4 * sg], vx_hi = a.seg[4 * sg + 1];
-    const int32_t vy_lo = a.seg[4 * sg + 2], vy_hi = a.seg[4 * sg + 3];
+    const int32_t vx_lo = gmem(a.seg)[4 * sg], vx_hi = gmem(a.seg)[4 * sg + 1];
+    const int32_t vy_lo = gmem(a.seg)[4 * sg + 2], vy_hi = gmem(a.seg)[4 * sg + 3];
     __syncthreads();  // the previous item no longer reads the segment tables
     if (tid < NV) {
         const int64_t o = (int64_t)sg * NV + tid;
-        sh.sv[tid] = a.seg_v[o];
-        sh.svx[tid] = a.seg_vel[2 * o];
-        sh.svy[tid] = a.seg_vel[2 * o + 1];
-        sh.sg[tid] = a.seg_guard[o];
+        sh.sv[tid] = gmem(a.seg_v)[o];
+        sh.svx[tid] = gmem(a.seg_vel)[2 * o];
+        sh.svy[tid] = gmem(a.seg_vel)[2 * o + 1];
+        sh.sg[tid] = gmem(a.seg_guard)[o];
     }
     if (tid < E) {  // shifts of the segment's box edges
         const int32_t d = sh.dt[tid];
@@ -594,7 +616,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                     sb = q < 64 ? sb : sbh;
                 }
                 if (p < c1) {
-                    ent[u] = c.sxy[p + sb];
+                    ent[u] = load_g(c.sxy + p + sb);
                     ek[u] = q >> LR;
                 }
             }
@@ -647,7 +669,8 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
     __syncthreads();
     if (sh.bad) {  // excluded by the planner's guard cells; block uniform
         if (tid == 0) {
-            atomicOr(&a.res->status, SAS_DATA_INTERNAL);
+            __hip_atomic_fetch_or(gmem(&a.res->status), (int32_t)SAS_DATA_INTERNAL, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
             sh.voted[tseq & 3] = 0;  // the first tile is not voted
         }
         return;
@@ -760,7 +783,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                     if (refined_mode<MODE>()) {
                         const int64_t idx = wave_append(ok, a.refine_count);
                         if (ok && idx < a.refine_cap)
-                            a.refine[idx] = make_int4((int32_t)v, bx, by, 0);
+                            store_g(a.refine + idx, v, (uint32_t)bx, (uint32_t)by, 0u);
                     } else {
                         const int64_t idx = wave_append(ok, (unsigned long long *)&a.res->n_cand);
                         if (ok && idx < a.cand_cap)
@@ -910,7 +933,8 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(kWavesPe
         sh.n_spill = 0;
     }
     int later_t0 = 0;  // some chip's reference epoch is later than its earliest epoch
-    for (int c = tid; c < n_chips; c += T) later_t0 |= chips[c].cat.dt[chips[c].e_first] != 0;
+    for (int c = tid; c < n_chips; c += T)
+        later_t0 |= gmem(chips[c].cat.dt)[chips[c].e_first] != 0;
     later_t0 = __syncthreads_or(later_t0);
     const int64_t n_walk = later_t0 ? n_items : n_kept;
     const int x0 = blockIdx.x % kXcds;
@@ -927,16 +951,17 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(kWavesPe
         int chip = it[0];
         if (chip < 0) {  // skipped tiles of chip ~chip: block uniform
             chip = ~chip;
-            if (chips[chip].cat.dt[chips[chip].e_first] == 0) continue;
+            if (gmem(chips[chip].cat.dt)[chips[chip].e_first] == 0) continue;
         }
         const DenseArgs &a = chips[chip];
         if (chip != chip_now) {
             __syncthreads();  // the previous item no longer reads sh.dt or the stage
             if (tid == 0 && sh.n_spill) {  // the previous chip's chunked tiles
-                atomicAdd(&chips[chip_now].res->n_spilled, sh.n_spill);
+                __hip_atomic_fetch_add(gmem(&chips[chip_now].res->n_spilled), sh.n_spill,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 sh.n_spill = 0;
             }
-            if (tid < a.cat.n_epochs) sh.dt[tid] = a.cat.dt[tid];
+            if (tid < a.cat.n_epochs) sh.dt[tid] = gmem(a.cat.dt)[tid];
             // this chip's histogram may cover what was the previous chip's stage
             const int hw = a.hx * a.hy * (64 / G) / (a.halves == 2 ? 2 : 1);
             for (int i = tid; i < hw / 4; i += T) smem4[i] = make_uint4(0, 0, 0, 0);
@@ -947,7 +972,9 @@ __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(kWavesPe
     }
     __syncthreads();
     if (tid == 0 && sh.count_on && sh.n_instr) atomicAdd(atomics, sh.n_instr);
-    if (tid == 0 && sh.n_spill) atomicAdd(&chips[chip_now].res->n_spilled, sh.n_spill);
+    if (tid == 0 && sh.n_spill)
+        __hip_atomic_fetch_add(gmem(&chips[chip_now].res->n_spilled), sh.n_spill, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Exact bins of a queued cell: for velocity v and the cell's 2^m x 2^m
@@ -1069,9 +1096,11 @@ hipError_t set_lds_limit(const void *fn, size_t lds, size_t *lds_set) {
 // epoch is a later one); the item queues balance the work.
 template <int G, bool PK>
 int64_t resident_grid(size_t lds, int64_t kept) {
-    int dev = 0, n_cu = 256;
-    if (hipGetDevice(&dev) == hipSuccess)
-        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    int dev = 0, n_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n_cu <= 0)
+        n_cu = 256;  // MI355X
     const int64_t per_cu = std::max<int64_t>(
         1, std::min<int64_t>(kLdsPerCU / (int64_t)(lds + sizeof(Shared)),
                              kWavesPerSimd<G, PK> * 4 / NW));
