@@ -389,6 +389,9 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
     Entry *stage = (Entry *)(hist + (a.halves == 2 ? hist_words / 2 : hist_words));
 
     const PreparedCatalog &c = a.cat;
+    // held in registers: the batched kernel's arguments live in device memory,
+    // and the staging's wavefront fences would reload it per block of entries
+    const int2 *const sxy = c.sxy;
     const int E = c.n_epochs;
     const int tid = threadIdx.x, lane = __lane_id();
     // the wave index in a scalar register: the per-epoch and per-chunk
@@ -616,7 +619,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                     sb = q < 64 ? sb : sbh;
                 }
                 if (p < c1) {
-                    ent[u] = load_g(c.sxy + p + sb);
+                    ent[u] = load_g(sxy + p + sb);
                     ek[u] = q >> LR;
                 }
             }
