@@ -531,6 +531,10 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
     int32_t rsb[2], rlen[2], rpre[2];  // per slot: run source - position, length, position
     int32_t Mw = 0;              // this wave's window-index entries of the tile (wave uniform)
     int32_t my_b = 0, my_n = 0;  // lane k < KW: stage start and count of epoch k
+    // lane k < KW: d of epoch wave + k NW.  The per-epoch loop takes it with a
+    // lane read: an LDS load there would wait for every vote the wave has in
+    // flight.
+    const int32_t my_d = lane < KW ? sh.dt[wave + lane * NW] : -1;
     int32_t rowb[2];             // window-index row of each slot's pair (-1: none)
     // epoch of slot s2's pair (clamped for empty slots)
     const auto pair_epoch = [&](int s2) __attribute__((always_inline)) {
@@ -721,7 +725,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
                     const int32_t n = __builtin_amdgcn_readlane(my_n, k);
                     if (n == 0) continue;
                     const int32_t b = __builtin_amdgcn_readlane(my_b, k);
-                    const int32_t d = sh.dt[e];
+                    const int32_t d = __builtin_amdgcn_readlane(my_d, k);
                     const int32_t sx = shift_q8(my_vx, d) + (int32_t)ox_lane;
                     const int32_t sy = shift_q8(my_vy, d) + (int32_t)oy_lane;
                     const int32_t sxv = PK   ? (int32_t)pack16(sx, sy)
