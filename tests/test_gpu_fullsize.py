@@ -216,3 +216,43 @@ def test_batch_with_a_later_reference_epoch(gpu):
     finally:
         for plan in plans:
             plan.close()
+
+
+def test_repeated_and_replayed_votes_keep_the_list(gpu):
+    """The persistent vote takes its work items by tickets from per-XCD
+    queues that the preparation clears on every vote, and most items are
+    taken by workgroups of other XCDs once their own range is done.  Votes
+    repeated on one workspace, and replays of a captured vote with other
+    work between them, each give the oracle's whole wide list."""
+    import torch
+    if not os.path.exists(golden.path_of("wide")):
+        pytest.skip("the oracle's wide list is not written yet (tests/golden/make_full_lists.py)")
+    head, ref = golden.read("wide")
+    wl, v = golden.workload("wide")
+    plan = sas.Plan(v, wl.t_q16, wl.binw_q8, wl.n_min, wl.extent_q8,
+                    count_sat=golden.SAT["wide"], tuning=dict(n_det_hint=wl.n))
+    try:
+        info = plan.info()
+        _say(f"wide: {info['n_items_kept']} kept items, {info['n_tiles_kept']} kept tiles")
+        assert info["n_items_kept"] > 8 * 256  # far more items than resident workgroups
+        s = sas.Search(plan, wl.n, cand_cap=1 << 22)
+        x, y, e = s.upload(wl.x_q8, wl.y_q8, wl.epoch)
+        for rep in range(3):
+            _say(f"eager vote {rep}")
+            s.vote(x, y, e)
+            assert_same(s.peaks(), ref)
+        stream = torch.cuda.Stream()
+        g = torch.cuda.CUDAGraph()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=stream):
+            s.vote(x, y, e, stream=torch.cuda.current_stream())
+        for rep in range(3):
+            _say(f"graph replay {rep}")
+            s.res.fill_(-1)  # eager work between replays
+            s.cand.fill_(-1)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert_same(s.peaks(), ref)
+    finally:
+        plan.close()
