@@ -363,8 +363,9 @@ __device__ inline void put_entry(int2 *dst, int2 q) { *dst = q; }
 __device__ inline void put_entry(uint32_t *dst, int2 q) { *dst = pack16(q.x, q.y); }
 
 // Blocks of 64 window-index entries whose loads a wave issues before testing
-// any of them.
-constexpr int kStageBlocks = 2;
+// any of them (one: measured faster than two, three or four in every kernel,
+// whose other waves keep the loads' latency covered).
+constexpr int kStageBlocks = 1;
 
 // Dynamic LDS: histogram [HY][HX][NV] words, then the stage (int2), one
 // part of stage_cap / NW detections per wave.
@@ -595,7 +596,7 @@ __device__ void vote_item(const DenseArgs &a, Shared &sh, uint4 *smem4, int32_t 
         const int32_t pk0 = __shfl(rpre[0], qk & 63, 64), pk1 = __shfl(rpre[1], qk & 63, 64);
         const int32_t pk = min(max(lane < KW ? (qk < 64 ? pk0 : pk1) : Mw, c0), c1);
         int32_t mb = 0, kept = 0;
-        constexpr int SB = kWavesPerSimd<G, PK> == 6 ? 1 : kStageBlocks;
+        constexpr int SB = kStageBlocks;
         for (int32_t b0 = c0; b0 < c1; b0 += SB * 64) {
             int2 ent[SB];
             int32_t ek[SB];
